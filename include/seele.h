@@ -1,0 +1,255 @@
+/*
+ * seele.h -- C ABI of the MI355X (gfx950) Gaussian-splatting hot path of
+ * "Seele: A Unified Acceleration Framework for Real-Time Gaussian Splatting
+ * on Mobile Devices" (arXiv 2503.05168).
+ *
+ * The pipeline the paper describes for one frame (Sec. 3.1 Preliminaries):
+ *   preprocessing  -> seele_preprocess   (frustum/opacity culling, EWA
+ *                                          projection, SH colour, tile extent;
+ *                                          the opacity-aware extent of Sec. 3.3
+ *                                          Eqs. 4-5; the hybrid-preprocessing
+ *                                          active set of Sec. 3.3 "Algorithm")
+ *   sorting        -> seele_bin_sort     (Gaussian-tile pairs, per-tile
+ *                                          closest-to-furthest order)
+ *   rasterization  -> seele_rasterize_fwd (Eqs. 1-2, plain or the
+ *                                          contribution-aware Algorithm 1 of
+ *                                          Sec. 3.4)
+ *   fine-tuning    -> seele_rasterize_bwd (Sec. 3.5: gradients of the unchanged
+ *                                          pipeline with the HP/CR decisions
+ *                                          held fixed)
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a device pointer to caller-owned memory unless
+ *    the comment says "host".  The library allocates and frees nothing and
+ *    keeps no state between calls; calls on different streams may overlap.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and nothing synchronises.  Inputs are read-only; outputs are fully
+ *    overwritten.
+ *  - Arguments are validated on the host before anything is enqueued.  On
+ *    any non-zero status nothing has been enqueued unless the status is
+ *    SEELE_ERR_HIP (a launch failed; the stream state is then undefined).
+ *    seele_last_error() returns a thread-local message for the last failure.
+ *  - Several views are handled by one call: per-view outputs are stored view
+ *    after view (view v's block starts after views 0..v-1's blocks).
+ *  - Cameras use OpenCV axes (+x right, +y down, +z forward), a world-to-
+ *    camera transform x_c = R x_w + t, pinhole intrinsics and pixel centres
+ *    at integer + 0.5.
+ */
+#ifndef SEELE_H
+#define SEELE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every entry point. */
+enum {
+  SEELE_OK = 0,
+  SEELE_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, bad size or option */
+  SEELE_ERR_UNSUPPORTED = 2,  /* valid but not supported by this build       */
+  SEELE_ERR_CAPACITY = 3,     /* a caller buffer is too small                */
+  SEELE_ERR_HIP = 4           /* a HIP runtime call or launch failed         */
+};
+
+/* Tile extent of a projected Gaussian (Sec. 3.3 "Online Filtering"). */
+enum {
+  SEELE_EXTENT_3SIGMA = 0,  /* circle of radius 3 sqrt(lambda_max(Sigma')), Eq. 3 */
+  SEELE_EXTENT_OPACITY = 1  /* box of the ellipse d^T Sigma'^-1 d <= min(2 ln(o/alpha_theta), 9), Eq. 5 */
+};
+
+/* Rasterization form. */
+enum {
+  SEELE_RASTER_PLAIN = 0,   /* every pixel evaluates every listed Gaussian (Eqs. 1-2) */
+  SEELE_RASTER_CONTRIB = 1  /* contribution-aware: a pixel group follows its leader's
+                               alpha test (Sec. 3.4, Algorithm 1) */
+};
+
+/* 3D Gaussians, structure of arrays (device, float32).  sh_degree in 0..3;
+ * the SH coefficient stride is always 16 (unused higher-degree slots are
+ * not read). */
+typedef struct seele_gaussians {
+  int64_t n;                    /* number of Gaussians, 0 <= n < 2^31        */
+  int32_t sh_degree;            /* 0..3                                       */
+  int32_t reserved;
+  const float* means;           /* [3][n] world positions                     */
+  const float* log_scales;      /* [3][n] log of the per-axis std deviations  */
+  const float* quats;           /* [4][n] rotation (w, x, y, z), any norm > 0 */
+  const float* opacity_logits;  /* [n]    o = sigmoid(logit)                  */
+  const float* sh;              /* [16][3][n] (coefficient, channel, Gaussian)
+                                   coefficient index l*l + l + m             */
+} seele_gaussians;
+
+/* Gradients in the layout of seele_gaussians (device, float32, overwritten). */
+typedef struct seele_gaussian_grads {
+  float* means;           /* [3][n]  */
+  float* log_scales;      /* [3][n]  */
+  float* quats;           /* [4][n]  */
+  float* opacity_logits;  /* [n]     */
+  float* sh;              /* [16][3][n] */
+} seele_gaussian_grads;
+
+/* A pinhole camera (host struct, 72 bytes). */
+typedef struct seele_camera {
+  float R[9];             /* world->camera rotation, row-major */
+  float t[3];             /* world->camera translation         */
+  float fx, fy, cx, cy;   /* focal lengths and principal point, pixels */
+  int32_t width, height;  /* image size, pixels, >= 1          */
+} seele_camera;
+
+/* One projected Gaussian for one view (48 bytes).  Written by
+ * seele_preprocess for visible Gaussians only (records of culled Gaussians
+ * are left untouched and never read).  rect_x = x0 | x1 << 16 and
+ * rect_y = y0 | y1 << 16 give the half-open tile rectangle
+ * [x0, x1) x [y0, y1). */
+typedef struct seele_splat {
+  float mean_x, mean_y;              /* x' (pixels)                         */
+  float conic_a, conic_b, conic_c;   /* Sigma'^-1 = [[a, b], [b, c]]       */
+  float opacity;                     /* o                                   */
+  float r, g, b;                     /* view-dependent colour (clamped >= 0) */
+  float depth;                       /* camera-space z                      */
+  uint32_t rect_x, rect_y;
+} seele_splat;
+
+/* Preprocessing options. */
+typedef struct seele_preprocess_opts {
+  int32_t tile;             /* tile edge in pixels: 8 or 16                     */
+  int32_t extent;           /* SEELE_EXTENT_*                                    */
+  float alpha_min;          /* alpha_theta (1/255)                               */
+  float lowpass;            /* added to the diagonal of Sigma' (0.3 px^2)        */
+  float z_near;             /* Gaussians with camera z <= z_near are culled (0.2) */
+  int32_t n_segs;           /* active segments (hybrid preprocessing); 0 = all   */
+  const int64_t* seg_begin; /* host [n_segs], disjoint, inside [0, n)            */
+  const int64_t* seg_count; /* host [n_segs]                                     */
+} seele_preprocess_opts;
+
+/* Rasterization options. */
+typedef struct seele_raster_opts {
+  int32_t tile;             /* must equal the tile used by preprocess/bin_sort */
+  int32_t mode;             /* SEELE_RASTER_*                                  */
+  int32_t group_w, group_h; /* contribution-aware pixel group (2, 2); each of
+                               1, 2, 4 with group_w * group_h <= 16            */
+  float alpha_min;          /* alpha_theta (1/255)                             */
+  float alpha_max;          /* clamp of alpha (0.99)                           */
+  float T_min;              /* a pixel stops before T would fall below (1e-4)   */
+  float bg[3];              /* background colour added as T_final * bg         */
+} seele_raster_opts;
+
+/* Number of tiles of view v is ceil(W/tile) * ceil(H/tile); this returns the
+ * sum over the views (the length of the tile_ranges array), or -1 on bad
+ * arguments.  cams is a host array. */
+int64_t seele_total_tiles(const seele_camera* cams, int32_t n_views, int32_t tile);
+
+/* Preprocess n_views views of g (Sec. 3.1 "Preprocessing", Sec. 3.3 "Online
+ * Filtering").  For view v and Gaussian i, record v*n + i of `splats` and
+ * `n_tiles` is written: n_tiles = number of tiles of its rectangle, or 0 if
+ * the Gaussian is culled (inactive segment, non-finite attribute, z <=
+ * z_near, degenerate Sigma', o < alpha_min (3-sigma extent) or
+ * tau <= 0 (opacity extent), empty rectangle).
+ *   cams    host [n_views]
+ *   splats  device [n_views * n] seele_splat, 16-byte aligned
+ *   n_tiles device [n_views * n] int32 */
+int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                         const seele_preprocess_opts* opts, seele_splat* splats,
+                         int32_t* n_tiles, void* stream);
+
+/* Workspace bytes seele_bin_sort needs for n_records = n_views * n records,
+ * a pair capacity and the total tile count. */
+size_t seele_bin_sort_workspace_size(int64_t n_records, int64_t capacity, int64_t n_tiles_total);
+
+/* Tile binning and depth sort (Sec. 3.1 "Preprocessing" and "Sorting").
+ * Every record with n_tiles > 0 yields one pair per tile of its rectangle.
+ * Pairs are ordered by (global tile id, float32 depth, record id), where the
+ * global tile id of local tile (tx, ty) in view v is
+ * sum_{u<v} tiles(u) + ty * ceil(W_v/tile) + tx.
+ *   sorted_ids  device [capacity] uint32: record ids v*n + i in that order
+ *   tile_ranges device [n_tiles_total][2] int32: [start, end) into sorted_ids
+ *                (start = end = 0 for an empty tile)
+ *   num_pairs   device [1] int64: the number of pairs the frame needs.
+ * If that number exceeds `capacity`, every tile range is written empty and
+ * sorted_ids is not written; the caller reads num_pairs, grows the buffer
+ * and calls again (the call itself still returns SEELE_OK because the count
+ * is only known on the device).  capacity < 2^31.  n_views <= 256. */
+int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+                       const seele_camera* cams, int32_t n_views, int32_t tile,
+                       void* workspace, size_t workspace_bytes, uint32_t* sorted_ids,
+                       int64_t capacity, int32_t* tile_ranges, int64_t* num_pairs,
+                       void* stream);
+
+/* Front-to-back blending of every tile of every view (Eqs. 1-2; Algorithm 1
+ * when opts->mode == SEELE_RASTER_CONTRIB).
+ *   image     device, per view [3][H][W] float32, views concatenated
+ *   final_T   device, per view [H][W] float32: transmittance after the last
+ *             blended Gaussian (>= T_min)
+ *   n_contrib device, per view [H][W] int32: 1-based position, in the pixel's
+ *             tile list, of the last Gaussian it blended (0 if none). */
+int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_ids,
+                            const int32_t* tile_ranges, const seele_camera* cams,
+                            int32_t n_views, const seele_raster_opts* opts, float* image,
+                            float* final_T, int32_t* n_contrib, void* stream);
+
+/* seele_rasterize_fwd with work counters (an instrumented, slower kernel
+ * that writes the same outputs).  counters: device [4] uint64, overwritten:
+ *   [0] per-pixel alpha evaluations by pixels that have not stopped
+ *       (contribution-aware form: only in groups whose leader accepted),
+ *   [1] blends (Gaussians accumulated into a pixel),
+ *   [2] leader tests of groups with a pixel that has not stopped,
+ *   [3] of those, tests that accepted the Gaussian.
+ * These are the algorithmic work units of Eqs. 1-2 and Algorithm 1. */
+int32_t seele_rasterize_fwd_counted(const seele_splat* splats, const uint32_t* sorted_ids,
+                                    const int32_t* tile_ranges, const seele_camera* cams,
+                                    int32_t n_views, const seele_raster_opts* opts, float* image,
+                                    float* final_T, int32_t* n_contrib, uint64_t* counters,
+                                    void* stream);
+
+/* Gradients of a scalar loss L for the fine-tuning of Sec. 3.5, given
+ * dL/dimage (same layout as image).  The forward's decisions (culling,
+ * rectangles, order, alpha skips, leader tests, termination) are constants;
+ * the blend is recomputed backwards from final_T and n_contrib, so no
+ * per-pixel lists are stored.
+ *   grad2d device [n_views * n][9] float32, written by the call: per record
+ *          dL/d(mean_x, mean_y, conic_a, conic_b, conic_c, opacity, r, g, b)
+ *          (zero for records no pixel blended)
+ *   grads  overwritten with dL/d(raw parameters), summed over views.
+ * g, cams, popts and n_views must be those of the forward call that wrote
+ * splats/n_tiles; ropts those of the seele_rasterize_fwd call. */
+int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                            const seele_preprocess_opts* popts, const seele_raster_opts* ropts,
+                            const seele_splat* splats, const int32_t* n_tiles,
+                            const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                            const float* final_T, const int32_t* n_contrib,
+                            const float* dL_dimage, float* grad2d,
+                            const seele_gaussian_grads* grads, void* stream);
+
+/* Hybrid preprocessing, runtime cluster choice (Sec. 3.3 "Algorithm").  The
+ * camera feature is (centre / pos_scale, beta * view direction); the nearest
+ * of the K centroids (host [K][6]) is chosen, then the M centroids nearest to
+ * it; ties go to the lower index.  clusters: host [1 + M] output.  Host only,
+ * enqueues nothing. */
+int32_t seele_hp_select(const float* centroids, int32_t K, const seele_camera* cam,
+                        float pos_scale, float beta, int32_t M, int32_t* clusters);
+
+/* Active segments for the chosen clusters of a layout
+ * [shared | excl_0 | ... | excl_{K-1}] given by host arrays
+ * layout_begin[1 + K], layout_count[1 + K]: the shared segment plus each
+ * chosen cluster's segment, sorted by begin, empty ones dropped.  out_begin
+ * and out_count are host arrays of capacity 1 + n_sel; *n_out receives the
+ * segment count.  Host only. */
+int32_t seele_hp_segments(const int64_t* layout_begin, const int64_t* layout_count, int32_t K,
+                          const int32_t* clusters, int32_t n_sel, int64_t* out_begin,
+                          int64_t* out_count, int32_t* n_out);
+
+/* Thread-local message describing the last non-OK status on this thread. */
+const char* seele_last_error(void);
+/* Static name of a status code. */
+const char* seele_status_string(int32_t status);
+/* ABI version (major * 100 + minor). */
+int32_t seele_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEELE_H */

@@ -107,9 +107,11 @@ def project_view(scene, cam, tile: int = 16, extent: str = "3sigma",
     grid_w, grid_h = -(-W // tile), -(-H // tile)
 
     with np.errstate(all="ignore"):
+        nb_used = (g["sh_degree"] + 1) ** 2
         finite = (np.isfinite(g["means"]).all(1) & np.isfinite(g["log_scales"]).all(1)
                   & np.isfinite(g["quats"]).all(1) & np.isfinite(g["logits"])
-                  & np.isfinite(g["sh"]).all((1, 2)) & (np.linalg.norm(g["quats"], axis=1) > 0))
+                  & np.isfinite(g["sh"][:, :nb_used, :]).all((1, 2))
+                  & (np.linalg.norm(g["quats"], axis=1) > 0))
         Sigma = covariance3d(g["log_scales"], g["quats"])
         o = sigmoid(g["logits"])
         t = g["means"] @ Rw.T + tw

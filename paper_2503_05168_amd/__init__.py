@@ -1,0 +1,21 @@
+"""MI355X (gfx950) hot path of Seele (arXiv 2503.05168): preprocessing with
+hybrid view-dependent filtering, tile binning with a depth-keyed radix sort,
+plain and contribution-aware rasterization, and its backward pass, as HIP
+kernels behind the C ABI in include/seele.h.  This package is the Python
+binding: argument marshalling only."""
+from ._abi import lib, SeeleError  # noqa: F401
+from .pipeline import (  # noqa: F401
+    GaussianTensors,
+    Settings,
+    Renderer,
+    Frame,
+    seele_preprocess,
+    seele_bin_sort,
+    seele_rasterize_fwd,
+    seele_rasterize_fwd_counted,
+    seele_hp_select,
+    seele_hp_segments,
+    total_tiles,
+    pixel_count,
+    split_views,
+)

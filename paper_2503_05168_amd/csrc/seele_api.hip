@@ -1,0 +1,457 @@
+// extern "C" entry points of libseele: argument validation on the host, then
+// kernel launches on the caller's stream.  Nothing here allocates device
+// memory or synchronises.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "seele_internal.h"
+
+using namespace seele;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* where) {
+  return fail(SEELE_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool is_finite(float v) { return std::isfinite(v); }
+
+int32_t check_camera(const seele_camera& c, int v, int tile) {
+  for (int k = 0; k < 9; ++k)
+    if (!is_finite(c.R[k])) return fail(SEELE_ERR_INVALID_ARG, "camera %d: non-finite R", v);
+  for (int k = 0; k < 3; ++k)
+    if (!is_finite(c.t[k])) return fail(SEELE_ERR_INVALID_ARG, "camera %d: non-finite t", v);
+  if (!is_finite(c.fx) || !is_finite(c.fy) || !is_finite(c.cx) || !is_finite(c.cy) || c.fx <= 0 ||
+      c.fy <= 0)
+    return fail(SEELE_ERR_INVALID_ARG, "camera %d: bad intrinsics", v);
+  if (c.width < 1 || c.height < 1)
+    return fail(SEELE_ERR_INVALID_ARG, "camera %d: image size %dx%d", v, c.width, c.height);
+  const int64_t gw = (c.width + tile - 1) / tile, gh = (c.height + tile - 1) / tile;
+  if (gw > 65535 || gh > 65535)
+    return fail(SEELE_ERR_UNSUPPORTED, "camera %d: more than 65535 tiles along an axis", v);
+  return SEELE_OK;
+}
+
+int32_t check_cams(const seele_camera* cams, int32_t n_views, int tile, int max_views) {
+  if (!cams) return fail(SEELE_ERR_INVALID_ARG, "cams is null");
+  if (n_views < 1) return fail(SEELE_ERR_INVALID_ARG, "n_views must be >= 1 (got %d)", n_views);
+  if (n_views > max_views)
+    return fail(SEELE_ERR_UNSUPPORTED, "n_views %d exceeds %d", n_views, max_views);
+  if (tile != 8 && tile != 16) return fail(SEELE_ERR_INVALID_ARG, "tile must be 8 or 16");
+  for (int v = 0; v < n_views; ++v) {
+    const int32_t s = check_camera(cams[v], v, tile);
+    if (s != SEELE_OK) return s;
+  }
+  return SEELE_OK;
+}
+
+int64_t tiles_of(const seele_camera& c, int tile) {
+  return (int64_t)((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
+}
+
+CamK to_camk(const seele_camera& c, int tile) {
+  CamK k{};
+  for (int i = 0; i < 9; ++i) k.R[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) k.t[i] = c.t[i];
+  k.fx = c.fx;
+  k.fy = c.fy;
+  k.cx = c.cx;
+  k.cy = c.cy;
+  // camera centre C = -R^T t, in double
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < 3; ++j) s -= (double)c.R[j * 3 + i] * (double)c.t[j];
+    k.C[i] = (float)s;
+  }
+  k.W = c.width;
+  k.H = c.height;
+  k.gridW = (c.width + tile - 1) / tile;
+  k.gridH = (c.height + tile - 1) / tile;
+  return k;
+}
+
+int32_t check_gaussians(const seele_gaussians* g) {
+  if (!g) return fail(SEELE_ERR_INVALID_ARG, "gaussians is null");
+  if (g->n < 0 || g->n >= ((int64_t)1 << 31))
+    return fail(SEELE_ERR_INVALID_ARG, "n = %lld out of range", (long long)g->n);
+  if (g->sh_degree < 0 || g->sh_degree > 3)
+    return fail(SEELE_ERR_INVALID_ARG, "sh_degree %d not in 0..3", g->sh_degree);
+  if (g->n > 0) {
+    const void* p[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->sh};
+    const char* nm[5] = {"means", "log_scales", "quats", "opacity_logits", "sh"};
+    for (int k = 0; k < 5; ++k) {
+      if (!p[k]) return fail(SEELE_ERR_INVALID_ARG, "%s is null", nm[k]);
+      if (!aligned(p[k], 4)) return fail(SEELE_ERR_INVALID_ARG, "%s is misaligned", nm[k]);
+    }
+  }
+  return SEELE_OK;
+}
+
+int32_t check_preprocess_opts(const seele_preprocess_opts* o, int64_t n) {
+  if (!o) return fail(SEELE_ERR_INVALID_ARG, "opts is null");
+  if (o->tile != 8 && o->tile != 16) return fail(SEELE_ERR_INVALID_ARG, "tile must be 8 or 16");
+  if (o->extent != SEELE_EXTENT_3SIGMA && o->extent != SEELE_EXTENT_OPACITY)
+    return fail(SEELE_ERR_INVALID_ARG, "unknown extent mode %d", o->extent);
+  if (!(o->alpha_min > 0.0f && o->alpha_min < 1.0f))
+    return fail(SEELE_ERR_INVALID_ARG, "alpha_min must be in (0, 1)");
+  if (!(o->lowpass >= 0.0f) || !is_finite(o->lowpass))
+    return fail(SEELE_ERR_INVALID_ARG, "lowpass must be finite and >= 0");
+  if (!(o->z_near > 0.0f) || !is_finite(o->z_near))
+    return fail(SEELE_ERR_INVALID_ARG, "z_near must be finite and > 0");
+  if (o->n_segs < 0 || o->n_segs > kMaxSegs)
+    return fail(SEELE_ERR_UNSUPPORTED, "n_segs %d not in 0..%d", o->n_segs, kMaxSegs);
+  if (o->n_segs > 0 && (!o->seg_begin || !o->seg_count))
+    return fail(SEELE_ERR_INVALID_ARG, "segment arrays are null");
+  for (int s = 0; s < o->n_segs; ++s) {
+    const int64_t b = o->seg_begin[s], c = o->seg_count[s];
+    if (b < 0 || c < 0 || b > n || c > n - b)
+      return fail(SEELE_ERR_INVALID_ARG, "segment %d [%lld, +%lld) outside [0, %lld)", s,
+                  (long long)b, (long long)c, (long long)n);
+  }
+  return SEELE_OK;
+}
+
+int32_t check_raster_opts(const seele_raster_opts* o) {
+  if (!o) return fail(SEELE_ERR_INVALID_ARG, "raster opts is null");
+  if (o->tile != 8 && o->tile != 16) return fail(SEELE_ERR_INVALID_ARG, "tile must be 8 or 16");
+  if (o->mode != SEELE_RASTER_PLAIN && o->mode != SEELE_RASTER_CONTRIB)
+    return fail(SEELE_ERR_INVALID_ARG, "unknown raster mode %d", o->mode);
+  if (o->mode == SEELE_RASTER_CONTRIB) {
+    auto ok = [](int g) { return g == 1 || g == 2 || g == 4; };
+    if (!ok(o->group_w) || !ok(o->group_h) || o->group_w * o->group_h > 16)
+      return fail(SEELE_ERR_INVALID_ARG, "group %dx%d unsupported (each of 1, 2, 4; area <= 16)",
+                  o->group_w, o->group_h);
+  }
+  if (!(o->alpha_min > 0.0f && o->alpha_min < 1.0f))
+    return fail(SEELE_ERR_INVALID_ARG, "alpha_min must be in (0, 1)");
+  if (!(o->alpha_max > o->alpha_min && o->alpha_max < 1.0f))
+    return fail(SEELE_ERR_INVALID_ARG, "alpha_max must be in (alpha_min, 1)");
+  if (!(o->T_min > 0.0f && o->T_min < 1.0f))
+    return fail(SEELE_ERR_INVALID_ARG, "T_min must be in (0, 1)");
+  for (int c = 0; c < 3; ++c)
+    if (!is_finite(o->bg[c])) return fail(SEELE_ERR_INVALID_ARG, "non-finite background");
+  return SEELE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* seele_last_error(void) { return g_err.c_str(); }
+
+const char* seele_status_string(int32_t s) {
+  switch (s) {
+    case SEELE_OK: return "SEELE_OK";
+    case SEELE_ERR_INVALID_ARG: return "SEELE_ERR_INVALID_ARG";
+    case SEELE_ERR_UNSUPPORTED: return "SEELE_ERR_UNSUPPORTED";
+    case SEELE_ERR_CAPACITY: return "SEELE_ERR_CAPACITY";
+    case SEELE_ERR_HIP: return "SEELE_ERR_HIP";
+    default: return "SEELE_ERR_UNKNOWN";
+  }
+}
+
+int32_t seele_abi_version(void) { return 100; }
+
+int64_t seele_total_tiles(const seele_camera* cams, int32_t n_views, int32_t tile) {
+  if (!cams || n_views < 1 || (tile != 8 && tile != 16)) return -1;
+  int64_t t = 0;
+  for (int v = 0; v < n_views; ++v) {
+    if (cams[v].width < 1 || cams[v].height < 1) return -1;
+    t += tiles_of(cams[v], tile);
+  }
+  return t;
+}
+
+int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                         const seele_preprocess_opts* opts, seele_splat* splats,
+                         int32_t* n_tiles, void* stream) {
+  int32_t s = check_gaussians(g);
+  if (s != SEELE_OK) return s;
+  if ((s = check_preprocess_opts(opts, g->n)) != SEELE_OK) return s;
+  if ((s = check_cams(cams, n_views, opts->tile, 1 << 20)) != SEELE_OK) return s;
+  if ((int64_t)n_views * g->n >= ((int64_t)1 << 32))
+    return fail(SEELE_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+  if (g->n > 0) {
+    if (!splats || !aligned(splats, 16))
+      return fail(SEELE_ERR_INVALID_ARG, "splats must be non-null and 16-byte aligned");
+    if (!n_tiles || !aligned(n_tiles, 4))
+      return fail(SEELE_ERR_INVALID_ARG, "n_tiles must be non-null and 4-byte aligned");
+  }
+  if (g->n == 0) return SEELE_OK;
+  PreArgs a{};
+  a.n = g->n;
+  a.sh_degree = g->sh_degree;
+  a.tile = opts->tile;
+  a.extent = opts->extent;
+  a.alpha_min = opts->alpha_min;
+  a.lowpass = opts->lowpass;
+  a.z_near = opts->z_near;
+  a.n_segs = opts->n_segs;
+  for (int k = 0; k < opts->n_segs; ++k) {
+    a.seg_begin[k] = opts->seg_begin[k];
+    a.seg_end[k] = opts->seg_begin[k] + opts->seg_count[k];
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPre) {
+    const int nv = std::min(kMaxViewsPre, n_views - v0);
+    a.n_views = nv;
+    a.view0 = v0;
+    for (int k = 0; k < nv; ++k) a.cam[k] = to_camk(cams[v0 + k], opts->tile);
+    const hipError_t e = launch_preprocess(a, *g, splats, n_tiles, st);
+    if (e != hipSuccess) return hip_fail(e, "preprocess launch");
+  }
+  return SEELE_OK;
+}
+
+size_t seele_bin_sort_workspace_size(int64_t n_records, int64_t capacity, int64_t n_tiles_total) {
+  if (n_records < 0 || capacity < 0 || n_tiles_total < 0) return 0;
+  return plan_bin_sort(n_records, capacity, n_tiles_total).total;
+}
+
+int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+                       const seele_camera* cams, int32_t n_views, int32_t tile,
+                       void* workspace, size_t workspace_bytes, uint32_t* sorted_ids,
+                       int64_t capacity, int32_t* tile_ranges, int64_t* num_pairs,
+                       void* stream) {
+  int32_t s = check_cams(cams, n_views, tile, kMaxViewsBin);
+  if (s != SEELE_OK) return s;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SEELE_ERR_INVALID_ARG, "n out of range");
+  const int64_t R = (int64_t)n_views * n;
+  if (R >= ((int64_t)1 << 32)) return fail(SEELE_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+  if (capacity < 0 || capacity >= ((int64_t)1 << 31))
+    return fail(SEELE_ERR_INVALID_ARG, "capacity must be in [0, 2^31)");
+  const int64_t TT = seele_total_tiles(cams, n_views, tile);
+  if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
+  if (R > 0 && (!splats || !aligned(splats, 16) || !n_tiles || !aligned(n_tiles, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "splats/n_tiles null or misaligned");
+  if (capacity > 0 && (!sorted_ids || !aligned(sorted_ids, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "sorted_ids null or misaligned");
+  if (!tile_ranges || !aligned(tile_ranges, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
+  if (!num_pairs || !aligned(num_pairs, 8))
+    return fail(SEELE_ERR_INVALID_ARG, "num_pairs null or misaligned");
+  const BinSortPlan plan = plan_bin_sort(R, capacity, TT);
+  if (!workspace || !aligned(workspace, 256))
+    return fail(SEELE_ERR_INVALID_ARG, "workspace null or not 256-byte aligned");
+  if (workspace_bytes < plan.total)
+    return fail(SEELE_ERR_CAPACITY, "workspace %zu bytes < required %zu", workspace_bytes,
+                plan.total);
+  BinViews bv{};
+  bv.n_views = n_views;
+  bv.n = n;
+  int64_t base = 0;
+  for (int v = 0; v < n_views; ++v) {
+    bv.v[v].tile_base = (int32_t)base;
+    bv.v[v].grid_w = (cams[v].width + tile - 1) / tile;
+    base += tiles_of(cams[v], tile);
+  }
+  const hipError_t e = launch_bin_sort(plan, bv, splats, n_tiles, workspace, sorted_ids,
+                                       tile_ranges, num_pairs, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "bin_sort launch");
+  return SEELE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
+                  const int32_t* tile_ranges, const seele_camera* cams, int32_t n_views,
+                  const seele_raster_opts* opts, float* image, float* final_T,
+                  int32_t* n_contrib, uint64_t* counters, void* stream) {
+  int32_t s = check_raster_opts(opts);
+  if (s != SEELE_OK) return s;
+  if ((s = check_cams(cams, n_views, opts->tile, 1 << 20)) != SEELE_OK) return s;
+  const int64_t TT = seele_total_tiles(cams, n_views, opts->tile);
+  if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
+  if (!tile_ranges || !aligned(tile_ranges, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
+  if (!image || !aligned(image, 4) || !final_T || !aligned(final_T, 4) || !n_contrib ||
+      !aligned(n_contrib, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "output buffers null or misaligned");
+  if ((splats && !aligned(splats, 16)) || (sorted_ids && !aligned(sorted_ids, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "splats/sorted_ids misaligned");
+  RasterParams rp{};
+  rp.alpha_min = opts->alpha_min;
+  rp.alpha_max = opts->alpha_max;
+  rp.T_min = opts->T_min;
+  rp.bg0 = opts->bg[0];
+  rp.bg1 = opts->bg[1];
+  rp.bg2 = opts->bg[2];
+  rp.group_w = opts->mode == SEELE_RASTER_CONTRIB ? opts->group_w : 1;
+  rp.group_h = opts->mode == SEELE_RASTER_CONTRIB ? opts->group_h : 1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
+  if (cnt) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 4);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
+  }
+  int64_t tile_base = 0, pix_base = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsRaster) {
+    const int nv = std::min(kMaxViewsRaster, n_views - v0);
+    RasterViews rv{};
+    rv.n_views = nv;
+    rv.tile_base = (int32_t)tile_base;
+    int64_t t = 0;
+    for (int k = 0; k < nv; ++k) {
+      const seele_camera& c = cams[v0 + k];
+      rv.v[k].tile_begin = (int32_t)t;
+      rv.v[k].W = c.width;
+      rv.v[k].H = c.height;
+      rv.v[k].grid_w = (c.width + opts->tile - 1) / opts->tile;
+      rv.v[k].pix_base = pix_base;
+      t += tiles_of(c, opts->tile);
+      pix_base += (int64_t)c.width * c.height;
+    }
+    const hipError_t e = launch_raster_fwd(opts->tile, opts->mode, rv, (int)t, rp, splats,
+                                           sorted_ids, tile_ranges, image, final_T, n_contrib,
+                                           cnt, st);
+    if (e != hipSuccess) return hip_fail(e, "raster launch");
+    tile_base += t;
+  }
+  return SEELE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_ids,
+                            const int32_t* tile_ranges, const seele_camera* cams,
+                            int32_t n_views, const seele_raster_opts* opts, float* image,
+                            float* final_T, int32_t* n_contrib, void* stream) {
+  return rasterize(splats, sorted_ids, tile_ranges, cams, n_views, opts, image, final_T,
+                   n_contrib, nullptr, stream);
+}
+
+int32_t seele_rasterize_fwd_counted(const seele_splat* splats, const uint32_t* sorted_ids,
+                                    const int32_t* tile_ranges, const seele_camera* cams,
+                                    int32_t n_views, const seele_raster_opts* opts, float* image,
+                                    float* final_T, int32_t* n_contrib, uint64_t* counters,
+                                    void* stream) {
+  if (!counters || !aligned(counters, 8))
+    return fail(SEELE_ERR_INVALID_ARG, "counters null or misaligned");
+  return rasterize(splats, sorted_ids, tile_ranges, cams, n_views, opts, image, final_T,
+                   n_contrib, counters, stream);
+}
+
+int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                            const seele_preprocess_opts* popts, const seele_raster_opts* ropts,
+                            const seele_splat* splats, const int32_t* n_tiles,
+                            const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                            const float* final_T, const int32_t* n_contrib,
+                            const float* dL_dimage, float* grad2d,
+                            const seele_gaussian_grads* grads, void* stream) {
+  (void)g; (void)cams; (void)n_views; (void)popts; (void)ropts; (void)splats; (void)n_tiles;
+  (void)sorted_ids; (void)tile_ranges; (void)final_T; (void)n_contrib; (void)dL_dimage;
+  (void)grad2d; (void)grads; (void)stream;
+  return fail(SEELE_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+int32_t seele_hp_select(const float* centroids, int32_t K, const seele_camera* cam,
+                        float pos_scale, float beta, int32_t M, int32_t* clusters) {
+  if (!centroids || !cam || !clusters) return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (K < 1 || M < 0 || M > K - 1) return fail(SEELE_ERR_INVALID_ARG, "need K >= 1, 0 <= M < K");
+  if (!(pos_scale > 0.0f) || !is_finite(pos_scale) || !is_finite(beta))
+    return fail(SEELE_ERR_INVALID_ARG, "bad pos_scale/beta");
+  double f[6];
+  for (int i = 0; i < 3; ++i) {
+    double c = 0.0;
+    for (int j = 0; j < 3; ++j) c -= (double)cam->R[j * 3 + i] * (double)cam->t[j];
+    f[i] = c / (double)pos_scale;
+    f[3 + i] = (double)beta * (double)cam->R[6 + i];  // camera +z axis in world coordinates
+  }
+  auto dist2 = [&](int k, const double* p) {
+    double s = 0.0;
+    for (int i = 0; i < 6; ++i) {
+      const double d = (double)centroids[k * 6 + i] - p[i];
+      s += d * d;
+    }
+    return s;
+  };
+  int best = 0;
+  double bd = dist2(0, f);
+  for (int k = 1; k < K; ++k) {
+    const double d = dist2(k, f);
+    if (d < bd) {
+      bd = d;
+      best = k;
+    }
+  }
+  clusters[0] = best;
+  double c[6];
+  for (int i = 0; i < 6; ++i) c[i] = centroids[best * 6 + i];
+  // M nearest other centroids to the chosen one; selection keeps ties in index order
+  for (int m = 0; m < M; ++m) {
+    int pick = -1;
+    double pd = 0.0;
+    for (int k = 0; k < K; ++k) {
+      bool used = false;
+      for (int q = 0; q <= m; ++q) used |= clusters[q] == k;
+      if (used) continue;
+      const double d = dist2(k, c);
+      if (pick < 0 || d < pd) {
+        pick = k;
+        pd = d;
+      }
+    }
+    clusters[1 + m] = pick;
+  }
+  return SEELE_OK;
+}
+
+int32_t seele_hp_segments(const int64_t* layout_begin, const int64_t* layout_count, int32_t K,
+                          const int32_t* clusters, int32_t n_sel, int64_t* out_begin,
+                          int64_t* out_count, int32_t* n_out) {
+  if (!layout_begin || !layout_count || !out_begin || !out_count || !n_out ||
+      (n_sel > 0 && !clusters))
+    return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (K < 0 || n_sel < 0) return fail(SEELE_ERR_INVALID_ARG, "negative K or n_sel");
+  int cnt = 0;
+  auto add = [&](int64_t b, int64_t c) {
+    if (c <= 0) return;
+    for (int i = 0; i < cnt; ++i)
+      if (out_begin[i] == b) return;  // a cluster chosen twice
+    out_begin[cnt] = b;
+    out_count[cnt] = c;
+    ++cnt;
+  };
+  add(layout_begin[0], layout_count[0]);
+  for (int s = 0; s < n_sel; ++s) {
+    const int c = clusters[s];
+    if (c < 0 || c >= K) return fail(SEELE_ERR_INVALID_ARG, "cluster %d not in 0..%d", c, K - 1);
+    add(layout_begin[1 + c], layout_count[1 + c]);
+  }
+  // insertion sort by begin
+  for (int i = 1; i < cnt; ++i)
+    for (int j = i; j > 0 && out_begin[j] < out_begin[j - 1]; --j) {
+      std::swap(out_begin[j], out_begin[j - 1]);
+      std::swap(out_count[j], out_count[j - 1]);
+    }
+  *n_out = cnt;
+  return SEELE_OK;
+}
+
+}  // extern "C"

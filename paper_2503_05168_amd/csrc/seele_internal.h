@@ -1,0 +1,193 @@
+// Internal definitions shared by the gfx950 kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "seele.h"
+
+namespace seele {
+
+constexpr int kMaxViewsPre = 8;       // views handled by one preprocess launch
+constexpr int kMaxSegs = 16;          // active segments per preprocess call
+constexpr int kMaxViewsBin = 256;     // views per bin_sort call (kernel-argument table)
+constexpr int kMaxViewsRaster = 64;   // views per raster launch (kernel-argument table)
+
+constexpr int kSortBlock = 256;       // threads per sort/scan block (4 waves)
+constexpr int kSortItems = 16;        // items per thread
+constexpr int kSortTile = kSortBlock * kSortItems;
+
+
+struct CamK {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float C[3];  // camera centre -R^T t (computed on the host in double)
+  int W, H, gridW, gridH;
+};
+
+struct PreArgs {
+  int64_t n;
+  int sh_degree;
+  int n_views;        // views in this launch (<= kMaxViewsPre)
+  int64_t view0;      // index of this launch's first view
+  int tile;
+  int extent;
+  float alpha_min, lowpass, z_near;
+  int n_segs;
+  int64_t seg_begin[kMaxSegs];
+  int64_t seg_end[kMaxSegs];
+  CamK cam[kMaxViewsPre];
+};
+
+struct BinView {
+  int32_t tile_base;
+  int32_t grid_w;
+};
+
+struct BinViews {
+  int n_views;
+  int64_t n;  // Gaussians per view
+  BinView v[kMaxViewsBin];
+};
+
+struct RasterView {
+  int32_t tile_begin;  // first tile of this view, relative to the launch
+  int32_t W, H, grid_w;
+  int64_t pix_base;    // first pixel of this view in final_T / n_contrib
+};
+
+struct RasterViews {
+  int n_views;
+  int32_t tile_base;   // global id of the launch's first tile
+  RasterView v[kMaxViewsRaster];
+};
+
+struct RasterParams {
+  float alpha_min, alpha_max, T_min;
+  float bg0, bg1, bg2;
+  int group_w, group_h;
+};
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T y = __shfl_up(x, d, 64);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Block-wide exclusive scan for blockDim.x == kSortBlock; returns the
+// exclusive prefix of `x` and the block total in `total`.  `smem` holds at
+// least kSortBlock/64 + 1 elements.  Contains barriers: call uniformly.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T* smem, T& total) {
+  constexpr int kWaves = kSortBlock / 64;
+  const int w = threadIdx.x >> 6;
+  const T inc = wave_inclusive_scan(x);
+  if (lane_id() == 63) smem[w] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const T s = smem[i];
+    if (i < w) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - x;
+}
+
+// -------------------------------------------------------------- blending math
+// The rasterizers evaluate q = d^T A d (A = conic, d = pixel centre - mean) as
+// a sum of squares through the Cholesky factor of A scaled by sqrt(k),
+// k = log2(e)/2:
+//   A k = L L^T,  L = [[l11, 0], [l21, l22]],
+//   k q = (l11 dx + l21 dy)^2 + (l22 dy)^2,   exp(-q/2) = exp2(-k q).
+// Unlike the expanded quadratic, the sum of squares does not cancel for
+// elongated footprints and needs no clamp at zero.  The factor is computed
+// once per Gaussian and tile, in double precision, from the float32 conic.
+struct Chol {
+  float l11, l21, l22;
+};
+
+__device__ __forceinline__ Chol conic_factor(float a, float b, float c) {
+  const double k = 0.72134752044448170;  // log2(e)/2
+  const double ad = a > 0.0f ? (double)a : 0.0;
+  const double det = (double)a * (double)c - (double)b * (double)b;  // exact products
+  Chol f;
+  if (ad > 0.0) {
+    const double sa = sqrt(ad);
+    f.l11 = (float)(sqrt(k) * sa);
+    f.l21 = (float)(sqrt(k) * (double)b / sa);
+    f.l22 = (float)sqrt(k * fmax(det / ad, 0.0));
+  } else {
+    f.l11 = 0.0f;
+    f.l21 = 0.0f;
+    f.l22 = (float)sqrt(k * fmax((double)c, 0.0));
+  }
+  return f;
+}
+
+// Power p = -k q at pixel centre (px, py).  Shared by the forward and
+// backward kernels so that both take identical decisions: the kernels are
+// compiled with floating-point contraction off and the fused multiply-adds
+// below are explicit.
+__device__ __forceinline__ float splat_power(float px, float py, float mx, float my, float l11,
+                                             float l21, float l22, float& dx, float& dy) {
+  dx = px - mx;
+  dy = py - my;
+  const float u = __builtin_fmaf(l21, dy, l11 * dx);
+  const float w = l22 * dy;
+  return -__builtin_fmaf(u, u, w * w);
+}
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ------------------------------------------------------------- host launchers
+hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_splat* splats,
+                             int32_t* n_tiles, hipStream_t stream);
+
+struct BinSortPlan {
+  int64_t n_records;      // n_views * n
+  int64_t capacity;       // pair capacity
+  int64_t n_tiles_total;
+  int tile_bits;          // bits of the global tile id
+  // workspace carve-up (byte offsets)
+  size_t off_hdr, off_partial, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
+  size_t off_tkeys0, off_tkeys1, off_tvals, off_hist, off_digits, total;
+};
+BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_total);
+hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,
+                           const int32_t* n_tiles, void* ws, uint32_t* sorted_ids,
+                           int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream);
+
+hipError_t launch_raster_fwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
+                             const RasterParams& rp, const seele_splat* splats,
+                             const uint32_t* sorted_ids, const int32_t* tile_ranges, float* image,
+                             float* final_T, int32_t* n_contrib, unsigned long long* counters,
+                             hipStream_t stream);
+
+}  // namespace seele

@@ -1,0 +1,278 @@
+"""Torch-facing wrappers around the C ABI.
+
+PyTorch only provides device memory and the current HIP stream here; every
+step of the hot path runs inside libseele.so.  Each ``seele_*`` function has
+the name of the C entry point it calls and only marshals arguments.
+``Renderer`` chains them into a frame and grows the pair buffer when the
+device reports that it was too small.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _abi as A
+
+SPLAT_FLOATS = 12  # 48-byte seele_splat
+
+
+@dataclass
+class GaussianTensors:
+    """Device SoA arrays matching ``seele_gaussians``."""
+    means: torch.Tensor           # [3, N] float32
+    log_scales: torch.Tensor      # [3, N]
+    quats: torch.Tensor           # [4, N] (w, x, y, z)
+    opacity_logits: torch.Tensor  # [N]
+    sh: torch.Tensor              # [16, 3, N]
+    sh_degree: int = 3
+
+    @property
+    def n(self) -> int:
+        return int(self.opacity_logits.shape[0])
+
+    @classmethod
+    def from_arrays(cls, scene, device="cuda") -> "GaussianTensors":
+        """From any object with numpy SoA attributes means, log_scales, quats,
+        opacity_logits, sh and sh_degree."""
+        t = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+        return cls(t(scene.means), t(scene.log_scales), t(scene.quats), t(scene.opacity_logits),
+                   t(scene.sh), int(getattr(scene, "sh_degree", 3)))
+
+    def struct(self) -> A.seele_gaussians:
+        g = A.seele_gaussians()
+        g.n = self.n
+        g.sh_degree = self.sh_degree
+        for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            ten = getattr(self, name)
+            assert ten.is_contiguous() and ten.dtype == torch.float32
+            setattr(g, name, ten.data_ptr() if ten.numel() else None)
+        return g
+
+
+@dataclass
+class Settings:
+    tile: int = 16
+    extent: str = "3sigma"         # or "opacity" (Eq. 5)
+    mode: str = "plain"            # or "contrib" (Algorithm 1)
+    group: tuple = (2, 2)
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    lowpass: float = 0.3
+    z_near: float = 0.2
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    def preprocess_opts(self, segments=None):
+        o = A.seele_preprocess_opts()
+        o.tile = self.tile
+        o.extent = {"3sigma": A.SEELE_EXTENT_3SIGMA, "opacity": A.SEELE_EXTENT_OPACITY}[self.extent]
+        o.alpha_min, o.lowpass, o.z_near = self.alpha_min, self.lowpass, self.z_near
+        keep = None
+        if segments:
+            b = (ctypes.c_int64 * len(segments))(*[int(s[0]) for s in segments])
+            c = (ctypes.c_int64 * len(segments))(*[int(s[1]) for s in segments])
+            o.n_segs = len(segments)
+            o.seg_begin = ctypes.cast(b, ctypes.POINTER(ctypes.c_int64))
+            o.seg_count = ctypes.cast(c, ctypes.POINTER(ctypes.c_int64))
+            keep = (b, c)
+        else:
+            o.n_segs = 0
+        return o, keep
+
+    def raster_opts(self):
+        o = A.seele_raster_opts()
+        o.tile = self.tile
+        o.mode = {"plain": A.SEELE_RASTER_PLAIN, "contrib": A.SEELE_RASTER_CONTRIB}[self.mode]
+        o.group_w, o.group_h = int(self.group[0]), int(self.group[1])
+        o.alpha_min, o.alpha_max, o.T_min = self.alpha_min, self.alpha_max, self.T_min
+        for i in range(3):
+            o.bg[i] = float(self.bg[i])
+        return o
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _p(t: torch.Tensor | None):
+    return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
+
+
+def total_tiles(cams, tile: int) -> int:
+    arr = A.camera_array(cams)
+    return int(A.lib().seele_total_tiles(arr, len(cams), tile))
+
+
+def pixel_count(cams) -> int:
+    return sum(int(c.width) * int(c.height) for c in cams)
+
+
+def seele_preprocess(g: GaussianTensors, cams, settings: Settings, segments=None,
+                     splats: torch.Tensor | None = None, n_tiles: torch.Tensor | None = None,
+                     stream=None):
+    V, n = len(cams), g.n
+    dev = g.means.device
+    if splats is None:
+        splats = torch.empty((V * n, SPLAT_FLOATS), dtype=torch.float32, device=dev)
+    if n_tiles is None:
+        n_tiles = torch.empty(V * n, dtype=torch.int32, device=dev)
+    opts, keep = settings.preprocess_opts(segments)
+    gs = g.struct()
+    st = A.lib().seele_preprocess(ctypes.byref(gs), A.camera_array(cams), V, ctypes.byref(opts),
+                                  _p(splats), _p(n_tiles), _stream(stream))
+    del keep
+    A.check(st, "seele_preprocess")
+    return splats, n_tiles
+
+
+def bin_sort_workspace_size(n_records: int, capacity: int, n_tiles_total: int) -> int:
+    return int(A.lib().seele_bin_sort_workspace_size(n_records, capacity, n_tiles_total))
+
+
+def seele_bin_sort(splats, n_tiles, n: int, cams, tile: int, capacity: int,
+                   workspace: torch.Tensor | None = None, sorted_ids=None, tile_ranges=None,
+                   num_pairs=None, stream=None):
+    dev = splats.device
+    V = len(cams)
+    TT = total_tiles(cams, tile)
+    ws_bytes = bin_sort_workspace_size(V * n, capacity, TT)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    if sorted_ids is None:
+        sorted_ids = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    if tile_ranges is None:
+        tile_ranges = torch.empty((TT, 2), dtype=torch.int32, device=dev)
+    if num_pairs is None:
+        num_pairs = torch.empty(1, dtype=torch.int64, device=dev)
+    st = A.lib().seele_bin_sort(_p(splats), _p(n_tiles), n, A.camera_array(cams), V, tile,
+                                _p(workspace), workspace.numel(), _p(sorted_ids), capacity,
+                                _p(tile_ranges), _p(num_pairs), _stream(stream))
+    A.check(st, "seele_bin_sort")
+    return sorted_ids, tile_ranges, num_pairs, workspace
+
+
+def seele_rasterize_fwd(splats, sorted_ids, tile_ranges, cams, settings: Settings, image=None,
+                        final_T=None, n_contrib=None, stream=None):
+    dev = tile_ranges.device
+    npix = pixel_count(cams)
+    if image is None:
+        image = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    if final_T is None:
+        final_T = torch.empty(npix, dtype=torch.float32, device=dev)
+    if n_contrib is None:
+        n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    opts = settings.raster_opts()
+    st = A.lib().seele_rasterize_fwd(_p(splats), _p(sorted_ids), _p(tile_ranges),
+                                     A.camera_array(cams), len(cams), ctypes.byref(opts),
+                                     _p(image), _p(final_T), _p(n_contrib), _stream(stream))
+    A.check(st, "seele_rasterize_fwd")
+    return image, final_T, n_contrib
+
+
+def seele_rasterize_fwd_counted(splats, sorted_ids, tile_ranges, cams, settings: Settings,
+                                counters=None, stream=None):
+    """Instrumented forward: same outputs plus the four work counters."""
+    dev = tile_ranges.device
+    npix = pixel_count(cams)
+    image = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    final_T = torch.empty(npix, dtype=torch.float32, device=dev)
+    n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    if counters is None:
+        counters = torch.empty(4, dtype=torch.int64, device=dev)
+    opts = settings.raster_opts()
+    st = A.lib().seele_rasterize_fwd_counted(_p(splats), _p(sorted_ids), _p(tile_ranges),
+                                             A.camera_array(cams), len(cams), ctypes.byref(opts),
+                                             _p(image), _p(final_T), _p(n_contrib), _p(counters),
+                                             _stream(stream))
+    A.check(st, "seele_rasterize_fwd_counted")
+    return image, final_T, n_contrib, counters
+
+
+def seele_hp_select(centroids, cam, pos_scale: float, beta: float, M: int):
+    """Nearest view cluster + its M nearest neighbours (host-only C call)."""
+    import numpy as np
+    c = np.ascontiguousarray(centroids, dtype=np.float32)
+    K = int(c.shape[0])
+    buf = (ctypes.c_float * c.size)(*c.ravel().tolist())
+    out = (ctypes.c_int32 * (1 + M))()
+    cam_s = A.make_camera(cam)
+    st = A.lib().seele_hp_select(buf, K, ctypes.byref(cam_s), float(pos_scale), float(beta),
+                                 int(M), out)
+    A.check(st, "seele_hp_select")
+    return list(out)
+
+
+def seele_hp_segments(layout_begin, layout_count, clusters):
+    """Active (begin, count) segments: shared + the chosen clusters' (host-only C call)."""
+    K = len(layout_begin) - 1
+    lb = (ctypes.c_int64 * (K + 1))(*[int(x) for x in layout_begin])
+    lc = (ctypes.c_int64 * (K + 1))(*[int(x) for x in layout_count])
+    cl = (ctypes.c_int32 * max(1, len(clusters)))(*[int(x) for x in clusters])
+    ob = (ctypes.c_int64 * (1 + len(clusters)))()
+    oc = (ctypes.c_int64 * (1 + len(clusters)))()
+    no = ctypes.c_int32()
+    st = A.lib().seele_hp_segments(lb, lc, K, cl, len(clusters), ob, oc, ctypes.byref(no))
+    A.check(st, "seele_hp_segments")
+    return [(int(ob[i]), int(oc[i])) for i in range(no.value)]
+
+
+def split_views(flat: torch.Tensor, cams, channels: int):
+    """Per-view [C, H, W] (or [H, W]) views into a concatenated output buffer."""
+    out, off = [], 0
+    for c in cams:
+        k = channels * c.width * c.height
+        v = flat[off:off + k]
+        out.append(v.view(channels, c.height, c.width) if channels > 1
+                   else v.view(c.height, c.width))
+        off += k
+    return out
+
+
+@dataclass
+class Frame:
+    image: torch.Tensor       # concatenated per-view [3][H][W]
+    final_T: torch.Tensor
+    n_contrib: torch.Tensor
+    splats: torch.Tensor
+    n_tiles: torch.Tensor
+    sorted_ids: torch.Tensor
+    tile_ranges: torch.Tensor
+    num_pairs: torch.Tensor
+    cams: list = field(default_factory=list)
+
+    def images(self):
+        return split_views(self.image, self.cams, 3)
+
+
+class Renderer:
+    """preprocess -> bin_sort -> rasterize for a list of views, reusing buffers.
+
+    The pair capacity grows (x1.5 of the reported need) and the sort is
+    repeated when the device reports overflow; ``check=False`` skips that
+    host read (the caller then checks ``num_pairs`` itself)."""
+
+    def __init__(self, settings: Settings | None = None, capacity: int = 1 << 20):
+        self.settings = settings or Settings()
+        self.capacity = int(capacity)
+        self._ws = None
+
+    def render(self, g: GaussianTensors, cams, segments=None, check: bool = True,
+               stream=None) -> Frame:
+        s = self.settings
+        splats, n_tiles = seele_preprocess(g, cams, s, segments, stream=stream)
+        while True:
+            ids, ranges, npairs, self._ws = seele_bin_sort(splats, n_tiles, g.n, cams, s.tile,
+                                                           self.capacity, self._ws,
+                                                           stream=stream)
+            if not check:
+                break
+            need = int(npairs.item())
+            if need <= self.capacity:
+                break
+            self.capacity = min(int(need * 1.5) + 1024, (1 << 31) - 1)
+        image, final_T, n_contrib = seele_rasterize_fwd(splats, ids, ranges, cams, s,
+                                                        stream=stream)
+        return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs, list(cams))

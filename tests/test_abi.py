@@ -1,0 +1,216 @@
+"""The C ABI without a GPU: every declared symbol is exported, the struct
+layouts agree between the header (compiled by gcc) and the binding, argument
+validation rejects bad calls before anything is enqueued, and the host-only
+hybrid-preprocessing selection matches the oracle."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import hp as ohp
+from paper_2503_05168_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "seele.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(seele_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(A.SIGNATURES)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    structs = {
+        "seele_gaussians": [f for f, _ in A.seele_gaussians._fields_],
+        "seele_gaussian_grads": [f for f, _ in A.seele_gaussian_grads._fields_],
+        "seele_camera": [f for f, _ in A.seele_camera._fields_],
+        "seele_splat": [f for f, _ in A.seele_splat._fields_],
+        "seele_preprocess_opts": [f for f, _ in A.seele_preprocess_opts._fields_],
+        "seele_raster_opts": [f for f, _ in A.seele_raster_opts._fields_],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(){"]
+    for s, fields in structs.items():
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fields:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(l.rsplit(" ", 1) for l in out.strip().splitlines())
+    for s, fields in structs.items():
+        cls = getattr(A, s)
+        assert int(got[s]) == ctypes.sizeof(cls), s
+        for f in fields:
+            assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
+    assert int(got["seele_splat"]) == 48 and int(got["seele_camera"]) == 72
+
+
+def _cam(w=64, h=48):
+    return A.camera_array([synthetic.look_at((0, 0, -3), width=w, height=h)])
+
+
+def _popts(tile=16, extent=0):
+    o = A.seele_preprocess_opts()
+    o.tile, o.extent, o.alpha_min, o.lowpass, o.z_near, o.n_segs = tile, extent, 1 / 255, 0.3, 0.2, 0
+    return o
+
+
+def _ropts(tile=16, mode=0, gw=2, gh=2):
+    o = A.seele_raster_opts()
+    o.tile, o.mode, o.group_w, o.group_h = tile, mode, gw, gh
+    o.alpha_min, o.alpha_max, o.T_min = 1 / 255, 0.99, 1e-4
+    return o
+
+
+FAKE = ctypes.c_void_p(0x10000)  # aligned, never dereferenced: every call below fails validation
+
+
+def _gauss(n=10, deg=3, null_field=None):
+    g = A.seele_gaussians()
+    g.n, g.sh_degree = n, deg
+    for f in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        setattr(g, f, None if f == null_field else 0x10000)
+    return g
+
+
+@pytest.mark.parametrize("case", ["null_g", "neg_n", "deg4", "null_means", "tile12", "extent7",
+                                  "alpha0", "nviews0", "cam0x0", "seg_oob", "segs_too_many",
+                                  "splats_misaligned"])
+def test_preprocess_rejects_bad_arguments(case):
+    L = A.lib()
+    g, cams, nv, o, sp = _gauss(), _cam(), 1, _popts(), ctypes.c_void_p(0x10000)
+    keep = None
+    if case == "null_g":
+        g = None
+    elif case == "neg_n":
+        g = _gauss(n=-1)
+    elif case == "deg4":
+        g = _gauss(deg=4)
+    elif case == "null_means":
+        g = _gauss(null_field="means")
+    elif case == "tile12":
+        o = _popts(tile=12)
+    elif case == "extent7":
+        o = _popts(extent=7)
+    elif case == "alpha0":
+        o.alpha_min = 0.0
+    elif case == "nviews0":
+        nv = 0
+    elif case == "cam0x0":
+        cams = _cam(0, 0)
+    elif case == "seg_oob":
+        b, c = (ctypes.c_int64 * 1)(5), (ctypes.c_int64 * 1)(6)
+        o.n_segs, o.seg_begin, o.seg_count = 1, b, c
+        keep = (b, c)
+    elif case == "segs_too_many":
+        b, c = (ctypes.c_int64 * 17)(), (ctypes.c_int64 * 17)()
+        o.n_segs, o.seg_begin, o.seg_count = 17, b, c
+        keep = (b, c)
+    elif case == "splats_misaligned":
+        sp = ctypes.c_void_p(0x10004)
+    st = L.seele_preprocess(ctypes.byref(g) if g is not None else None, cams, nv,
+                            ctypes.byref(o), sp, FAKE, None)
+    assert st in (A.SEELE_ERR_INVALID_ARG, A.SEELE_ERR_UNSUPPORTED), (case, st)
+    assert L.seele_last_error()
+    del keep
+
+
+def test_bin_sort_rejects_bad_arguments():
+    L = A.lib()
+    cams = _cam()
+    need = L.seele_bin_sort_workspace_size(10, 1000, 12)
+    assert need > 0
+    args = lambda ws_bytes, cap, ws=FAKE, nv=1: L.seele_bin_sort(
+        FAKE, FAKE, 10, cams, nv, 16, ws, ws_bytes, FAKE, cap, FAKE, FAKE, None)
+    assert args(need - 1, 1000) == A.SEELE_ERR_CAPACITY
+    assert args(need, -1) == A.SEELE_ERR_INVALID_ARG
+    assert args(need, 1 << 31) == A.SEELE_ERR_INVALID_ARG
+    assert args(need, 1000, ws=ctypes.c_void_p(0x10010)) == A.SEELE_ERR_INVALID_ARG
+    assert args(need, 1000, nv=300) == A.SEELE_ERR_UNSUPPORTED
+    assert L.seele_bin_sort(FAKE, FAKE, 10, cams, 1, 16, FAKE, need, FAKE, 1000, FAKE,
+                            ctypes.c_void_p(0x10004), None) == A.SEELE_ERR_INVALID_ARG
+
+
+def test_total_tiles_and_workspace_size():
+    L = A.lib()
+    cams = A.camera_array([synthetic.look_at((0, 0, -3), width=w, height=h)
+                           for w, h in ((1920, 1080), (37, 23), (1, 1))])
+    assert L.seele_total_tiles(cams, 3, 16) == 120 * 68 + 3 * 2 + 1
+    assert L.seele_total_tiles(cams, 3, 8) == 240 * 135 + 5 * 3 + 1
+    assert L.seele_total_tiles(cams, 3, 12) == -1
+    assert L.seele_bin_sort_workspace_size(100, 1000, 64) >= 4 * (4 * 100 + 3 * 1000)
+
+
+@pytest.mark.parametrize("mutate", ["tile", "mode", "group3", "group_big", "amax", "tmin", "null"])
+def test_raster_rejects_bad_arguments(mutate):
+    L = A.lib()
+    o = _ropts(mode=1)
+    out = FAKE
+    if mutate == "tile":
+        o.tile = 32
+    elif mutate == "mode":
+        o.mode = 5
+    elif mutate == "group3":
+        o.group_w = 3
+    elif mutate == "group_big":
+        o.group_w, o.group_h = 4, 8
+    elif mutate == "amax":
+        o.alpha_max = 1.0
+    elif mutate == "tmin":
+        o.T_min = 0.0
+    elif mutate == "null":
+        out = None
+    st = L.seele_rasterize_fwd(FAKE, FAKE, FAKE, _cam(), 1, ctypes.byref(o), out, FAKE, FAKE, None)
+    assert st == A.SEELE_ERR_INVALID_ARG, mutate
+
+
+def test_hp_select_matches_oracle():
+    L = A.lib()
+    rng = np.random.default_rng(0)
+    K = 24
+    cents = rng.normal(size=(K, 6)).astype(np.float32)
+    cbuf = (ctypes.c_float * (K * 6))(*cents.ravel().tolist())
+    for k in range(40):
+        d = rng.normal(size=3)
+        cam = synthetic.look_at(d / np.linalg.norm(d) * rng.uniform(2, 6))
+        for M in (0, 1, 3):
+            out = (ctypes.c_int32 * (1 + M))()
+            assert L.seele_hp_select(cbuf, K, ctypes.byref(A.make_camera(cam)), 4.0, 1.0, M,
+                                     out) == A.SEELE_OK
+            want = ohp.select_clusters(cents.astype(np.float64), ohp.camera_feature(cam, 4.0), M)
+            assert list(out) == want
+
+
+def test_hp_segments_match_oracle():
+    L = A.lib()
+    cfg = synthetic.config(3, n=5000)
+    lay = cfg["hp"]
+    K = len(lay.seg_begin) - 1
+    lb = (ctypes.c_int64 * (K + 1))(*lay.seg_begin.tolist())
+    lc = (ctypes.c_int64 * (K + 1))(*lay.seg_count.tolist())
+    for sel in ([0], [3, 4], [7, 0, 1, 2], [5, 5]):
+        cl = (ctypes.c_int32 * len(sel))(*sel)
+        ob, oc, no = (ctypes.c_int64 * 8)(), (ctypes.c_int64 * 8)(), ctypes.c_int32()
+        assert L.seele_hp_segments(lb, lc, K, cl, len(sel), ob, oc, ctypes.byref(no)) == A.SEELE_OK
+        got = [(ob[i], oc[i]) for i in range(no.value)]
+        assert got == ohp.active_segments(lay.seg_begin, lay.seg_count, sel)
+    cl = (ctypes.c_int32 * 1)(9)
+    ob, oc, no = (ctypes.c_int64 * 2)(), (ctypes.c_int64 * 2)(), ctypes.c_int32()
+    assert L.seele_hp_segments(lb, lc, K, cl, 1, ob, oc, ctypes.byref(no)) == A.SEELE_ERR_INVALID_ARG

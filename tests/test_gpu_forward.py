@@ -1,0 +1,257 @@
+"""GPU parity of the forward hot path against the FP64 oracle.
+
+Stage-wise: the oracle is fed the HIP path's previous-stage output, so the
+tile order is compared bit for bit and the blend within a float tolerance.
+Floating-point decisions (alpha >= 1/255, clamp, termination, leader test,
+rect edges, culling) whose float64 value lies within the float32 error band
+of the threshold are "borderline": both outcomes are valid, such pixels or
+Gaussians are counted and excluded from the strict comparison.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import blend as oblend
+from oracle import project as oproj
+from oracle import hp as ohp
+from paper_2503_05168_amd import Settings
+
+pytestmark = pytest.mark.gpu
+
+import gpu_util as gu  # noqa: E402
+
+IMG_TOL = 1e-5  # max abs per channel, exact path
+
+
+def _ids(f):
+    return f.sorted_ids.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+
+
+def _check_preprocess(scene, cam, f, view, settings, active=None):
+    n = scene.n
+    sp = gu.splats_np(f)
+    sl = slice(view * n, (view + 1) * n)
+    o = oproj.project_view(scene, cam, tile=settings.tile, extent=settings.extent, active=active)
+    g_vis = sp["n_tiles"][sl] > 0
+    o_vis = o["visible"]
+    border = (o["rect_margin"] < gu.RECT_MARGIN_PX) | (o["op_margin"] < gu.ALPHA_MARGIN) | (
+        o["near_margin"] < 1e-5)
+    bad = (g_vis != o_vis) & ~border
+    assert not bad.any(), f"visibility differs for {np.nonzero(bad)[0][:10]}"
+    both = g_vis & o_vis
+    idx = np.nonzero(both)[0]
+    rec = view * n + idx
+    np.testing.assert_allclose(sp["mean2d"][rec], o["mean2d"][idx], rtol=1e-6, atol=2e-4)
+    np.testing.assert_allclose(sp["depth_f32"][rec], o["depth"][idx], rtol=2e-6)
+    np.testing.assert_allclose(sp["opacity"][rec], o["opacity"][idx], rtol=2e-6)
+    np.testing.assert_allclose(sp["rgb"][rec], o["rgb"][idx], atol=2e-5)
+    # conic: relative to the largest entry of each conic (elongated footprints cancel in det)
+    scale = np.abs(o["conic"][idx]).max(1, keepdims=True)
+    cerr = (np.abs(sp["conic"][rec] - o["conic"][idx]) / scale).max(initial=0)
+    assert cerr < 1e-3, cerr
+    strict = idx[~border[idx]]
+    np.testing.assert_array_equal(sp["rect"][view * n + strict], o["rect"][strict])
+    np.testing.assert_array_equal(sp["n_tiles"][view * n + strict], o["n_tiles"][strict])
+    return int(((g_vis != o_vis) & border).sum())
+
+
+def _check_sort(f, cams, tile, n):
+    sp = gu.splats_np(f)
+    ob = gu.oracle_binning(sp, cams, tile, n)
+    P = int(f.num_pairs.item())
+    assert P == ob["n_pairs"]
+    np.testing.assert_array_equal(_ids(f)[:P], ob["ids"])
+    np.testing.assert_array_equal(f.tile_ranges.cpu().numpy(), ob["ranges"])
+    return sp, ob
+
+
+def _check_raster(f, sp, cams, settings, n, tiles=None):
+    imgs, Ts, ncs = gu.outputs_np(f)
+    ids = _ids(f)
+    ranges = f.tile_ranges.cpu().numpy().astype(np.int64)
+    base = 0
+    stats = []
+    for v, cam in enumerate(cams):
+        mode = "plain" if settings.mode == "plain" else "cr"
+        r = oblend.render_tiles(sp, ranges, ids, cam.width, cam.height, settings.tile, base, mode,
+                                settings.group, settings.bg, settings.alpha_min,
+                                settings.alpha_max, settings.T_min, tiles=tiles)
+        base += (-(-cam.width // settings.tile)) * (-(-cam.height // settings.tile))
+        safe = r["margin"] >= gu.ALPHA_MARGIN
+        if tiles is not None:
+            gw = -(-cam.width // settings.tile)
+            m = np.zeros_like(safe)
+            for t in tiles:
+                ty, tx = divmod(t, gw)
+                m[ty * settings.tile:(ty + 1) * settings.tile,
+                  tx * settings.tile:(tx + 1) * settings.tile] = True
+            safe &= m
+        err = np.abs(imgs[v] - r["image"]).max(0)
+        assert err[safe].max(initial=0) <= IMG_TOL, f"view {v}: image err {err[safe].max()}"
+        terr = np.abs(Ts[v] - r["final_T"])[safe]
+        assert terr.max(initial=0) <= IMG_TOL
+        np.testing.assert_array_equal(ncs[v][safe], r["n_contrib"][safe])
+        n_border = int((~safe).sum()) if tiles is None else int((~(r["margin"] >= gu.ALPHA_MARGIN)
+                                                                 & m).sum())
+        stats.append((float(err[safe].max(initial=0)), n_border, safe.size))
+        if tiles is None:
+            _check_counters(f, cams, settings, v, r["counters"], n_border)
+    return stats
+
+
+def _check_counters(f, cams, settings, v, oc, n_border):
+    """The instrumented kernel's work counters equal the oracle's counts
+    (exactly when no pixel of the view is borderline)."""
+    import paper_2503_05168_amd as P
+    cam = cams[v]
+    base = sum((-(-c.width // settings.tile)) * (-(-c.height // settings.tile)) for c in cams[:v])
+    nt = (-(-cam.width // settings.tile)) * (-(-cam.height // settings.tile))
+    ranges = f.tile_ranges[base:base + nt].contiguous()
+    _, _, _, cnt = P.seele_rasterize_fwd_counted(f.splats, f.sorted_ids, ranges, [cam], settings)
+    got = cnt.cpu().numpy().tolist()
+    want = [oc["evals"] if settings.mode == "plain" else oc["pass_evals"], oc["blends"],
+            oc["leader_tests"], oc["leader_pass"]]
+    if n_border == 0:
+        assert got == want, (got, want)
+    else:
+        for g_, w_ in zip(got, want):
+            assert abs(g_ - w_) <= max(2, 1e-3 * w_), (got, want)
+
+
+CASES = [
+    # name, config builder, settings
+    ("c1-plain", lambda: (synthetic.config(1)["scene"], synthetic.config(1)["cams"]),
+     Settings()),
+    ("c1-cr", lambda: (synthetic.config(1)["scene"], synthetic.config(1)["cams"]),
+     Settings(mode="contrib", extent="opacity")),
+    ("c1-cr-2x4-bg-tile8", lambda: (synthetic.config(1)["scene"], synthetic.config(1)["cams"]),
+     Settings(mode="contrib", group=(2, 4), tile=8, bg=(0.2, 0.5, 0.1))),
+    ("c2shape-ragged-2views", lambda: (synthetic.cluster_scene(2, 40_000),
+                                       [synthetic.look_at((0, 0, -4), width=500, height=333),
+                                        synthetic.look_at((4, 0, 0), width=331, height=197)]),
+     Settings(extent="opacity")),
+    ("c2shape-cr-tile8", lambda: (synthetic.cluster_scene(2, 40_000),
+                                  [synthetic.look_at((2, 1, -3.5), width=480, height=270)]),
+     Settings(mode="contrib", tile=8)),
+]
+
+
+@pytest.mark.parametrize("name,build,settings", CASES, ids=[c[0] for c in CASES])
+def test_forward_stagewise_parity(name, build, settings):
+    gu.log(f"[case] {name}")
+    scene, cams = build()
+    f = gu.run(scene, cams, settings)
+    border_vis = [_check_preprocess(scene, c, f, v, settings) for v, c in enumerate(cams)]
+    sp, ob = _check_sort(f, cams, settings.tile, scene.n)
+    stats = _check_raster(f, sp, cams, settings, scene.n)
+    for (err, nb, npx) in stats:
+        assert nb <= max(3, 2e-3 * npx), f"{nb} borderline pixels of {npx}"
+    gu.log(f"[done] {name} pairs={ob['n_pairs']} border_vis={border_vis} raster={stats}")
+
+
+def test_contrib_group1_is_bit_identical_to_plain():
+    cfg = synthetic.config(1)
+    a = gu.run(cfg["scene"], cfg["cams"], Settings())
+    b = gu.run(cfg["scene"], cfg["cams"], Settings(mode="contrib", group=(1, 1)))
+    for x, y in ((a.image, b.image), (a.final_T, b.final_T), (a.n_contrib, b.n_contrib)):
+        assert torch.equal(x, y)
+
+
+def test_forward_is_deterministic():
+    scene = synthetic.cluster_scene(2, 40_000)
+    cams = [synthetic.look_at((0, 0, -4), width=640, height=360)]
+    a = gu.run(scene, cams, Settings(mode="contrib"))
+    b = gu.run(scene, cams, Settings(mode="contrib"))
+    P = int(a.num_pairs.item())
+    assert P == int(b.num_pairs.item())
+    assert torch.equal(a.image, b.image) and torch.equal(a.sorted_ids[:P], b.sorted_ids[:P])
+    assert torch.equal(a.tile_ranges, b.tile_ranges) and torch.equal(a.n_contrib, b.n_contrib)
+
+
+def test_depth_ties_break_by_id_and_big_gaussian():
+    # many exact duplicates (equal depth, equal rect) and one Gaussian covering every tile
+    base = synthetic.ball_scene(5, 300, log_scale_mu=-3.0)
+    idx = np.concatenate([np.arange(300), np.full(40, 7), np.full(30, 123)])
+    scene = base.subset(idx)
+    scene.log_scales[:, 0] = 1.0  # Gaussian 0 huge
+    cams = [synthetic.look_at((0, 0, -3), width=96, height=64)]
+    st = Settings()
+    f = gu.run(scene, cams, st)
+    sp, ob = _check_sort(f, cams, st.tile, scene.n)
+    assert sp["n_tiles"][0] == 6 * 4
+    _check_raster(f, sp, cams, st, scene.n)
+
+
+def test_empty_and_fully_culled_scenes():
+    cams = [synthetic.look_at((0, 0, -3), width=40, height=30)]
+    empty = synthetic.ball_scene(1, 0)
+    f = gu.run(empty, cams, Settings())
+    assert int(f.num_pairs.item()) == 0
+    assert torch.all(f.final_T == 1) and torch.all(f.image == 0) and torch.all(f.n_contrib == 0)
+    behind = synthetic.ball_scene(1, 500)
+    behind.means[2] = -10.0  # all behind the camera
+    f = gu.run(behind, cams, Settings(bg=(0.1, 0.2, 0.3)))
+    assert int(f.num_pairs.item()) == 0 and int(f.n_tiles.sum()) == 0
+    img = f.image.view(3, 30, 40)
+    assert torch.allclose(img[1], torch.full_like(img[1], 0.2))
+
+
+def test_non_finite_attributes_are_culled():
+    scene = synthetic.ball_scene(3, 200, log_scale_mu=-3)
+    scene.means[0, 5] = np.nan
+    scene.log_scales[1, 6] = np.inf
+    scene.quats[:, 7] = 0.0
+    scene.opacity_logits[8] = np.nan
+    scene.sh[4, 1, 9] = np.inf
+    cams = [synthetic.look_at((0, 0, -3), width=64, height=64)]
+    f = gu.run(scene, cams, Settings())
+    nt = f.n_tiles.cpu().numpy()
+    assert (nt[5:10] == 0).all()
+    o = oproj.project_view(scene, cams[0], tile=16)
+    assert not o["visible"][5:10].any()
+    assert torch.isfinite(f.image).all()
+
+
+def test_capacity_overflow_reports_need_and_leaves_tiles_empty():
+    import paper_2503_05168_amd as P
+    cfg = synthetic.config(1)
+    g = P.GaussianTensors.from_arrays(cfg["scene"])
+    st = Settings()
+    splats, nt = P.seele_preprocess(g, cfg["cams"], st)
+    ids, ranges, npairs, _ = P.seele_bin_sort(splats, nt, g.n, cfg["cams"], 16, capacity=100)
+    torch.cuda.synchronize()
+    need = int(npairs.item())
+    assert need == int(nt.sum().item()) and need > 100
+    assert int(ranges.abs().sum().item()) == 0
+    ids, ranges, npairs, _ = P.seele_bin_sort(splats, nt, g.n, cfg["cams"], 16, capacity=need)
+    torch.cuda.synchronize()
+    assert int(ranges[:, 1].max().item()) == need
+
+
+def test_hybrid_preprocessing_segments():
+    cfg = synthetic.config(3, n=60_000)
+    lay, scene = cfg["hp"], cfg["scene"]
+    cam = synthetic.orbit_cameras(32, 4.0, 480, 270)[6]
+    sel = ohp.select_clusters(lay.centroids, ohp.camera_feature(cam, lay.pos_scale), 1)
+    segs = ohp.active_segments(lay.seg_begin, lay.seg_count, sel)
+    st = Settings(extent="opacity", mode="contrib")
+    f = gu.run(scene, [cam], st, segments=segs)
+    mask = ohp.active_mask(scene.n, segs)
+    _check_preprocess(scene, cam, f, 0, st, active=mask)
+    assert (f.n_tiles.cpu().numpy()[~mask] == 0).all()
+    sp, ob = _check_sort(f, [cam], st.tile, scene.n)
+    _check_raster(f, sp, [cam], st, scene.n)
+
+
+def test_end_to_end_c1_against_float64_pipeline():
+    cfg = synthetic.config(1)
+    scene, cam = cfg["scene"], cfg["cams"][0]
+    for st, mode in ((Settings(), "plain"), (Settings(mode="contrib", extent="opacity"), "cr")):
+        f = gu.run(scene, [cam], st)
+        imgs, Ts, _ = gu.outputs_np(f)
+        p = oproj.project_view(scene, cam, tile=16, extent=st.extent)
+        r = oblend.render_view(p, mode=mode)
+        ps = gu.psnr(imgs[0], r["image"])
+        gu.log(f"[e2e c1 {mode}] psnr={ps:.1f} maxabs={np.abs(imgs[0] - r['image']).max():.2e}")
+        assert ps > 70.0
