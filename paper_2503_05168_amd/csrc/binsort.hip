@@ -116,63 +116,218 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
 }
 
 // ---- stable LSD radix sort of (u32 key, u32 value) with a device-side count
-// hist layout: [digit][block]
+//
+// A radix block owns BLK = 256 * IT consecutive items.  Items either come
+// from arrays (LOAD) or are generated on the fly as the depth-ordered
+// Gaussian-tile pairs [b*BLK, (b+1)*BLK) (GEN: the pair emission fused into
+// the first tile pass, so the pairs are never written unsorted).
+// hist layout: [digit][block].
+
+constexpr int kGenIT = 8;                 // GEN blocks hold 2048 pairs
+constexpr int kGenBlk = B * kGenIT;
+
+struct GenSrc {
+  const uint32_t* ids;          // depth-ordered visible records
+  const seele_splat* splats;
+  const uint32_t* goff;         // first pair of each depth-ordered record
+  const uint32_t* block_first;  // record holding the first pair of each GEN block
+  const Hdr* hdr;
+};
+
+// Block-wide inclusive max-scan of IT consecutive values per thread (in place).
+template <int IT>
+__device__ __forceinline__ void block_inclusive_max(uint32_t* s_rec, uint32_t* s_tmp) {
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+  uint32_t v[IT];
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    v[i] = s_rec[tid * IT + i];
+    m = v[i] > m ? v[i] : m;
+    v[i] = m;
+  }
+  // inclusive max over lanes, then over waves
+  uint32_t x = m;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (l >= d) x = y > x ? y : x;
+  }
+  if (l == 63) s_tmp[w] = x;
+  __syncthreads();
+  uint32_t prev = __shfl_up(x, 1, 64);
+  if (l == 0) prev = 0;
+  for (int i = 0; i < w; ++i) prev = s_tmp[i] > prev ? s_tmp[i] : prev;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) s_rec[tid * IT + i] = v[i] > prev ? v[i] : prev;
+  __syncthreads();
+}
+
+// Exact k / w for 1 <= w < 2^16: a float reciprocal estimate is within one of
+// the quotient for k < 2^22 and is corrected once; larger k divide exactly.
+__device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t w) {
+  if (k < (1u << 22)) {
+    uint32_t q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
+    const int32_t r = (int32_t)(k - q * w);
+    if (r < 0) --q;
+    else if (r >= (int32_t)w) ++q;
+    return q;
+  }
+  return k / w;
+}
+
+// Stage the records covering pairs [S, S + BLK) in LDS (first pair, id, global
+// tile of the rectangle's top-left corner, rectangle width | grid width << 16;
+// W <= BLK + 1 records) and map every position of the block to its record:
+// each record marks the block position of its first pair, and an inclusive
+// max-scan spreads the marks over the record's pairs.
+template <int IT>
+__device__ __forceinline__ void gen_window(const GenSrc& g, const BinViews& views, uint32_t blk,
+                                           uint32_t nblk, uint32_t* s_off, uint32_t* s_id,
+                                           uint32_t* s_t0, uint32_t* s_wg, uint32_t* s_rec,
+                                           uint32_t* s_tmp) {
+  constexpr int BLK = B * IT;
+  const uint32_t nv = g.hdr->n_vis;
+  const uint32_t S = blk * (uint32_t)BLK;
+  const uint32_t g_lo = g.block_first[blk];
+  const uint32_t g_hi = blk + 1 < nblk ? g.block_first[blk + 1] : nv - 1;
+  const int W = (int)(g_hi - g_lo + 1);
+  const uint32_t n = (uint32_t)views.n;
+  for (int j = threadIdx.x; j < BLK; j += B) s_rec[j] = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < W; j += B) {
+    const uint32_t id = g.ids[g_lo + j];
+    const uint32_t o = g.goff[g_lo + j];
+    const uint32_t rx = g.splats[id].rect_x, ry = g.splats[id].rect_y;
+    const BinView bv = views.v[id / n];
+    const uint32_t x0 = rx & 0xffffu, y0 = ry & 0xffffu;
+    s_off[j] = o;
+    s_id[j] = id;
+    s_t0[j] = (uint32_t)bv.tile_base + y0 * (uint32_t)bv.grid_w + x0;
+    s_wg[j] = ((rx >> 16) - x0) | ((uint32_t)bv.grid_w << 16);
+    if (j > 0 && o - S < (uint32_t)BLK) s_rec[o - S] = (uint32_t)j;
+  }
+  __syncthreads();
+  block_inclusive_max<IT>(s_rec, s_tmp);
+}
+
+// Pair at block position p (global position q).
+__device__ __forceinline__ void gen_pair(uint32_t q, uint32_t p, const uint32_t* s_off,
+                                         const uint32_t* s_id, const uint32_t* s_t0,
+                                         const uint32_t* s_wg, const uint32_t* s_rec,
+                                         uint32_t& key, uint32_t& val) {
+  const uint32_t j = s_rec[p];
+  const uint32_t k = q - s_off[j];
+  const uint32_t wg = s_wg[j];
+  const uint32_t w = wg & 0xffffu;
+  const uint32_t dy = div_small(k, w);
+  key = s_t0[j] + dy * (wg >> 16) + (k - dy * w);
+  val = s_id[j];
+}
+
+template <int IT, bool GEN>
 __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ d_count,
-                                                   int shift, int bits,
-                                                   uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t h[256];
+                                                   GenSrc gs, BinViews views, int shift,
+                                                   int bits, uint32_t* __restrict__ hist,
+                                                   int nblocks) {
+  constexpr int BLK = B * IT;
+  constexpr int kWin = GEN ? 5 * (BLK + 1) : 1;
+  __shared__ uint32_t h[WAVES][256];
+  __shared__ uint32_t s_win[kWin];
+  __shared__ uint32_t s_tmp[WAVES + 1];
   const int radix = 1 << bits;
-  for (int d = threadIdx.x; d < radix; d += B) h[d] = 0;
-  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < WAVES * 256; d += B) (&h[0][0])[d] = 0;
   const uint32_t count = *d_count;
-  const int64_t begin = (int64_t)blockIdx.x * TILE;
+  const int64_t begin = (int64_t)blockIdx.x * BLK;
   const uint32_t mask = (uint32_t)radix - 1u;
+  uint32_t* s_off = s_win;
+  uint32_t* s_id = s_win + (BLK + 1);
+  uint32_t* s_t0 = s_win + 2 * (BLK + 1);
+  uint32_t* s_wg = s_win + 3 * (BLK + 1);
+  uint32_t* s_rec = s_win + 4 * (BLK + 1);
+  if (GEN && begin < count) {
+    const uint32_t nblk = (count + BLK - 1) / BLK;
+    gen_window<IT>(gs, views, blockIdx.x, nblk, s_off, s_id, s_t0, s_wg, s_rec, s_tmp);
+  }
+  __syncthreads();
   if (begin < count) {
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int64_t idx = begin + it * B + threadIdx.x;
-      if (idx < count) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    for (int it = 0; it < IT; ++it) {
+      const uint32_t p = it * B + threadIdx.x;
+      const int64_t idx = begin + p;
+      if (idx < count) {
+        uint32_t k, v;
+        if (GEN)
+          gen_pair((uint32_t)idx, p, s_off, s_id, s_t0, s_wg, s_rec, k, v);
+        else
+          k = keys[idx];
+        atomicAdd(&h[w][(k >> shift) & mask], 1u);
+      }
     }
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += B) hist[(int64_t)d * nblocks + blockIdx.x] = h[d];
+  for (int d = threadIdx.x; d < radix; d += B) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) t += h[ww][d];
+    hist[(int64_t)d * nblocks + blockIdx.x] = t;
+  }
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts in
-// place; the digit total goes to digit_total[d].
+// place (16 consecutive entries per thread); the digit total goes to
+// digit_total[d].
 __global__ __launch_bounds__(B) void k_radix_rowscan(uint32_t* __restrict__ hist, int nblocks,
                                                       uint32_t* __restrict__ digit_total) {
+  constexpr int R = 16;
   __shared__ uint32_t s[WAVES + 1];
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
   uint32_t carry = 0;
-  for (int base = 0; base < nblocks; base += B) {
-    const int idx = base + threadIdx.x;
-    const uint32_t x = idx < nblocks ? row[idx] : 0u;
+  for (int base = 0; base < nblocks; base += B * R) {
+    const int i0 = base + threadIdx.x * R;
+    uint32_t v[R];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = i0 + r < nblocks ? row[i0 + r] : 0u;
+      sum += v[r];
+    }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(x, s, tot);
-    if (idx < nblocks) row[idx] = carry + ex;
+    uint32_t run = carry + block_exclusive_scan<uint32_t>(sum, s, tot);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (i0 + r < nblocks) row[i0 + r] = run;
+      run += v[r];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter.  Block b owns items [b*TILE, (b+1)*TILE); wave w owns the
-// contiguous quarter w, processed 64 items at a time in index order.  Within
-// a 64-item step a lane's rank among equal digits comes from ballots over the
-// digit bits; per-wave running counts in LDS order the steps; per-digit wave
-// offsets order the waves.  Final position = digit base + block offset +
-// wave offset + rank, which preserves input order among equal digits.
+// Stable scatter.  Wave w owns the contiguous quarter w of the block,
+// processed 64 items at a time in index order.  Within a 64-item step a
+// lane's rank among equal digits comes from ballots over the digit bits;
+// per-wave running counts in LDS order the steps; per-digit wave offsets
+// order the waves.  Items are first placed in LDS in block-sorted order and
+// then written out digit run by digit run, so consecutive lanes store to
+// consecutive addresses.  Input order is preserved among equal digits.
+template <int IT, bool GEN>
 __global__ __launch_bounds__(B) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count,
-    int shift, int bits, const uint32_t* __restrict__ hist,
+    GenSrc gs, BinViews views, int shift, int bits, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ digit_total, int nblocks) {
+  constexpr int BLK = B * IT;
+  constexpr int kWords = GEN ? 5 * (BLK + 1) : 2 * BLK;
+  __shared__ uint32_t s_mem[kWords];  // GEN window, then the staged (key, value) pairs
   __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_loc[256];
   __shared__ uint32_t s_w[WAVES][256];
   __shared__ uint32_t s_tmp[WAVES + 1];
   const uint32_t count = *d_count;
-  const int64_t begin = (int64_t)blockIdx.x * TILE;
+  const int64_t begin = (int64_t)blockIdx.x * BLK;
   if (begin >= count) return;  // uniform per block
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1u;
@@ -186,20 +341,34 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     if (tid < radix) s_base[tid] = ex + hist[(int64_t)tid * nblocks + blockIdx.x];
   }
   for (int d = tid; d < WAVES * 256; d += B) (&s_w[0][0])[d] = 0;
+  if (GEN) {
+    const uint32_t nblk = (count + BLK - 1) / BLK;
+    gen_window<IT>(gs, views, blockIdx.x, nblk, s_mem, s_mem + (BLK + 1), s_mem + 2 * (BLK + 1),
+                   s_mem + 3 * (BLK + 1), s_mem + 4 * (BLK + 1), s_tmp);
+  }
   __syncthreads();
 
-  uint32_t k[ITEMS], v[ITEMS], rank[ITEMS];
-  const int64_t wbase = begin + (int64_t)w * 64 * ITEMS;
+  uint32_t k[IT], v[IT], rank[IT];
+  const int64_t wbase = begin + (int64_t)w * 64 * IT;
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
+  for (int it = 0; it < IT; ++it) {
     const int64_t idx = wbase + it * 64 + lane;
-    const bool valid = idx < count;
-    k[it] = valid ? kin[idx] : 0u;
-    v[it] = valid ? vin[idx] : 0u;
+    k[it] = 0u;
+    v[it] = 0u;
+    if (idx < count) {
+      if (GEN)
+        gen_pair((uint32_t)idx, (uint32_t)(idx - begin), s_mem, s_mem + (BLK + 1),
+                 s_mem + 2 * (BLK + 1), s_mem + 3 * (BLK + 1), s_mem + 4 * (BLK + 1), k[it],
+                 v[it]);
+      else {
+        k[it] = kin[idx];
+        v[it] = vin[idx];
+      }
+    }
   }
   const uint64_t lt = lanemask_lt();
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
+  for (int it = 0; it < IT; ++it) {
     const int64_t idx = wbase + it * 64 + lane;
     const bool valid = idx < count;
     const uint32_t d = (k[it] >> shift) & mask;
@@ -214,26 +383,43 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     rank[it] = before + below;
     if (valid && below == 0) s_w[w][d] = before + (uint32_t)__popcll(peers);
   }
-  __syncthreads();
+  __syncthreads();  // s_w complete; the GEN window is no longer read
+  // per digit: wave offsets, block total, block-local digit start
+  uint32_t dtot = 0;
   if (tid < radix) {
-    uint32_t run = 0;
 #pragma unroll
     for (int ww = 0; ww < WAVES; ++ww) {
       const uint32_t c = s_w[ww][tid];
-      s_w[ww][tid] = run;
-      run += c;
+      s_w[ww][tid] = dtot;
+      dtot += c;
     }
   }
+  {
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(tid < radix ? dtot : 0u, s_tmp, tot);
+    if (tid < radix) s_loc[tid] = ex;
+  }
   __syncthreads();
+  uint32_t* s_k = s_mem;
+  uint32_t* s_v = s_mem + BLK;
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
+  for (int it = 0; it < IT; ++it) {
     const int64_t idx = wbase + it * 64 + lane;
     if (idx < count) {
       const uint32_t d = (k[it] >> shift) & mask;
-      const uint32_t pos = s_base[d] + s_w[w][d] + rank[it];
-      kout[pos] = k[it];
-      vout[pos] = v[it];
+      const uint32_t lp = s_loc[d] + s_w[w][d] + rank[it];
+      s_k[lp] = k[it];
+      s_v[lp] = v[it];
     }
+  }
+  __syncthreads();
+  const uint32_t n_here = (uint32_t)min<int64_t>(BLK, (int64_t)count - begin);
+  for (uint32_t j = tid; j < n_here; j += B) {
+    const uint32_t kk = s_k[j];
+    const uint32_t d = (kk >> shift) & mask;
+    const uint32_t pos = s_base[d] + (j - s_loc[d]);
+    if (kout) kout[pos] = kk;
+    vout[pos] = s_v[j];
   }
 }
 
@@ -263,14 +449,18 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
   }
 }
 
-__global__ __launch_bounds__(B) void k_pair_emit(const uint32_t* __restrict__ ids,
-                                                  const int32_t* __restrict__ n_tiles,
-                                                  const seele_splat* __restrict__ splats,
-                                                  const Hdr* __restrict__ hdr,
-                                                  const uint64_t* __restrict__ partial,
-                                                  BinViews views, int64_t capacity,
-                                                  uint32_t* __restrict__ tile_keys,
-                                                  uint32_t* __restrict__ pair_vals) {
+// Per-record pair offsets in depth order (exclusive scan of tile counts), and
+// for every output block of kEmitBlock pairs the record holding its first
+// pair.  Skipped when the frame overflows the pair capacity.
+constexpr int kEmitBlock = kGenBlk;
+
+__global__ __launch_bounds__(B) void k_pair_offsets(const uint32_t* __restrict__ ids,
+                                                     const int32_t* __restrict__ n_tiles,
+                                                     const Hdr* __restrict__ hdr,
+                                                     const uint64_t* __restrict__ partial,
+                                                     int64_t capacity,
+                                                     uint32_t* __restrict__ goff,
+                                                     uint32_t* __restrict__ block_first) {
   __shared__ uint64_t s[WAVES + 1];
   const uint32_t nv = hdr->n_vis;
   const int64_t begin = (int64_t)blockIdx.x * TILE;
@@ -279,29 +469,15 @@ __global__ __launch_bounds__(B) void k_pair_emit(const uint32_t* __restrict__ id
 #pragma unroll 1
   for (int it = 0; it < ITEMS; ++it) {
     const int64_t i = begin + it * B + threadIdx.x;
-    uint32_t id = 0;
-    int32_t c = 0;
-    if (i < nv) {
-      id = ids[i];
-      c = n_tiles[id];
-    }
+    const uint32_t c = i < nv ? (uint32_t)n_tiles[ids[i]] : 0u;
     uint64_t tot;
     const uint64_t off = carry + block_exclusive_scan<uint64_t>((uint64_t)c, s, tot);
     carry += tot;
-    if (c > 0) {
-      const int v = (int)((int64_t)id / views.n);
-      const BinView bv = views.v[v];
-      const seele_splat& sp = splats[id];
-      const uint32_t x0 = sp.rect_x & 0xffffu, x1 = sp.rect_x >> 16;
-      const uint32_t y0 = sp.rect_y & 0xffffu, y1 = sp.rect_y >> 16;
-      uint64_t o = off;
-      for (uint32_t ty = y0; ty < y1; ++ty) {
-        const uint32_t row = (uint32_t)bv.tile_base + ty * (uint32_t)bv.grid_w;
-        for (uint32_t tx = x0; tx < x1; ++tx, ++o) {
-          tile_keys[o] = row + tx;
-          pair_vals[o] = id;
-        }
-      }
+    if (i < nv) {
+      goff[i] = (uint32_t)off;
+      // output blocks whose first pair belongs to this record
+      for (uint64_t b = (off + kEmitBlock - 1) / kEmitBlock; b * kEmitBlock < off + c; ++b)
+        block_first[b] = (uint32_t)i;
     }
   }
 }
@@ -319,17 +495,21 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const Hdr* __re
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t nblocks_for(int64_t n) { return (n + TILE - 1) / TILE; }
+int64_t gen_blocks_for(int64_t n) { return (n + kGenBlk - 1) / kGenBlk; }
 
+template <int IT, bool GEN>
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      const uint32_t* d_count, int64_t max_count, int shift, int bits,
-                      uint32_t* hist, uint32_t* digits, hipStream_t stream) {
-  const int nb = (int)nblocks_for(max_count);
+                      const uint32_t* d_count, int64_t max_count, const GenSrc& gs,
+                      const BinViews& views, int shift, int bits, uint32_t* hist,
+                      uint32_t* digits, hipStream_t stream) {
+  constexpr int BLK = B * IT;
+  const int nb = (int)((max_count + BLK - 1) / BLK);
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(B), 0, stream, kin, d_count, shift, bits, hist,
-                     nb);
+  hipLaunchKernelGGL((k_radix_hist<IT, GEN>), dim3(nb), dim3(B), 0, stream, kin, d_count, gs,
+                     views, shift, bits, hist, nb);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(B), 0, stream, hist, nb, digits);
-  hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(B), 0, stream, kin, vin, kout, vout, d_count,
-                     shift, bits, hist, digits, nb);
+  hipLaunchKernelGGL((k_radix_scatter<IT, GEN>), dim3(nb), dim3(B), 0, stream, kin, vin, kout,
+                     vout, d_count, gs, views, shift, bits, hist, digits, nb);
   return hipGetLastError();
 }
 
@@ -343,7 +523,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   int bits = 0;
   while (bits < 32 && ((int64_t)1 << bits) < n_tiles_total) ++bits;
   p.tile_bits = bits;
-  const int64_t nb_max = std::max<int64_t>(nblocks_for(n_records), nblocks_for(capacity));
+  const int64_t nb_max = std::max<int64_t>(nblocks_for(n_records), gen_blocks_for(capacity));
   size_t off = 0;
   p.off_hdr = off;
   off = align_up(off + sizeof(Hdr));
@@ -363,6 +543,10 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   off = align_up(off + 4 * (size_t)capacity);
   p.off_tvals = off;
   off = align_up(off + 4 * (size_t)capacity);
+  p.off_goff = off;
+  off = align_up(off + 4 * (size_t)n_records);
+  p.off_bfirst = off;
+  off = align_up(off + 4 * (size_t)(capacity / kEmitBlock + 2));
   p.off_hist = off;
   off = align_up(off + 4 * (size_t)256 * (size_t)std::max<int64_t>(nb_max, 1));
   p.off_digits = off;
@@ -385,6 +569,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
                      reinterpret_cast<uint32_t*>(base + p.off_tkeys1)};
   uint32_t* tv_ws = reinterpret_cast<uint32_t*>(base + p.off_tvals);
   uint32_t* hist = reinterpret_cast<uint32_t*>(base + p.off_hist);
+  uint32_t* goff = reinterpret_cast<uint32_t*>(base + p.off_goff);
+  uint32_t* bfirst = reinterpret_cast<uint32_t*>(base + p.off_bfirst);
   uint32_t* digits = reinterpret_cast<uint32_t*>(base + p.off_digits);
   const uint32_t* d_nvis = &hdr->n_vis;
   const uint32_t* d_npairs = &hdr->n_pairs;
@@ -409,40 +595,44 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     // 2. stable sort by float32 depth bits (4 x 8-bit passes, ends in buffer 0)
     for (int pass = 0; pass < 4; ++pass) {
       const int src = pass & 1, dst = src ^ 1;
-      e = radix_pass(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8, hist, digits,
-                     stream);
+      e = radix_pass<ITEMS, false>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, GenSrc{}, views,
+                                   8 * pass, 8, hist, digits, stream);
       if (e != hipSuccess) return e;
     }
   }
-  // 3. pair offsets in depth order, total -> num_pairs; emission
-  const int tile_passes = (p.tile_bits + 7) / 8;
-  uint32_t* emit_vals = (tile_passes % 2 == 0) ? sorted_ids : tv_ws;
+  // 3. pair offsets in depth order, total -> num_pairs
   if (nbR > 0) {
     hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], n_tiles, hdr, partial);
   }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, (int64_t)nbR, hdr, 1,
                      p.capacity, num_pairs);
   if (nbR > 0) {
-    hipLaunchKernelGGL(k_pair_emit, dim3(nbR), dim3(B), 0, stream, dv[0], n_tiles, splats, hdr,
-                       partial, views, p.capacity, tk[0], emit_vals);
+    hipLaunchKernelGGL(k_pair_offsets, dim3(nbR), dim3(B), 0, stream, dv[0], n_tiles, hdr,
+                       partial, p.capacity, goff, bfirst);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // 4. stable sort by tile id over tile_bits, balanced digit widths <= 8
+  // 4. stable sort by tile id over tile_bits (balanced digit widths <= 8); the
+  //    first pass generates the pairs from the depth-ordered records
+  const int tile_passes = std::max(1, (p.tile_bits + 7) / 8);
+  const int per = (p.tile_bits + tile_passes - 1) / tile_passes;
+  uint32_t* vcur = (tile_passes % 2 == 1) ? sorted_ids : tv_ws;
   int kcur = 0;
-  uint32_t* vcur = emit_vals;
-  if (tile_passes > 0) {
-    const int per = (p.tile_bits + tile_passes - 1) / tile_passes;
-    int shift = 0;
-    for (int pass = 0; pass < tile_passes; ++pass) {
-      const int bits = std::min(per, p.tile_bits - shift);
-      uint32_t* vdst = (vcur == sorted_ids) ? tv_ws : sorted_ids;
-      e = radix_pass(tk[kcur], vcur, tk[kcur ^ 1], vdst, d_npairs, p.capacity, shift, bits, hist,
-                     digits, stream);
-      if (e != hipSuccess) return e;
-      kcur ^= 1;
-      vcur = vdst;
-      shift += bits;
-    }
+  int shift = std::min(per, p.tile_bits);
+  {
+    const GenSrc gs{dv[0], splats, goff, bfirst, hdr};
+    e = radix_pass<kGenIT, true>(nullptr, nullptr, tk[0], vcur, d_npairs, p.capacity, gs, views, 0,
+                                 shift, hist, digits, stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int pass = 1; pass < tile_passes; ++pass) {
+    const int bits = std::min(per, p.tile_bits - shift);
+    uint32_t* vdst = (vcur == sorted_ids) ? tv_ws : sorted_ids;
+    e = radix_pass<ITEMS, false>(tk[kcur], vcur, tk[kcur ^ 1], vdst, d_npairs, p.capacity,
+                                 GenSrc{}, views, shift, bits, hist, digits, stream);
+    if (e != hipSuccess) return e;
+    kcur ^= 1;
+    vcur = vdst;
+    shift += bits;
   }
   // 5. per-tile ranges
   if (p.capacity > 0)

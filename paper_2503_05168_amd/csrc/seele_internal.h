@@ -177,7 +177,7 @@ struct BinSortPlan {
   int tile_bits;          // bits of the global tile id
   // workspace carve-up (byte offsets)
   size_t off_hdr, off_partial, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
-  size_t off_tkeys0, off_tkeys1, off_tvals, off_hist, off_digits, total;
+  size_t off_tkeys0, off_tkeys1, off_tvals, off_goff, off_bfirst, off_hist, off_digits, total;
 };
 BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_total);
 hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,
