@@ -1,0 +1,198 @@
+// Backward of front-to-back blending on gfx950 (fine-tuning, Sec. 3.5), for
+// the plain (Eqs. 1-2) and contribution-aware (Algorithm 1) forms.
+//
+// No per-pixel lists are stored by the forward pass: each pixel walks its
+// tile list backwards from its last blended position (n_contrib) with the
+// final transmittance T, recomputing alpha with the forward's own device
+// function, so every skip / leader / blend decision is reproduced exactly.
+// For a blended entry j with colour c_j and the colour S accumulated behind
+// it (background included):
+//   T_j = T / (1 - alpha_j)                     (transmittance before j)
+//   dL/dalpha_j = sum_ch g_ch (T_j c_j - S / (1 - alpha_j))
+//   dL/dc_j = T_j alpha_j g
+// and through alpha = o exp(-q/2), q = d^T A d (zero where the alpha clamp
+// was active).  Per-Gaussian gradients are reduced across the wave and added
+// to the record's 9 gradient slots with float atomics.
+#include "seele_internal.h"
+
+namespace seele {
+
+namespace {
+
+struct LdsBwd {
+  float4 a;  // mean_x, mean_y, l11, l21
+  float4 b;  // l22, opacity, r, g
+  float4 c;  // blue, conic a, conic b, conic c
+};
+
+template <int TS, int MODE>
+__global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, RasterParams rp,
+                                                       const seele_splat* __restrict__ splats,
+                                                       const uint32_t* __restrict__ ids,
+                                                       const int32_t* __restrict__ ranges,
+                                                       const float* __restrict__ final_T,
+                                                       const int32_t* __restrict__ n_contrib,
+                                                       const float* __restrict__ dL_dimage,
+                                                       float* __restrict__ grad2d) {
+  constexpr int NT = TS * TS;
+  __shared__ LdsBwd s_e[NT];
+  __shared__ uint32_t s_id[NT];
+  __shared__ int s_max;
+
+  const int gt = blockIdx.x;
+  int v = 0;
+  for (int k = 1; k < views.n_views; ++k)
+    if (views.v[k].tile_begin <= gt) v = k;
+  const RasterView rv = views.v[v];
+  const int lt = gt - rv.tile_begin;
+  const int tile_x = lt % rv.grid_w, tile_y = lt / rv.grid_w;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wx = (TS == 16) ? (wave & 1) * 8 : 0;
+  const int wy = (TS == 16) ? (wave >> 1) * 8 : 0;
+  const int gw = MODE ? rp.group_w : 1, gh = MODE ? rp.group_h : 1;
+  const int gsz = gw * gh, gpr = 8 / gw;
+  const int grp = lane / gsz, r = lane % gsz;
+  const int leader_lane = lane - r;
+  const int x = tile_x * TS + wx + (grp % gpr) * gw + r % gw;
+  const int y = tile_y * TS + wy + (grp / gpr) * gh + r / gw;
+  const bool inside = x < rv.W && y < rv.H;
+  const float fx = (float)x + 0.5f, fy = (float)y + 0.5f;
+
+  const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
+  const int start = ranges[ri];
+  const float amin = rp.alpha_min, amax = rp.alpha_max;
+
+  float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  int last = 0;
+  if (inside) {
+    const int64_t hw = (int64_t)rv.W * rv.H;
+    const int64_t pix = (int64_t)y * rv.W + x;
+    T = final_T[rv.pix_base + pix];
+    last = n_contrib[rv.pix_base + pix];
+    const float* g = dL_dimage + 3 * rv.pix_base;
+    g0 = g[pix];
+    g1 = g[hw + pix];
+    g2 = g[2 * hw + pix];
+  }
+  float S0 = T * rp.bg0, S1 = T * rp.bg1, S2 = T * rp.bg2;
+
+  if (tid == 0) s_max = 0;
+  __syncthreads();
+  atomicMax(&s_max, last);
+  __syncthreads();
+  const int jmax = s_max;
+
+  for (int hi = jmax; hi > 0; hi -= NT) {
+    const int lo = hi > NT ? hi - NT : 0;
+    if (tid < hi - lo) {
+      const uint32_t id = ids[start + lo + tid];
+      const float4* src = reinterpret_cast<const float4*>(splats + id);
+      const float4 A = src[0], Bv = src[1];
+      const float blue = src[2].x;
+      const Chol L = conic_factor(A.z, A.w, Bv.x);
+      s_e[tid].a = make_float4(A.x, A.y, L.l11, L.l21);
+      s_e[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
+      s_e[tid].c = make_float4(blue, A.z, A.w, Bv.x);
+      s_id[tid] = id;
+    }
+    __syncthreads();
+    for (int j = hi - 1; j >= lo; --j) {
+      const bool need = j < last;
+      if (__ballot(need) == 0) continue;  // wave-uniform
+      const int k = j - lo;
+      const float4 a = s_e[k].a, b = s_e[k].b;
+      float dx, dy;
+      const float p = splat_power(fx, fy, a.x, a.y, a.z, a.w, b.x, dx, dy);
+      const float e = fast_exp2(p);
+      const float raw = b.y * e;
+      const float alpha = __builtin_fminf(amax, raw);
+      bool blended = need && alpha >= amin;
+      if (MODE) {
+        // the leader's alpha is the leader lane's own alpha (same function, same pixel)
+        const float lead = __shfl(alpha, leader_lane, 64);
+        blended = blended && lead >= amin;
+      }
+      float gmx = 0.0f, gmy = 0.0f, gca = 0.0f, gcb = 0.0f, gcc = 0.0f, gop = 0.0f;
+      float gr = 0.0f, gg = 0.0f, gbl = 0.0f;
+      if (blended) {
+        const float4 cc = s_e[k].c;
+        const float om = 1.0f - alpha;
+        const float Tj = T / om;
+        const float ta = Tj * alpha;
+        const float dal = g0 * (Tj * b.z - S0 / om) + g1 * (Tj * b.w - S1 / om) +
+                          g2 * (Tj * cc.x - S2 / om);
+        gr = ta * g0;
+        gg = ta * g1;
+        gbl = ta * g2;
+        S0 = __builtin_fmaf(ta, b.z, S0);
+        S1 = __builtin_fmaf(ta, b.w, S1);
+        S2 = __builtin_fmaf(ta, cc.x, S2);
+        T = Tj;
+        if (raw <= amax) {
+          gop = dal * e;
+          const float dq = -0.5f * alpha * dal;  // dL/dq
+          // q = a dx^2 + 2 b dx dy + c dy^2 with d = pixel - mean: dq/dmean = -2 A d
+          gmx = -2.0f * dq * (cc.y * dx + cc.z * dy);
+          gmy = -2.0f * dq * (cc.z * dx + cc.w * dy);
+          gca = dq * dx * dx;
+          gcb = dq * 2.0f * dx * dy;
+          gcc = dq * dy * dy;
+        }
+      }
+      if (__ballot(blended) != 0) {
+        gmx = wave_sum(gmx);
+        gmy = wave_sum(gmy);
+        gca = wave_sum(gca);
+        gcb = wave_sum(gcb);
+        gcc = wave_sum(gcc);
+        gop = wave_sum(gop);
+        gr = wave_sum(gr);
+        gg = wave_sum(gg);
+        gbl = wave_sum(gbl);
+        if (lane == 0) {
+          float* dst = grad2d + (int64_t)s_id[k] * 9;
+          atomicAdd(dst + 0, gmx);
+          atomicAdd(dst + 1, gmy);
+          atomicAdd(dst + 2, gca);
+          atomicAdd(dst + 3, gcb);
+          atomicAdd(dst + 4, gcc);
+          atomicAdd(dst + 5, gop);
+          atomicAdd(dst + 6, gr);
+          atomicAdd(dst + 7, gg);
+          atomicAdd(dst + 8, gbl);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_raster_bwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
+                             const RasterParams& rp, const seele_splat* splats,
+                             const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                             const float* final_T, const int32_t* n_contrib,
+                             const float* dL_dimage, float* grad2d, hipStream_t stream) {
+  if (n_tiles_launch <= 0) return hipSuccess;
+  const dim3 grid(n_tiles_launch);
+  if (tile == 16) {
+    if (mode == SEELE_RASTER_CONTRIB)
+      hipLaunchKernelGGL((k_raster_bwd<16, 1>), grid, dim3(256), 0, stream, views, rp, splats,
+                         sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, grad2d);
+    else
+      hipLaunchKernelGGL((k_raster_bwd<16, 0>), grid, dim3(256), 0, stream, views, rp, splats,
+                         sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, grad2d);
+  } else {
+    if (mode == SEELE_RASTER_CONTRIB)
+      hipLaunchKernelGGL((k_raster_bwd<8, 1>), grid, dim3(64), 0, stream, views, rp, splats,
+                         sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, grad2d);
+    else
+      hipLaunchKernelGGL((k_raster_bwd<8, 0>), grid, dim3(64), 0, stream, views, rp, splats,
+                         sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, grad2d);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace seele

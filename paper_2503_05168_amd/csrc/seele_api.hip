@@ -150,6 +150,65 @@ int32_t check_raster_opts(const seele_raster_opts* o) {
   return SEELE_OK;
 }
 
+PreArgs make_pre_args(const seele_gaussians* g, const seele_preprocess_opts* opts) {
+  PreArgs a{};
+  a.n = g->n;
+  a.sh_degree = g->sh_degree;
+  a.tile = opts->tile;
+  a.extent = opts->extent;
+  a.alpha_min = opts->alpha_min;
+  a.lowpass = opts->lowpass;
+  a.z_near = opts->z_near;
+  a.n_segs = opts->n_segs;
+  for (int k = 0; k < opts->n_segs; ++k) {
+    a.seg_begin[k] = opts->seg_begin[k];
+    a.seg_end[k] = opts->seg_begin[k] + opts->seg_count[k];
+  }
+  return a;
+}
+
+RasterParams make_raster_params(const seele_raster_opts* opts) {
+  RasterParams rp{};
+  rp.alpha_min = opts->alpha_min;
+  rp.alpha_max = opts->alpha_max;
+  rp.T_min = opts->T_min;
+  rp.bg0 = opts->bg[0];
+  rp.bg1 = opts->bg[1];
+  rp.bg2 = opts->bg[2];
+  rp.group_w = opts->mode == SEELE_RASTER_CONTRIB ? opts->group_w : 1;
+  rp.group_h = opts->mode == SEELE_RASTER_CONTRIB ? opts->group_h : 1;
+  return rp;
+}
+
+// Views [v0, v0 + nv) as one raster launch; tile_base / pix_base are the
+// global tile and pixel offsets of view v0.
+RasterViews make_raster_views(const seele_camera* cams, int v0, int nv, int tile,
+                              int64_t tile_base, int64_t pix_base, int64_t& n_tiles_out,
+                              int64_t& n_pix_out) {
+  RasterViews rv{};
+  rv.n_views = nv;
+  rv.tile_base = (int32_t)tile_base;
+  int64_t t = 0, px = 0;
+  for (int k = 0; k < nv; ++k) {
+    const seele_camera& c = cams[v0 + k];
+    rv.v[k].tile_begin = (int32_t)t;
+    rv.v[k].W = c.width;
+    rv.v[k].H = c.height;
+    rv.v[k].grid_w = (c.width + tile - 1) / tile;
+    rv.v[k].pix_base = pix_base + px;
+    t += tiles_of(c, tile);
+    px += (int64_t)c.width * c.height;
+  }
+  n_tiles_out = t;
+  n_pix_out = px;
+  return rv;
+}
+
+__global__ void k_fill_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -195,19 +254,7 @@ int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int
       return fail(SEELE_ERR_INVALID_ARG, "n_tiles must be non-null and 4-byte aligned");
   }
   if (g->n == 0) return SEELE_OK;
-  PreArgs a{};
-  a.n = g->n;
-  a.sh_degree = g->sh_degree;
-  a.tile = opts->tile;
-  a.extent = opts->extent;
-  a.alpha_min = opts->alpha_min;
-  a.lowpass = opts->lowpass;
-  a.z_near = opts->z_near;
-  a.n_segs = opts->n_segs;
-  for (int k = 0; k < opts->n_segs; ++k) {
-    a.seg_begin[k] = opts->seg_begin[k];
-    a.seg_end[k] = opts->seg_begin[k] + opts->seg_count[k];
-  }
+  PreArgs a = make_pre_args(g, opts);
   hipStream_t st = static_cast<hipStream_t>(stream);
   for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPre) {
     const int nv = std::min(kMaxViewsPre, n_views - v0);
@@ -292,15 +339,7 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
     return fail(SEELE_ERR_INVALID_ARG, "output buffers null or misaligned");
   if ((splats && !aligned(splats, 16)) || (sorted_ids && !aligned(sorted_ids, 4)))
     return fail(SEELE_ERR_INVALID_ARG, "splats/sorted_ids misaligned");
-  RasterParams rp{};
-  rp.alpha_min = opts->alpha_min;
-  rp.alpha_max = opts->alpha_max;
-  rp.T_min = opts->T_min;
-  rp.bg0 = opts->bg[0];
-  rp.bg1 = opts->bg[1];
-  rp.bg2 = opts->bg[2];
-  rp.group_w = opts->mode == SEELE_RASTER_CONTRIB ? opts->group_w : 1;
-  rp.group_h = opts->mode == SEELE_RASTER_CONTRIB ? opts->group_h : 1;
+  const RasterParams rp = make_raster_params(opts);
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
   if (cnt) {
@@ -311,20 +350,9 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
   int64_t tile_base = 0, pix_base = 0;
   for (int v0 = 0; v0 < n_views; v0 += kMaxViewsRaster) {
     const int nv = std::min(kMaxViewsRaster, n_views - v0);
-    RasterViews rv{};
-    rv.n_views = nv;
-    rv.tile_base = (int32_t)tile_base;
-    int64_t t = 0;
-    for (int k = 0; k < nv; ++k) {
-      const seele_camera& c = cams[v0 + k];
-      rv.v[k].tile_begin = (int32_t)t;
-      rv.v[k].W = c.width;
-      rv.v[k].H = c.height;
-      rv.v[k].grid_w = (c.width + opts->tile - 1) / opts->tile;
-      rv.v[k].pix_base = pix_base;
-      t += tiles_of(c, opts->tile);
-      pix_base += (int64_t)c.width * c.height;
-    }
+    int64_t t = 0, npx = 0;
+    const RasterViews rv = make_raster_views(cams, v0, nv, opts->tile, tile_base, pix_base, t, npx);
+    pix_base += npx;
     const hipError_t e = launch_raster_fwd(opts->tile, opts->mode, rv, (int)t, rp, splats,
                                            sorted_ids, tile_ranges, image, final_T, n_contrib,
                                            cnt, st);
@@ -364,10 +392,61 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
                             const float* final_T, const int32_t* n_contrib,
                             const float* dL_dimage, float* grad2d,
                             const seele_gaussian_grads* grads, void* stream) {
-  (void)g; (void)cams; (void)n_views; (void)popts; (void)ropts; (void)splats; (void)n_tiles;
-  (void)sorted_ids; (void)tile_ranges; (void)final_T; (void)n_contrib; (void)dL_dimage;
-  (void)grad2d; (void)grads; (void)stream;
-  return fail(SEELE_ERR_UNSUPPORTED, "backward not built yet");
+  int32_t s = check_gaussians(g);
+  if (s != SEELE_OK) return s;
+  if ((s = check_preprocess_opts(popts, g->n)) != SEELE_OK) return s;
+  if ((s = check_raster_opts(ropts)) != SEELE_OK) return s;
+  if (popts->tile != ropts->tile)
+    return fail(SEELE_ERR_INVALID_ARG, "preprocess and raster tile sizes differ");
+  if ((s = check_cams(cams, n_views, ropts->tile, 1 << 20)) != SEELE_OK) return s;
+  const int64_t R = (int64_t)n_views * g->n;
+  if (R >= ((int64_t)1 << 32)) return fail(SEELE_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+  const int64_t TT = seele_total_tiles(cams, n_views, ropts->tile);
+  if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
+  if (!grads) return fail(SEELE_ERR_INVALID_ARG, "grads is null");
+  if (!tile_ranges || !aligned(tile_ranges, 4) || !final_T || !aligned(final_T, 4) ||
+      !n_contrib || !aligned(n_contrib, 4) || !dL_dimage || !aligned(dL_dimage, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "tile_ranges/final_T/n_contrib/dL_dimage null or misaligned");
+  if (R > 0) {
+    if (!splats || !aligned(splats, 16) || !n_tiles || !aligned(n_tiles, 4) || !grad2d ||
+        !aligned(grad2d, 4))
+      return fail(SEELE_ERR_INVALID_ARG, "splats/n_tiles/grad2d null or misaligned");
+    const void* p[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
+                        grads->sh};
+    for (int k = 0; k < 5; ++k)
+      if (!p[k] || !aligned(p[k], 4))
+        return fail(SEELE_ERR_INVALID_ARG, "gradient output %d null or misaligned", k);
+  }
+  if (g->n == 0) return SEELE_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // 1. per-record 2D gradients, accumulated by the blend backward
+  const int64_t n2 = R * 9;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, grad2d, n2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "grad2d reset");
+  const RasterParams rp = make_raster_params(ropts);
+  int64_t tile_base = 0, pix_base = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsRaster) {
+    const int nv = std::min(kMaxViewsRaster, n_views - v0);
+    int64_t t = 0, npx = 0;
+    const RasterViews rv = make_raster_views(cams, v0, nv, ropts->tile, tile_base, pix_base, t, npx);
+    e = launch_raster_bwd(ropts->tile, ropts->mode, rv, (int)t, rp, splats, sorted_ids,
+                          tile_ranges, final_T, n_contrib, dL_dimage, grad2d, st);
+    if (e != hipSuccess) return hip_fail(e, "raster backward launch");
+    tile_base += t;
+    pix_base += npx;
+  }
+  // 2. chain to the raw parameters, views summed
+  PreArgs a = make_pre_args(g, popts);
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPre) {
+    const int nv = std::min(kMaxViewsPre, n_views - v0);
+    a.n_views = nv;
+    a.view0 = v0;
+    for (int k = 0; k < nv; ++k) a.cam[k] = to_camk(cams[v0 + k], popts->tile);
+    e = launch_preprocess_bwd(a, *g, n_tiles, grad2d, *grads, v0 > 0, st);
+    if (e != hipSuccess) return hip_fail(e, "preprocess backward launch");
+  }
+  return SEELE_OK;
 }
 
 int32_t seele_hp_select(const float* centroids, int32_t K, const seele_camera* cam,

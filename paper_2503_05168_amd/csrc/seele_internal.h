@@ -190,4 +190,15 @@ hipError_t launch_raster_fwd(int tile, int mode, const RasterViews& views, int n
                              float* final_T, int32_t* n_contrib, unsigned long long* counters,
                              hipStream_t stream);
 
+hipError_t launch_preprocess_bwd(const PreArgs& a, const seele_gaussians& g,
+                                 const int32_t* n_tiles, const float* grad2d,
+                                 const seele_gaussian_grads& out, bool accumulate,
+                                 hipStream_t stream);
+
+hipError_t launch_raster_bwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
+                             const RasterParams& rp, const seele_splat* splats,
+                             const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                             const float* final_T, const int32_t* n_contrib,
+                             const float* dL_dimage, float* grad2d, hipStream_t stream);
+
 }  // namespace seele

@@ -219,6 +219,80 @@ def seele_hp_segments(layout_begin, layout_count, clusters):
     return [(int(ob[i]), int(oc[i])) for i in range(no.value)]
 
 
+def seele_rasterize_bwd(g: GaussianTensors, cams, settings: Settings, splats, n_tiles,
+                        sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, segments=None,
+                        grad2d=None, grads=None, stream=None):
+    """Backward of preprocess + rasterize: returns (grads, grad2d) where grads
+    has the layout of the Gaussian arrays and grad2d holds per-record
+    dL/d(mean_x, mean_y, conic a, b, c, opacity, r, g, b)."""
+    dev = g.means.device
+    V, n = len(cams), g.n
+    if grad2d is None:
+        grad2d = torch.empty((V * n, 9), dtype=torch.float32, device=dev)
+    if grads is None:
+        grads = GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.log_scales),
+                                torch.empty_like(g.quats), torch.empty_like(g.opacity_logits),
+                                torch.empty_like(g.sh), g.sh_degree)
+    gs = A.seele_gaussian_grads()
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        t = getattr(grads, name)
+        setattr(gs, name, t.data_ptr() if t.numel() else None)
+    popts, keep = settings.preprocess_opts(segments)
+    ropts = settings.raster_opts()
+    gst = g.struct()
+    dL = dL_dimage.contiguous()
+    st = A.lib().seele_rasterize_bwd(ctypes.byref(gst), A.camera_array(cams), V,
+                                     ctypes.byref(popts), ctypes.byref(ropts), _p(splats),
+                                     _p(n_tiles), _p(sorted_ids), _p(tile_ranges), _p(final_T),
+                                     _p(n_contrib), _p(dL), _p(grad2d), ctypes.byref(gs),
+                                     _stream(stream))
+    del keep
+    A.check(st, "seele_rasterize_bwd")
+    return grads, grad2d
+
+
+class SeeleRender(torch.autograd.Function):
+    """Differentiable render of several views (fine-tuning, Sec. 3.5): the
+    forward runs preprocess -> bin_sort -> rasterize, the backward the
+    library's blend and preprocess backward.  Culling, order, alpha skips,
+    leader tests and termination are constants of the backward."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, cams, settings, segments,
+                renderer, sh_degree):
+        g = GaussianTensors(means.detach().contiguous(), log_scales.detach().contiguous(),
+                            quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                            sh.detach().contiguous(), sh_degree)
+        f = renderer.render(g, cams, segments)
+        ctx.save_for_backward(f.splats, f.n_tiles, f.sorted_ids, f.tile_ranges, f.final_T,
+                              f.n_contrib)
+        ctx.g = g
+        ctx.cams, ctx.settings, ctx.segments = cams, settings, segments
+        ctx.mark_non_differentiable(f.final_T, f.n_contrib)
+        return f.image, f.final_T, f.n_contrib
+
+    @staticmethod
+    def backward(ctx, d_image, d_T, d_nc):
+        splats, n_tiles, ids, ranges, final_T, n_contrib = ctx.saved_tensors
+        if d_image is None:
+            d_image = torch.zeros(3 * final_T.numel(), dtype=torch.float32,
+                                  device=final_T.device)
+        grads, _ = seele_rasterize_bwd(ctx.g, ctx.cams, ctx.settings, splats, n_tiles, ids,
+                                       ranges, final_T, n_contrib, d_image, ctx.segments)
+        return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh,
+                None, None, None, None, None)
+
+
+def render(means, log_scales, quats, opacity_logits, sh, cams, settings: Settings | None = None,
+           segments=None, renderer: "Renderer | None" = None, sh_degree: int = 3):
+    """Differentiable render: returns the concatenated per-view [3][H][W] images
+    plus final transmittance and contributor counts."""
+    settings = settings or Settings()
+    renderer = renderer or Renderer(settings)
+    return SeeleRender.apply(means, log_scales, quats, opacity_logits, sh, list(cams), settings,
+                             segments, renderer, sh_degree)
+
+
 def split_views(flat: torch.Tensor, cams, channels: int):
     """Per-view [C, H, W] (or [H, W]) views into a concatenated output buffer."""
     out, off = [], 0
