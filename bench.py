@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--forms", default="plain,contrib,hp,hp_contrib")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=24)
+    ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     return ap.parse_args()
 
 
@@ -182,6 +183,62 @@ def run_form(name, form, cams, steps, warmup):
     return out
 
 
+def run_fwd_bwd(n, n_views, steps, warmup, mode):
+    """Fine-tuning step of the paper's Sec. 3.5 on the 1.0M-Gaussian workload:
+    the 8 views rendered in one batched call, L1 loss against images of a
+    perturbed copy of the scene, then the batched backward to every raw
+    parameter.  Returns ms per view (forward, backward, both)."""
+    import torch
+    import synthetic
+    import paper_2503_05168_amd as P
+
+    scene = synthetic.cluster_scene(4, n)
+    target_scene = synthetic.perturbed_scene(scene, 40)
+    cams = synthetic.orbit_cameras(n_views, 4.0, 1280, 720)
+    st = P.Settings(mode=mode)
+    g = P.GaussianTensors.from_arrays(scene)
+    gt = P.GaussianTensors.from_arrays(target_scene)
+    r = P.Renderer(P.Settings(), capacity=1 << 24)
+    target = r.render(gt, cams).image.clone()
+    rr = P.Renderer(st, capacity=r.capacity)
+    f = rr.render(g, cams)  # sizes the pair buffer (one synchronising pass)
+    rr.capacity = int(rr.capacity * 1.05) + 4096
+    numel = target.numel()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        f = rr.render(g, cams, check=False)
+        if ev is not None:
+            ev[1].record()
+        dL = torch.sign(f.image - target) / numel
+        P.seele_rasterize_bwd(g, cams, st, f.splats, f.n_tiles, f.sorted_ids, f.tile_ranges,
+                              f.final_T, f.n_contrib, dL)
+        if ev is not None:
+            ev[2].record()
+        return f
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    npairs = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        f = step(evs[i])
+        npairs.append(f.num_pairs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert max(int(x.item()) for x in npairs) <= rr.capacity, "pair buffer overflow"
+    fwd = sum(e[0].elapsed_time(e[1]) for e in evs) / steps / n_views
+    bwd = sum(e[1].elapsed_time(e[2]) for e in evs) / steps / n_views
+    out = dict(ms_per_view=1000.0 * wall / steps / n_views, fwd_ms_per_view=fwd,
+               bwd_ms_per_view=bwd, pairs_per_view=int(npairs[-1].item()) / n_views,
+               gaussians=n, views=n_views, width=1280, height=720)
+    log(f"[bench] fwd+bwd {mode}: {out['ms_per_view']:.3f} ms/view (fwd {fwd:.3f}, bwd {bwd:.3f})")
+    return out
+
+
 def cpu_baseline(scene, cam, n_tiles_sample):
     """Float64 oracle, one view: full preprocessing; binning of every pair of
     the Gaussians that touch a random sample of tiles, scaled to all pairs;
@@ -239,6 +296,11 @@ def main():
     results = {}
     for name in names:
         results[name] = run_form(name, forms[name], cams, args.steps, args.warmup)
+    fwd_bwd = None
+    if not args.no_bwd:
+        del forms
+        torch.cuda.empty_cache()
+        fwd_bwd = {m: run_fwd_bwd(1_000_000, 8, 4, 1, m) for m in ("plain", "contrib")}
     head = results.get("plain") or results[names[0]]
     # roofline of the dominant kernel of the headline form
     st = head["stage_ms"]
@@ -281,6 +343,9 @@ def main():
                                 f"plain 3DGS forward (preprocess + bin/sort + raster)"),
                    "gaussians": args.n, "views": 32, "width": 1920, "height": 1080, "tile": 16},
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
+        "fwd_bwd_ms_per_view": (None if fwd_bwd is None else
+                                {k: v["ms_per_view"] for k, v in fwd_bwd.items()}),
+        "fwd_bwd": fwd_bwd,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -131,6 +131,9 @@ typedef struct seele_raster_opts {
   int32_t mode;             /* SEELE_RASTER_*                                  */
   int32_t group_w, group_h; /* contribution-aware pixel group (2, 2); each of
                                1, 2, 4 with group_w * group_h <= 16            */
+  int32_t lds_batch;        /* Gaussians staged in LDS per step: 0 = one per
+                               pixel of the tile; 16x16 tiles also take 64 or
+                               128 (a tuning knob; results do not change)      */
   float alpha_min;          /* alpha_theta (1/255)                             */
   float alpha_max;          /* clamp of alpha (0.99)                           */
   float T_min;              /* a pixel stops before T would fall below (1e-4)   */
@@ -189,6 +192,28 @@ int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_id
                             const int32_t* tile_ranges, const seele_camera* cams,
                             int32_t n_views, const seele_raster_opts* opts, float* image,
                             float* final_T, int32_t* n_contrib, void* stream);
+
+/* Order of the (view, tile) work queue of seele_rasterize_fwd_queue. */
+enum {
+  SEELE_QUEUE_LIST = 0,           /* tiles in id order                       */
+  SEELE_QUEUE_HEAVIEST_FIRST = 1  /* tiles with the longest lists first       */
+};
+
+/* Workspace bytes for seele_rasterize_fwd_queue over n_tiles_total tiles. */
+size_t seele_raster_queue_workspace_size(int64_t n_tiles_total);
+
+/* seele_rasterize_fwd for batches of views as one persistent launch per 64
+ * views: a fixed grid of workgroups (enough to fill the GPU) pulls
+ * (view, tile) items from a device counter in `order` until the queue is
+ * empty.  Same outputs as seele_rasterize_fwd (bit-identical).  The
+ * workspace (caller-owned device memory, 256-byte aligned) holds the queue
+ * counter and the heaviest-first order; no host synchronisation, so the call
+ * can be captured in a HIP graph. */
+int32_t seele_rasterize_fwd_queue(const seele_splat* splats, const uint32_t* sorted_ids,
+                                  const int32_t* tile_ranges, const seele_camera* cams,
+                                  int32_t n_views, const seele_raster_opts* opts, int32_t order,
+                                  void* workspace, size_t workspace_bytes, float* image,
+                                  float* final_T, int32_t* n_contrib, void* stream);
 
 /* seele_rasterize_fwd with work counters (an instrumented, slower kernel
  * that writes the same outputs).  counters: device [4] uint64, overwritten:

@@ -13,6 +13,7 @@ from .pipeline import (  # noqa: F401
     seele_bin_sort,
     seele_rasterize_fwd,
     seele_rasterize_fwd_counted,
+    seele_rasterize_fwd_queue,
     seele_rasterize_bwd,
     SeeleRender,
     render,

@@ -21,6 +21,8 @@ SEELE_EXTENT_3SIGMA = 0
 SEELE_EXTENT_OPACITY = 1
 SEELE_RASTER_PLAIN = 0
 SEELE_RASTER_CONTRIB = 1
+SEELE_QUEUE_LIST = 0
+SEELE_QUEUE_HEAVIEST_FIRST = 1
 
 
 class seele_gaussians(ctypes.Structure):
@@ -54,8 +56,8 @@ class seele_preprocess_opts(ctypes.Structure):
 
 class seele_raster_opts(ctypes.Structure):
     _fields_ = [("tile", c_int32), ("mode", c_int32), ("group_w", c_int32), ("group_h", c_int32),
-                ("alpha_min", c_float), ("alpha_max", c_float), ("T_min", c_float),
-                ("bg", c_float * 3)]
+                ("lds_batch", c_int32), ("alpha_min", c_float), ("alpha_max", c_float),
+                ("T_min", c_float), ("bg", c_float * 3)]
 
 
 SIGNATURES = {
@@ -69,6 +71,11 @@ SIGNATURES = {
     "seele_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
                                       c_int32, POINTER(seele_raster_opts), c_void_p, c_void_p,
                                       c_void_p, c_void_p]),
+    "seele_raster_queue_workspace_size": (c_size_t, [c_int64]),
+    "seele_rasterize_fwd_queue": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
+                                            c_int32, POINTER(seele_raster_opts), c_int32,
+                                            c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
+                                            c_void_p]),
     "seele_rasterize_fwd_counted": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
                                               c_int32, POINTER(seele_raster_opts), c_void_p,
                                               c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -513,7 +513,56 @@ hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
   return hipGetLastError();
 }
 
+__global__ void k_set_count(uint32_t* d_count, uint32_t n) {
+  if (threadIdx.x == 0) *d_count = n;
+}
+
 }  // namespace
+
+size_t radix_sort_workspace_size(int64_t n) {
+  const int64_t nb = std::max<int64_t>(nblocks_for(n), 1);
+  return align_up(256) + 4 * align_up(4 * (size_t)std::max<int64_t>(n, 1)) +
+         align_up(4 * 256 * (size_t)nb) + align_up(4 * 256);
+}
+
+// Stable LSD sort of (key, value) pairs by the low `bits` key bits (8-bit
+// passes); the result is left in (keys, vals).  ws holds the count, the
+// ping-pong buffers and the digit histograms.
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int bits, void* ws,
+                            hipStream_t stream) {
+  if (n <= 1) return hipSuccess;
+  char* b = static_cast<char*>(ws);
+  uint32_t* d_count = reinterpret_cast<uint32_t*>(b);
+  size_t off = align_up(256);
+  uint32_t* k1 = reinterpret_cast<uint32_t*>(b + off);
+  off += align_up(4 * (size_t)n);
+  uint32_t* v1 = reinterpret_cast<uint32_t*>(b + off);
+  off += align_up(4 * (size_t)n);
+  off += 2 * align_up(4 * (size_t)n);  // reserved
+  uint32_t* hist = reinterpret_cast<uint32_t*>(b + off);
+  off += align_up(4 * 256 * (size_t)std::max<int64_t>(nblocks_for(n), 1));
+  uint32_t* digits = reinterpret_cast<uint32_t*>(b + off);
+  hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, stream, d_count, (uint32_t)n);
+  uint32_t* k[2] = {keys, k1};
+  uint32_t* v[2] = {vals, v1};
+  const int passes = (bits + 7) / 8;
+  BinViews none{};
+  for (int pass = 0; pass < passes; ++pass) {
+    const int src = pass & 1, dst = src ^ 1;
+    const int pb = std::min(8, bits - 8 * pass);
+    const hipError_t e = radix_pass<ITEMS, false>(k[src], v[src], k[dst], v[dst], d_count, n,
+                                                  GenSrc{}, none, 8 * pass, pb, hist, digits,
+                                                  stream);
+    if (e != hipSuccess) return e;
+  }
+  if (passes % 2 == 1) {
+    hipError_t e = hipMemcpyAsync(keys, k1, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(vals, v1, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
 
 BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_total) {
   BinSortPlan p{};

@@ -42,25 +42,29 @@ __device__ __forceinline__ float alpha_at(float px, float py, const float4& a, c
 // [0] alpha evaluations by pixels that have not stopped (contribution-aware:
 // only in groups whose leader accepted), [1] blends, [2] leader tests of
 // groups holding a live pixel, [3] of those, acceptances.
-template <int TS, int MODE, bool COUNT>
-__global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterViews views, RasterParams rp,
-                                                       const seele_splat* __restrict__ splats,
-                                                       const uint32_t* __restrict__ ids,
-                                                       const int32_t* __restrict__ ranges,
-                                                       float* __restrict__ image,
-                                                       float* __restrict__ final_T,
-                                                       int32_t* __restrict__ n_contrib,
-                                                       unsigned long long* __restrict__ counters) {
+// The tile list is consumed in LDS batches of BATCH records (<= TS*TS: threads
+// tid < BATCH stage one record each); BATCH trades barrier and early-exit
+// granularity against LDS latency and is chosen by the autotuner.
+template <int TS, int MODE, bool COUNT, int BATCH>
+__device__ __forceinline__ void raster_tile(const int gt, const RasterViews& views,
+                                            const RasterParams& rp,
+                                            const seele_splat* __restrict__ splats,
+                                            const uint32_t* __restrict__ ids,
+                                            const int32_t* __restrict__ ranges,
+                                            float* __restrict__ image,
+                                            float* __restrict__ final_T,
+                                            int32_t* __restrict__ n_contrib,
+                                            unsigned long long* __restrict__ counters) {
   constexpr int NT = TS * TS;
-  __shared__ LdsBatch s_ab[NT];
-  __shared__ float s_blue[NT];
+  static_assert(BATCH <= NT && BATCH % 64 == 0 || BATCH == NT, "batch depth");
+  __shared__ LdsBatch s_ab[BATCH];
+  __shared__ float s_blue[BATCH];
   __shared__ unsigned long long s_cnt[4];
   uint32_t c_eval = 0, c_blend = 0, c_ltest = 0, c_lpass = 0;
   if (COUNT) {
     if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
   }
 
-  const int gt = blockIdx.x;
   int v = 0;
   for (int k = 1; k < views.n_views; ++k)
     if (views.v[k].tile_begin <= gt) v = k;
@@ -92,10 +96,10 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterViews views, Raster
   int last = 0;
   bool done = !inside;
 
-  for (int base = 0; base < n; base += NT) {
+  for (int base = 0; base < n; base += BATCH) {
     if (__syncthreads_count(done) == NT) break;
     const int j = base + tid;
-    if (j < n) {
+    if (tid < BATCH && j < n) {
       const float4* src = reinterpret_cast<const float4*>(splats + ids[start + j]);
       const float4 A = src[0], Bv = src[1];
       const float blue = src[2].x;
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterViews views, Raster
       s_blue[tid] = blue;
     }
     __syncthreads();
-    const int cnt = min(NT, n - base);
+    const int cnt = min(BATCH, n - base);
     if (MODE == 0) {
       for (int k = 0; k < cnt; ++k) {
         if (__ballot(!done) == 0) break;
@@ -199,43 +203,171 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterViews views, Raster
   }
 }
 
-template <int TS, bool COUNT>
-void launch_ts(int mode, dim3 grid, const RasterViews& views, const RasterParams& rp,
-               const seele_splat* splats, const uint32_t* ids, const int32_t* ranges, float* image,
-               float* final_T, int32_t* n_contrib, unsigned long long* counters,
-               hipStream_t stream) {
+template <int TS, int MODE, bool COUNT, int BATCH>
+__global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterViews views, RasterParams rp,
+                                                       const seele_splat* __restrict__ splats,
+                                                       const uint32_t* __restrict__ ids,
+                                                       const int32_t* __restrict__ ranges,
+                                                       float* __restrict__ image,
+                                                       float* __restrict__ final_T,
+                                                       int32_t* __restrict__ n_contrib,
+                                                       unsigned long long* __restrict__ counters) {
+  raster_tile<TS, MODE, COUNT, BATCH>(blockIdx.x, views, rp, splats, ids, ranges, image, final_T,
+                                      n_contrib, counters);
+}
+
+// Persistent form for batches of views: a fixed grid of workgroups pulls
+// (view, tile) items from a device counter until the queue is empty, in list
+// order or in the order given by `order` (heaviest tile lists first, so the
+// longest items start early and the tail stays short).  Every workgroup exits
+// once the counter passes the item count.
+template <int TS, int MODE, int BATCH>
+__global__ __launch_bounds__(TS* TS) void k_raster_fwd_queue(
+    RasterViews views, RasterParams rp, const seele_splat* __restrict__ splats,
+    const uint32_t* __restrict__ ids, const int32_t* __restrict__ ranges,
+    float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ n_contrib,
+    uint32_t* __restrict__ counter, const uint32_t* __restrict__ order, uint32_t n_items) {
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int t = (int)(order ? order[item] : item);
+    raster_tile<TS, MODE, false, BATCH>(t, views, rp, splats, ids, ranges, image, final_T,
+                                        n_contrib, nullptr);
+  }
+}
+
+// Sort keys for heaviest-first scheduling: ~(list length) so an ascending
+// stable sort puts long lists first (ties in tile order).
+__global__ void k_tile_len_keys(const int32_t* __restrict__ ranges, int32_t tile_base,
+                                uint32_t n, uint32_t* __restrict__ keys,
+                                uint32_t* __restrict__ vals, uint32_t* __restrict__ counter) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *counter = 0u;
+  if (i >= n) return;
+  const int64_t r = 2 * ((int64_t)tile_base + i);
+  keys[i] = ~(uint32_t)(ranges[r + 1] - ranges[r]);
+  vals[i] = i;
+}
+
+__global__ void k_zero_counter(uint32_t* counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+template <int TS, int BATCH>
+void launch_fwd(int mode, bool count, dim3 grid, const RasterViews& views, const RasterParams& rp,
+                const seele_splat* splats, const uint32_t* ids, const int32_t* ranges,
+                float* image, float* final_T, int32_t* n_contrib, unsigned long long* counters,
+                hipStream_t stream) {
+  const dim3 block(TS * TS);
+  if (mode == SEELE_RASTER_CONTRIB) {
+    if (count)
+      hipLaunchKernelGGL((k_raster_fwd<TS, 1, true, BATCH>), grid, block, 0, stream, views, rp,
+                         splats, ids, ranges, image, final_T, n_contrib, counters);
+    else
+      hipLaunchKernelGGL((k_raster_fwd<TS, 1, false, BATCH>), grid, block, 0, stream, views, rp,
+                         splats, ids, ranges, image, final_T, n_contrib, counters);
+  } else {
+    if (count)
+      hipLaunchKernelGGL((k_raster_fwd<TS, 0, true, BATCH>), grid, block, 0, stream, views, rp,
+                         splats, ids, ranges, image, final_T, n_contrib, counters);
+    else
+      hipLaunchKernelGGL((k_raster_fwd<TS, 0, false, BATCH>), grid, block, 0, stream, views, rp,
+                         splats, ids, ranges, image, final_T, n_contrib, counters);
+  }
+}
+
+template <int TS, int BATCH>
+void launch_queue(int mode, dim3 grid, const RasterViews& views, const RasterParams& rp,
+                  const seele_splat* splats, const uint32_t* ids, const int32_t* ranges,
+                  float* image, float* final_T, int32_t* n_contrib, uint32_t* counter,
+                  const uint32_t* order, uint32_t n_items, hipStream_t stream) {
+  const dim3 block(TS * TS);
   if (mode == SEELE_RASTER_CONTRIB)
-    hipLaunchKernelGGL((k_raster_fwd<TS, 1, COUNT>), grid, dim3(TS * TS), 0, stream, views, rp,
-                       splats, ids, ranges, image, final_T, n_contrib, counters);
+    hipLaunchKernelGGL((k_raster_fwd_queue<TS, 1, BATCH>), grid, block, 0, stream, views, rp,
+                       splats, ids, ranges, image, final_T, n_contrib, counter, order, n_items);
   else
-    hipLaunchKernelGGL((k_raster_fwd<TS, 0, COUNT>), grid, dim3(TS * TS), 0, stream, views, rp,
-                       splats, ids, ranges, image, final_T, n_contrib, counters);
+    hipLaunchKernelGGL((k_raster_fwd_queue<TS, 0, BATCH>), grid, block, 0, stream, views, rp,
+                       splats, ids, ranges, image, final_T, n_contrib, counter, order, n_items);
 }
 
 }  // namespace
 
-hipError_t launch_raster_fwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
-                             const RasterParams& rp, const seele_splat* splats,
-                             const uint32_t* sorted_ids, const int32_t* tile_ranges, float* image,
-                             float* final_T, int32_t* n_contrib, unsigned long long* counters,
+// Batch depths offered per tile size (the default is one record per thread).
+bool raster_batch_supported(int tile, int batch) {
+  if (tile == 16) return batch == 64 || batch == 128 || batch == 256;
+  return batch == 64;
+}
+
+hipError_t launch_raster_fwd(int tile, int mode, int batch, const RasterViews& views,
+                             int n_tiles_launch, const RasterParams& rp,
+                             const seele_splat* splats, const uint32_t* sorted_ids,
+                             const int32_t* tile_ranges, float* image, float* final_T,
+                             int32_t* n_contrib, unsigned long long* counters,
                              hipStream_t stream) {
   if (n_tiles_launch <= 0) return hipSuccess;
   const dim3 grid(n_tiles_launch);
+  const bool cnt = counters != nullptr;
   if (tile == 16) {
-    if (counters)
-      launch_ts<16, true>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image, final_T,
-                          n_contrib, counters, stream);
+    if (batch == 64)
+      launch_fwd<16, 64>(mode, cnt, grid, views, rp, splats, sorted_ids, tile_ranges, image,
+                         final_T, n_contrib, counters, stream);
+    else if (batch == 128)
+      launch_fwd<16, 128>(mode, cnt, grid, views, rp, splats, sorted_ids, tile_ranges, image,
+                          final_T, n_contrib, counters, stream);
     else
-      launch_ts<16, false>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image, final_T,
-                           n_contrib, counters, stream);
+      launch_fwd<16, 256>(mode, cnt, grid, views, rp, splats, sorted_ids, tile_ranges, image,
+                          final_T, n_contrib, counters, stream);
   } else {
-    if (counters)
-      launch_ts<8, true>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image, final_T,
-                         n_contrib, counters, stream);
-    else
-      launch_ts<8, false>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image, final_T,
-                          n_contrib, counters, stream);
+    launch_fwd<8, 64>(mode, cnt, grid, views, rp, splats, sorted_ids, tile_ranges, image,
+                      final_T, n_contrib, counters, stream);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_fwd_queue(int tile, int mode, int batch, const RasterViews& views,
+                                   int n_tiles_launch, const RasterParams& rp,
+                                   const seele_splat* splats, const uint32_t* sorted_ids,
+                                   const int32_t* tile_ranges, float* image, float* final_T,
+                                   int32_t* n_contrib, uint32_t* counter, const uint32_t* order,
+                                   int n_workgroups, hipStream_t stream) {
+  if (n_tiles_launch <= 0) return hipSuccess;
+  const dim3 grid(std::min(n_workgroups, n_tiles_launch));
+  const uint32_t items = (uint32_t)n_tiles_launch;
+  if (tile == 16) {
+    if (batch == 64)
+      launch_queue<16, 64>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image, final_T,
+                           n_contrib, counter, order, items, stream);
+    else if (batch == 128)
+      launch_queue<16, 128>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image,
+                            final_T, n_contrib, counter, order, items, stream);
+    else
+      launch_queue<16, 256>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image,
+                            final_T, n_contrib, counter, order, items, stream);
+  } else {
+    launch_queue<8, 64>(mode, grid, views, rp, splats, sorted_ids, tile_ranges, image, final_T,
+                        n_contrib, counter, order, items, stream);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order_keys(const int32_t* tile_ranges, int32_t tile_base, uint32_t n,
+                                  uint32_t* keys, uint32_t* vals, uint32_t* counter,
+                                  hipStream_t stream) {
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_tile_len_keys, dim3((n + 255) / 256), dim3(256), 0, stream, tile_ranges,
+                     tile_base, n, keys, vals, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counter(uint32_t* counter, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
   return hipGetLastError();
 }
 

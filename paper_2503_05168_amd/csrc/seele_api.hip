@@ -147,7 +147,14 @@ int32_t check_raster_opts(const seele_raster_opts* o) {
     return fail(SEELE_ERR_INVALID_ARG, "T_min must be in (0, 1)");
   for (int c = 0; c < 3; ++c)
     if (!is_finite(o->bg[c])) return fail(SEELE_ERR_INVALID_ARG, "non-finite background");
+  if (o->lds_batch != 0 && !raster_batch_supported(o->tile, o->lds_batch))
+    return fail(SEELE_ERR_INVALID_ARG, "lds_batch %d unsupported for tile %d", o->lds_batch,
+                o->tile);
   return SEELE_OK;
+}
+
+int batch_of(const seele_raster_opts* o) {
+  return o->lds_batch != 0 ? o->lds_batch : o->tile * o->tile;
 }
 
 PreArgs make_pre_args(const seele_gaussians* g, const seele_preprocess_opts* opts) {
@@ -353,9 +360,9 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
     int64_t t = 0, npx = 0;
     const RasterViews rv = make_raster_views(cams, v0, nv, opts->tile, tile_base, pix_base, t, npx);
     pix_base += npx;
-    const hipError_t e = launch_raster_fwd(opts->tile, opts->mode, rv, (int)t, rp, splats,
-                                           sorted_ids, tile_ranges, image, final_T, n_contrib,
-                                           cnt, st);
+    const hipError_t e = launch_raster_fwd(opts->tile, opts->mode, batch_of(opts), rv, (int)t,
+                                           rp, splats, sorted_ids, tile_ranges, image, final_T,
+                                           n_contrib, cnt, st);
     if (e != hipSuccess) return hip_fail(e, "raster launch");
     tile_base += t;
   }
@@ -372,6 +379,87 @@ int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_id
                             float* final_T, int32_t* n_contrib, void* stream) {
   return rasterize(splats, sorted_ids, tile_ranges, cams, n_views, opts, image, final_T,
                    n_contrib, nullptr, stream);
+}
+
+size_t seele_raster_queue_workspace_size(int64_t n_tiles_total) {
+  if (n_tiles_total < 0) return 0;
+  const int64_t n = std::max<int64_t>(n_tiles_total, 1);
+  return 256 + 2 * ((4 * (size_t)n + 255) & ~(size_t)255) + radix_sort_workspace_size(n);
+}
+
+int32_t seele_rasterize_fwd_queue(const seele_splat* splats, const uint32_t* sorted_ids,
+                                  const int32_t* tile_ranges, const seele_camera* cams,
+                                  int32_t n_views, const seele_raster_opts* opts, int32_t order,
+                                  void* workspace, size_t workspace_bytes, float* image,
+                                  float* final_T, int32_t* n_contrib, void* stream) {
+  int32_t s = check_raster_opts(opts);
+  if (s != SEELE_OK) return s;
+  if ((s = check_cams(cams, n_views, opts->tile, 1 << 20)) != SEELE_OK) return s;
+  if (order != SEELE_QUEUE_LIST && order != SEELE_QUEUE_HEAVIEST_FIRST)
+    return fail(SEELE_ERR_INVALID_ARG, "unknown queue order %d", order);
+  const int64_t TT = seele_total_tiles(cams, n_views, opts->tile);
+  if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
+  if (!tile_ranges || !aligned(tile_ranges, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
+  if (!image || !aligned(image, 4) || !final_T || !aligned(final_T, 4) || !n_contrib ||
+      !aligned(n_contrib, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "output buffers null or misaligned");
+  if ((splats && !aligned(splats, 16)) || (sorted_ids && !aligned(sorted_ids, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "splats/sorted_ids misaligned");
+  if (!workspace || !aligned(workspace, 256))
+    return fail(SEELE_ERR_INVALID_ARG, "workspace null or not 256-byte aligned");
+  // the largest chunk of views decides the workspace
+  int64_t max_chunk = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsRaster) {
+    const int64_t t = seele_total_tiles(cams + v0, std::min(kMaxViewsRaster, n_views - v0),
+                                        opts->tile);
+    max_chunk = std::max(max_chunk, t);
+  }
+  const size_t need = seele_raster_queue_workspace_size(max_chunk);
+  if (workspace_bytes < need)
+    return fail(SEELE_ERR_CAPACITY, "workspace %zu bytes < required %zu", workspace_bytes, need);
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      return fail(SEELE_ERR_HIP, "cannot query the compute-unit count");
+    cus = n;
+  }
+  const int workgroups = cus * (opts->tile == 16 ? 8 : 32);
+  char* base = static_cast<char*>(workspace);
+  uint32_t* counter = reinterpret_cast<uint32_t*>(base);
+  const size_t tb = (4 * (size_t)std::max<int64_t>(max_chunk, 1) + 255) & ~(size_t)255;
+  uint32_t* keys = reinterpret_cast<uint32_t*>(base + 256);
+  uint32_t* vals = reinterpret_cast<uint32_t*>(base + 256 + tb);
+  void* sort_ws = base + 256 + 2 * tb;
+  const RasterParams rp = make_raster_params(opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t tile_base = 0, pix_base = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsRaster) {
+    const int nv = std::min(kMaxViewsRaster, n_views - v0);
+    int64_t t = 0, npx = 0;
+    const RasterViews rv = make_raster_views(cams, v0, nv, opts->tile, tile_base, pix_base, t, npx);
+    hipError_t e;
+    const uint32_t* ord = nullptr;
+    if (order == SEELE_QUEUE_HEAVIEST_FIRST) {
+      e = launch_tile_order_keys(tile_ranges, (int32_t)tile_base, (uint32_t)t, keys, vals, counter,
+                                 st);
+      if (e == hipSuccess) e = radix_sort_pairs(keys, vals, t, 32, sort_ws, st);
+      ord = vals;
+    } else {
+      e = launch_zero_counter(counter, st);
+    }
+    if (e == hipSuccess)
+      e = launch_raster_fwd_queue(opts->tile, opts->mode, batch_of(opts), rv, (int)t, rp, splats,
+                                  sorted_ids, tile_ranges, image, final_T, n_contrib, counter, ord,
+                                  workgroups, st);
+    if (e != hipSuccess) return hip_fail(e, "queued raster launch");
+    tile_base += t;
+    pix_base += npx;
+  }
+  return SEELE_OK;
 }
 
 int32_t seele_rasterize_fwd_counted(const seele_splat* splats, const uint32_t* sorted_ids,

@@ -184,11 +184,30 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
                            const int32_t* n_tiles, void* ws, uint32_t* sorted_ids,
                            int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream);
 
-hipError_t launch_raster_fwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
-                             const RasterParams& rp, const seele_splat* splats,
-                             const uint32_t* sorted_ids, const int32_t* tile_ranges, float* image,
-                             float* final_T, int32_t* n_contrib, unsigned long long* counters,
+bool raster_batch_supported(int tile, int batch);
+
+hipError_t launch_raster_fwd(int tile, int mode, int batch, const RasterViews& views,
+                             int n_tiles_launch, const RasterParams& rp,
+                             const seele_splat* splats, const uint32_t* sorted_ids,
+                             const int32_t* tile_ranges, float* image, float* final_T,
+                             int32_t* n_contrib, unsigned long long* counters,
                              hipStream_t stream);
+
+hipError_t launch_raster_fwd_queue(int tile, int mode, int batch, const RasterViews& views,
+                                   int n_tiles_launch, const RasterParams& rp,
+                                   const seele_splat* splats, const uint32_t* sorted_ids,
+                                   const int32_t* tile_ranges, float* image, float* final_T,
+                                   int32_t* n_contrib, uint32_t* counter, const uint32_t* order,
+                                   int n_workgroups, hipStream_t stream);
+
+hipError_t launch_tile_order_keys(const int32_t* tile_ranges, int32_t tile_base, uint32_t n,
+                                  uint32_t* keys, uint32_t* vals, uint32_t* counter,
+                                  hipStream_t stream);
+hipError_t launch_zero_counter(uint32_t* counter, hipStream_t stream);
+
+size_t radix_sort_workspace_size(int64_t n);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int bits, void* ws,
+                            hipStream_t stream);
 
 hipError_t launch_preprocess_bwd(const PreArgs& a, const seele_gaussians& g,
                                  const int32_t* n_tiles, const float* grad2d,

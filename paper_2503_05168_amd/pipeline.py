@@ -57,6 +57,7 @@ class Settings:
     extent: str = "3sigma"         # or "opacity" (Eq. 5)
     mode: str = "plain"            # or "contrib" (Algorithm 1)
     group: tuple = (2, 2)
+    lds_batch: int = 0             # 0 = one Gaussian per tile pixel per LDS step
     alpha_min: float = 1.0 / 255.0
     alpha_max: float = 0.99
     T_min: float = 1e-4
@@ -86,6 +87,7 @@ class Settings:
         o.tile = self.tile
         o.mode = {"plain": A.SEELE_RASTER_PLAIN, "contrib": A.SEELE_RASTER_CONTRIB}[self.mode]
         o.group_w, o.group_h = int(self.group[0]), int(self.group[1])
+        o.lds_batch = int(self.lds_batch)
         o.alpha_min, o.alpha_max, o.T_min = self.alpha_min, self.alpha_max, self.T_min
         for i in range(3):
             o.bg[i] = float(self.bg[i])
@@ -170,6 +172,33 @@ def seele_rasterize_fwd(splats, sorted_ids, tile_ranges, cams, settings: Setting
                                      _p(image), _p(final_T), _p(n_contrib), _stream(stream))
     A.check(st, "seele_rasterize_fwd")
     return image, final_T, n_contrib
+
+
+QUEUE_ORDERS = {"list": A.SEELE_QUEUE_LIST, "heaviest": A.SEELE_QUEUE_HEAVIEST_FIRST}
+
+
+def seele_rasterize_fwd_queue(splats, sorted_ids, tile_ranges, cams, settings: Settings,
+                              order: str = "heaviest", workspace=None, image=None, final_T=None,
+                              n_contrib=None, stream=None):
+    """Persistent (view, tile) work-queue form of the forward rasterizer."""
+    dev = tile_ranges.device
+    npix = pixel_count(cams)
+    if image is None:
+        image = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    if final_T is None:
+        final_T = torch.empty(npix, dtype=torch.float32, device=dev)
+    if n_contrib is None:
+        n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    need = int(A.lib().seele_raster_queue_workspace_size(total_tiles(cams, settings.tile)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    opts = settings.raster_opts()
+    st = A.lib().seele_rasterize_fwd_queue(_p(splats), _p(sorted_ids), _p(tile_ranges),
+                                           A.camera_array(cams), len(cams), ctypes.byref(opts),
+                                           QUEUE_ORDERS[order], _p(workspace), workspace.numel(),
+                                           _p(image), _p(final_T), _p(n_contrib), _stream(stream))
+    A.check(st, "seele_rasterize_fwd_queue")
+    return image, final_T, n_contrib, workspace
 
 
 def seele_rasterize_fwd_counted(splats, sorted_ids, tile_ranges, cams, settings: Settings,
@@ -328,10 +357,15 @@ class Renderer:
     repeated when the device reports overflow; ``check=False`` skips that
     host read (the caller then checks ``num_pairs`` itself)."""
 
-    def __init__(self, settings: Settings | None = None, capacity: int = 1 << 20):
+    def __init__(self, settings: Settings | None = None, capacity: int = 1 << 20,
+                 schedule: str = "grid"):
+        """schedule: "grid" (one workgroup per tile), "queue" or "queue_heavy"
+        (persistent work queue in list / heaviest-first order)."""
         self.settings = settings or Settings()
         self.capacity = int(capacity)
+        self.schedule = schedule
         self._ws = None
+        self._qws = None
 
     def render(self, g: GaussianTensors, cams, segments=None, check: bool = True,
                stream=None) -> Frame:
@@ -347,6 +381,11 @@ class Renderer:
             if need <= self.capacity:
                 break
             self.capacity = min(int(need * 1.5) + 1024, (1 << 31) - 1)
-        image, final_T, n_contrib = seele_rasterize_fwd(splats, ids, ranges, cams, s,
-                                                        stream=stream)
+        if self.schedule == "grid":
+            image, final_T, n_contrib = seele_rasterize_fwd(splats, ids, ranges, cams, s,
+                                                            stream=stream)
+        else:
+            order = "heaviest" if self.schedule == "queue_heavy" else "list"
+            image, final_T, n_contrib, self._qws = seele_rasterize_fwd_queue(
+                splats, ids, ranges, cams, s, order, self._qws, stream=stream)
         return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs, list(cams))

@@ -1,0 +1,153 @@
+"""Batched multi-view rendering on the GPU: one call over many cameras of
+mixed resolution, the persistent (view, tile) work queue, LDS batch depths
+and HIP-graph capture all give the same result as the per-tile launch, and
+that result matches the FP64 oracle on sampled tiles."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import blend as oblend
+from paper_2503_05168_amd import (GaussianTensors, Renderer, Settings, seele_bin_sort,
+                                  seele_preprocess, seele_rasterize_fwd,
+                                  seele_rasterize_fwd_queue, split_views, total_tiles)
+
+pytestmark = pytest.mark.gpu
+
+import gpu_util as gu  # noqa: E402
+
+
+def _mixed_cams(n_views, seed=50):
+    return synthetic.sphere_cameras(seed, n_views, resolutions=((160, 120), (320, 180),
+                                                                  (480, 270)))
+
+
+@pytest.fixture(scope="module")
+def c5_small():
+    scene = synthetic.cluster_scene(5, 60_000)
+    cams = _mixed_cams(12)
+    return scene, cams
+
+
+@pytest.mark.parametrize("mode", ["plain", "contrib"])
+def test_queue_schedules_equal_grid_and_oracle(c5_small, mode):
+    scene, cams = c5_small
+    st = Settings(mode=mode)
+    f = gu.run(scene, cams, st)
+    for order in ("list", "heaviest"):
+        img, T, nc, _ = seele_rasterize_fwd_queue(f.splats, f.sorted_ids, f.tile_ranges, cams, st,
+                                                  order)
+        torch.cuda.synchronize()
+        assert torch.equal(img, f.image) and torch.equal(T, f.final_T)
+        assert torch.equal(nc, f.n_contrib)
+    # oracle on a few tiles of two views
+    sp = gu.splats_np(f)
+    ids = f.sorted_ids.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    ranges = f.tile_ranges.cpu().numpy().astype(np.int64)
+    imgs, Ts, ncs = gu.outputs_np(f)
+    base = 0
+    for v, cam in enumerate(cams):
+        gw = -(-cam.width // 16)
+        ntl = gw * (-(-cam.height // 16))
+        if v in (0, len(cams) - 1):
+            tiles = sorted(set(np.random.default_rng(v).integers(0, ntl, 6).tolist()))
+            r = oblend.render_tiles(sp, ranges, ids, cam.width, cam.height, 16, base,
+                                    "plain" if mode == "plain" else "cr", st.group, st.bg,
+                                    st.alpha_min, st.alpha_max, st.T_min, tiles=tiles)
+            for t in tiles:
+                ty, tx = divmod(t, gw)
+                sl = (slice(ty * 16, (ty + 1) * 16), slice(tx * 16, (tx + 1) * 16))
+                safe = r["margin"][sl] >= gu.ALPHA_MARGIN
+                err = np.abs(imgs[v][(slice(None),) + sl] - r["image"][(slice(None),) + sl]).max(0)
+                assert err[safe].max(initial=0) <= 1e-5
+                np.testing.assert_array_equal(ncs[v][sl][safe], r["n_contrib"][sl][safe])
+        base += ntl
+
+
+@pytest.mark.parametrize("batch", [64, 128])
+def test_lds_batch_depth_does_not_change_results(c5_small, batch):
+    scene, cams = c5_small
+    for mode in ("plain", "contrib"):
+        st = Settings(mode=mode)
+        f = gu.run(scene, cams, st)
+        st2 = Settings(mode=mode, lds_batch=batch)
+        img, T, nc = seele_rasterize_fwd(f.splats, f.sorted_ids, f.tile_ranges, cams, st2)
+        img2, T2, nc2, _ = seele_rasterize_fwd_queue(f.splats, f.sorted_ids, f.tile_ranges, cams,
+                                                     st2, "heaviest")
+        torch.cuda.synchronize()
+        for a, b in ((img, f.image), (T, f.final_T), (nc, f.n_contrib), (img2, f.image)):
+            assert torch.equal(a, b)
+        assert torch.equal(nc2, f.n_contrib)
+
+
+def test_tile8_batched_matches_oracle():
+    scene = synthetic.cluster_scene(5, 30_000)
+    cams = _mixed_cams(5, seed=51)
+    st = Settings(tile=8, mode="contrib", extent="opacity")
+    f = gu.run(scene, cams, st)
+    img, T, nc, _ = seele_rasterize_fwd_queue(f.splats, f.sorted_ids, f.tile_ranges, cams, st,
+                                              "heaviest")
+    torch.cuda.synchronize()
+    assert torch.equal(img, f.image) and torch.equal(nc, f.n_contrib)
+    sp, ob = None, None
+    sp = gu.splats_np(f)
+    ob = gu.oracle_binning(sp, cams, 8, scene.n)
+    P = int(f.num_pairs.item())
+    np.testing.assert_array_equal(f.sorted_ids.cpu().numpy()[:P].astype(np.int64) & 0xFFFFFFFF,
+                                  ob["ids"])
+
+
+def test_hip_graph_replay_matches_eager(c5_small):
+    scene, cams = c5_small
+    st = Settings(mode="contrib")
+    g = GaussianTensors.from_arrays(scene)
+    n = g.n
+    V = len(cams)
+    TT = total_tiles(cams, st.tile)
+    npix = sum(c.width * c.height for c in cams)
+    eager = Renderer(st, schedule="queue_heavy").render(g, cams)
+    torch.cuda.synchronize()
+    cap = int(eager.num_pairs.item() * 1.2) + 1024
+    # static buffers for the captured frame
+    splats = torch.empty((V * n, 12), dtype=torch.float32, device="cuda")
+    n_tiles = torch.empty(V * n, dtype=torch.int32, device="cuda")
+    from paper_2503_05168_amd.pipeline import bin_sort_workspace_size
+    ws = torch.empty(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8, device="cuda")
+    ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ranges = torch.empty((TT, 2), dtype=torch.int32, device="cuda")
+    npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+    image = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
+    final_T = torch.empty(npix, dtype=torch.float32, device="cuda")
+    n_contrib = torch.empty(npix, dtype=torch.int32, device="cuda")
+    _, _, _, qws = seele_rasterize_fwd_queue(eager.splats, eager.sorted_ids, eager.tile_ranges,
+                                             cams, st, "heaviest")
+
+    def frame():
+        seele_preprocess(g, cams, st, None, splats, n_tiles)
+        seele_bin_sort(splats, n_tiles, n, cams, st.tile, cap, ws, ids, ranges, npairs)
+        seele_rasterize_fwd_queue(splats, ids, ranges, cams, st, "heaviest", qws, image, final_T,
+                                  n_contrib)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        frame()  # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        frame()
+    for rep in range(4):
+        image.zero_()
+        final_T.zero_()
+        n_contrib.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(npairs.item()) <= cap
+        assert torch.equal(image, eager.image), rep
+        assert torch.equal(final_T, eager.final_T) and torch.equal(n_contrib, eager.n_contrib)
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    imgs = split_views(image, cams, 3)
+    assert imgs[-1].shape == (3, cams[-1].height, cams[-1].width)
