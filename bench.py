@@ -38,6 +38,24 @@ OPS_EVAL = 11
 OPS_BLEND = 7
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of the rasterizer from the committed rocprofv3
+    counter summary, if the kernel source is still the one that was
+    profiled (otherwise None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("paper_2503_05168_amd/csrc/raster_fwd.hip",
+              "paper_2503_05168_amd/csrc/seele_internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != d.get("source_sha256_16"):
+        return None
+    return d["hbm_read_bytes_per_launch"] + d["hbm_write_bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -52,6 +70,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=24)
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="first copy 256 MiB device to device (a known-size kernel that "
+                         "scales hardware byte counters)")
     return ap.parse_args()
 
 
@@ -291,16 +312,26 @@ def main():
         sys.exit(1)
     import paper_2503_05168_amd as P
     P.lib()
+    if args.pmc_calibrate:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+    t_start = time.time()
     names = [s.strip() for s in args.forms.split(",") if s.strip()]
     scene, cams, forms = build_forms(names, args.n)
     results = {}
     for name in names:
         results[name] = run_form(name, forms[name], cams, args.steps, args.warmup)
+        log(f"[bench] t+{time.time() - t_start:.0f}s form {name} done")
     fwd_bwd = None
     if not args.no_bwd:
         del forms
         torch.cuda.empty_cache()
         fwd_bwd = {m: run_fwd_bwd(1_000_000, 8, 4, 1, m) for m in ("plain", "contrib")}
+        log(f"[bench] t+{time.time() - t_start:.0f}s fwd+bwd done")
     head = results.get("plain") or results[names[0]]
     # roofline of the dominant kernel of the headline form
     st = head["stage_ms"]
@@ -309,7 +340,9 @@ def main():
         ops = head["evals"] * OPS_EVAL + head["blends"] * OPS_BLEND
         ach = ops / (st["raster"] * 1e-3) / 1e12
         roof = dict(bound="alu", kernel="raster_fwd", achieved=ach, peak=PEAK_LANE_OPS / 1e12,
-                    unit="Tlane-op/s", frac=ach / (PEAK_LANE_OPS / 1e12), traffic=None)
+                    unit="Tlane-op/s", frac=ach / (PEAK_LANE_OPS / 1e12),
+                    traffic=measured_traffic("raster_fwd_plain_c2_1080p_3M"),
+                    traffic_unit="bytes/launch")
     elif dom == "bin_sort":
         byts = 16 * head["visible"] + 4 * head["pairs"] + 8 * 8160
         ach = byts / (st["bin_sort"] * 1e-3) / 1e9
@@ -324,7 +357,7 @@ def main():
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         cpu = cpu_baseline(scene, cams[0], args.cpu_tiles)
-        log(f"[bench] cpu baseline {cpu['value']:.3e} frames/s")
+        log(f"[bench] t+{time.time() - t_start:.0f}s cpu baseline {cpu['value']:.3e} frames/s")
     line = {
         "metric": "1080p FPS @3M Gaussians, plain vs contribution-aware; fwd+bwd ms/view",
         "value": head["fps"],
