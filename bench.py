@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=24)
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="first copy 256 MiB device to device (a known-size kernel that "
                          "scales hardware byte counters)")
@@ -260,6 +261,110 @@ def run_fwd_bwd(n, n_views, steps, warmup, mode):
     return out
 
 
+def run_batched(n, n_views, mode, reps=3):
+    """64 cameras of mixed resolution (640x480 / 1280x720 / 1920x1080, radius
+    3-6 shell) over 2.0M Gaussians: sequential per-view frames vs one batched
+    call (autotuned tile size, LDS batch depth and schedule) vs the batched
+    frame captured in a HIP graph and replayed.  Returns ms per view."""
+    import torch
+    import synthetic
+    import paper_2503_05168_amd as P
+    from paper_2503_05168_amd.autotune import autotune
+    from paper_2503_05168_amd.pipeline import bin_sort_workspace_size
+
+    scene = synthetic.cluster_scene(5, n)
+    cams = synthetic.sphere_cameras(50, n_views)
+    g = P.GaussianTensors.from_arrays(scene)
+    del scene
+    base = P.Settings(mode=mode)
+    tuned = autotune(g, cams, base, reps=reps, log=log)
+    st, sch = tuned["settings"], tuned["schedule"]
+    log(f"[bench] batched {mode}: autotuned tile={st.tile} lds_batch={st.lds_batch} "
+        f"schedule={sch} ({tuned['ms']:.2f} ms/frame of {n_views} views)")
+
+    # sequential: one frame per camera, default settings
+    seq = P.Renderer(base, capacity=1 << 22)
+    for cam in cams:
+        seq.render(g, [cam])
+    seq.capacity = int(seq.capacity * 1.05) + 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for cam in cams:
+            seq.render(g, [cam], check=False)
+    torch.cuda.synchronize()
+    seq_ms = 1000.0 * (time.perf_counter() - t0) / reps / n_views
+
+    # batched eager, tuned
+    r = P.Renderer(st, capacity=1 << 24, schedule=sch)
+    f = r.render(g, cams)
+    r.capacity = int(r.capacity * 1.05) + 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f = r.render(g, cams, check=False)
+    torch.cuda.synchronize()
+    eager_ms = 1000.0 * (time.perf_counter() - t0) / reps / n_views
+    assert int(f.num_pairs.item()) <= r.capacity
+
+    # batched frame in a HIP graph (static buffers, device-side counts)
+    V = len(cams)
+    TT = P.total_tiles(cams, st.tile)
+    npix = P.pixel_count(cams)
+    cap = r.capacity
+    splats = torch.empty((V * n, P.pipeline.SPLAT_FLOATS), dtype=torch.float32, device="cuda")
+    n_tiles = torch.empty(V * n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8, device="cuda")
+    ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ranges = torch.empty((TT, 2), dtype=torch.int32, device="cuda")
+    npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+    image = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
+    final_T = torch.empty(npix, dtype=torch.float32, device="cuda")
+    n_contrib = torch.empty(npix, dtype=torch.int32, device="cuda")
+    del f
+    qws = None
+    if sch != "grid":
+        qws = torch.empty(int(P.lib().seele_raster_queue_workspace_size(TT)), dtype=torch.uint8,
+                          device="cuda")
+
+    def frame():
+        P.seele_preprocess(g, cams, st, None, splats, n_tiles)
+        P.seele_bin_sort(splats, n_tiles, n, cams, st.tile, cap, ws, ids, ranges, npairs)
+        if sch == "grid":
+            P.seele_rasterize_fwd(splats, ids, ranges, cams, st, image, final_T, n_contrib)
+        else:
+            P.seele_rasterize_fwd_queue(splats, ids, ranges, cams, st,
+                                        "heaviest" if sch == "queue_heavy" else "list", qws,
+                                        image, final_T, n_contrib)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        frame()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        frame()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = 1000.0 * (time.perf_counter() - t0) / reps / n_views
+    assert int(npairs.item()) <= cap, "pair buffer overflow in the graph"
+    out = dict(sequential_ms_per_view=seq_ms, batched_ms_per_view=eager_ms,
+               graph_ms_per_view=graph_ms, tile=st.tile, lds_batch=st.lds_batch, schedule=sch,
+               pairs=int(npairs.item()), views=n_views, gaussians=n,
+               autotune=[dict(t) for t in tuned["table"]])
+    log(f"[bench] batched {mode}: sequential {seq_ms:.3f} ms/view, batched {eager_ms:.3f}, "
+        f"graph {graph_ms:.3f}")
+    del graph, splats, ws, ids, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(scene, cam, n_tiles_sample):
     """Float64 oracle, one view: full preprocessing; binning of every pair of
     the Gaussians that touch a random sample of tiles, scaled to all pairs;
@@ -332,6 +437,11 @@ def main():
         torch.cuda.empty_cache()
         fwd_bwd = {m: run_fwd_bwd(1_000_000, 8, 4, 1, m) for m in ("plain", "contrib")}
         log(f"[bench] t+{time.time() - t_start:.0f}s fwd+bwd done")
+    batched = None
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        batched = {m: run_batched(2_000_000, 64, m) for m in ("plain", "contrib")}
+        log(f"[bench] t+{time.time() - t_start:.0f}s batched done")
     head = results.get("plain") or results[names[0]]
     # roofline of the dominant kernel of the headline form
     st = head["stage_ms"]
@@ -379,6 +489,7 @@ def main():
         "fwd_bwd_ms_per_view": (None if fwd_bwd is None else
                                 {k: v["ms_per_view"] for k, v in fwd_bwd.items()}),
         "fwd_bwd": fwd_bwd,
+        "batched_64_views": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -9,6 +9,7 @@ from .pipeline import (  # noqa: F401
     Settings,
     Renderer,
     Frame,
+    CapacityError,
     seele_preprocess,
     seele_bin_sort,
     seele_rasterize_fwd,

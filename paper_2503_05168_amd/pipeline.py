@@ -350,6 +350,13 @@ class Frame:
         return split_views(self.image, self.cams, 3)
 
 
+MAX_PAIRS = (1 << 31) - 1  # pair capacity limit of seele_bin_sort (int32 tile ranges)
+
+
+class CapacityError(RuntimeError):
+    """A frame needs more Gaussian-tile pairs than one bin_sort call can hold."""
+
+
 class Renderer:
     """preprocess -> bin_sort -> rasterize for a list of views, reusing buffers.
 
@@ -380,7 +387,10 @@ class Renderer:
             need = int(npairs.item())
             if need <= self.capacity:
                 break
-            self.capacity = min(int(need * 1.5) + 1024, (1 << 31) - 1)
+            if need > MAX_PAIRS:
+                raise CapacityError(f"the frame needs {need} Gaussian-tile pairs, more than the "
+                                    f"{MAX_PAIRS} one call can sort: render fewer views per call")
+            self.capacity = min(int(need * 1.5) + 1024, MAX_PAIRS)
         if self.schedule == "grid":
             image, final_T, n_contrib = seele_rasterize_fwd(splats, ids, ranges, cams, s,
                                                             stream=stream)

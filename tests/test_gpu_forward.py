@@ -255,3 +255,13 @@ def test_end_to_end_c1_against_float64_pipeline():
         ps = gu.psnr(imgs[0], r["image"])
         gu.log(f"[e2e c1 {mode}] psnr={ps:.1f} maxabs={np.abs(imgs[0] - r['image']).max():.2e}")
         assert ps > 70.0
+
+
+def test_renderer_raises_when_a_frame_exceeds_the_pair_limit(monkeypatch):
+    import paper_2503_05168_amd as P
+    from paper_2503_05168_amd import pipeline
+    cfg = synthetic.config(1)
+    monkeypatch.setattr(pipeline, "MAX_PAIRS", 1000)
+    with pytest.raises(P.CapacityError):
+        P.Renderer(Settings(), capacity=100).render(P.GaussianTensors.from_arrays(cfg["scene"]),
+                                                    cfg["cams"])
