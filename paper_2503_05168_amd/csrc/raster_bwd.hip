@@ -13,6 +13,11 @@
 // and through alpha = o exp(-q/2), q = d^T A d (zero where the alpha clamp
 // was active).  Per-Gaussian gradients are reduced across the wave and added
 // to the record's 9 gradient slots with float atomics.
+//
+// As in the forward kernels, each wave visits only the records whose culling
+// bit for its 8x8 block is set (quad_mask), and only those below the largest
+// n_contrib of its pixels: a skipped record is blended by none of its pixels
+// and so has no gradient from them.
 #include "seele_internal.h"
 
 namespace seele {
@@ -24,6 +29,79 @@ struct LdsBwd {
   float4 b;  // l22, opacity, r, g
   float4 c;  // blue, conic a, conic b, conic c
 };
+
+// One record of the reverse walk for one pixel: recompute alpha, undo the
+// blend (T, S) if the forward blended it, and add the record's 2D gradients
+// (reduced over the wave) to its gradient slots.
+template <int MODE>
+__device__ __forceinline__ void blend_grad(const LdsBwd& e, uint32_t id, bool need, float fx,
+                                           float fy, int leader_lane, int lane, float amin,
+                                           float amax, float g0, float g1, float g2, float& T,
+                                           float& S0, float& S1, float& S2,
+                                           float* __restrict__ grad2d) {
+  const float4 a = e.a, b = e.b;
+  float dx, dy;
+  const float p = splat_power(fx, fy, a.x, a.y, a.z, a.w, b.x, dx, dy);
+  const float ex = fast_exp2(p);
+  const float raw = b.y * ex;
+  const float alpha = clamp_alpha(raw, amax);
+  bool blended = need && alpha >= amin;
+  if (MODE) {
+    // the leader's alpha is the leader lane's own alpha (same function, same pixel)
+    const float lead = __shfl(alpha, leader_lane, 64);
+    blended = blended && lead >= amin;
+  }
+  float gmx = 0.0f, gmy = 0.0f, gca = 0.0f, gcb = 0.0f, gcc = 0.0f, gop = 0.0f;
+  float gr = 0.0f, gg = 0.0f, gbl = 0.0f;
+  if (blended) {
+    const float4 cc = e.c;
+    const float om = 1.0f - alpha;
+    const float Tj = T / om;
+    const float ta = Tj * alpha;
+    const float dal = g0 * (Tj * b.z - S0 / om) + g1 * (Tj * b.w - S1 / om) +
+                      g2 * (Tj * cc.x - S2 / om);
+    gr = ta * g0;
+    gg = ta * g1;
+    gbl = ta * g2;
+    S0 = __builtin_fmaf(ta, b.z, S0);
+    S1 = __builtin_fmaf(ta, b.w, S1);
+    S2 = __builtin_fmaf(ta, cc.x, S2);
+    T = Tj;
+    if (raw <= amax) {
+      gop = dal * ex;
+      const float dq = -0.5f * alpha * dal;  // dL/dq
+      // q = a dx^2 + 2 b dx dy + c dy^2 with d = pixel - mean: dq/dmean = -2 A d
+      gmx = -2.0f * dq * (cc.y * dx + cc.z * dy);
+      gmy = -2.0f * dq * (cc.z * dx + cc.w * dy);
+      gca = dq * dx * dx;
+      gcb = dq * 2.0f * dx * dy;
+      gcc = dq * dy * dy;
+    }
+  }
+  if (__ballot(blended) != 0) {
+    gmx = wave_sum(gmx);
+    gmy = wave_sum(gmy);
+    gca = wave_sum(gca);
+    gcb = wave_sum(gcb);
+    gcc = wave_sum(gcc);
+    gop = wave_sum(gop);
+    gr = wave_sum(gr);
+    gg = wave_sum(gg);
+    gbl = wave_sum(gbl);
+    if (lane == 0) {
+      float* dst = grad2d + (int64_t)id * 9;
+      atomicAdd(dst + 0, gmx);
+      atomicAdd(dst + 1, gmy);
+      atomicAdd(dst + 2, gca);
+      atomicAdd(dst + 3, gcb);
+      atomicAdd(dst + 4, gcc);
+      atomicAdd(dst + 5, gop);
+      atomicAdd(dst + 6, gr);
+      atomicAdd(dst + 7, gg);
+      atomicAdd(dst + 8, gbl);
+    }
+  }
+}
 
 template <int TS, int MODE>
 __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, RasterParams rp,
@@ -37,6 +115,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
   constexpr int NT = TS * TS;
   __shared__ LdsBwd s_e[NT];
   __shared__ uint32_t s_id[NT];
+  __shared__ uint8_t s_qm[NT];
   __shared__ int s_max;
 
   const int gt = blockIdx.x;
@@ -82,6 +161,8 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
   atomicMax(&s_max, last);
   __syncthreads();
   const int jmax = s_max;
+  int wave_last = last;
+  for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
   for (int hi = jmax; hi > 0; hi -= NT) {
     const int lo = hi > NT ? hi - NT : 0;
@@ -95,73 +176,20 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       s_e[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
       s_e[tid].c = make_float4(blue, A.z, A.w, Bv.x);
       s_id[tid] = id;
+      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin, tile_x * TS,
+                                         tile_y * TS);
     }
     __syncthreads();
-    for (int j = hi - 1; j >= lo; --j) {
-      const bool need = j < last;
-      if (__ballot(need) == 0) continue;  // wave-uniform
-      const int k = j - lo;
-      const float4 a = s_e[k].a, b = s_e[k].b;
-      float dx, dy;
-      const float p = splat_power(fx, fy, a.x, a.y, a.z, a.w, b.x, dx, dy);
-      const float e = fast_exp2(p);
-      const float raw = b.y * e;
-      const float alpha = __builtin_fminf(amax, raw);
-      bool blended = need && alpha >= amin;
-      if (MODE) {
-        // the leader's alpha is the leader lane's own alpha (same function, same pixel)
-        const float lead = __shfl(alpha, leader_lane, 64);
-        blended = blended && lead >= amin;
-      }
-      float gmx = 0.0f, gmy = 0.0f, gca = 0.0f, gcb = 0.0f, gcc = 0.0f, gop = 0.0f;
-      float gr = 0.0f, gg = 0.0f, gbl = 0.0f;
-      if (blended) {
-        const float4 cc = s_e[k].c;
-        const float om = 1.0f - alpha;
-        const float Tj = T / om;
-        const float ta = Tj * alpha;
-        const float dal = g0 * (Tj * b.z - S0 / om) + g1 * (Tj * b.w - S1 / om) +
-                          g2 * (Tj * cc.x - S2 / om);
-        gr = ta * g0;
-        gg = ta * g1;
-        gbl = ta * g2;
-        S0 = __builtin_fmaf(ta, b.z, S0);
-        S1 = __builtin_fmaf(ta, b.w, S1);
-        S2 = __builtin_fmaf(ta, cc.x, S2);
-        T = Tj;
-        if (raw <= amax) {
-          gop = dal * e;
-          const float dq = -0.5f * alpha * dal;  // dL/dq
-          // q = a dx^2 + 2 b dx dy + c dy^2 with d = pixel - mean: dq/dmean = -2 A d
-          gmx = -2.0f * dq * (cc.y * dx + cc.z * dy);
-          gmy = -2.0f * dq * (cc.z * dx + cc.w * dy);
-          gca = dq * dx * dx;
-          gcb = dq * 2.0f * dx * dy;
-          gcc = dq * dy * dy;
-        }
-      }
-      if (__ballot(blended) != 0) {
-        gmx = wave_sum(gmx);
-        gmy = wave_sum(gmy);
-        gca = wave_sum(gca);
-        gcb = wave_sum(gcb);
-        gcc = wave_sum(gcc);
-        gop = wave_sum(gop);
-        gr = wave_sum(gr);
-        gg = wave_sum(gg);
-        gbl = wave_sum(gbl);
-        if (lane == 0) {
-          float* dst = grad2d + (int64_t)s_id[k] * 9;
-          atomicAdd(dst + 0, gmx);
-          atomicAdd(dst + 1, gmy);
-          atomicAdd(dst + 2, gca);
-          atomicAdd(dst + 3, gcb);
-          atomicAdd(dst + 4, gcc);
-          atomicAdd(dst + 5, gop);
-          atomicAdd(dst + 6, gr);
-          atomicAdd(dst + 7, gg);
-          atomicAdd(dst + 8, gbl);
-        }
+    // this wave's records of the batch, highest position first, 64 at a time
+    const int nb = min(hi, wave_last) - lo;
+    for (int c = (nb - 1) & ~63; c >= 0; c -= 64) {
+      const int jj = c + lane;
+      uint64_t bits = __ballot(jj < nb && ((s_qm[jj] >> wave) & 1u));
+      while (bits != 0) {
+        const int k = c + 63 - __builtin_clzll(bits);
+        bits &= ~(1ull << (k - c));
+        blend_grad<MODE>(s_e[k], s_id[k], lo + k < last, fx, fy, leader_lane, lane, amin, amax,
+                         g0, g1, g2, T, S0, S1, S2, grad2d);
       }
     }
     __syncthreads();

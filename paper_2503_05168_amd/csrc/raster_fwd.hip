@@ -18,6 +18,15 @@
 // skip of Sec. 3.4 "GPU Parallelism"); otherwise only lanes of accepting
 // groups evaluate and blend it.  Leaders keep testing after they stop.
 //
+// Wave-level culling: when a batch is staged, each record also gets a bit per
+// 8x8 wave block that its alpha >= alpha_min region can reach (a conservative
+// bound, see quad_mask).  A wave then visits only the records whose bit it
+// holds, walking the ballot of those bits with scalar bit scans.  A record a
+// wave skips has alpha < alpha_min at every pixel of its block, so no pixel
+// (and no group leader) of that block blends it or passes its test: results
+// are identical to visiting every record.  The instrumented (COUNT) kernels
+// visit every record, as the method states, to count its work.
+//
 // Early exit: a wave leaves a batch when all its lanes are done; the block
 // stops loading batches when all its pixels are done.
 #include "seele_internal.h"
@@ -26,16 +35,41 @@ namespace seele {
 
 namespace {
 
-struct LdsBatch {
+struct LdsRec {
   float4 a;  // mean_x, mean_y, l11, l21  (Cholesky factor of k * conic)
   float4 b;  // l22, opacity, r, g
+  float blue, pad0, pad1, pad2;
 };
 
 __device__ __forceinline__ float alpha_at(float px, float py, const float4& a, const float4& b,
                                           float alpha_max) {
   float dx, dy;
   const float p = splat_power(px, py, a.x, a.y, a.z, a.w, b.x, dx, dy);
-  return __builtin_fminf(alpha_max, b.y * fast_exp2(p));
+  return clamp_alpha(b.y * fast_exp2(p), alpha_max);
+}
+
+// One front-to-back step of Eqs. 1-2 for one pixel, with the alpha skip, the
+// clamp and the termination rule.  A pixel's state is (T, colour, last); a
+// pixel that has stopped carries -T (T >= T_min > 0 while it runs), so every
+// later step leaves it unchanged without a separate flag.  True if blended.
+__device__ __forceinline__ bool blend_step(float fx, float fy, const float4& a, const float4& b,
+                                           float blue, int pos, float amin, float amax,
+                                           float tmin, float& T, float& c0, float& c1, float& c2,
+                                           int& last) {
+  const float alpha = alpha_at(fx, fy, a, b, amax);
+  const bool pass = alpha >= amin;
+  const float Tn = T * (1.0f - alpha);
+  const bool stop = Tn < tmin;
+  const bool take = pass && !stop;
+  if (take) {
+    const float wgt = alpha * T;
+    c0 = __builtin_fmaf(wgt, b.z, c0);
+    c1 = __builtin_fmaf(wgt, b.w, c1);
+    c2 = __builtin_fmaf(wgt, blue, c2);
+    last = pos;
+  }
+  T = take ? Tn : ((pass && stop) ? -__builtin_fabsf(T) : T);
+  return take;
 }
 
 // COUNT instantiations also accumulate the method's work counters:
@@ -56,9 +90,11 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
                                             int32_t* __restrict__ n_contrib,
                                             unsigned long long* __restrict__ counters) {
   constexpr int NT = TS * TS;
+  constexpr int NW = NT / 64;
   static_assert(BATCH <= NT && BATCH % 64 == 0 || BATCH == NT, "batch depth");
-  __shared__ LdsBatch s_ab[BATCH];
-  __shared__ float s_blue[BATCH];
+  __shared__ LdsRec s_rec[BATCH];
+  __shared__ uint8_t s_qm[BATCH];
+  __shared__ uint8_t s_list[NW][64];
   __shared__ unsigned long long s_cnt[4];
   uint32_t c_eval = 0, c_blend = 0, c_ltest = 0, c_lpass = 0;
   if (COUNT) {
@@ -92,89 +128,127 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   const int start = ranges[ri], n = ranges[ri + 1] - start;
   const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.T_min;
 
-  float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+  // pixels outside the image start stopped
+  float T = inside ? 1.0f : -1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
   int last = 0;
-  bool done = !inside;
 
   for (int base = 0; base < n; base += BATCH) {
-    if (__syncthreads_count(done) == NT) break;
+    if (__syncthreads_count(T < 0.0f) == NT) break;
     const int j = base + tid;
     if (tid < BATCH && j < n) {
       const float4* src = reinterpret_cast<const float4*>(splats + ids[start + j]);
       const float4 A = src[0], Bv = src[1];
       const float blue = src[2].x;
       const Chol L = conic_factor(A.z, A.w, Bv.x);
-      s_ab[tid].a = make_float4(A.x, A.y, L.l11, L.l21);
-      s_ab[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
-      s_blue[tid] = blue;
+      s_rec[tid].a = make_float4(A.x, A.y, L.l11, L.l21);
+      s_rec[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
+      s_rec[tid].blue = blue;
+      if (!COUNT)
+        s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin,
+                                           tile_x * TS, tile_y * TS);
     }
     __syncthreads();
     const int cnt = min(BATCH, n - base);
-    if (MODE == 0) {
+    if (COUNT && MODE == 0) {
       for (int k = 0; k < cnt; ++k) {
-        if (__ballot(!done) == 0) break;
-        if (!done) {
-          if (COUNT) ++c_eval;
-          const float4 a = s_ab[k].a, b = s_ab[k].b;
-          const float alpha = alpha_at(fx, fy, a, b, amax);
-          if (alpha >= amin) {
-            const float Tn = T * (1.0f - alpha);
-            if (Tn < tmin) {
-              done = true;
-            } else {
-              const float wgt = alpha * T;
-              c0 = __builtin_fmaf(wgt, b.z, c0);
-              c1 = __builtin_fmaf(wgt, b.w, c1);
-              c2 = __builtin_fmaf(wgt, s_blue[k], c2);
-              T = Tn;
-              last = base + k + 1;
-              if (COUNT) ++c_blend;
-            }
+        if (__ballot(T >= 0.0f) == 0) break;
+        if (T >= 0.0f) {
+          ++c_eval;
+          if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
+                         amax, tmin, T, c0, c1, c2, last))
+            ++c_blend;
+        }
+      }
+    } else if (COUNT) {
+      const int per = 64 / G;
+      const uint64_t gl = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1ull);
+      for (int k0 = 0; k0 < cnt; k0 += per) {
+        if (__ballot(T >= 0.0f) == 0) break;
+        const int kk = k0 + sub;
+        bool pass = false;
+        if (kk < cnt) pass = alpha_at(lfx, lfy, s_rec[kk].a, s_rec[kk].b, amax) >= amin;
+        const uint64_t bal = __ballot(pass);
+        for (int s = 0; s < per && k0 + s < cnt; ++s) {
+          const uint64_t gm = (bal >> (s * G)) & gmask;
+          const uint64_t live = __ballot(T >= 0.0f);  // all lanes take part in the ballot
+          uint64_t glive = 0;
+          for (int q = 0; q < G; ++q)
+            if ((live >> (q * gsz)) & gl) glive |= 1ull << q;
+          if (lane == 0) {
+            c_ltest += (uint32_t)__popcll(glive);
+            c_lpass += (uint32_t)__popcll(glive & gm);
+          }
+          if (gm == 0) continue;
+          if (T >= 0.0f && ((gm >> grp) & 1ull)) {
+            const int k = k0 + s;
+            ++c_eval;
+            if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
+                           amax, tmin, T, c0, c1, c2, last))
+              ++c_blend;
           }
         }
       }
     } else {
-      const int per = 64 / G;
-      for (int k0 = 0; k0 < cnt; k0 += per) {
-        if (__ballot(!done) == 0) break;
-        const int kk = k0 + sub;
-        bool pass = false;
-        if (kk < cnt) pass = alpha_at(lfx, lfy, s_ab[kk].a, s_ab[kk].b, amax) >= amin;
-        const uint64_t bal = __ballot(pass);
-        for (int s = 0; s < per; ++s) {
-          const uint64_t gm = (bal >> (s * G)) & gmask;
-          if (COUNT && k0 + s < cnt) {
-            const uint64_t live = __ballot(!done);  // all lanes take part in the ballot
-            uint64_t glive = 0;
-            const uint64_t gl = gsz >= 64 ? ~0ull : ((1ull << gsz) - 1ull);
-            for (int q = 0; q < G; ++q)
-              if ((live >> (q * gsz)) & gl) glive |= 1ull << q;
-            if (lane == 0) {
-              c_ltest += (uint32_t)__popcll(glive);
-              c_lpass += (uint32_t)__popcll(glive & gm);
-            }
+      for (int c = 0; c < cnt; c += 64) {
+        if (__ballot(T >= 0.0f) == 0) break;
+        const int jj = c + lane;
+        const bool need = jj < cnt && ((s_qm[jj] >> wave) & 1u);
+        uint64_t bits = __ballot(need);
+        if (bits == 0) continue;
+        if (MODE == 0) {
+          // Walk this wave's records in depth order with scalar bit scans,
+          // two at a time: the next record's LDS reads are in flight while
+          // the current one is blended.
+          int ka = c + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          float4 aa = s_rec[ka].a, ab = s_rec[ka].b;
+          float abl = s_rec[ka].blue;
+          for (;;) {
+            const bool mb = bits != 0;
+            const int kb = mb ? c + __builtin_ctzll(bits) : ka;
+            bits &= bits - 1;
+            const float4 ba = s_rec[kb].a, bb = s_rec[kb].b;
+            const float bbl = s_rec[kb].blue;
+            blend_step(fx, fy, aa, ab, abl, base + ka + 1, amin, amax, tmin, T, c0, c1, c2, last);
+            if (!mb) break;
+            const bool ma = bits != 0;
+            ka = ma ? c + __builtin_ctzll(bits) : kb;
+            bits &= bits - 1;
+            aa = s_rec[ka].a;
+            ab = s_rec[ka].b;
+            abl = s_rec[ka].blue;
+            blend_step(fx, fy, ba, bb, bbl, base + kb + 1, amin, amax, tmin, T, c0, c1, c2, last);
+            if (!ma) break;
           }
-          if (gm == 0) continue;  // no leader of this wave accepts it: wave-uniform skip
-          if (!done && ((gm >> grp) & 1ull)) {
-            const int k = k0 + s;
-            if (COUNT) ++c_eval;
-            const float4 a = s_ab[k].a, b = s_ab[k].b;
-            const float alpha = alpha_at(fx, fy, a, b, amax);
-            if (alpha >= amin) {
-              const float Tn = T * (1.0f - alpha);
-              if (Tn < tmin) {
-                done = true;
-              } else {
-                const float wgt = alpha * T;
-                c0 = __builtin_fmaf(wgt, b.z, c0);
-                c1 = __builtin_fmaf(wgt, b.w, c1);
-                c2 = __builtin_fmaf(wgt, s_blue[k], c2);
-                T = Tn;
-                last = base + k + 1;
-                if (COUNT) ++c_blend;
-              }
+        } else {
+          // compact this wave's records of the chunk, then run the packed
+          // leader test on per = 64/G of them at a time
+          const int nsel = __popcll(bits);
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
+          if (need) s_list[wave][rank] = (uint8_t)lane;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const int per = 64 / G;
+          for (int i = 0; i < nsel; i += per) {
+            const int li = i + sub;
+            const int kk = li < nsel ? c + (int)s_list[wave][li] : 0;
+            const bool pass =
+                li < nsel && alpha_at(lfx, lfy, s_rec[kk].a, s_rec[kk].b, amax) >= amin;
+            const uint64_t bal = __ballot(pass);
+            const int ns = min(per, nsel - i);
+            for (int s = 0; s < ns; ++s) {
+              const uint64_t gm = (bal >> (s * G)) & gmask;
+              if (gm == 0) continue;  // no leader of this wave accepts it: wave-uniform skip
+              const int k = __builtin_amdgcn_readlane(kk, s * G);
+              if ((gm >> grp) & 1ull)
+                blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
+                           amax, tmin, T, c0, c1, c2, last);
             }
+            if (__ballot(T >= 0.0f) == 0) break;
           }
+          __builtin_amdgcn_wave_barrier();  // list reads finish before the next chunk's writes
         }
       }
     }
@@ -192,13 +266,14 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   }
 
   if (inside) {
+    const float Tf = __builtin_fabsf(T);
     const int64_t hw = (int64_t)rv.W * rv.H;
     const int64_t pix = (int64_t)y * rv.W + x;
     float* img = image + 3 * rv.pix_base;
-    img[pix] = c0 + T * rp.bg0;
-    img[hw + pix] = c1 + T * rp.bg1;
-    img[2 * hw + pix] = c2 + T * rp.bg2;
-    final_T[rv.pix_base + pix] = T;
+    img[pix] = c0 + Tf * rp.bg0;
+    img[hw + pix] = c1 + Tf * rp.bg1;
+    img[2 * hw + pix] = c2 + Tf * rp.bg2;
+    final_T[rv.pix_base + pix] = Tf;
     n_contrib[rv.pix_base + pix] = last;
   }
 }

@@ -166,6 +166,47 @@ __device__ __forceinline__ float splat_power(float px, float py, float mx, float
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// alpha = min(alpha_max, raw) for raw = o * exp2(p) >= 0 and alpha_max > 0,
+// as one median-of-three (which needs no NaN canonicalisation of alpha_max).
+__device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
+  return __builtin_amdgcn_fmed3f(raw, 0.0f, alpha_max);
+}
+
+// Wave-level culling mask of one record for one tile whose top-left pixel is
+// (x0, y0).  Bit q (q = 2*row + column of the 8x8 block that wave q owns) is
+// cleared only if alpha < alpha_min at every pixel centre of block q as the
+// blending loops compute it in float32 (splat_power, fast_exp2, clamp_alpha).
+// Over the block's centres the two linear forms u = l11 dx + l21 dy and
+// w = l22 dy range over intervals; the sum of their smallest squares bounds
+// k q from below.  alpha >= alpha_min needs
+// k q <= log2(o / alpha_min), so a block is cleared when the bound exceeds
+// that by a margin covering the float32 rounding of the loop's evaluation
+// (relative to the squared magnitude S^2 of the terms it adds) and of the
+// bound itself, plus 1e-3 for the logarithm, exp2 and the product with o.
+// NaN anywhere leaves the bit set.
+template <int TS>
+__device__ __forceinline__ uint32_t quad_mask(float mx, float my, float l11, float l21, float l22,
+                                              float opacity, float alpha_min, int x0, int y0) {
+  const float lim = __log2f(opacity / alpha_min) + 1e-3f;
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < (TS / 8) * (TS / 8); ++q) {
+    const float dx0 = (float)(x0 + (q & 1) * 8) + 0.5f - mx, dx1 = dx0 + 7.0f;
+    const float dy0 = (float)(y0 + (q >> 1) * 8) + 0.5f - my, dy1 = dy0 + 7.0f;
+    const float umin = l11 * dx0 + (l21 >= 0.0f ? l21 * dy0 : l21 * dy1);
+    const float umax = l11 * dx1 + (l21 >= 0.0f ? l21 * dy1 : l21 * dy0);
+    const float u2 = umin > 0.0f ? umin * umin : (umax < 0.0f ? umax * umax : 0.0f);
+    const float wy = dy0 > 0.0f ? dy0 : (dy1 < 0.0f ? dy1 : 0.0f);
+    const float w2 = (l22 * wy) * (l22 * wy);
+    const float ax = __builtin_fmaxf(__builtin_fabsf(dx0), __builtin_fabsf(dx1));
+    const float ay = __builtin_fmaxf(__builtin_fabsf(dy0), __builtin_fabsf(dy1));
+    const float S = l11 * ax + __builtin_fabsf(l21) * ay, Wm = l22 * ay;
+    const float thr = lim + 4e-6f * (S * S + Wm * Wm);
+    if (!(u2 + w2 > thr)) m |= 1u << q;
+  }
+  return m;
+}
+
 // ------------------------------------------------------------- host launchers
 hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_splat* splats,
                              int32_t* n_tiles, hipStream_t stream);

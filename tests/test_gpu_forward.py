@@ -108,7 +108,15 @@ def _check_counters(f, cams, settings, v, oc, n_border):
     base = sum((-(-c.width // settings.tile)) * (-(-c.height // settings.tile)) for c in cams[:v])
     nt = (-(-cam.width // settings.tile)) * (-(-cam.height // settings.tile))
     ranges = f.tile_ranges[base:base + nt].contiguous()
-    _, _, _, cnt = P.seele_rasterize_fwd_counted(f.splats, f.sorted_ids, ranges, [cam], settings)
+    img, T, nc, cnt = P.seele_rasterize_fwd_counted(f.splats, f.sorted_ids, ranges, [cam],
+                                                    settings)
+    # the instrumented kernel visits every record; the production kernel skips
+    # records that cannot reach its 8x8 blocks -- both give the same bits
+    imgs = P.split_views(f.image, cams, 3)[v]
+    Ts = P.split_views(f.final_T, cams, 1)[v]
+    ncs = P.split_views(f.n_contrib, cams, 1)[v]
+    assert torch.equal(img.reshape(imgs.shape), imgs) and torch.equal(T.reshape(Ts.shape), Ts)
+    assert torch.equal(nc.reshape(ncs.shape), ncs)
     got = cnt.cpu().numpy().tolist()
     want = [oc["evals"] if settings.mode == "plain" else oc["pass_evals"], oc["blends"],
             oc["leader_tests"], oc["leader_pass"]]
