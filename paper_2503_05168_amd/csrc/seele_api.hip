@@ -310,12 +310,19 @@ int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_
   BinViews bv{};
   bv.n_views = n_views;
   bv.n = n;
-  int64_t base = 0;
+  int64_t base = 0, st_base = 0;
   for (int v = 0; v < n_views; ++v) {
+    const int gw = (cams[v].width + tile - 1) / tile, gh = (cams[v].height + tile - 1) / tile;
     bv.v[v].tile_base = (int32_t)base;
-    bv.v[v].grid_w = (cams[v].width + tile - 1) / tile;
+    bv.v[v].st_base = (int32_t)st_base;
+    bv.v[v].grid_w = (uint16_t)gw;
+    bv.v[v].grid_h = (uint16_t)gh;
     base += tiles_of(cams[v], tile);
+    st_base += (int64_t)((gw + kSuperTile - 1) / kSuperTile) * ((gh + kSuperTile - 1) / kSuperTile);
   }
+  if (st_base > ((int64_t)1 << 24))
+    return fail(SEELE_ERR_UNSUPPORTED, "more than 2^24 super-tiles (%lld)", (long long)st_base);
+  bv.n_st = st_base;
   const hipError_t e = launch_bin_sort(plan, bv, splats, n_tiles, workspace, sorted_ids,
                                        tile_ranges, num_pairs, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "bin_sort launch");

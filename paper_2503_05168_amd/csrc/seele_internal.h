@@ -42,14 +42,20 @@ struct PreArgs {
   CamK cam[kMaxViewsPre];
 };
 
+// Super-tiles: square blocks of kSuperTile x kSuperTile tiles (row-major per
+// view, numbered after the previous views' super-tiles).
+constexpr int kSuperTile = 4;
+
 struct BinView {
-  int32_t tile_base;
-  int32_t grid_w;
+  int32_t tile_base;  // first global tile of the view
+  int32_t st_base;    // first global super-tile of the view
+  uint16_t grid_w, grid_h;
 };
 
 struct BinViews {
   int n_views;
-  int64_t n;  // Gaussians per view
+  int64_t n;     // Gaussians per view
+  int64_t n_st;  // super-tiles over all views
   BinView v[kMaxViewsBin];
 };
 
@@ -215,10 +221,13 @@ struct BinSortPlan {
   int64_t n_records;      // n_views * n
   int64_t capacity;       // pair capacity
   int64_t n_tiles_total;
-  int tile_bits;          // bits of the global tile id
+  int64_t max_st;         // bound on super-tiles (n_tiles_total)
+  int64_t max_seg;        // bound on write segments
   // workspace carve-up (byte offsets)
-  size_t off_hdr, off_partial, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
-  size_t off_tkeys0, off_tkeys1, off_tvals, off_goff, off_bfirst, off_hist, off_digits, total;
+  size_t off_hdr, off_partial, off_partial2, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
+  size_t off_skeys0, off_skeys1, off_svals0, off_svals1, off_mcount, off_goff, off_bfirst;
+  size_t off_hist, off_digits, off_st_range, off_st_seg, off_seg_st, off_seg_cnt;
+  size_t off_tile_cnt, off_tile_start, total;
 };
 BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_total);
 hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,

@@ -151,3 +151,24 @@ def test_hip_graph_replay_matches_eager(c5_small):
         (x * 2).sum().item()
     imgs = split_views(image, cams, 3)
     assert imgs[-1].shape == (3, cams[-1].height, cams[-1].width)
+
+
+@pytest.mark.parametrize("tile,n_views,passes", [(16, 1, 2), (8, 34, 3)],
+                         ids=["1080p-tile16-2passes", "34x1080p-tile8-3passes"])
+def test_bin_sort_super_tile_sort_passes_match_oracle(tile, n_views, passes):
+    # the super-tile count of the cameras sets how many radix passes the
+    # super-tile sort takes (and which buffer the value ping-pong ends in)
+    scene = synthetic.cluster_scene(7, 4000)
+    cams = synthetic.orbit_cameras(n_views, 4.0, 1920, 1080)
+    n_st = sum(-(-(-(-c.width // tile)) // 4) * -(-(-(-c.height // tile)) // 4) for c in cams)
+    bits = max(1, int(np.ceil(np.log2(n_st))))
+    assert -(-bits // 8) == passes
+    gu.log(f"[case] bin_sort tile={tile} views={n_views} super-tiles={n_st}")
+    f = gu.run(scene, cams, Settings(tile=tile))
+    sp = gu.splats_np(f)
+    ob = gu.oracle_binning(sp, cams, tile, scene.n)
+    P = int(f.num_pairs.item())
+    assert P == ob["n_pairs"]
+    np.testing.assert_array_equal(f.sorted_ids.cpu().numpy()[:P].astype(np.int64) & 0xFFFFFFFF,
+                                  ob["ids"])
+    np.testing.assert_array_equal(f.tile_ranges.cpu().numpy().astype(np.int64), ob["ranges"])
