@@ -11,11 +11,12 @@
 //     clipped to that super-tile (2 bits per edge) above the super-tile id.
 //     The entries (several times fewer than pairs) are stably sorted by
 //     super-tile id, so each super-tile's list is in depth order.
-//  3. Each super-tile list is cut into segments of kSegLen entries.  Per
-//     segment and tile, the entries covering the tile are counted; a prefix
-//     over the super-tile's segments and one scan over all tiles give the
-//     tile ranges.  A last pass writes every record id straight to its slot:
-//     inside a wave the rank among entries covering a tile is a ballot count.
+//  3. Each super-tile list is cut into segments of kSegLen entries, each
+//     segment into four wave quarters.  Per quarter and tile, the entries
+//     covering the tile are counted; a prefix over the super-tile's quarters
+//     and one scan over all tiles give the tile ranges.  A last pass writes
+//     every record id straight to its slot: inside a wave the rank among
+//     entries covering a tile is a ballot count.
 // Every step is stable, so the result is exactly the lexicographic order.
 //
 // Every count (visible records, pairs, entries, segments) stays on the
@@ -108,12 +109,12 @@ __device__ __forceinline__ StLoc st_locate(const BinViews& views, uint32_t s) {
   return L;
 }
 
-// Does an entry with clipped rectangle `clip` cover tile t (t = 4 iy + ix)
-// of its super-tile?
-__device__ __forceinline__ bool clip_covers(uint32_t clip, int t) {
-  const uint32_t ix = (uint32_t)(t & 3), iy = (uint32_t)(t >> 2);
-  return ix >= (clip & 3u) && ix <= ((clip >> 2) & 3u) && iy >= ((clip >> 4) & 3u) &&
-         iy <= ((clip >> 6) & 3u);
+// 16-bit coverage mask of an entry over its super-tile's tiles (bit 4 iy + ix).
+__device__ __forceinline__ uint32_t clip_mask(uint32_t clip) {
+  const uint32_t xm = ((2u << ((clip >> 2) & 3u)) - 1u) & ~((1u << (clip & 3u)) - 1u);
+  const uint32_t y0 = (clip >> 4) & 3u, y1 = (clip >> 6) & 3u;
+  const uint32_t rows = ((2u << (4u * y1 + 3u)) - 1u) & ~((1u << (4u * y0)) - 1u);
+  return (xm * 0x1111u) & rows;
 }
 
 // ---- visible-record compaction: count per block, scan, then write (depth, id)
@@ -195,149 +196,17 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
 
 // ---- stable LSD radix sort of (u32 key, u32 value) with a device-side count
 //
-// A radix block owns BLK = 256 * IT consecutive items.  Items either come
-// from arrays (LOAD) or are generated on the fly as the super-tile entries
-// [b*BLK, (b+1)*BLK) of the depth-ordered records (GEN: the entry emission
-// fused into the first pass, so the entries are never written unsorted).
-// A fixed grid loops over the live blocks.  hist layout: [digit][block] with
-// row stride `stride`.
-
-constexpr int kGenIT = 8;                 // GEN blocks hold 2048 entries
-constexpr int kGenBlk = B * kGenIT;
-// GEN window arrays (W <= BLK + 1 records each): first entry, id, global
-// super-tile of the top-left covered super-tile, covered super-tile columns |
-// super-tile grid width << 16, tile rectangle x0 | x1 << 16 and y0 | y1 << 16,
-// and the block position -> window record map.
-enum { kWinOff, kWinId, kWinT0, kWinWg, kWinRx, kWinRy, kWinRec, kWinArrays };
-
-struct GenSrc {
-  const uint32_t* ids;          // depth-ordered visible records
-  const seele_splat* splats;
-  const uint32_t* goff;         // first entry of each depth-ordered record
-  const uint32_t* block_first;  // record holding the first entry of each GEN block
-  const Hdr* hdr;
-};
-
-// Block-wide inclusive max-scan of IT consecutive values per thread (in place).
-template <int IT>
-__device__ __forceinline__ void block_inclusive_max(uint32_t* s_rec, uint32_t* s_tmp) {
-  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
-  uint32_t v[IT];
-  uint32_t m = 0;
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    v[i] = s_rec[tid * IT + i];
-    m = v[i] > m ? v[i] : m;
-    v[i] = m;
-  }
-  // inclusive max over lanes, then over waves
-  uint32_t x = m;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (l >= d) x = y > x ? y : x;
-  }
-  if (l == 63) s_tmp[w] = x;
-  __syncthreads();
-  uint32_t prev = __shfl_up(x, 1, 64);
-  if (l == 0) prev = 0;
-  for (int i = 0; i < w; ++i) prev = s_tmp[i] > prev ? s_tmp[i] : prev;
-#pragma unroll
-  for (int i = 0; i < IT; ++i) s_rec[tid * IT + i] = v[i] > prev ? v[i] : prev;
-  __syncthreads();
-}
-
-// Exact k / w for 1 <= w < 2^16: a float reciprocal estimate is within one of
-// the quotient for k < 2^22 and is corrected once; larger k divide exactly.
-__device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t w) {
-  if (k < (1u << 22)) {
-    uint32_t q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
-    const int32_t r = (int32_t)(k - q * w);
-    if (r < 0) --q;
-    else if (r >= (int32_t)w) ++q;
-    return q;
-  }
-  return k / w;
-}
-
-// Stage the records covering entries [S, S + BLK) in the LDS window and map
-// every position of the block to its record: each record marks the block
-// position of its first entry and an inclusive max-scan spreads the marks
-// over the record's entries.
-template <int IT>
-__device__ __forceinline__ void gen_window(const GenSrc& g, const BinViews& views, uint32_t blk,
-                                           uint32_t nblk, uint32_t* s_win, uint32_t* s_tmp) {
-  constexpr int BLK = B * IT;
-  constexpr int L = BLK + 1;
-  uint32_t* s_rec = s_win + kWinRec * L;
-  const uint32_t nv = g.hdr->n_vis;
-  const uint32_t S = blk * (uint32_t)BLK;
-  const uint32_t g_lo = g.block_first[blk];
-  const uint32_t g_hi = blk + 1 < nblk ? g.block_first[blk + 1] : nv - 1;
-  // records without entries (only from malformed rectangles) could widen the
-  // window past its LDS arrays; the cap keeps every access inside
-  const int W = min((int)(g_hi - g_lo + 1), L);
-  const uint32_t n = (uint32_t)views.n;
-  for (int j = threadIdx.x; j < BLK; j += B) s_rec[j] = 0;
-  __syncthreads();
-  for (int j = threadIdx.x; j < W; j += B) {
-    const uint32_t id = g.ids[g_lo + j];
-    const uint32_t o = g.goff[g_lo + j];
-    const BinView bv = views.v[id / n];
-    const Rect r = rect_of(g.splats[id], bv);
-    const uint32_t sgw = ((uint32_t)bv.grid_w + ST - 1) / ST;
-    const uint32_t sx0 = r.x0 / ST, sy0 = r.y0 / ST;
-    const uint32_t sw = r.x1 > r.x0 ? (r.x1 - 1) / ST - sx0 + 1 : 1u;
-    s_win[kWinOff * L + j] = o;
-    s_win[kWinId * L + j] = id;
-    s_win[kWinT0 * L + j] = (uint32_t)bv.st_base + sy0 * sgw + sx0;
-    s_win[kWinWg * L + j] = sw | (sgw << 16);
-    s_win[kWinRx * L + j] = r.x0 | (r.x1 << 16);
-    s_win[kWinRy * L + j] = r.y0 | (r.y1 << 16);
-    // records without entries own no position (their offset is the next one's)
-    if (j > 0 && st_count(r) > 0 && o - S < (uint32_t)BLK) s_rec[o - S] = (uint32_t)j;
-  }
-  __syncthreads();
-  block_inclusive_max<IT>(s_rec, s_tmp);
-}
-
-// Entry at block position p (global position q).
-template <int IT>
-__device__ __forceinline__ void gen_entry(uint32_t q, uint32_t p, const uint32_t* s_win,
-                                          uint32_t& key, uint32_t& val) {
-  constexpr int L = B * IT + 1;
-  const uint32_t j = s_win[kWinRec * L + p];
-  const uint32_t k = q - s_win[kWinOff * L + j];
-  const uint32_t wg = s_win[kWinWg * L + j];
-  const uint32_t sw = wg & 0xffffu;
-  const uint32_t dy = div_small(k, sw);
-  const uint32_t dx = k - dy * sw;
-  const uint32_t rx = s_win[kWinRx * L + j], ry = s_win[kWinRy * L + j];
-  const uint32_t x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu, y1 = ry >> 16;
-  const uint32_t ox = (x0 / ST + dx) * ST, oy = (y0 / ST + dy) * ST;
-  const uint32_t cx0 = max(x0, ox) - ox, cx1 = min(x1, ox + ST) - 1u - ox;
-  const uint32_t cy0 = max(y0, oy) - oy, cy1 = min(y1, oy + ST) - 1u - oy;
-  const uint32_t clip = cx0 | (cx1 << 2) | (cy0 << 4) | (cy1 << 6);
-  key = (clip << kClipShift) | (s_win[kWinT0 * L + j] + dy * (wg >> 16) + dx);
-  val = s_win[kWinId * L + j];
-}
+// A radix block owns BLK = 256 * IT consecutive items; a fixed grid loops
+// over the live blocks.  hist layout: [digit][block] with row stride
+// `stride`.
 
 template <int IT>
-constexpr int gen_lds_words() {
-  return kWinArrays * (B * IT + 1);
-}
-
-template <int IT, bool GEN>
 __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                   const uint32_t* __restrict__ d_count,
-                                                   GenSrc gs, BinViews views, int shift,
+                                                   const uint32_t* __restrict__ d_count, int shift,
                                                    int bits, uint32_t* __restrict__ hist,
                                                    int stride) {
   constexpr int BLK = B * IT;
-  constexpr int kWin = GEN ? gen_lds_words<IT>() : 1;
   __shared__ uint32_t h[WAVES][256];
-  __shared__ uint32_t s_win[kWin];
-  __shared__ uint32_t s_tmp[WAVES + 1];
   const int radix = 1 << bits;
   const int w = threadIdx.x >> 6;
   const uint32_t count = *d_count;
@@ -345,21 +214,12 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ k
   const uint32_t mask = (uint32_t)radix - 1u;
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
     for (int d = threadIdx.x; d < WAVES * 256; d += B) (&h[0][0])[d] = 0;
-    if (GEN) gen_window<IT>(gs, views, vb, nbl, s_win, s_tmp);
     __syncthreads();
     const int64_t begin = (int64_t)vb * BLK;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const uint32_t p = it * B + threadIdx.x;
-      const int64_t idx = begin + p;
-      if (idx < count) {
-        uint32_t k, v;
-        if (GEN)
-          gen_entry<IT>((uint32_t)idx, p, s_win, k, v);
-        else
-          k = keys[idx];
-        atomicAdd(&h[w][(k >> shift) & mask], 1u);
-      }
+      const int64_t idx = begin + it * B + threadIdx.x;
+      if (idx < count) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < radix; d += B) {
@@ -411,15 +271,15 @@ __global__ __launch_bounds__(B) void k_radix_rowscan(uint32_t* __restrict__ hist
 // order the waves.  Items are first placed in LDS in block-sorted order and
 // then written out digit run by digit run, so consecutive lanes store to
 // consecutive addresses.  Input order is preserved among equal digits.
-template <int IT, bool GEN>
+template <int IT>
 __global__ __launch_bounds__(B) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count,
-    GenSrc gs, BinViews views, int shift, int bits, const uint32_t* __restrict__ hist,
+    int shift, int bits, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ digit_total, int stride) {
   constexpr int BLK = B * IT;
-  constexpr int kWords = GEN ? gen_lds_words<IT>() : 2 * BLK;
-  __shared__ uint32_t s_mem[kWords];  // GEN window, then the staged (key, value) pairs
+  __shared__ uint32_t s_k[BLK];
+  __shared__ uint32_t s_v[BLK];
   __shared__ uint32_t s_dig[256];     // global start of each digit
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loc[256];
@@ -442,7 +302,6 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     const int64_t begin = (int64_t)vb * BLK;
     if (tid < radix) s_base[tid] = s_dig[tid] + hist[(int64_t)tid * stride + vb];
     for (int d = tid; d < WAVES * 256; d += B) (&s_w[0][0])[d] = 0;
-    if (GEN) gen_window<IT>(gs, views, vb, nbl, s_mem, s_tmp);
     __syncthreads();
 
     uint32_t k[IT], v[IT], rank[IT];
@@ -450,16 +309,8 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int64_t idx = wbase + it * 64 + lane;
-      k[it] = 0u;
-      v[it] = 0u;
-      if (idx < count) {
-        if (GEN)
-          gen_entry<IT>((uint32_t)idx, (uint32_t)(idx - begin), s_mem, k[it], v[it]);
-        else {
-          k[it] = kin[idx];
-          v[it] = vin[idx];
-        }
-      }
+      k[it] = idx < count ? kin[idx] : 0u;
+      v[it] = idx < count ? vin[idx] : 0u;
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -477,7 +328,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
       rank[it] = before + below;
       if (valid && below == 0) s_w[w][d] = before + (uint32_t)__popcll(peers);
     }
-    __syncthreads();  // s_w complete; the GEN window is no longer read
+    __syncthreads();  // s_w complete
     // per digit: wave offsets, block total, block-local digit start
     uint32_t dtot = 0;
     if (tid < radix) {
@@ -494,8 +345,6 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
       if (tid < radix) s_loc[tid] = ex;
     }
     __syncthreads();
-    uint32_t* s_k = s_mem;
-    uint32_t* s_v = s_mem + BLK;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int64_t idx = wbase + it * 64 + lane;
@@ -520,12 +369,13 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
 }
 
 // ---- super-tile entries of the depth-ordered records
-// Per record: pairs (tiles of its rectangle) and entries (super-tiles it
-// touches); block sums of both.
+// Per record: its clipped rectangle (kept for the emission), pairs (tiles of
+// the rectangle) and entries (super-tiles it touches); block sums of both.
 __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ ids,
                                                    const seele_splat* __restrict__ splats,
                                                    BinViews views, const Hdr* __restrict__ hdr,
-                                                   uint32_t* __restrict__ ecount,
+                                                   uint32_t* __restrict__ rx_s,
+                                                   uint32_t* __restrict__ ry_s,
                                                    uint64_t* __restrict__ partial,
                                                    uint64_t* __restrict__ partial2) {
   const uint32_t nv = hdr->n_vis;
@@ -541,7 +391,8 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
         const Rect r = rect_of(splats[id], views.v[id / n]);
         const uint32_t m = st_count(r);
         if (m > 0) c += (uint64_t)(r.x1 - r.x0) * (r.y1 - r.y0);
-        ecount[i] = m;
+        rx_s[i] = r.x0 | (r.x1 << 16);
+        ry_s[i] = r.y0 | (r.y1 << 16);
         q += m;
       }
     }
@@ -565,32 +416,90 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
   }
 }
 
-// Per-record entry offsets in depth order (exclusive scan of entry counts),
-// and for every GEN block of kGenBlk entries the record holding its first
-// entry.  Skipped when the frame overflows the pair capacity.
-__global__ __launch_bounds__(B) void k_entry_offsets(const uint32_t* __restrict__ ecount,
-                                                      const Hdr* __restrict__ hdr,
-                                                      const uint64_t* __restrict__ partial,
-                                                      int64_t capacity,
-                                                      uint32_t* __restrict__ goff,
-                                                      uint32_t* __restrict__ block_first) {
+// Entry k (row-major over the covered super-tiles) of a record with tile
+// rectangle r: key = clipped rectangle << 24 | global super-tile.
+__device__ __forceinline__ uint32_t entry_key(const Rect& r, uint32_t k, uint32_t sw, uint32_t sgw,
+                                              uint32_t st_base) {
+  const uint32_t dy = k / sw, dx = k - dy * sw;
+  const uint32_t sx = r.x0 / ST + dx, sy = r.y0 / ST + dy;
+  const uint32_t ox = sx * ST, oy = sy * ST;
+  const uint32_t clip = (max(r.x0, ox) - ox) | (min(r.x1, ox + ST) - 1u - ox) << 2 |
+                        (max(r.y0, oy) - oy) << 4 | (min(r.y1, oy + ST) - 1u - oy) << 6;
+  return (clip << kClipShift) | (st_base + sy * sgw + sx);
+}
+
+// Emit the entries of every depth-ordered record at its offset (exclusive
+// scan of entry counts), value = record id.  A record with few entries is
+// emitted by its own lane; a larger one (a Gaussian spanning much of the
+// image) by the whole wave, 64 entries per step.  Skipped when the frame
+// overflows the pair capacity.
+constexpr uint32_t kLaneEntries = 8;
+
+__global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ ids,
+                                                   const uint32_t* __restrict__ rx_s,
+                                                   const uint32_t* __restrict__ ry_s,
+                                                   BinViews views, const Hdr* __restrict__ hdr,
+                                                   const uint64_t* __restrict__ partial,
+                                                   int64_t capacity, uint32_t* __restrict__ ekeys,
+                                                   uint32_t* __restrict__ evals) {
   __shared__ uint64_t s[WAVES + 1];
   const uint32_t nv = hdr->n_vis;
   const int64_t begin = (int64_t)blockIdx.x * TILE;
   if (begin >= nv || hdr->p_total > (uint64_t)capacity) return;  // uniform per block
+  const uint32_t n = (uint32_t)views.n;
+  const int lane = lane_id();
   uint64_t carry = partial[blockIdx.x];
 #pragma unroll 1
   for (int it = 0; it < ITEMS; ++it) {
     const int64_t i = begin + it * B + threadIdx.x;
-    const uint32_t c = i < nv ? ecount[i] : 0u;
-    uint64_t tot;
-    const uint64_t off = carry + block_exclusive_scan<uint64_t>((uint64_t)c, s, tot);
-    carry += tot;
+    Rect r{0u, 0u, 0u, 0u};
+    uint32_t id = 0;
     if (i < nv) {
-      goff[i] = (uint32_t)off;
-      // GEN blocks whose first entry belongs to this record
-      for (uint64_t b = (off + kGenBlk - 1) / kGenBlk; b * kGenBlk < off + c; ++b)
-        block_first[b] = (uint32_t)i;
+      id = ids[i];
+      const uint32_t rx = rx_s[i], ry = ry_s[i];
+      r.x0 = rx & 0xffffu;
+      r.x1 = rx >> 16;
+      r.y0 = ry & 0xffffu;
+      r.y1 = ry >> 16;
+    }
+    const uint32_t m = st_count(r);
+    uint64_t tot;
+    const uint64_t off = carry + block_exclusive_scan<uint64_t>((uint64_t)m, s, tot);
+    carry += tot;
+    uint32_t sgw = 0, stb = 0, sw = 1;
+    if (m > 0) {
+      const BinView bv = views.v[id / n];
+      sgw = ((uint32_t)bv.grid_w + ST - 1) / ST;
+      stb = (uint32_t)bv.st_base;
+      sw = (r.x1 - 1) / ST - r.x0 / ST + 1;
+    }
+    if (m > 0 && m <= kLaneEntries) {
+      for (uint32_t k = 0; k < m; ++k) {
+        ekeys[off + k] = entry_key(r, k, sw, sgw, stb);
+        evals[off + k] = id;
+      }
+    }
+    uint64_t big = __ballot(m > kLaneEntries);
+    while (big != 0) {
+      const int src = __builtin_ctzll(big);
+      big &= big - 1;
+      Rect rb;
+      rb.x0 = __builtin_amdgcn_readlane(r.x0, src);
+      rb.x1 = __builtin_amdgcn_readlane(r.x1, src);
+      rb.y0 = __builtin_amdgcn_readlane(r.y0, src);
+      rb.y1 = __builtin_amdgcn_readlane(r.y1, src);
+      const uint32_t mb = __builtin_amdgcn_readlane(m, src);
+      const uint32_t swb = __builtin_amdgcn_readlane(sw, src);
+      const uint32_t sgwb = __builtin_amdgcn_readlane(sgw, src);
+      const uint32_t stbb = __builtin_amdgcn_readlane(stb, src);
+      const uint32_t idb = __builtin_amdgcn_readlane(id, src);
+      const uint32_t olo = __builtin_amdgcn_readlane((uint32_t)off, src);
+      const uint32_t ohi = __builtin_amdgcn_readlane((uint32_t)(off >> 32), src);
+      const uint64_t ob = ((uint64_t)ohi << 32) | olo;
+      for (uint32_t k = lane; k < mb; k += 64) {
+        ekeys[ob + k] = entry_key(rb, k, swb, sgwb, stbb);
+        evals[ob + k] = idb;
+      }
     }
   }
 }
@@ -656,64 +565,53 @@ __global__ __launch_bounds__(B) void k_seg_emit(const int32_t* __restrict__ st_r
   }
 }
 
-// Entries [a, e) of segment `seg` and its super-tile.
-struct Seg {
+// Entries [a, e) of quarter w of segment `seg`, and its super-tile.
+struct Quarter {
   uint32_t st;
   int32_t a, e;
 };
 
-__device__ __forceinline__ Seg segment(uint32_t seg, const uint32_t* seg_st,
-                                       const uint32_t* st_seg, const int32_t* st_range) {
-  Seg g;
+__device__ __forceinline__ Quarter quarter(uint32_t seg, int w, const uint32_t* seg_st,
+                                           const uint32_t* st_seg, const int32_t* st_range) {
+  Quarter g;
   g.st = seg_st[seg];
   const int32_t lo = st_range[2 * (int64_t)g.st], hi = st_range[2 * (int64_t)g.st + 1];
-  g.a = lo + (int32_t)(seg - st_seg[g.st]) * kSegLen;
-  g.e = min(hi, g.a + kSegLen);
+  const int32_t a = lo + (int32_t)(seg - st_seg[g.st]) * kSegLen + w * (kSegLen / WAVES);
+  g.a = min(hi, a);
+  g.e = min(hi, a + kSegLen / WAVES);
   return g;
 }
 
-// Per segment and tile of its super-tile: entries covering the tile.
+// Per wave quarter of a segment and tile of its super-tile: entries covering
+// the tile.  seg_cnt layout: [segment][wave quarter][tile].
 __global__ __launch_bounds__(B) void k_seg_tile_count(const Hdr* __restrict__ hdr,
                                                        const uint32_t* __restrict__ seg_st,
                                                        const uint32_t* __restrict__ st_seg,
                                                        const int32_t* __restrict__ st_range,
                                                        const uint32_t* __restrict__ ekeys,
                                                        uint32_t* __restrict__ seg_cnt) {
-  __shared__ uint32_t s_c[WAVES][ST2];
-  const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nseg = hdr->n_seg;
   for (uint32_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-    const Seg g = segment(seg, seg_st, st_seg, st_range);
-    uint32_t c[ST2];
-#pragma unroll
-    for (int t = 0; t < ST2; ++t) c[t] = 0;
-    for (int32_t base = g.a + w * 64; base < g.e; base += B) {
+    const Quarter g = quarter(seg, w, seg_st, st_seg, st_range);
+    uint32_t mine = 0;  // lane t < 16: count of tile t
+    for (int32_t base = g.a; base < g.e; base += 64) {
       const int32_t i = base + lane;
       const bool valid = i < g.e;
-      const uint32_t clip = valid ? ekeys[i] >> kClipShift : 0u;
+      const uint32_t cov = valid ? clip_mask(ekeys[i] >> kClipShift) : 0u;
 #pragma unroll
-      for (int t = 0; t < ST2; ++t) c[t] += (uint32_t)__popcll(__ballot(valid && clip_covers(clip, t)));
+      for (int t = 0; t < ST2; ++t) {
+        const uint32_t c = (uint32_t)__popcll(__ballot((cov >> t) & 1u));
+        if (lane == t) mine += c;
+      }
     }
-    if (lane < ST2) {
-      uint32_t x = 0;
-#pragma unroll
-      for (int t = 0; t < ST2; ++t)
-        if (t == lane) x = c[t];
-      s_c[w][lane] = x;
-    }
-    __syncthreads();
-    if (tid < ST2) {
-      uint32_t t = 0;
-#pragma unroll
-      for (int ww = 0; ww < WAVES; ++ww) t += s_c[ww][tid];
-      seg_cnt[(int64_t)seg * ST2 + tid] = t;
-    }
-    __syncthreads();
+    if (lane < ST2) seg_cnt[((int64_t)seg * WAVES + w) * ST2 + lane] = mine;
   }
 }
 
 // One thread per (super-tile, tile): exclusive prefix of the tile's counts
-// over the super-tile's segments (in place) and the tile's total pair count.
+// over the super-tile's wave quarters in order (in place) and the tile's
+// total pair count.
 __global__ void k_st_tile_prefix(const int32_t* __restrict__ st_range,
                                  const uint32_t* __restrict__ st_seg, int64_t n_st,
                                  BinViews views, uint32_t* __restrict__ seg_cnt,
@@ -726,10 +624,15 @@ __global__ void k_st_tile_prefix(const int32_t* __restrict__ st_range,
   const uint32_t first = st_seg[s];
   uint32_t run = 0;
   for (uint32_t k = 0; k < ns; ++k) {
-    uint32_t* p = seg_cnt + (int64_t)(first + k) * ST2 + t;
-    const uint32_t c = *p;
-    *p = run;
-    run += c;
+    uint32_t* p = seg_cnt + (int64_t)(first + k) * WAVES * ST2 + t;
+    uint32_t c[WAVES];
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) c[w] = p[w * ST2];
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      p[w * ST2] = run;
+      run += c[w];
+    }
   }
   const StLoc L = st_locate(views, (uint32_t)s);
   const int ix = t & 3, iy = t >> 2;
@@ -783,10 +686,11 @@ __global__ __launch_bounds__(B) void k_tile_ranges(const uint32_t* __restrict__ 
   }
 }
 
-// Write every record id of a segment to its slots: for each tile of the
-// super-tile, the segment's base slot, plus the entries covering the tile in
-// earlier 256-entry steps, earlier waves of this step, and (ballot count)
-// lower lanes of this wave.
+// Write every record id of a wave quarter to its slots.  The next free slot
+// of each of the 16 tiles (initially the quarter's base: tile start plus the
+// prefix of earlier quarters) is wave-uniform; per 64-entry step the covering
+// lanes of tile t take consecutive slots in lane order.  Waves run
+// independently.
 __global__ __launch_bounds__(B) void k_seg_write(const Hdr* __restrict__ hdr,
                                                   const uint32_t* __restrict__ seg_st,
                                                   const uint32_t* __restrict__ st_seg,
@@ -796,51 +700,38 @@ __global__ __launch_bounds__(B) void k_seg_write(const Hdr* __restrict__ hdr,
                                                   const uint32_t* __restrict__ seg_cnt,
                                                   const uint32_t* __restrict__ tile_start,
                                                   BinViews views, uint32_t* __restrict__ out) {
-  __shared__ uint32_t s_run[ST2];
-  __shared__ uint32_t s_c[WAVES][ST2];
-  const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-  const uint64_t lt = lanemask_lt();
+  const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nseg = hdr->n_seg;
   for (uint32_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-    const Seg g = segment(seg, seg_st, st_seg, st_range);
-    if (tid < ST2) {
+    const Quarter g = quarter(seg, w, seg_st, st_seg, st_range);
+    if (g.a >= g.e) continue;  // uniform per wave
+    uint32_t start = 0;
+    if (lane < ST2) {
       const StLoc L = st_locate(views, g.st);
-      const int ix = tid & 3, iy = tid >> 2;
-      s_run[tid] = (ix < L.nx && iy < L.ny)
-                       ? tile_start[L.tile0 + iy * L.grid_w + ix] + seg_cnt[(int64_t)seg * ST2 + tid]
-                       : 0u;
+      const int ix = lane & 3, iy = lane >> 2;
+      if (ix < L.nx && iy < L.ny)
+        start = tile_start[L.tile0 + iy * L.grid_w + ix] +
+                seg_cnt[((int64_t)seg * WAVES + w) * ST2 + lane];
     }
-    for (int32_t base = g.a; base < g.e; base += B) {
-      const int32_t i = base + tid;
+    uint32_t next[ST2];
+#pragma unroll
+    for (int t = 0; t < ST2; ++t) next[t] = __builtin_amdgcn_readlane(start, t);
+    for (int32_t base = g.a; base < g.e; base += 64) {
+      const int32_t i = base + lane;
       const bool valid = i < g.e;
-      const uint32_t clip = valid ? ekeys[i] >> kClipShift : 0u;
+      const uint32_t cov = valid ? clip_mask(ekeys[i] >> kClipShift) : 0u;
       const uint32_t id = valid ? evals[i] : 0u;
-      uint64_t bal[ST2];
 #pragma unroll
-      for (int t = 0; t < ST2; ++t) bal[t] = __ballot(valid && clip_covers(clip, t));
-      if (lane < ST2) {
-        uint32_t x = 0;
-#pragma unroll
-        for (int t = 0; t < ST2; ++t)
-          if (t == lane) x = (uint32_t)__popcll(bal[t]);
-        s_c[w][lane] = x;
-      }
-      __syncthreads();
-      if (tid < ST2) {
-        uint32_t o = s_run[tid];
-#pragma unroll
-        for (int ww = 0; ww < WAVES; ++ww) {
-          const uint32_t c = s_c[ww][tid];
-          s_c[ww][tid] = o;
-          o += c;
+      for (int t = 0; t < ST2; ++t) {
+        const bool c = (cov >> t) & 1u;
+        const uint64_t bal = __ballot(c);
+        if (c) {
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          out[next[t] + rank] = id;
         }
-        s_run[tid] = o;
+        next[t] += (uint32_t)__popcll(bal);
       }
-      __syncthreads();
-#pragma unroll
-      for (int t = 0; t < ST2; ++t)
-        if ((bal[t] >> lane) & 1ull) out[s_c[w][t] + (uint32_t)__popcll(bal[t] & lt)] = id;
-      __syncthreads();
     }
   }
 }
@@ -852,22 +743,21 @@ int64_t nblocks_for(int64_t n) { return (n + TILE - 1) / TILE; }
 int grid_for(int64_t nb) { return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid)); }
 
 // One radix pass over a device-side count of at most max_count items.
-template <int IT, bool GEN>
+template <int IT>
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      const uint32_t* d_count, int64_t max_count, const GenSrc& gs,
-                      const BinViews& views, int shift, int bits, uint32_t* hist,
-                      uint32_t* digits, hipStream_t stream) {
+                      const uint32_t* d_count, int64_t max_count, int shift, int bits,
+                      uint32_t* hist, uint32_t* digits, hipStream_t stream) {
   constexpr int BLK = B * IT;
   const int64_t nb = (max_count + BLK - 1) / BLK;
   if (nb == 0) return hipSuccess;
   const int stride = (int)nb;
   const dim3 grid(grid_for(nb));
-  hipLaunchKernelGGL((k_radix_hist<IT, GEN>), grid, dim3(B), 0, stream, kin, d_count, gs, views,
-                     shift, bits, hist, stride);
+  hipLaunchKernelGGL((k_radix_hist<IT>), grid, dim3(B), 0, stream, kin, d_count, shift, bits, hist,
+                     stride);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(B), 0, stream, hist, stride, d_count,
                      BLK, digits);
-  hipLaunchKernelGGL((k_radix_scatter<IT, GEN>), grid, dim3(B), 0, stream, kin, vin, kout, vout,
-                     d_count, gs, views, shift, bits, hist, digits, stride);
+  hipLaunchKernelGGL((k_radix_scatter<IT>), grid, dim3(B), 0, stream, kin, vin, kout, vout,
+                     d_count, shift, bits, hist, digits, stride);
   return hipGetLastError();
 }
 
@@ -908,13 +798,11 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
   uint32_t* k[2] = {keys, k1};
   uint32_t* v[2] = {vals, v1};
   const int passes = (bits + 7) / 8;
-  BinViews none{};
   for (int pass = 0; pass < passes; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     const int pb = std::min(8, bits - 8 * pass);
-    const hipError_t e = radix_pass<ITEMS, false>(k[src], v[src], k[dst], v[dst], d_count, n,
-                                                  GenSrc{}, none, 8 * pass, pb, hist, digits,
-                                                  stream);
+    const hipError_t e = radix_pass<ITEMS>(k[src], v[src], k[dst], v[dst], d_count, n, 8 * pass,
+                                           pb, hist, digits, stream);
     if (e != hipSuccess) return e;
   }
   if (passes % 2 == 1) {
@@ -934,8 +822,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.max_st = std::max<int64_t>(n_tiles_total, 1);
   p.max_seg = max_segments(capacity, p.max_st);
   const int64_t nb_rec = std::max<int64_t>(nblocks_for(n_records), 1);
-  const int64_t nb_hist = std::max<int64_t>(
-      {nb_rec, (capacity + kGenBlk - 1) / kGenBlk, nblocks_for(capacity), 1});
+  const int64_t nb_hist = std::max<int64_t>({nb_rec, nblocks_for(capacity), 1});
   const int64_t nb_part =
       std::max<int64_t>({nb_rec, nblocks_for(p.max_st), nblocks_for(n_tiles_total), 1});
   size_t off = 0;
@@ -955,15 +842,14 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_skeys1 = take(4 * (size_t)capacity);
   p.off_svals0 = take(4 * (size_t)capacity);
   p.off_svals1 = 0;  // the second value buffer is the caller's sorted_ids
-  p.off_mcount = take(4 * (size_t)n_records);
-  p.off_goff = take(4 * (size_t)n_records);
-  p.off_bfirst = take(4 * (size_t)(capacity / kGenBlk + 2));
+  p.off_rx = take(4 * (size_t)n_records);
+  p.off_ry = take(4 * (size_t)n_records);
   p.off_hist = take(4 * 256 * (size_t)nb_hist);
   p.off_digits = take(4 * 256);
   p.off_st_range = take(8 * (size_t)p.max_st);
   p.off_st_seg = take(4 * (size_t)p.max_st);
   p.off_seg_st = take(4 * (size_t)p.max_seg);
-  p.off_seg_cnt = take(4 * ST2 * (size_t)p.max_seg);
+  p.off_seg_cnt = take(4 * WAVES * ST2 * (size_t)p.max_seg);
   p.off_tile_cnt = take(4 * (size_t)std::max<int64_t>(n_tiles_total, 1));
   p.off_tile_start = take(4 * (size_t)std::max<int64_t>(n_tiles_total, 1));
   p.total = off;
@@ -980,10 +866,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   uint64_t* partial2 = reinterpret_cast<uint64_t*>(base + p.off_partial2);
   uint32_t* dk[2] = {at(p.off_dkeys0), at(p.off_dkeys1)};
   uint32_t* dv[2] = {at(p.off_dvals0), at(p.off_dvals1)};
-  uint32_t* sk[2] = {at(p.off_skeys0), at(p.off_skeys1)};
-  uint32_t* ecount = at(p.off_mcount);
-  uint32_t* goff = at(p.off_goff);
-  uint32_t* bfirst = at(p.off_bfirst);
+  uint32_t* rx_s = at(p.off_rx);
+  uint32_t* ry_s = at(p.off_ry);
   uint32_t* hist = at(p.off_hist);
   uint32_t* digits = at(p.off_digits);
   int32_t* st_range = reinterpret_cast<int32_t*>(base + p.off_st_range);
@@ -1016,50 +900,43 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     //    stable sort by float32 depth bits (4 x 8-bit passes, ends in buffer 0)
     for (int pass = 0; pass < 4; ++pass) {
       const int src = pass & 1, dst = src ^ 1;
-      e = radix_pass<ITEMS, false>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, GenSrc{}, views,
-                                   8 * pass, 8, hist, digits, stream);
+      e = radix_pass<ITEMS>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8, hist,
+                            digits, stream);
       if (e != hipSuccess) return e;
     }
-    // 2. pair and entry totals (pairs -> num_pairs), entry offsets
+    // 2. pair and entry totals (pairs -> num_pairs)
     hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], splats, views, hdr,
-                       ecount, partial, partial2);
+                       rx_s, ry_s, partial, partial2);
   }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, (int64_t)nbR, hdr, 1,
                      p.capacity, num_pairs);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial2, (int64_t)nbR, hdr, 2,
                      p.capacity, num_pairs);
-  if (nbR > 0)
-    hipLaunchKernelGGL(k_entry_offsets, dim3(nbR), dim3(B), 0, stream, ecount, hdr, partial2,
-                       p.capacity, goff, bfirst);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  //    entries sorted by super-tile id (balanced digit widths <= 8); the first
-  //    pass generates them; the value buffers alternate between svals0 and
-  //    sorted_ids so that the last pass ends in svals0
+  //    entries, then sorted by super-tile id (balanced digit widths <= 8); the
+  //    value buffers alternate between svals0 and sorted_ids so that the last
+  //    pass ends in svals0
   int st_bits = 0;
   while (st_bits < 24 && ((int64_t)1 << st_bits) < n_st) ++st_bits;
   const int passes = std::max(1, (st_bits + 7) / 8);
   const int per = (st_bits + passes - 1) / passes;
-  uint32_t* sv_final = at(p.off_svals0);
-  uint32_t* sv[2] = {(passes % 2 == 1) ? sv_final : sorted_ids,
-                     (passes % 2 == 1) ? sorted_ids : sv_final};
-  int shift = std::min(per, st_bits);
-  {
-    const GenSrc gs{dv[0], splats, goff, bfirst, hdr};
-    e = radix_pass<kGenIT, true>(nullptr, nullptr, sk[0], sv[0], d_nent, p.capacity, gs, views, 0,
-                                 shift, hist, digits, stream);
-    if (e != hipSuccess) return e;
-  }
-  int cur = 0;
-  for (int pass = 1; pass < passes; ++pass) {
+  uint32_t* sk[2] = {at(p.off_skeys0), at(p.off_skeys1)};
+  uint32_t* sv[2] = {(passes % 2 == 0) ? at(p.off_svals0) : sorted_ids,
+                     (passes % 2 == 0) ? sorted_ids : at(p.off_svals0)};
+  if (nbR > 0)
+    hipLaunchKernelGGL(k_entry_emit, dim3(nbR), dim3(B), 0, stream, dv[0], rx_s, ry_s, views, hdr,
+                       partial2, p.capacity, sk[0], sv[0]);
+  int shift = 0;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int src = pass & 1, dst = src ^ 1;
     const int bits = std::min(per, st_bits - shift);
-    e = radix_pass<ITEMS, false>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], d_nent, p.capacity,
-                                 GenSrc{}, views, shift, bits, hist, digits, stream);
+    e = radix_pass<ITEMS>(sk[src], sv[src], sk[dst], sv[dst], d_nent, p.capacity, shift, bits,
+                          hist, digits, stream);
     if (e != hipSuccess) return e;
-    cur ^= 1;
     shift += bits;
   }
-  const uint32_t* ekeys = sk[cur];
-  const uint32_t* evals = sv[cur];
+  const uint32_t* ekeys = sk[passes & 1];
+  const uint32_t* evals = sv[passes & 1];
   // 3. super-tile ranges, segments, per-tile counts, tile ranges, write
   if (p.capacity > 0)
     hipLaunchKernelGGL(k_st_ranges, dim3(grid_for((p.capacity + 255) / 256)), dim3(256), 0,

@@ -178,6 +178,9 @@ __device__ __forceinline__ void project(const CamK& c, const Act& g, float lowpa
   p.py = c.fy * p.ty * p.iz + c.cy;
 }
 
+// NB = (sh_degree + 1)^2 is a template argument so that the coefficient
+// loads carry no per-coefficient branch and are all in flight together.
+template <int NB>
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __restrict__ means,
                                                     const float* __restrict__ log_scales,
                                                     const float* __restrict__ quats,
@@ -197,7 +200,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __re
     return;
   }
 
-  const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
   const float inv_tile = 1.0f / (float)a.tile;
 
   for (int v = 0; v < a.n_views; ++v) {
@@ -238,15 +240,16 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __re
           dx *= dinv;
           dy *= dinv;
           dz *= dinv;
+          float coef[NB * 3];
+#pragma unroll
+          for (int k = 0; k < NB * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
           float Y[16];
           sh_basis(dx, dy, dz, Y);
           float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            if (k < nb) {
+          for (int k = 0; k < NB; ++k) {
 #pragma unroll
-              for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * sh[(int64_t)(k * 3 + ch) * n + i];
-            }
+            for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * coef[k * 3 + ch];
           }
           const float rgb[3] = {0.5f + acc[0], 0.5f + acc[1], 0.5f + acc[2]};
           if (finite(rgb[0]) && finite(rgb[1]) && finite(rgb[2])) {
@@ -511,8 +514,23 @@ hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_s
   if (a.n == 0) return hipSuccess;
   const int block = 256;
   const int64_t grid = (a.n + block - 1) / block;
-  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(block), 0, stream, a, g.means,
-                     g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+  switch (a.sh_degree) {
+    case 0:
+      hipLaunchKernelGGL(k_preprocess<1>, dim3((unsigned)grid), dim3(block), 0, stream, a,
+                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_preprocess<4>, dim3((unsigned)grid), dim3(block), 0, stream, a,
+                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_preprocess<9>, dim3((unsigned)grid), dim3(block), 0, stream, a,
+                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      break;
+    default:
+      hipLaunchKernelGGL(k_preprocess<16>, dim3((unsigned)grid), dim3(block), 0, stream, a,
+                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+  }
   return hipGetLastError();
 }
 
