@@ -193,10 +193,12 @@ def run_form(name, form, cams, steps, warmup):
     mean = lambda xs: sum(xs) / len(xs)
     evals = mean([c[0] + c[2] for c in cnt])  # per-pixel evaluations + leader tests
     blends = mean([c[1] for c in cnt])
+    need = mean([c[4] + c[2] for c in cnt])  # evaluations left to the culled kernel
     ms = 1000.0 * wall / steps
     out = dict(fps=1000.0 / ms, ms_per_frame=ms, stage_ms=stage, capacity=capacity,
                pairs=mean(pairs), visible=mean(vis), active=mean(act),
-               evals=evals, blends=blends,
+               evals=evals, blends=blends, evals_needed=need,
+               block_visits=mean([c[5] for c in cnt]),
                leader_tests=mean([c[2] for c in cnt]), leader_pass=mean([c[3] for c in cnt]),
                views_counted=k)
     log(f"[bench] {name}: {out['fps']:.1f} fps ({ms:.3f} ms/frame) stages="
@@ -443,26 +445,32 @@ def main():
         batched = {m: run_batched(2_000_000, 64, m) for m in ("plain", "contrib")}
         log(f"[bench] t+{time.time() - t_start:.0f}s batched done")
     head = results.get("plain") or results[names[0]]
-    # roofline of the dominant kernel of the headline form
     st = head["stage_ms"]
-    dom = max(st, key=st.get)
-    if dom == "raster":
-        ops = head["evals"] * OPS_EVAL + head["blends"] * OPS_BLEND
-        ach = ops / (st["raster"] * 1e-3) / 1e12
-        roof = dict(bound="alu", kernel="raster_fwd", achieved=ach, peak=PEAK_LANE_OPS / 1e12,
-                    unit="Tlane-op/s", frac=ach / (PEAK_LANE_OPS / 1e12),
+    # Per-stage rooflines.  The rasterizer is priced on the evaluations its
+    # culled loop must do (live pixels x records that can reach their 8x8
+    # block) and the blends; preprocessing and binning on their algorithmic
+    # HBM bytes (binning is a pipeline of ~30 kernels).
+    r_ops = head["evals_needed"] * OPS_EVAL + head["blends"] * OPS_BLEND
+    r_ach = r_ops / (st["raster"] * 1e-3) / 1e12
+    p_bytes = 48 * head["active"] + 240 * head["visible"]
+    p_ach = p_bytes / (st["preprocess"] * 1e-3) / 1e9
+    b_bytes = 16 * head["visible"] + 4 * head["pairs"] + 8 * 8160
+    b_ach = b_bytes / (st["bin_sort"] * 1e-3) / 1e9
+    stage_roof = {
+        "raster": dict(bound="alu", achieved=r_ach, peak=PEAK_LANE_OPS / 1e12,
+                       unit="Tlane-op/s", frac=r_ach / (PEAK_LANE_OPS / 1e12)),
+        "preprocess": dict(bound="hbm", achieved=p_ach, peak=PEAK_HBM / 1e9, unit="GB/s",
+                           frac=p_ach / (PEAK_HBM / 1e9)),
+        "bin_sort": dict(bound="hbm", achieved=b_ach, peak=PEAK_HBM / 1e9, unit="GB/s",
+                         frac=b_ach / (PEAK_HBM / 1e9)),
+    }
+    # the dominant single kernel: the rasterizer or the preprocessing kernel
+    if st["raster"] >= st["preprocess"]:
+        roof = dict(stage_roof["raster"], kernel="raster_fwd",
                     traffic=measured_traffic("raster_fwd_plain_c2_1080p_3M"),
                     traffic_unit="bytes/launch")
-    elif dom == "bin_sort":
-        byts = 16 * head["visible"] + 4 * head["pairs"] + 8 * 8160
-        ach = byts / (st["bin_sort"] * 1e-3) / 1e9
-        roof = dict(bound="hbm", kernel="bin_sort", achieved=ach, peak=PEAK_HBM / 1e9,
-                    unit="GB/s", frac=ach / (PEAK_HBM / 1e9), traffic=None)
     else:
-        byts = 48 * head["active"] + 240 * head["visible"]
-        ach = byts / (st["preprocess"] * 1e-3) / 1e9
-        roof = dict(bound="hbm", kernel="preprocess", achieved=ach, peak=PEAK_HBM / 1e9,
-                    unit="GB/s", frac=ach / (PEAK_HBM / 1e9), traffic=None)
+        roof = dict(stage_roof["preprocess"], kernel="preprocess", traffic=None)
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
@@ -491,6 +499,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batched_64_views": batched,
         "roofline": roof,
+        "stage_roofline": stage_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

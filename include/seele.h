@@ -216,13 +216,20 @@ int32_t seele_rasterize_fwd_queue(const seele_splat* splats, const uint32_t* sor
                                   float* final_T, int32_t* n_contrib, void* stream);
 
 /* seele_rasterize_fwd with work counters (an instrumented, slower kernel
- * that writes the same outputs).  counters: device [4] uint64, overwritten:
+ * that visits every record of every tile list and writes the same outputs).
+ * counters: device [6] uint64, overwritten:
  *   [0] per-pixel alpha evaluations by pixels that have not stopped
  *       (contribution-aware form: only in groups whose leader accepted),
  *   [1] blends (Gaussians accumulated into a pixel),
  *   [2] leader tests of groups with a pixel that has not stopped,
  *   [3] of those, tests that accepted the Gaussian.
- * These are the algorithmic work units of Eqs. 1-2 and Algorithm 1. */
+ * [0]-[3] are the algorithmic work units of Eqs. 1-2 and Algorithm 1.  The
+ * production kernels skip, per 8x8 pixel block, the records whose
+ * alpha >= alpha_min region cannot reach the block (exactly: those records
+ * blend into none of its pixels); the work they are left with is
+ *   [4] the evaluations of [0] on records that can reach the pixel's block,
+ *   [5] (8x8 block, record) visits of such records while the block has a
+ *       pixel that has not stopped. */
 int32_t seele_rasterize_fwd_counted(const seele_splat* splats, const uint32_t* sorted_ids,
                                     const int32_t* tile_ranges, const seele_camera* cams,
                                     int32_t n_views, const seele_raster_opts* opts, float* image,

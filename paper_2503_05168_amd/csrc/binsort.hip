@@ -78,6 +78,17 @@ __device__ __forceinline__ Rect rect_of(const seele_splat& s, const BinView& bv)
   return r;
 }
 
+// View of record id = view * n + i: id / n < n_views <= 256, so a float
+// reciprocal estimate is off by at most one and one correction makes it exact.
+__device__ __forceinline__ uint32_t view_of(uint32_t id, const BinViews& views) {
+  if (views.n_views == 1) return 0u;
+  const uint64_t n = (uint64_t)views.n;
+  uint32_t q = (uint32_t)((float)id * __builtin_amdgcn_rcpf((float)n));
+  if ((uint64_t)q * n > id) --q;
+  else if ((uint64_t)(q + 1) * n <= id) ++q;
+  return q;
+}
+
 __device__ __forceinline__ uint32_t st_count(const Rect& r) {
   if (r.x1 <= r.x0 || r.y1 <= r.y0) return 0u;
   return ((r.x1 - 1) / ST - r.x0 / ST + 1) * ((r.y1 - 1) / ST - r.y0 / ST + 1);
@@ -117,25 +128,23 @@ __device__ __forceinline__ uint32_t clip_mask(uint32_t clip) {
   return (xm * 0x1111u) & rows;
 }
 
-// ---- visible-record compaction: count per block, scan, then write (depth, id)
+// ---- visible-record compaction.  Wave w of block b owns records
+// [b*TILE + w*kWaveSpan, +kWaveSpan): per-wave counts, one scan, then each
+// wave writes its (depth, id) pairs independently (ballot ranks).
+constexpr int kWaveSpan = TILE / WAVES;
+
 __global__ __launch_bounds__(B) void k_vis_count(const int32_t* __restrict__ n_tiles, int64_t n,
                                                   uint64_t* __restrict__ partial) {
-  const int64_t begin = (int64_t)blockIdx.x * TILE;
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
   uint32_t c = 0;
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const int64_t idx = begin + it * B + threadIdx.x;
+  for (int it = 0; it < kWaveSpan / 64; ++it) {
+    const int64_t idx = begin + it * 64 + lane;
     if (idx < n && n_tiles[idx] > 0) ++c;
   }
-  __shared__ uint32_t s[WAVES];
   c = wave_sum(c);
-  if (lane_id() == 0) s[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < WAVES; ++w) t += s[w];
-    partial[blockIdx.x] = t;
-  }
+  if (lane == 0) partial[(int64_t)blockIdx.x * WAVES + w] = c;
 }
 
 // Exclusive scan of nb partial sums in place by one block; the total goes to
@@ -176,21 +185,22 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
                                                     const uint64_t* __restrict__ partial,
                                                     uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
-  __shared__ uint32_t s[WAVES + 1];
-  const int64_t begin = (int64_t)blockIdx.x * TILE;
-  uint32_t carry = (uint32_t)partial[blockIdx.x];
-#pragma unroll 1
-  for (int it = 0; it < ITEMS; ++it) {
-    const int64_t idx = begin + it * B + threadIdx.x;
-    const uint32_t f = (idx < n && n_tiles[idx] > 0) ? 1u : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(f, s, tot);
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
+  if (begin >= n) return;  // per wave; no barriers below
+  uint32_t carry = (uint32_t)partial[(int64_t)blockIdx.x * WAVES + w];
+  const uint64_t lt = lanemask_lt();
+#pragma unroll 4
+  for (int it = 0; it < kWaveSpan / 64; ++it) {
+    const int64_t idx = begin + it * 64 + lane;
+    const bool f = idx < n && n_tiles[idx] > 0;
+    const uint64_t bal = __ballot(f);
     if (f) {
-      const uint32_t pos = carry + ex;
+      const uint32_t pos = carry + (uint32_t)__popcll(bal & lt);
       keys[pos] = __float_as_uint(splats[idx].depth);
       vals[pos] = (uint32_t)idx;
     }
-    carry += tot;
+    carry += (uint32_t)__popcll(bal);
   }
 }
 
@@ -370,7 +380,8 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
 
 // ---- super-tile entries of the depth-ordered records
 // Per record: its clipped rectangle (kept for the emission), pairs (tiles of
-// the rectangle) and entries (super-tiles it touches); block sums of both.
+// the rectangle) and entries (super-tiles it touches); per-wave sums of both
+// over the same wave spans as the compaction.
 __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ ids,
                                                    const seele_splat* __restrict__ splats,
                                                    BinViews views, const Hdr* __restrict__ hdr,
@@ -378,17 +389,18 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
                                                    uint32_t* __restrict__ ry_s,
                                                    uint64_t* __restrict__ partial,
                                                    uint64_t* __restrict__ partial2) {
+  const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nv = hdr->n_vis;
-  const int64_t begin = (int64_t)blockIdx.x * TILE;
+  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
   uint64_t c = 0, q = 0;
   const uint32_t n = (uint32_t)views.n;
   if (begin < nv) {
 #pragma unroll 4
-    for (int it = 0; it < ITEMS; ++it) {
-      const int64_t i = begin + it * B + threadIdx.x;
+    for (int it = 0; it < kWaveSpan / 64; ++it) {
+      const int64_t i = begin + it * 64 + lane;
       if (i < nv) {
         const uint32_t id = ids[i];
-        const Rect r = rect_of(splats[id], views.v[id / n]);
+        const Rect r = rect_of(splats[id], views.v[view_of(id, views)]);
         const uint32_t m = st_count(r);
         if (m > 0) c += (uint64_t)(r.x1 - r.x0) * (r.y1 - r.y0);
         rx_s[i] = r.x0 | (r.x1 << 16);
@@ -397,30 +409,30 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
       }
     }
   }
-  __shared__ uint64_t s[2][WAVES];
   c = wave_sum(c);
   q = wave_sum(q);
-  if (lane_id() == 0) {
-    s[0][threadIdx.x >> 6] = c;
-    s[1][threadIdx.x >> 6] = q;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t = 0, u = 0;
-    for (int w = 0; w < WAVES; ++w) {
-      t += s[0][w];
-      u += s[1][w];
-    }
-    partial[blockIdx.x] = t;
-    partial2[blockIdx.x] = u;
+  if (lane == 0) {
+    partial[(int64_t)blockIdx.x * WAVES + w] = c;
+    partial2[(int64_t)blockIdx.x * WAVES + w] = q;
   }
 }
 
 // Entry k (row-major over the covered super-tiles) of a record with tile
-// rectangle r: key = clipped rectangle << 24 | global super-tile.
+// rectangle r: key = clipped rectangle << 24 | global super-tile.  For
+// k < 2^22 a float quotient estimate is within one of k / sw and is corrected
+// once; larger k divide exactly.
 __device__ __forceinline__ uint32_t entry_key(const Rect& r, uint32_t k, uint32_t sw, uint32_t sgw,
                                               uint32_t st_base) {
-  const uint32_t dy = k / sw, dx = k - dy * sw;
+  uint32_t dy;
+  if (k < (1u << 22)) {
+    dy = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)sw));
+    const int32_t rem = (int32_t)(k - dy * sw);
+    if (rem < 0) --dy;
+    else if (rem >= (int32_t)sw) ++dy;
+  } else {
+    dy = k / sw;
+  }
+  const uint32_t dx = k - dy * sw;
   const uint32_t sx = r.x0 / ST + dx, sy = r.y0 / ST + dy;
   const uint32_t ox = sx * ST, oy = sy * ST;
   const uint32_t clip = (max(r.x0, ox) - ox) | (min(r.x1, ox + ST) - 1u - ox) << 2 |
@@ -442,16 +454,15 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
                                                    const uint64_t* __restrict__ partial,
                                                    int64_t capacity, uint32_t* __restrict__ ekeys,
                                                    uint32_t* __restrict__ evals) {
-  __shared__ uint64_t s[WAVES + 1];
+  const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nv = hdr->n_vis;
-  const int64_t begin = (int64_t)blockIdx.x * TILE;
-  if (begin >= nv || hdr->p_total > (uint64_t)capacity) return;  // uniform per block
+  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
+  if (begin >= nv || hdr->p_total > (uint64_t)capacity) return;  // per wave; no barriers
   const uint32_t n = (uint32_t)views.n;
-  const int lane = lane_id();
-  uint64_t carry = partial[blockIdx.x];
+  uint64_t carry = partial[(int64_t)blockIdx.x * WAVES + w];
 #pragma unroll 1
-  for (int it = 0; it < ITEMS; ++it) {
-    const int64_t i = begin + it * B + threadIdx.x;
+  for (int it = 0; it < kWaveSpan / 64; ++it) {
+    const int64_t i = begin + it * 64 + lane;
     Rect r{0u, 0u, 0u, 0u};
     uint32_t id = 0;
     if (i < nv) {
@@ -463,20 +474,28 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
       r.y1 = ry >> 16;
     }
     const uint32_t m = st_count(r);
-    uint64_t tot;
-    const uint64_t off = carry + block_exclusive_scan<uint64_t>((uint64_t)m, s, tot);
-    carry += tot;
+    const uint32_t inc = wave_inclusive_scan(m);
+    const uint64_t off = carry + (inc - m);
+    carry += __builtin_amdgcn_readlane(inc, 63);
     uint32_t sgw = 0, stb = 0, sw = 1;
     if (m > 0) {
-      const BinView bv = views.v[id / n];
+      const BinView bv = views.v[view_of(id, views)];
       sgw = ((uint32_t)bv.grid_w + ST - 1) / ST;
       stb = (uint32_t)bv.st_base;
       sw = (r.x1 - 1) / ST - r.x0 / ST + 1;
     }
     if (m > 0 && m <= kLaneEntries) {
-      for (uint32_t k = 0; k < m; ++k) {
-        ekeys[off + k] = entry_key(r, k, sw, sgw, stb);
-        evals[off + k] = id;
+      // row-major walk of the covered super-tiles (no division)
+      uint64_t o = off;
+      for (uint32_t sy = r.y0 / ST; sy <= (r.y1 - 1) / ST; ++sy) {
+        const uint32_t oy = sy * ST;
+        const uint32_t cy = (max(r.y0, oy) - oy) << 4 | (min(r.y1, oy + ST) - 1u - oy) << 6;
+        for (uint32_t sx = r.x0 / ST; sx <= (r.x1 - 1) / ST; ++sx, ++o) {
+          const uint32_t ox = sx * ST;
+          const uint32_t clip = cy | (max(r.x0, ox) - ox) | (min(r.x1, ox + ST) - 1u - ox) << 2;
+          ekeys[o] = (clip << kClipShift) | (stb + sy * sgw + sx);
+          evals[o] = id;
+        }
       }
     }
     uint64_t big = __ballot(m > kLaneEntries);
@@ -823,8 +842,8 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.max_seg = max_segments(capacity, p.max_st);
   const int64_t nb_rec = std::max<int64_t>(nblocks_for(n_records), 1);
   const int64_t nb_hist = std::max<int64_t>({nb_rec, nblocks_for(capacity), 1});
-  const int64_t nb_part =
-      std::max<int64_t>({nb_rec, nblocks_for(p.max_st), nblocks_for(n_tiles_total), 1});
+  const int64_t nb_part = std::max<int64_t>(
+      {WAVES * nb_rec, nblocks_for(p.max_st), nblocks_for(n_tiles_total), 1});
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -833,7 +852,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   };
   p.off_hdr = take(sizeof(Hdr));
   p.off_partial = take(8 * (size_t)nb_part);
-  p.off_partial2 = take(8 * (size_t)nb_rec);
+  p.off_partial2 = take(8 * WAVES * (size_t)nb_rec);
   p.off_dkeys0 = take(4 * (size_t)n_records);
   p.off_dkeys1 = take(4 * (size_t)n_records);
   p.off_dvals0 = take(4 * (size_t)n_records);
@@ -892,7 +911,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   if (nbR > 0) {
     // 1. visible records (n_tiles > 0) in id order with their depth keys
     hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, (int64_t)nbR, hdr, 0,
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, WAVES * (int64_t)nbR,
+                       hdr, 0,
                        p.capacity, num_pairs);
     hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats, partial,
                        dk[0], dv[0]);
@@ -908,9 +928,11 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], splats, views, hdr,
                        rx_s, ry_s, partial, partial2);
   }
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, (int64_t)nbR, hdr, 1,
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, WAVES * (int64_t)nbR,
+                     hdr, 1,
                      p.capacity, num_pairs);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial2, (int64_t)nbR, hdr, 2,
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial2, WAVES * (int64_t)nbR,
+                     hdr, 2,
                      p.capacity, num_pairs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   //    entries, then sorted by super-tile id (balanced digit widths <= 8); the

@@ -75,7 +75,10 @@ __device__ __forceinline__ bool blend_step(float fx, float fy, const float4& a, 
 // COUNT instantiations also accumulate the method's work counters:
 // [0] alpha evaluations by pixels that have not stopped (contribution-aware:
 // only in groups whose leader accepted), [1] blends, [2] leader tests of
-// groups holding a live pixel, [3] of those, acceptances.
+// groups holding a live pixel, [3] of those, acceptances; and the work left
+// to the culled kernels: [4] evaluations of [0] on records whose block bit is
+// set, [5] (wave, record) visits with the bit set while the wave has a live
+// pixel.
 // The tile list is consumed in LDS batches of BATCH records (<= TS*TS: threads
 // tid < BATCH stage one record each); BATCH trades barrier and early-exit
 // granularity against LDS latency and is chosen by the autotuner.
@@ -95,10 +98,10 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   __shared__ LdsRec s_rec[BATCH];
   __shared__ uint8_t s_qm[BATCH];
   __shared__ uint8_t s_list[NW][64];
-  __shared__ unsigned long long s_cnt[4];
-  uint32_t c_eval = 0, c_blend = 0, c_ltest = 0, c_lpass = 0;
+  __shared__ unsigned long long s_cnt[6];
+  uint32_t c_eval = 0, c_blend = 0, c_ltest = 0, c_lpass = 0, c_need = 0, c_visit = 0;
   if (COUNT) {
-    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 6) s_cnt[threadIdx.x] = 0;
   }
 
   int v = 0;
@@ -143,17 +146,19 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
       s_rec[tid].a = make_float4(A.x, A.y, L.l11, L.l21);
       s_rec[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
       s_rec[tid].blue = blue;
-      if (!COUNT)
-        s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin,
-                                           tile_x * TS, tile_y * TS);
+      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin, tile_x * TS,
+                                         tile_y * TS);
     }
     __syncthreads();
     const int cnt = min(BATCH, n - base);
     if (COUNT && MODE == 0) {
       for (int k = 0; k < cnt; ++k) {
         if (__ballot(T >= 0.0f) == 0) break;
+        const bool bit = (s_qm[k] >> wave) & 1u;
+        if (bit && lane == 0) ++c_visit;
         if (T >= 0.0f) {
           ++c_eval;
+          if (bit) ++c_need;
           if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
                          amax, tmin, T, c0, c1, c2, last))
             ++c_blend;
@@ -177,11 +182,13 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
           if (lane == 0) {
             c_ltest += (uint32_t)__popcll(glive);
             c_lpass += (uint32_t)__popcll(glive & gm);
+            if ((s_qm[k0 + s] >> wave) & 1u) ++c_visit;
           }
           if (gm == 0) continue;
           if (T >= 0.0f && ((gm >> grp) & 1ull)) {
             const int k = k0 + s;
             ++c_eval;
+            ++c_need;
             if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
                            amax, tmin, T, c0, c1, c2, last))
               ++c_blend;
@@ -261,8 +268,10 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
     atomicAdd(&s_cnt[1], (unsigned long long)c_blend);
     atomicAdd(&s_cnt[2], (unsigned long long)c_ltest);
     atomicAdd(&s_cnt[3], (unsigned long long)c_lpass);
+    atomicAdd(&s_cnt[4], (unsigned long long)c_need);
+    atomicAdd(&s_cnt[5], (unsigned long long)c_visit);
     __syncthreads();
-    if (threadIdx.x < 4) atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]);
+    if (threadIdx.x < 6) atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]);
   }
 
   if (inside) {

@@ -357,7 +357,7 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
   if (cnt) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 4);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cnt, 6);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "counter reset");
   }

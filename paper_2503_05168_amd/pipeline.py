@@ -203,14 +203,14 @@ def seele_rasterize_fwd_queue(splats, sorted_ids, tile_ranges, cams, settings: S
 
 def seele_rasterize_fwd_counted(splats, sorted_ids, tile_ranges, cams, settings: Settings,
                                 counters=None, stream=None):
-    """Instrumented forward: same outputs plus the four work counters."""
+    """Instrumented forward: same outputs plus the six work counters."""
     dev = tile_ranges.device
     npix = pixel_count(cams)
     image = torch.empty(3 * npix, dtype=torch.float32, device=dev)
     final_T = torch.empty(npix, dtype=torch.float32, device=dev)
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
     if counters is None:
-        counters = torch.empty(4, dtype=torch.int64, device=dev)
+        counters = torch.empty(6, dtype=torch.int64, device=dev)
     opts = settings.raster_opts()
     st = A.lib().seele_rasterize_fwd_counted(_p(splats), _p(sorted_ids), _p(tile_ranges),
                                              A.camera_array(cams), len(cams), ctypes.byref(opts),

@@ -121,10 +121,14 @@ def _check_counters(f, cams, settings, v, oc, n_border):
     want = [oc["evals"] if settings.mode == "plain" else oc["pass_evals"], oc["blends"],
             oc["leader_tests"], oc["leader_pass"]]
     if n_border == 0:
-        assert got == want, (got, want)
+        assert got[:4] == want, (got, want)
     else:
         for g_, w_ in zip(got, want):
             assert abs(g_ - w_) <= max(2, 1e-3 * w_), (got, want)
+    # the culled kernels' share: a subset of the method's evaluations, and for
+    # the contribution-aware form all of them (no accepted group is culled)
+    assert got[4] <= got[0] and (settings.mode == "plain" or got[4] == got[0])
+    assert got[1] <= got[4] and 0 < got[5] or got[0] == 0
 
 
 CASES = [
