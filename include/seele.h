@@ -174,7 +174,8 @@ size_t seele_bin_sort_workspace_size(int64_t n_records, int64_t capacity, int64_
  * If that number exceeds `capacity`, every tile range is written empty and
  * sorted_ids is not written; the caller reads num_pairs, grows the buffer
  * and calls again (the call itself still returns SEELE_OK because the count
- * is only known on the device).  capacity < 2^31.  n_views <= 256. */
+ * is only known on the device).  capacity < 2^31.  n_views <= 256; at most
+ * 2^24 super-tiles (blocks of 4 x 4 tiles) over all views. */
 int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
                        const seele_camera* cams, int32_t n_views, int32_t tile,
                        void* workspace, size_t workspace_bytes, uint32_t* sorted_ids,

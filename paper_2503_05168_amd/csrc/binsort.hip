@@ -155,14 +155,25 @@ __global__ __launch_bounds__(B) void k_scan_partials(uint64_t* __restrict__ part
                                                       Hdr* __restrict__ hdr, int mode,
                                                       int64_t capacity,
                                                       int64_t* __restrict__ num_pairs) {
+  constexpr int R = 16;  // consecutive partials per thread
   __shared__ uint64_t s[WAVES + 1];
   uint64_t carry = 0;
-  for (int64_t base = 0; base < nb; base += B) {
-    const int64_t idx = base + threadIdx.x;
-    const uint64_t x = idx < nb ? partial[idx] : 0;
+  for (int64_t base = 0; base < nb; base += B * R) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * R;
+    uint64_t v[R];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = i0 + r < nb ? partial[i0 + r] : 0;
+      sum += v[r];
+    }
     uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(x, s, tot);
-    if (idx < nb) partial[idx] = carry + ex;
+    uint64_t run = carry + block_exclusive_scan<uint64_t>(sum, s, tot);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (i0 + r < nb) partial[i0 + r] = run;
+      run += v[r];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) {
@@ -393,7 +404,6 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
   const uint32_t nv = hdr->n_vis;
   const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
   uint64_t c = 0, q = 0;
-  const uint32_t n = (uint32_t)views.n;
   if (begin < nv) {
 #pragma unroll 4
     for (int it = 0; it < kWaveSpan / 64; ++it) {
@@ -441,10 +451,15 @@ __device__ __forceinline__ uint32_t entry_key(const Rect& r, uint32_t k, uint32_
 }
 
 // Emit the entries of every depth-ordered record at its offset (exclusive
-// scan of entry counts), value = record id.  A record with few entries is
-// emitted by its own lane; a larger one (a Gaussian spanning much of the
-// image) by the whole wave, 64 entries per step.  Skipped when the frame
+// scan of entry counts), value = record id.  Each wave handles 64 records at
+// a time; their entries form one contiguous output range.  When that range
+// fits the wave's LDS map (kStage entries), every record marks its entries'
+// positions with its lane, and the wave then writes the range in order, 64
+// consecutive entries per store (each lane computing the entry it writes from
+// its owner's rectangle).  Otherwise a record with few entries is emitted by
+// its own lane and a larger one by the whole wave.  Skipped when the frame
 // overflows the pair capacity.
+constexpr uint32_t kStage = 1024;
 constexpr uint32_t kLaneEntries = 8;
 
 __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ ids,
@@ -454,11 +469,11 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
                                                    const uint64_t* __restrict__ partial,
                                                    int64_t capacity, uint32_t* __restrict__ ekeys,
                                                    uint32_t* __restrict__ evals) {
+  __shared__ uint8_t s_own[WAVES][kStage];
   const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nv = hdr->n_vis;
   const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
   if (begin >= nv || hdr->p_total > (uint64_t)capacity) return;  // per wave; no barriers
-  const uint32_t n = (uint32_t)views.n;
   uint64_t carry = partial[(int64_t)blockIdx.x * WAVES + w];
 #pragma unroll 1
   for (int it = 0; it < kWaveSpan / 64; ++it) {
@@ -475,14 +490,41 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
     }
     const uint32_t m = st_count(r);
     const uint32_t inc = wave_inclusive_scan(m);
-    const uint64_t off = carry + (inc - m);
-    carry += __builtin_amdgcn_readlane(inc, 63);
+    const uint32_t rel = inc - m;
+    const uint64_t base = carry;
+    const uint64_t off = base + rel;
+    const uint32_t total = __builtin_amdgcn_readlane(inc, 63);
+    carry += total;
     uint32_t sgw = 0, stb = 0, sw = 1;
     if (m > 0) {
       const BinView bv = views.v[view_of(id, views)];
       sgw = ((uint32_t)bv.grid_w + ST - 1) / ST;
       stb = (uint32_t)bv.st_base;
       sw = (r.x1 - 1) / ST - r.x0 / ST + 1;
+    }
+    if (total <= kStage) {
+      // owner map, then ordered coalesced stores
+      for (uint32_t k = 0; k < m; ++k) s_own[w][rel + k] = (uint8_t)lane;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t rxp = r.x0 | (r.x1 << 16), ryp = r.y0 | (r.y1 << 16);
+      const uint32_t swg = sw | (sgw << 16);
+      for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        const int o = j < total ? (int)s_own[w][j] : 0;
+        const uint32_t ro = __shfl(rel, o, 64);
+        const uint32_t rxo = __shfl(rxp, o, 64), ryo = __shfl(ryp, o, 64);
+        const uint32_t swgo = __shfl(swg, o, 64), stbo = __shfl(stb, o, 64);
+        const uint32_t ido = __shfl(id, o, 64);
+        if (j < total) {
+          const Rect ro_r{rxo & 0xffffu, rxo >> 16, ryo & 0xffffu, ryo >> 16};
+          ekeys[base + j] = entry_key(ro_r, j - ro, swgo & 0xffffu, swgo >> 16, stbo);
+          evals[base + j] = ido;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();  // map reads finish before the next group's writes
+      continue;
     }
     if (m > 0 && m <= kLaneEntries) {
       // row-major walk of the covered super-tiles (no division)
@@ -912,8 +954,7 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     // 1. visible records (n_tiles > 0) in id order with their depth keys
     hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, WAVES * (int64_t)nbR,
-                       hdr, 0,
-                       p.capacity, num_pairs);
+                       hdr, 0, p.capacity, num_pairs);
     hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats, partial,
                        dk[0], dv[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -929,11 +970,9 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
                        rx_s, ry_s, partial, partial2);
   }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, WAVES * (int64_t)nbR,
-                     hdr, 1,
-                     p.capacity, num_pairs);
+                     hdr, 1, p.capacity, num_pairs);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial2, WAVES * (int64_t)nbR,
-                     hdr, 2,
-                     p.capacity, num_pairs);
+                     hdr, 2, p.capacity, num_pairs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   //    entries, then sorted by super-tile id (balanced digit widths <= 8); the
   //    value buffers alternate between svals0 and sorted_ids so that the last

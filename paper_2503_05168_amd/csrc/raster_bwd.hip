@@ -30,6 +30,26 @@ struct LdsBwd {
   float4 c;  // blue, conic a, conic b, conic c
 };
 
+// Sum of x over the 64 lanes of a wave, returned to every lane: inclusive
+// row sums by DPP row shifts (1, 2, 4, 8 within each 16-lane row), then the
+// row totals carried across rows by the row broadcasts of lanes 15 and 31,
+// so lane 63 holds the total.  Masked or out-of-row source lanes add 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_shifted(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf,
+                                                    false));
+}
+
+__device__ __forceinline__ float wave_total(float x) {
+  x += dpp_shifted<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_shifted<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_shifted<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_shifted<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_shifted<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_shifted<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
 // One record of the reverse walk for one pixel: recompute alpha, undo the
 // blend (T, S) if the forward blended it, and add the record's 2D gradients
 // (reduced over the wave) to its gradient slots.
@@ -56,10 +76,11 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, uint32_t id, bool ne
   if (blended) {
     const float4 cc = e.c;
     const float om = 1.0f - alpha;
-    const float Tj = T / om;
+    const float rom = __builtin_amdgcn_rcpf(om);  // 1 - alpha >= 1 - alpha_max > 0
+    const float Tj = T * rom;
     const float ta = Tj * alpha;
-    const float dal = g0 * (Tj * b.z - S0 / om) + g1 * (Tj * b.w - S1 / om) +
-                      g2 * (Tj * cc.x - S2 / om);
+    const float dal = g0 * (Tj * b.z - S0 * rom) + g1 * (Tj * b.w - S1 * rom) +
+                      g2 * (Tj * cc.x - S2 * rom);
     gr = ta * g0;
     gg = ta * g1;
     gbl = ta * g2;
@@ -79,15 +100,15 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, uint32_t id, bool ne
     }
   }
   if (__ballot(blended) != 0) {
-    gmx = wave_sum(gmx);
-    gmy = wave_sum(gmy);
-    gca = wave_sum(gca);
-    gcb = wave_sum(gcb);
-    gcc = wave_sum(gcc);
-    gop = wave_sum(gop);
-    gr = wave_sum(gr);
-    gg = wave_sum(gg);
-    gbl = wave_sum(gbl);
+    gmx = wave_total(gmx);
+    gmy = wave_total(gmy);
+    gca = wave_total(gca);
+    gcb = wave_total(gcb);
+    gcc = wave_total(gcc);
+    gop = wave_total(gop);
+    gr = wave_total(gr);
+    gg = wave_total(gg);
+    gbl = wave_total(gbl);
     if (lane == 0) {
       float* dst = grad2d + (int64_t)id * 9;
       atomicAdd(dst + 0, gmx);
