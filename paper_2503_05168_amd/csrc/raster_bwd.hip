@@ -11,8 +11,9 @@
 //   dL/dalpha_j = sum_ch g_ch (T_j c_j - S / (1 - alpha_j))
 //   dL/dc_j = T_j alpha_j g
 // and through alpha = o exp(-q/2), q = d^T A d (zero where the alpha clamp
-// was active).  Per-Gaussian gradients are reduced across the wave and added
-// to the record's 9 gradient slots with float atomics.
+// was active).  Per-Gaussian gradients are reduced across the wave (DPP),
+// summed over the block's waves in LDS, and added to the record's 9 gradient
+// slots in HBM with one set of float atomics per tile.
 //
 // As in the forward kernels, each wave visits only the records whose culling
 // bit for its 8x8 block is set (quad_mask), and only those below the largest
@@ -52,13 +53,13 @@ __device__ __forceinline__ float wave_total(float x) {
 
 // One record of the reverse walk for one pixel: recompute alpha, undo the
 // blend (T, S) if the forward blended it, and add the record's 2D gradients
-// (reduced over the wave) to its gradient slots.
+// (reduced over the wave) to the record's LDS accumulator `acc` (9 floats,
+// shared by the block's waves and flushed to HBM once per batch).
 template <int MODE>
-__device__ __forceinline__ void blend_grad(const LdsBwd& e, uint32_t id, bool need, float fx,
-                                           float fy, int leader_lane, int lane, float amin,
-                                           float amax, float g0, float g1, float g2, float& T,
-                                           float& S0, float& S1, float& S2,
-                                           float* __restrict__ grad2d) {
+__device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx, float fy,
+                                           int leader_lane, int lane, float amin, float amax,
+                                           float g0, float g1, float g2, float& T, float& S0,
+                                           float& S1, float& S2, float* acc) {
   const float4 a = e.a, b = e.b;
   float dx, dy;
   const float p = splat_power(fx, fy, a.x, a.y, a.z, a.w, b.x, dx, dy);
@@ -110,16 +111,15 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, uint32_t id, bool ne
     gg = wave_total(gg);
     gbl = wave_total(gbl);
     if (lane == 0) {
-      float* dst = grad2d + (int64_t)id * 9;
-      atomicAdd(dst + 0, gmx);
-      atomicAdd(dst + 1, gmy);
-      atomicAdd(dst + 2, gca);
-      atomicAdd(dst + 3, gcb);
-      atomicAdd(dst + 4, gcc);
-      atomicAdd(dst + 5, gop);
-      atomicAdd(dst + 6, gr);
-      atomicAdd(dst + 7, gg);
-      atomicAdd(dst + 8, gbl);
+      atomicAdd(acc + 0, gmx);
+      atomicAdd(acc + 1, gmy);
+      atomicAdd(acc + 2, gca);
+      atomicAdd(acc + 3, gcb);
+      atomicAdd(acc + 4, gcc);
+      atomicAdd(acc + 5, gop);
+      atomicAdd(acc + 6, gr);
+      atomicAdd(acc + 7, gg);
+      atomicAdd(acc + 8, gbl);
     }
   }
 }
@@ -137,6 +137,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
   __shared__ LdsBwd s_e[NT];
   __shared__ uint32_t s_id[NT];
   __shared__ uint8_t s_qm[NT];
+  __shared__ float s_g[NT][9];  // per staged record: the block's 2D gradient sum
   __shared__ int s_max;
 
   const int gt = blockIdx.x;
@@ -199,6 +200,8 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       s_id[tid] = id;
       s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin, tile_x * TS,
                                          tile_y * TS);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.0f;
     }
     __syncthreads();
     // this wave's records of the batch, highest position first, 64 at a time
@@ -209,11 +212,20 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       while (bits != 0) {
         const int k = c + 63 - __builtin_clzll(bits);
         bits &= ~(1ull << (k - c));
-        blend_grad<MODE>(s_e[k], s_id[k], lo + k < last, fx, fy, leader_lane, lane, amin, amax,
-                         g0, g1, g2, T, S0, S1, S2, grad2d);
+        blend_grad<MODE>(s_e[k], lo + k < last, fx, fy, leader_lane, lane, amin, amax, g0, g1,
+                         g2, T, S0, S1, S2, s_g[k]);
       }
     }
     __syncthreads();
+    // one set of global atomics per record and tile
+    if (tid < hi - lo) {
+      float* dst = grad2d + (int64_t)s_id[tid] * 9;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float v = s_g[tid][q];
+        if (v != 0.0f) atomicAdd(dst + q, v);
+      }
+    }
   }
 }
 
