@@ -283,6 +283,8 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __re
 // precision (half the float32 vector rate on this GPU, on per-Gaussian work)
 // keeps its relative error at the float32 input's.
 
+// NB = (sh_degree + 1)^2: the coefficients are loaded once, for all views.
+template <int NB>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_color(
     PreArgs a, const float* __restrict__ means, const float* __restrict__ sh,
     const int32_t* __restrict__ n_tiles, const float* __restrict__ grad2d,
@@ -290,52 +292,55 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_color(
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
-  float gsh[48];
+  float gsh[NB * 3];
 #pragma unroll
-  for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
+  for (int k = 0; k < NB * 3; ++k) gsh[k] = 0.0f;
   float gm0 = 0.0f, gm1 = 0.0f, gm2 = 0.0f;
-  const float mx = means[i], my = means[n + i], mz = means[2 * n + i];
-  for (int v = 0; v < a.n_views; ++v) {
-    const int64_t rec = (a.view0 + v) * n + i;
-    if (n_tiles[rec] <= 0) continue;
-    const CamK& c = a.cam[v];
-    const float* G = grad2d + rec * 9;
-    const float gcol[3] = {G[6], G[7], G[8]};
-    const float vx = mx - c.C[0], vy = my - c.C[1], vz = mz - c.C[2];
-    const float dinv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
-    const float dx = vx * dinv, dy = vy * dinv, dz = vz * dinv;
-    float Y[16], Gx[16], Gy[16], Gz[16];
-    sh_basis(dx, dy, dz, Y);
-    sh_basis_grad(dx, dy, dz, Gx, Gy, Gz);
-    float acc[3] = {0.0f, 0.0f, 0.0f};
+  bool any = false;
+  for (int v = 0; v < a.n_views; ++v) any |= n_tiles[(a.view0 + v) * n + i] > 0;
+  if (any) {
+    float coef[NB * 3];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (k < nb)
+    for (int k = 0; k < NB * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
+    const float mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    for (int v = 0; v < a.n_views; ++v) {
+      const int64_t rec = (a.view0 + v) * n + i;
+      if (n_tiles[rec] <= 0) continue;
+      const CamK& c = a.cam[v];
+      const float* G = grad2d + rec * 9;
+      const float gcol[3] = {G[6], G[7], G[8]};
+      const float vx = mx - c.C[0], vy = my - c.C[1], vz = mz - c.C[2];
+      const float dinv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+      const float dx = vx * dinv, dy = vy * dinv, dz = vz * dinv;
+      float Y[16], Gx[16], Gy[16], Gz[16];
+      sh_basis(dx, dy, dz, Y);
+      sh_basis_grad(dx, dy, dz, Gx, Gy, Gz);
+      float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * sh[(int64_t)(k * 3 + ch) * n + i];
-    float graw[3];
+      for (int k = 0; k < NB; ++k)
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) graw[ch] = (0.5f + acc[ch]) > 0.0f ? gcol[ch] : 0.0f;
-    float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+        for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * coef[k * 3 + ch];
+      float graw[3];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (k < nb) {
+      for (int ch = 0; ch < 3; ++ch) graw[ch] = (0.5f + acc[ch]) > 0.0f ? gcol[ch] : 0.0f;
+      float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
         float t = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
           gsh[k * 3 + ch] += Y[k] * graw[ch];
-          t += graw[ch] * sh[(int64_t)(k * 3 + ch) * n + i];
+          t += graw[ch] * coef[k * 3 + ch];
         }
         gdx += t * Gx[k];
         gdy += t * Gy[k];
         gdz += t * Gz[k];
       }
+      const float dotd = dx * gdx + dy * gdy + dz * gdz;
+      gm0 += (gdx - dx * dotd) * dinv;
+      gm1 += (gdy - dy * dotd) * dinv;
+      gm2 += (gdz - dz * dotd) * dinv;
     }
-    const float dotd = dx * gdx + dy * gdy + dz * gdz;
-    gm0 += (gdx - dx * dotd) * dinv;
-    gm1 += (gdy - dy * dotd) * dinv;
-    gm2 += (gdz - dz * dotd) * dinv;
   }
   const float outm[3] = {gm0, gm1, gm2};
 #pragma unroll
@@ -343,10 +348,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_color(
     float* pm = g_means + k * n + i;
     *pm = accumulate ? *pm + outm[k] : outm[k];
   }
+  // coefficients above the degree get no gradient
 #pragma unroll
   for (int k = 0; k < 48; ++k) {
     float* ps = g_sh + (int64_t)k * n + i;
-    *ps = accumulate ? *ps + gsh[k] : gsh[k];
+    const float gk = k < NB * 3 ? gsh[k < NB * 3 ? k : 0] : 0.0f;
+    *ps = accumulate ? *ps + gk : gk;
   }
 }
 
@@ -541,8 +548,24 @@ hipError_t launch_preprocess_bwd(const PreArgs& a, const seele_gaussians& g,
   if (a.n == 0) return hipSuccess;
   const int block = 256;
   const int64_t grid = (a.n + block - 1) / block;
-  hipLaunchKernelGGL(k_preprocess_bwd_color, dim3((unsigned)grid), dim3(block), 0, stream, a,
-                     g.means, g.sh, n_tiles, grad2d, out.means, out.sh, accumulate ? 1 : 0);
+  const int acc = accumulate ? 1 : 0;
+  switch (a.sh_degree) {
+    case 0:
+      hipLaunchKernelGGL(k_preprocess_bwd_color<1>, dim3((unsigned)grid), dim3(block), 0, stream,
+                         a, g.means, g.sh, n_tiles, grad2d, out.means, out.sh, acc);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_preprocess_bwd_color<4>, dim3((unsigned)grid), dim3(block), 0, stream,
+                         a, g.means, g.sh, n_tiles, grad2d, out.means, out.sh, acc);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_preprocess_bwd_color<9>, dim3((unsigned)grid), dim3(block), 0, stream,
+                         a, g.means, g.sh, n_tiles, grad2d, out.means, out.sh, acc);
+      break;
+    default:
+      hipLaunchKernelGGL(k_preprocess_bwd_color<16>, dim3((unsigned)grid), dim3(block), 0, stream,
+                         a, g.means, g.sh, n_tiles, grad2d, out.means, out.sh, acc);
+  }
   hipLaunchKernelGGL(k_preprocess_bwd_geom, dim3((unsigned)grid), dim3(block), 0, stream, a,
                      g.means, g.log_scales, g.quats, g.opacity_logits, n_tiles, grad2d, out.means,
                      out.log_scales, out.quats, out.opacity_logits, accumulate ? 1 : 0);

@@ -51,6 +51,47 @@ __device__ __forceinline__ float wave_total(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// Add the wave sums of nine per-lane values to acc[0..8] (LDS).  Eight of
+// them are reduced transposed: a 32-lane swap pairs v0/v1, v2/v3, ... so that
+// one register holds half-sums of one value in lanes 0-31 and of the other
+// in lanes 32-63; a 16-lane swap then leaves each 16-lane row of a register
+// with quarter-sums of a single value; row shifts finish each row, and the
+// last lane of each row adds its value's total.  The ninth takes the plain
+// DPP reduction.
+__device__ __forceinline__ float row_total(float x) {
+  x += dpp_shifted<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_shifted<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_shifted<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_shifted<0x118, 0xf>(x);  // row_shr:8
+  return x;                         // lane 15 of each row: the row's sum
+}
+
+__device__ __forceinline__ float pair_half(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float pair_quarter(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void wave_accumulate9(const float (&v)[9], float* acc, int lane) {
+  // rows of t0: v0, v2, v1, v3; rows of t1: v4, v6, v5, v7
+  const float t0 = row_total(pair_quarter(pair_half(v[0], v[1]), pair_half(v[2], v[3])));
+  const float t1 = row_total(pair_quarter(pair_half(v[4], v[5]), pair_half(v[6], v[7])));
+  const float t8 = wave_total(v[8]);
+  if ((lane & 15) == 15) {
+    const int row = lane >> 4;
+    const int idx = ((row & 1) << 1) | (row >> 1);
+    atomicAdd(acc + idx, t0);
+    atomicAdd(acc + 4 + idx, t1);
+    if (lane == 63) atomicAdd(acc + 8, t8);
+  }
+}
+
 // One record of the reverse walk for one pixel: recompute alpha, undo the
 // blend (T, S) if the forward blended it, and add the record's 2D gradients
 // (reduced over the wave) to the record's LDS accumulator `acc` (9 floats,
@@ -101,26 +142,8 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
     }
   }
   if (__ballot(blended) != 0) {
-    gmx = wave_total(gmx);
-    gmy = wave_total(gmy);
-    gca = wave_total(gca);
-    gcb = wave_total(gcb);
-    gcc = wave_total(gcc);
-    gop = wave_total(gop);
-    gr = wave_total(gr);
-    gg = wave_total(gg);
-    gbl = wave_total(gbl);
-    if (lane == 0) {
-      atomicAdd(acc + 0, gmx);
-      atomicAdd(acc + 1, gmy);
-      atomicAdd(acc + 2, gca);
-      atomicAdd(acc + 3, gcb);
-      atomicAdd(acc + 4, gcc);
-      atomicAdd(acc + 5, gop);
-      atomicAdd(acc + 6, gr);
-      atomicAdd(acc + 7, gg);
-      atomicAdd(acc + 8, gbl);
-    }
+    const float v[9] = {gmx, gmy, gca, gcb, gcc, gop, gr, gg, gbl};
+    wave_accumulate9(v, acc, lane);
   }
 }
 
