@@ -452,7 +452,7 @@ def main():
     # HBM bytes (binning is a pipeline of ~30 kernels).
     r_ops = head["evals_needed"] * OPS_EVAL + head["blends"] * OPS_BLEND
     r_ach = r_ops / (st["raster"] * 1e-3) / 1e12
-    p_bytes = 48 * head["active"] + 240 * head["visible"]
+    p_bytes = 48 * head["active"] + 256 * head["visible"]
     p_ach = p_bytes / (st["preprocess"] * 1e-3) / 1e9
     b_bytes = 16 * head["visible"] + 4 * head["pairs"] + 8 * 8160
     b_ach = b_bytes / (st["bin_sort"] * 1e-3) / 1e9

@@ -99,18 +99,25 @@ typedef struct seele_camera {
   int32_t width, height;  /* image size, pixels, >= 1          */
 } seele_camera;
 
-/* One projected Gaussian for one view (48 bytes).  Written by
- * seele_preprocess for visible Gaussians only (records of culled Gaussians
- * are left untouched and never read).  rect_x = x0 | x1 << 16 and
- * rect_y = y0 | y1 << 16 give the half-open tile rectangle
- * [x0, x1) x [y0, y1). */
+/* One projected Gaussian for one view (64 bytes, one aligned 64-byte
+ * sector).  Written by seele_preprocess for visible Gaussians only (records
+ * of culled Gaussians are left untouched and never read).
+ * chol = (l11, l21, l22) is the lower Cholesky factor of k * conic with
+ * k = log2(e) / 2, computed in double precision from the float32 conic:
+ * k * [[a, b], [b, c]] = [[l11, 0], [l21, l22]] [[l11, l21], [0, l22]],
+ * so that exp(-q/2) = exp2(-((l11 dx + l21 dy)^2 + (l22 dy)^2)).
+ * rect_x = x0 | x1 << 16 and rect_y = y0 | y1 << 16 give the half-open tile
+ * rectangle [x0, x1) x [y0, y1). */
 typedef struct seele_splat {
   float mean_x, mean_y;              /* x' (pixels)                         */
-  float conic_a, conic_b, conic_c;   /* Sigma'^-1 = [[a, b], [b, c]]       */
+  float chol_l11, chol_l21;          /* Cholesky factor of k * conic        */
+  float chol_l22;
   float opacity;                     /* o                                   */
   float r, g, b;                     /* view-dependent colour (clamped >= 0) */
+  float conic_a, conic_b, conic_c;   /* Sigma'^-1 = [[a, b], [b, c]]       */
   float depth;                       /* camera-space z                      */
   uint32_t rect_x, rect_y;
+  uint32_t reserved;                 /* written as 0                        */
 } seele_splat;
 
 /* Preprocessing options. */
@@ -152,7 +159,8 @@ int64_t seele_total_tiles(const seele_camera* cams, int32_t n_views, int32_t til
  * z_near, degenerate Sigma', o < alpha_min (3-sigma extent) or
  * tau <= 0 (opacity extent), empty rectangle).
  *   cams    host [n_views]
- *   splats  device [n_views * n] seele_splat, 16-byte aligned
+ *   splats  device [n_views * n] seele_splat, 16-byte aligned (64 keeps every
+ *           record in one 64-byte sector)
  *   n_tiles device [n_views * n] int32 */
 int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
                          const seele_preprocess_opts* opts, seele_splat* splats,

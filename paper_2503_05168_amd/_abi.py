@@ -42,10 +42,12 @@ class seele_camera(ctypes.Structure):
 
 
 class seele_splat(ctypes.Structure):
-    _fields_ = [("mean_x", c_float), ("mean_y", c_float), ("conic_a", c_float),
-                ("conic_b", c_float), ("conic_c", c_float), ("opacity", c_float),
-                ("r", c_float), ("g", c_float), ("b", c_float), ("depth", c_float),
-                ("rect_x", ctypes.c_uint32), ("rect_y", ctypes.c_uint32)]
+    _fields_ = [("mean_x", c_float), ("mean_y", c_float), ("chol_l11", c_float),
+                ("chol_l21", c_float), ("chol_l22", c_float), ("opacity", c_float),
+                ("r", c_float), ("g", c_float), ("b", c_float), ("conic_a", c_float),
+                ("conic_b", c_float), ("conic_c", c_float), ("depth", c_float),
+                ("rect_x", ctypes.c_uint32), ("rect_y", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class seele_preprocess_opts(ctypes.Structure):

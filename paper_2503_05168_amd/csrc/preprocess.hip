@@ -254,12 +254,13 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __re
           const float rgb[3] = {0.5f + acc[0], 0.5f + acc[1], 0.5f + acc[2]};
           if (finite(rgb[0]) && finite(rgb[1]) && finite(rgb[2])) {
             nt = (x1 - x0) * (y1 - y0);
+            const Chol L = conic_factor(p.ia, p.ib, p.ic);
             float4* dst = reinterpret_cast<float4*>(splats + rec);
-            dst[0] = make_float4(p.px, p.py, p.ia, p.ib);
-            dst[1] = make_float4(p.ic, g.o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f));
-            dst[2] = make_float4(fmaxf(rgb[2], 0.0f), p.tz,
-                                 __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)),
-                                 __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
+            dst[0] = make_float4(p.px, p.py, L.l11, L.l21);
+            dst[1] = make_float4(L.l22, g.o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f));
+            dst[2] = make_float4(fmaxf(rgb[2], 0.0f), p.ia, p.ib, p.ic);
+            dst[3] = make_float4(p.tz, __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)),
+                                 __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)), 0.0f);
           }
         }
       }

@@ -215,13 +215,11 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       const uint32_t id = ids[start + lo + tid];
       const float4* src = reinterpret_cast<const float4*>(splats + id);
       const float4 A = src[0], Bv = src[1];
-      const float blue = src[2].x;
-      const Chol L = conic_factor(A.z, A.w, Bv.x);
-      s_e[tid].a = make_float4(A.x, A.y, L.l11, L.l21);
-      s_e[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
-      s_e[tid].c = make_float4(blue, A.z, A.w, Bv.x);
+      s_e[tid].a = A;
+      s_e[tid].b = Bv;
+      s_e[tid].c = src[2];  // blue, conic a, b, c
       s_id[tid] = id;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin, tile_x * TS,
+      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, Bv.y, amin, tile_x * TS,
                                          tile_y * TS);
 #pragma unroll
       for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.0f;

@@ -5,9 +5,9 @@
 // pixel block laid out as pixel groups (2x2 by default): lanes
 // [k*g, (k+1)*g) hold group k with its leader (top-left pixel) first.  The
 // tile's depth-ordered list is staged through LDS in batches of one record
-// per thread; there the conic is replaced by the Cholesky factor of
-// (log2(e)/2) * conic, so that exp(-q/2) = exp2(-(u^2 + w^2)) with two linear
-// forms u, w of the pixel offset.
+// per thread; each record carries the Cholesky factor of (log2(e)/2) * conic,
+// so that exp(-q/2) = exp2(-(u^2 + w^2)) with two linear forms u, w of the
+// pixel offset.
 //
 // Plain form: every live lane evaluates every Gaussian of the batch.
 // Contribution-aware form: the leader tests are packed -- lane l tests group
@@ -142,11 +142,10 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
       const float4* src = reinterpret_cast<const float4*>(splats + ids[start + j]);
       const float4 A = src[0], Bv = src[1];
       const float blue = src[2].x;
-      const Chol L = conic_factor(A.z, A.w, Bv.x);
-      s_rec[tid].a = make_float4(A.x, A.y, L.l11, L.l21);
-      s_rec[tid].b = make_float4(L.l22, Bv.y, Bv.z, Bv.w);
+      s_rec[tid].a = A;
+      s_rec[tid].b = Bv;
       s_rec[tid].blue = blue;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, L.l11, L.l21, L.l22, Bv.y, amin, tile_x * TS,
+      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, Bv.y, amin, tile_x * TS,
                                          tile_y * TS);
     }
     __syncthreads();

@@ -133,8 +133,9 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T* smem, T& total) {
 //   A k = L L^T,  L = [[l11, 0], [l21, l22]],
 //   k q = (l11 dx + l21 dy)^2 + (l22 dy)^2,   exp(-q/2) = exp2(-k q).
 // Unlike the expanded quadratic, the sum of squares does not cancel for
-// elongated footprints and needs no clamp at zero.  The factor is computed
-// once per Gaussian and tile, in double precision, from the float32 conic.
+// elongated footprints and needs no clamp at zero.  Preprocessing computes the
+// factor once per record, in double precision, from the float32 conic, and
+// stores it in the record.
 struct Chol {
   float l11, l21, l22;
 };

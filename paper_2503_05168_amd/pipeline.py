@@ -15,7 +15,7 @@ import torch
 
 from . import _abi as A
 
-SPLAT_FLOATS = 12  # 48-byte seele_splat
+SPLAT_FLOATS = 16  # 64-byte seele_splat
 
 
 @dataclass
@@ -103,6 +103,15 @@ def _p(t: torch.Tensor | None):
     return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t: torch.Tensor, numel: int, dtype, name: str) -> torch.Tensor:
+    """The library sees plain pointers: check every caller-provided buffer's
+    element type, layout and size before handing it over."""
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{name}: need a contiguous {dtype} tensor of at least {numel} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} (contiguous={t.is_contiguous()})")
+    return t
+
+
 def total_tiles(cams, tile: int) -> int:
     arr = A.camera_array(cams)
     return int(A.lib().seele_total_tiles(arr, len(cams), tile))
@@ -121,6 +130,8 @@ def seele_preprocess(g: GaussianTensors, cams, settings: Settings, segments=None
         splats = torch.empty((V * n, SPLAT_FLOATS), dtype=torch.float32, device=dev)
     if n_tiles is None:
         n_tiles = torch.empty(V * n, dtype=torch.int32, device=dev)
+    _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+    _need(n_tiles, V * n, torch.int32, "n_tiles")
     opts, keep = settings.preprocess_opts(segments)
     gs = g.struct()
     st = A.lib().seele_preprocess(ctypes.byref(gs), A.camera_array(cams), V, ctypes.byref(opts),
@@ -149,6 +160,12 @@ def seele_bin_sort(splats, n_tiles, n: int, cams, tile: int, capacity: int,
         tile_ranges = torch.empty((TT, 2), dtype=torch.int32, device=dev)
     if num_pairs is None:
         num_pairs = torch.empty(1, dtype=torch.int64, device=dev)
+    _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+    _need(n_tiles, V * n, torch.int32, "n_tiles")
+    _need(sorted_ids, capacity, torch.int32, "sorted_ids")
+    _need(tile_ranges, 2 * TT, torch.int32, "tile_ranges")
+    _need(num_pairs, 1, torch.int64, "num_pairs")
+    _need(workspace, ws_bytes, torch.uint8, "workspace")
     st = A.lib().seele_bin_sort(_p(splats), _p(n_tiles), n, A.camera_array(cams), V, tile,
                                 _p(workspace), workspace.numel(), _p(sorted_ids), capacity,
                                 _p(tile_ranges), _p(num_pairs), _stream(stream))
@@ -166,6 +183,10 @@ def seele_rasterize_fwd(splats, sorted_ids, tile_ranges, cams, settings: Setting
         final_T = torch.empty(npix, dtype=torch.float32, device=dev)
     if n_contrib is None:
         n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    _need(tile_ranges, 2 * total_tiles(cams, settings.tile), torch.int32, "tile_ranges")
+    _need(image, 3 * npix, torch.float32, "image")
+    _need(final_T, npix, torch.float32, "final_T")
+    _need(n_contrib, npix, torch.int32, "n_contrib")
     opts = settings.raster_opts()
     st = A.lib().seele_rasterize_fwd(_p(splats), _p(sorted_ids), _p(tile_ranges),
                                      A.camera_array(cams), len(cams), ctypes.byref(opts),
@@ -192,6 +213,10 @@ def seele_rasterize_fwd_queue(splats, sorted_ids, tile_ranges, cams, settings: S
     need = int(A.lib().seele_raster_queue_workspace_size(total_tiles(cams, settings.tile)))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _need(tile_ranges, 2 * total_tiles(cams, settings.tile), torch.int32, "tile_ranges")
+    _need(image, 3 * npix, torch.float32, "image")
+    _need(final_T, npix, torch.float32, "final_T")
+    _need(n_contrib, npix, torch.int32, "n_contrib")
     opts = settings.raster_opts()
     st = A.lib().seele_rasterize_fwd_queue(_p(splats), _p(sorted_ids), _p(tile_ranges),
                                            A.camera_array(cams), len(cams), ctypes.byref(opts),
@@ -211,6 +236,11 @@ def seele_rasterize_fwd_counted(splats, sorted_ids, tile_ranges, cams, settings:
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
     if counters is None:
         counters = torch.empty(6, dtype=torch.int64, device=dev)
+    _need(counters, 6, torch.int64, "counters")
+    _need(tile_ranges, 2 * total_tiles(cams, settings.tile), torch.int32, "tile_ranges")
+    _need(image, 3 * npix, torch.float32, "image")
+    _need(final_T, npix, torch.float32, "final_T")
+    _need(n_contrib, npix, torch.int32, "n_contrib")
     opts = settings.raster_opts()
     st = A.lib().seele_rasterize_fwd_counted(_p(splats), _p(sorted_ids), _p(tile_ranges),
                                              A.camera_array(cams), len(cams), ctypes.byref(opts),
@@ -264,12 +294,19 @@ def seele_rasterize_bwd(g: GaussianTensors, cams, settings: Settings, splats, n_
                                 torch.empty_like(g.sh), g.sh_degree)
     gs = A.seele_gaussian_grads()
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
-        t = getattr(grads, name)
+        t = _need(getattr(grads, name), getattr(g, name).numel(), torch.float32, f"grads.{name}")
         setattr(gs, name, t.data_ptr() if t.numel() else None)
+    npix = pixel_count(cams)
+    _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+    _need(n_tiles, V * n, torch.int32, "n_tiles")
+    _need(tile_ranges, 2 * total_tiles(cams, settings.tile), torch.int32, "tile_ranges")
+    _need(final_T, npix, torch.float32, "final_T")
+    _need(n_contrib, npix, torch.int32, "n_contrib")
+    _need(grad2d, V * n * 9, torch.float32, "grad2d")
     popts, keep = settings.preprocess_opts(segments)
     ropts = settings.raster_opts()
     gst = g.struct()
-    dL = dL_dimage.contiguous()
+    dL = _need(dL_dimage.contiguous(), 3 * npix, torch.float32, "dL_dimage")
     st = A.lib().seele_rasterize_bwd(ctypes.byref(gst), A.camera_array(cams), V,
                                      ctypes.byref(popts), ctypes.byref(ropts), _p(splats),
                                      _p(n_tiles), _p(sorted_ids), _p(tile_ranges), _p(final_T),

@@ -32,14 +32,15 @@ def run(scene, cams, settings: Settings, segments=None, capacity=1 << 20):
 
 def splats_np(f, n_tiles=True):
     s = f.splats.cpu().numpy()
-    rect_x = s[:, 10].view(np.uint32)
-    rect_y = s[:, 11].view(np.uint32)
+    rect_x = s[:, 13].view(np.uint32)
+    rect_y = s[:, 14].view(np.uint32)
     out = dict(
         mean2d=s[:, 0:2].astype(np.float64),
-        conic=s[:, 2:5].astype(np.float64),
+        chol=s[:, 2:5].astype(np.float64),
+        conic=s[:, 9:12].astype(np.float64),
         opacity=s[:, 5].astype(np.float64),
         rgb=s[:, 6:9].astype(np.float64),
-        depth_f32=s[:, 9].copy(),
+        depth_f32=s[:, 12].copy(),
         rect=np.stack([rect_x & 0xFFFF, rect_y & 0xFFFF, rect_x >> 16, rect_y >> 16],
                       axis=1).astype(np.int64),
     )

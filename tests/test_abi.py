@@ -59,7 +59,7 @@ def test_struct_layout_matches_header(tmp_path):
         assert int(got[s]) == ctypes.sizeof(cls), s
         for f in fields:
             assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
-    assert int(got["seele_splat"]) == 48 and int(got["seele_camera"]) == 72
+    assert int(got["seele_splat"]) == 64 and int(got["seele_camera"]) == 72
 
 
 def _cam(w=64, h=48):
@@ -214,3 +214,15 @@ def test_hp_segments_match_oracle():
     cl = (ctypes.c_int32 * 1)(9)
     ob, oc, no = (ctypes.c_int64 * 2)(), (ctypes.c_int64 * 2)(), ctypes.c_int32()
     assert L.seele_hp_segments(lb, lc, K, cl, 1, ob, oc, ctypes.byref(no)) == A.SEELE_ERR_INVALID_ARG
+
+
+def test_bindings_refuse_undersized_buffers():
+    # the library sees plain pointers; the binding checks sizes before the call
+    import torch
+    from paper_2503_05168_amd import pipeline as pl
+    ok = torch.empty(64, dtype=torch.float32)
+    assert pl._need(ok, 64, torch.float32, "x") is ok
+    for bad in (torch.empty(63, dtype=torch.float32), torch.empty(64, dtype=torch.int32),
+                torch.empty(128, dtype=torch.float32)[::2]):
+        with pytest.raises(ValueError):
+            pl._need(bad, 64, torch.float32, "x")

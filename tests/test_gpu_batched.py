@@ -109,7 +109,8 @@ def test_hip_graph_replay_matches_eager(c5_small):
     torch.cuda.synchronize()
     cap = int(eager.num_pairs.item() * 1.2) + 1024
     # static buffers for the captured frame
-    splats = torch.empty((V * n, 12), dtype=torch.float32, device="cuda")
+    from paper_2503_05168_amd.pipeline import SPLAT_FLOATS
+    splats = torch.empty((V * n, SPLAT_FLOATS), dtype=torch.float32, device="cuda")
     n_tiles = torch.empty(V * n, dtype=torch.int32, device="cuda")
     from paper_2503_05168_amd.pipeline import bin_sort_workspace_size
     ws = torch.empty(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8, device="cuda")

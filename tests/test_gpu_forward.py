@@ -50,6 +50,13 @@ def _check_preprocess(scene, cam, f, view, settings, active=None):
     scale = np.abs(o["conic"][idx]).max(1, keepdims=True)
     cerr = (np.abs(sp["conic"][rec] - o["conic"][idx]) / scale).max(initial=0)
     assert cerr < 1e-3, cerr
+    # the stored Cholesky factor reproduces (log2(e)/2) * the record's own conic
+    k = np.log2(np.e) / 2
+    l11, l21, l22 = (sp["chol"][rec, c] for c in range(3))
+    a, b, c = (sp["conic"][rec, j] for j in range(3))
+    lscale = k * np.maximum(np.abs(a), np.abs(c))
+    for got, want in ((l11 * l11, k * a), (l11 * l21, k * b), (l21 * l21 + l22 * l22, k * c)):
+        assert (np.abs(got - want) / lscale).max(initial=0) < 1e-6
     strict = idx[~border[idx]]
     np.testing.assert_array_equal(sp["rect"][view * n + strict], o["rect"][strict])
     np.testing.assert_array_equal(sp["n_tiles"][view * n + strict], o["n_tiles"][strict])
