@@ -129,14 +129,16 @@ __device__ __forceinline__ uint32_t clip_mask(uint32_t clip) {
 }
 
 // ---- visible-record compaction.  Wave w of block b owns records
-// [b*TILE + w*kWaveSpan, +kWaveSpan): per-wave counts, one scan, then each
+// [b*kSpanBlock + w*kWaveSpan, +kWaveSpan): per-wave counts, one scan, then each
 // wave writes its (depth, id) pairs independently (ballot ranks).
-constexpr int kWaveSpan = TILE / WAVES;
+constexpr int kRadixIT = 8;                       // radix items per thread (2048 per block)
+constexpr int kWaveSpan = 256;                    // records per wave (4 steps of 64)
+constexpr int kSpanBlock = WAVES * kWaveSpan;      // records per workgroup
 
 __global__ __launch_bounds__(B) void k_vis_count(const int32_t* __restrict__ n_tiles, int64_t n,
                                                   uint64_t* __restrict__ partial) {
   const int w = threadIdx.x >> 6, lane = lane_id();
-  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
+  const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
   uint32_t c = 0;
 #pragma unroll
   for (int it = 0; it < kWaveSpan / 64; ++it) {
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
                                                     uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
   const int w = threadIdx.x >> 6, lane = lane_id();
-  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
+  const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
   if (begin >= n) return;  // per wave; no barriers below
   uint32_t carry = (uint32_t)partial[(int64_t)blockIdx.x * WAVES + w];
   const uint64_t lt = lanemask_lt();
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
                                                    uint64_t* __restrict__ partial2) {
   const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nv = hdr->n_vis;
-  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
+  const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
   uint64_t c = 0, q = 0;
   if (begin < nv) {
 #pragma unroll 4
@@ -450,11 +452,18 @@ __device__ __forceinline__ uint32_t entry_key(const Rect& r, uint32_t k, uint32_
   return (clip << kClipShift) | (st_base + sy * sgw + sx);
 }
 
+// Order a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Emit the entries of every depth-ordered record at its offset (exclusive
 // scan of entry counts), value = record id.  Each wave handles 64 records at
 // a time; their entries form one contiguous output range.  When that range
-// fits the wave's LDS map (kStage entries), every record marks its entries'
-// positions with its lane, and the wave then writes the range in order, 64
+// fits the wave's LDS map (kStage entries), the map gives each position of
+// the range its owning lane, and the wave then writes the range in order, 64
 // consecutive entries per store (each lane computing the entry it writes from
 // its owner's rectangle).  Otherwise a record with few entries is emitted by
 // its own lane and a larger one by the whole wave.  Skipped when the frame
@@ -472,7 +481,7 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
   __shared__ uint8_t s_own[WAVES][kStage];
   const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nv = hdr->n_vis;
-  const int64_t begin = (int64_t)blockIdx.x * TILE + w * kWaveSpan;
+  const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
   if (begin >= nv || hdr->p_total > (uint64_t)capacity) return;  // per wave; no barriers
   uint64_t carry = partial[(int64_t)blockIdx.x * WAVES + w];
 #pragma unroll 1
@@ -503,11 +512,36 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
       sw = (r.x1 - 1) / ST - r.x0 / ST + 1;
     }
     if (total <= kStage) {
-      // owner map, then ordered coalesced stores
-      for (uint32_t k = 0; k < m; ++k) s_own[w][rel + k] = (uint8_t)lane;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // owner map: every record with entries marks its first slot with its
+      // lane, a prefix max spreads the marks (lane l scans the chunk
+      // [l*C, (l+1)*C) after a max-scan of the chunk maxima); then ordered
+      // coalesced stores
+      for (uint32_t j = lane; j < total; j += 64) s_own[w][j] = 0;
+      wave_lds_sync();
+      if (m > 0) s_own[w][rel] = (uint8_t)lane;
+      wave_lds_sync();
+      {
+        const uint32_t C = (total + 63) / 64;
+        const uint32_t c0 = (uint32_t)lane * C;
+        uint32_t run = 0;
+        for (uint32_t c = 0; c < C; ++c)
+          if (c0 + c < total) run = max(run, (uint32_t)s_own[w][c0 + c]);
+        uint32_t inc_max = run;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(inc_max, d, 64);
+          if (lane >= d) inc_max = max(inc_max, y);
+        }
+        uint32_t cur = __shfl_up(inc_max, 1, 64);
+        if (lane == 0) cur = 0;
+        wave_lds_sync();
+        for (uint32_t c = 0; c < C; ++c)
+          if (c0 + c < total) {
+            cur = max(cur, (uint32_t)s_own[w][c0 + c]);
+            s_own[w][c0 + c] = (uint8_t)cur;
+          }
+      }
+      wave_lds_sync();
       const uint32_t rxp = r.x0 | (r.x1 << 16), ryp = r.y0 | (r.y1 << 16);
       const uint32_t swg = sw | (sgw << 16);
       for (uint32_t j0 = 0; j0 < total; j0 += 64) {
@@ -523,7 +557,7 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
           evals[base + j] = ido;
         }
       }
-      __builtin_amdgcn_wave_barrier();  // map reads finish before the next group's writes
+      wave_lds_sync();  // map reads finish before the next group's writes
       continue;
     }
     if (m > 0 && m <= kLaneEntries) {
@@ -883,9 +917,12 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.max_st = std::max<int64_t>(n_tiles_total, 1);
   p.max_seg = max_segments(capacity, p.max_st);
   const int64_t nb_rec = std::max<int64_t>(nblocks_for(n_records), 1);
-  const int64_t nb_hist = std::max<int64_t>({nb_rec, nblocks_for(capacity), 1});
+  const int64_t nb_span = std::max<int64_t>((n_records + kSpanBlock - 1) / kSpanBlock, 1);
+  const int64_t rblk = (int64_t)B * kRadixIT;
+  const int64_t nb_hist =
+      std::max<int64_t>({(n_records + rblk - 1) / rblk, (capacity + rblk - 1) / rblk, 1});
   const int64_t nb_part = std::max<int64_t>(
-      {WAVES * nb_rec, nblocks_for(p.max_st), nblocks_for(n_tiles_total), 1});
+      {WAVES * nb_span, nblocks_for(p.max_st), nblocks_for(n_tiles_total), 1});
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -894,7 +931,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   };
   p.off_hdr = take(sizeof(Hdr));
   p.off_partial = take(8 * (size_t)nb_part);
-  p.off_partial2 = take(8 * WAVES * (size_t)nb_rec);
+  p.off_partial2 = take(8 * WAVES * (size_t)nb_span);
   p.off_dkeys0 = take(4 * (size_t)n_records);
   p.off_dkeys1 = take(4 * (size_t)n_records);
   p.off_dvals0 = take(4 * (size_t)n_records);
@@ -949,7 +986,7 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
                        st_range, 2 * n_st, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t R = p.n_records;
-  const int nbR = (int)nblocks_for(R);
+  const int nbR = (int)((R + kSpanBlock - 1) / kSpanBlock);  // record-span workgroups
   if (nbR > 0) {
     // 1. visible records (n_tiles > 0) in id order with their depth keys
     hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
@@ -961,8 +998,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     //    stable sort by float32 depth bits (4 x 8-bit passes, ends in buffer 0)
     for (int pass = 0; pass < 4; ++pass) {
       const int src = pass & 1, dst = src ^ 1;
-      e = radix_pass<ITEMS>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8, hist,
-                            digits, stream);
+      e = radix_pass<kRadixIT>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8, hist,
+                               digits, stream);
       if (e != hipSuccess) return e;
     }
     // 2. pair and entry totals (pairs -> num_pairs)
@@ -991,8 +1028,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   for (int pass = 0; pass < passes; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     const int bits = std::min(per, st_bits - shift);
-    e = radix_pass<ITEMS>(sk[src], sv[src], sk[dst], sv[dst], d_nent, p.capacity, shift, bits,
-                          hist, digits, stream);
+    e = radix_pass<kRadixIT>(sk[src], sv[src], sk[dst], sv[dst], d_nent, p.capacity, shift, bits,
+                             hist, digits, stream);
     if (e != hipSuccess) return e;
     shift += bits;
   }
