@@ -153,30 +153,59 @@ __global__ __launch_bounds__(B) void k_vis_count(const int32_t* __restrict__ n_t
 // mode 0: hdr->n_vis.  1: hdr->p_total, *num_pairs and hdr->n_pairs (zero
 // when the total exceeds capacity).  2: hdr->n_ent (zero when the pairs
 // exceed capacity).  3: hdr->n_seg.  4: nowhere.
-__global__ __launch_bounds__(B) void k_scan_partials(uint64_t* __restrict__ partial, int64_t nb,
-                                                      Hdr* __restrict__ hdr, int mode,
-                                                      int64_t capacity,
-                                                      int64_t* __restrict__ num_pairs) {
-  constexpr int R = 16;  // consecutive partials per thread
-  __shared__ uint64_t s[WAVES + 1];
+constexpr int kScanThreads = 1024;
+
+// Chunks of 4096 partials go through LDS: coalesced loads, then each thread
+// scans 4 consecutive values, then coalesced stores.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __restrict__ partial,
+                                                                 int64_t nb, Hdr* __restrict__ hdr,
+                                                                 int mode, int64_t capacity,
+                                                                 int64_t* __restrict__ num_pairs) {
+  constexpr int R = 4;
+  constexpr int CH = kScanThreads * R;
+  constexpr int NW = kScanThreads / 64;
+  __shared__ uint64_t s_v[CH];
+  __shared__ uint64_t s_w[NW];
+  const int tid = threadIdx.x, w = tid >> 6;
   uint64_t carry = 0;
-  for (int64_t base = 0; base < nb; base += B * R) {
-    const int64_t i0 = base + (int64_t)threadIdx.x * R;
+  for (int64_t base = 0; base < nb; base += CH) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + r * kScanThreads + tid;
+      s_v[r * kScanThreads + tid] = i < nb ? partial[i] : 0;
+    }
+    __syncthreads();
     uint64_t v[R];
     uint64_t sum = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      v[r] = i0 + r < nb ? partial[i0 + r] : 0;
+      v[r] = s_v[tid * R + r];
       sum += v[r];
     }
-    uint64_t tot;
-    uint64_t run = carry + block_exclusive_scan<uint64_t>(sum, s, tot);
+    const uint64_t inc = wave_inclusive_scan(sum);
+    if (lane_id() == 63) s_w[w] = inc;
+    __syncthreads();
+    uint64_t wbase = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint64_t x = s_w[i];
+      if (i < w) wbase += x;
+      tot += x;
+    }
+    uint64_t run = carry + wbase + inc - sum;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (i0 + r < nb) partial[i0 + r] = run;
+      s_v[tid * R + r] = run;
       run += v[r];
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + r * kScanThreads + tid;
+      if (i < nb) partial[i] = s_v[r * kScanThreads + tid];
+    }
     carry += tot;
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
     if (mode == 0) {
@@ -642,7 +671,7 @@ __global__ __launch_bounds__(B) void k_seg_count(const int32_t* __restrict__ st_
 __global__ __launch_bounds__(B) void k_seg_emit(const int32_t* __restrict__ st_range,
                                                  int64_t n_st, const uint64_t* __restrict__ partial,
                                                  uint32_t* __restrict__ st_seg,
-                                                 uint32_t* __restrict__ seg_st) {
+                                                 uint4* __restrict__ seg_meta) {
   __shared__ uint32_t sm[WAVES + 1];
   const int64_t begin = (int64_t)blockIdx.x * TILE;
   uint32_t carry = (uint32_t)partial[blockIdx.x];
@@ -655,40 +684,42 @@ __global__ __launch_bounds__(B) void k_seg_emit(const int32_t* __restrict__ st_r
     carry += tot;
     if (s < n_st) {
       st_seg[s] = first;
-      for (uint32_t k = 0; k < c; ++k) seg_st[first + k] = (uint32_t)s;
+      const int32_t lo = st_range[2 * s], hi = st_range[2 * s + 1];
+      for (uint32_t k = 0; k < c; ++k) {
+        const int32_t a = lo + (int32_t)k * kSegLen;
+        seg_meta[first + k] =
+            make_uint4((uint32_t)s, (uint32_t)a, (uint32_t)min(hi, a + kSegLen), 0u);
+      }
     }
   }
 }
 
-// Entries [a, e) of quarter w of segment `seg`, and its super-tile.
+// Entries [a, e) of quarter w of a segment, and its super-tile, from the
+// segment's record {super-tile, begin, end}.
 struct Quarter {
   uint32_t st;
   int32_t a, e;
 };
 
-__device__ __forceinline__ Quarter quarter(uint32_t seg, int w, const uint32_t* seg_st,
-                                           const uint32_t* st_seg, const int32_t* st_range) {
+__device__ __forceinline__ Quarter quarter(const uint4& m, int w) {
   Quarter g;
-  g.st = seg_st[seg];
-  const int32_t lo = st_range[2 * (int64_t)g.st], hi = st_range[2 * (int64_t)g.st + 1];
-  const int32_t a = lo + (int32_t)(seg - st_seg[g.st]) * kSegLen + w * (kSegLen / WAVES);
-  g.a = min(hi, a);
-  g.e = min(hi, a + kSegLen / WAVES);
+  g.st = m.x;
+  const int32_t a = (int32_t)m.y + w * (kSegLen / WAVES);
+  g.a = min((int32_t)m.z, a);
+  g.e = min((int32_t)m.z, a + kSegLen / WAVES);
   return g;
 }
 
 // Per wave quarter of a segment and tile of its super-tile: entries covering
 // the tile.  seg_cnt layout: [segment][wave quarter][tile].
 __global__ __launch_bounds__(B) void k_seg_tile_count(const Hdr* __restrict__ hdr,
-                                                       const uint32_t* __restrict__ seg_st,
-                                                       const uint32_t* __restrict__ st_seg,
-                                                       const int32_t* __restrict__ st_range,
+                                                       const uint4* __restrict__ seg_meta,
                                                        const uint32_t* __restrict__ ekeys,
                                                        uint32_t* __restrict__ seg_cnt) {
   const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nseg = hdr->n_seg;
   for (uint32_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-    const Quarter g = quarter(seg, w, seg_st, st_seg, st_range);
+    const Quarter g = quarter(seg_meta[seg], w);
     uint32_t mine = 0;  // lane t < 16: count of tile t
     for (int32_t base = g.a; base < g.e; base += 64) {
       const int32_t i = base + lane;
@@ -787,9 +818,7 @@ __global__ __launch_bounds__(B) void k_tile_ranges(const uint32_t* __restrict__ 
 // lanes of tile t take consecutive slots in lane order.  Waves run
 // independently.
 __global__ __launch_bounds__(B) void k_seg_write(const Hdr* __restrict__ hdr,
-                                                  const uint32_t* __restrict__ seg_st,
-                                                  const uint32_t* __restrict__ st_seg,
-                                                  const int32_t* __restrict__ st_range,
+                                                  const uint4* __restrict__ seg_meta,
                                                   const uint32_t* __restrict__ ekeys,
                                                   const uint32_t* __restrict__ evals,
                                                   const uint32_t* __restrict__ seg_cnt,
@@ -798,7 +827,7 @@ __global__ __launch_bounds__(B) void k_seg_write(const Hdr* __restrict__ hdr,
   const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nseg = hdr->n_seg;
   for (uint32_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-    const Quarter g = quarter(seg, w, seg_st, st_seg, st_range);
+    const Quarter g = quarter(seg_meta[seg], w);
     if (g.a >= g.e) continue;  // uniform per wave
     uint32_t start = 0;
     if (lane < ST2) {
@@ -946,7 +975,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_digits = take(4 * 256);
   p.off_st_range = take(8 * (size_t)p.max_st);
   p.off_st_seg = take(4 * (size_t)p.max_st);
-  p.off_seg_st = take(4 * (size_t)p.max_seg);
+  p.off_seg_st = take(16 * (size_t)p.max_seg);  // per segment {super-tile, begin, end, 0}
   p.off_seg_cnt = take(4 * WAVES * ST2 * (size_t)p.max_seg);
   p.off_tile_cnt = take(4 * (size_t)std::max<int64_t>(n_tiles_total, 1));
   p.off_tile_start = take(4 * (size_t)std::max<int64_t>(n_tiles_total, 1));
@@ -970,7 +999,7 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   uint32_t* digits = at(p.off_digits);
   int32_t* st_range = reinterpret_cast<int32_t*>(base + p.off_st_range);
   uint32_t* st_seg = at(p.off_st_seg);
-  uint32_t* seg_st = at(p.off_seg_st);
+  uint4* seg_meta = reinterpret_cast<uint4*>(base + p.off_seg_st);
   uint32_t* seg_cnt = at(p.off_seg_cnt);
   uint32_t* tile_cnt = at(p.off_tile_cnt);
   uint32_t* tile_start = at(p.off_tile_start);
@@ -990,8 +1019,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   if (nbR > 0) {
     // 1. visible records (n_tiles > 0) in id order with their depth keys
     hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, WAVES * (int64_t)nbR,
-                       hdr, 0, p.capacity, num_pairs);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
+                       WAVES * (int64_t)nbR, hdr, 0, p.capacity, num_pairs);
     hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats, partial,
                        dk[0], dv[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1006,10 +1035,10 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], splats, views, hdr,
                        rx_s, ry_s, partial, partial2);
   }
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, WAVES * (int64_t)nbR,
-                     hdr, 1, p.capacity, num_pairs);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial2, WAVES * (int64_t)nbR,
-                     hdr, 2, p.capacity, num_pairs);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
+                     WAVES * (int64_t)nbR, hdr, 1, p.capacity, num_pairs);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial2,
+                     WAVES * (int64_t)nbR, hdr, 2, p.capacity, num_pairs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   //    entries, then sorted by super-tile id (balanced digit widths <= 8); the
   //    value buffers alternate between svals0 and sorted_ids so that the last
@@ -1042,27 +1071,29 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   const int nbS = (int)nblocks_for(n_st);
   if (nbS > 0) {
     hipLaunchKernelGGL(k_seg_count, dim3(nbS), dim3(B), 0, stream, st_range, n_st, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, (int64_t)nbS, hdr, 3,
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
+                       (int64_t)nbS, hdr, 3,
                        p.capacity, num_pairs);
     hipLaunchKernelGGL(k_seg_emit, dim3(nbS), dim3(B), 0, stream, st_range, n_st, partial, st_seg,
-                       seg_st);
+                       seg_meta);
   }
   const int seg_grid = grid_for(p.max_seg);
-  hipLaunchKernelGGL(k_seg_tile_count, dim3(seg_grid), dim3(B), 0, stream, hdr, seg_st, st_seg,
-                     st_range, ekeys, seg_cnt);
+  hipLaunchKernelGGL(k_seg_tile_count, dim3(seg_grid), dim3(B), 0, stream, hdr, seg_meta, ekeys,
+                     seg_cnt);
   if (n_st > 0)
     hipLaunchKernelGGL(k_st_tile_prefix, dim3((unsigned)((n_st * ST2 + 255) / 256)), dim3(256), 0,
                        stream, st_range, st_seg, n_st, views, seg_cnt, tile_cnt);
   const int nbT = (int)nblocks_for(TT);
   if (nbT > 0) {
     hipLaunchKernelGGL(k_tile_partials, dim3(nbT), dim3(B), 0, stream, tile_cnt, TT, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(B), 0, stream, partial, (int64_t)nbT, hdr, 4,
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
+                       (int64_t)nbT, hdr, 4,
                        p.capacity, num_pairs);
     hipLaunchKernelGGL(k_tile_ranges, dim3(nbT), dim3(B), 0, stream, tile_cnt, TT, partial, hdr,
                        tile_start, tile_ranges);
   }
-  hipLaunchKernelGGL(k_seg_write, dim3(seg_grid), dim3(B), 0, stream, hdr, seg_st, st_seg,
-                     st_range, ekeys, evals, seg_cnt, tile_start, views, sorted_ids);
+  hipLaunchKernelGGL(k_seg_write, dim3(seg_grid), dim3(B), 0, stream, hdr, seg_meta, ekeys, evals,
+                     seg_cnt, tile_start, views, sorted_ids);
   return hipGetLastError();
 }
 

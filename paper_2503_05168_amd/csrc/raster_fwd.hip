@@ -72,6 +72,26 @@ __device__ __forceinline__ bool blend_step(float fx, float fy, const float4& a, 
   return take;
 }
 
+// The same step without branches (selects only), for the production loop:
+// a step that does not blend adds 0 * colour (colours are finite and >= 0,
+// the sums start at +0), so it writes the same bits as blend_step.
+__device__ __forceinline__ void blend_select(float fx, float fy, const float4& a, const float4& b,
+                                             float blue, int pos, float amin, float amax,
+                                             float tmin, float& T, float& c0, float& c1,
+                                             float& c2, int& last) {
+  const float alpha = alpha_at(fx, fy, a, b, amax);
+  const bool pass = alpha >= amin;
+  const float Tn = T * (1.0f - alpha);
+  const bool stop = Tn < tmin;
+  const bool take = pass && !stop;
+  const float wgt = take ? alpha * T : 0.0f;
+  c0 = __builtin_fmaf(wgt, b.z, c0);
+  c1 = __builtin_fmaf(wgt, b.w, c1);
+  c2 = __builtin_fmaf(wgt, blue, c2);
+  last = take ? pos : last;
+  T = take ? Tn : (pass ? -__builtin_fabsf(T) : T);
+}
+
 // COUNT instantiations also accumulate the method's work counters:
 // [0] alpha evaluations by pixels that have not stopped (contribution-aware:
 // only in groups whose leader accepted), [1] blends, [2] leader tests of
@@ -135,20 +155,39 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   float T = inside ? 1.0f : -1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
   int last = 0;
 
+  // Staging loads are software-pipelined: while a batch is blended, each
+  // staging thread already has the next batch's record and the id of the
+  // batch after in flight.
+  const bool stager = tid < BATCH;
+  float4 pa = make_float4(0.0f, 0.0f, 0.0f, 0.0f), pb = pa;
+  float pblue = 0.0f;
+  uint32_t pid = 0;
+  if (stager && tid < n) {
+    const float4* src = reinterpret_cast<const float4*>(splats + ids[start + tid]);
+    pa = src[0];
+    pb = src[1];
+    pblue = src[2].x;
+  }
+  if (stager && BATCH + tid < n) pid = ids[start + BATCH + tid];
+
   for (int base = 0; base < n; base += BATCH) {
     if (__syncthreads_count(T < 0.0f) == NT) break;
     const int j = base + tid;
-    if (tid < BATCH && j < n) {
-      const float4* src = reinterpret_cast<const float4*>(splats + ids[start + j]);
-      const float4 A = src[0], Bv = src[1];
-      const float blue = src[2].x;
-      s_rec[tid].a = A;
-      s_rec[tid].b = Bv;
-      s_rec[tid].blue = blue;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, Bv.y, amin, tile_x * TS,
+    if (stager && j < n) {
+      s_rec[tid].a = pa;
+      s_rec[tid].b = pb;
+      s_rec[tid].blue = pblue;
+      s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, amin, tile_x * TS,
                                          tile_y * TS);
     }
     __syncthreads();
+    if (stager && j + BATCH < n) {
+      const float4* src = reinterpret_cast<const float4*>(splats + pid);
+      pa = src[0];
+      pb = src[1];
+      pblue = src[2].x;
+      if (j + 2 * BATCH < n) pid = ids[start + j + 2 * BATCH];
+    }
     const int cnt = min(BATCH, n - base);
     if (COUNT && MODE == 0) {
       for (int k = 0; k < cnt; ++k) {
@@ -202,29 +241,32 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         uint64_t bits = __ballot(need);
         if (bits == 0) continue;
         if (MODE == 0) {
-          // Walk this wave's records in depth order with scalar bit scans,
-          // two at a time: the next record's LDS reads are in flight while
-          // the current one is blended.
-          int ka = c + __builtin_ctzll(bits);
-          bits &= bits - 1;
+          // Pack the chunk indices of this wave's records into consecutive
+          // lanes (lane r < nsel holds the r-th selected index; the other
+          // lanes the unselected ones, so the mapping is a permutation and
+          // every lane holds an index inside the chunk), then walk them in
+          // depth order with a counter, two at a time: the next record's
+          // LDS reads are in flight while the current one is blended.
+          const int nsel = __popcll(bits);
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
+          const int slot = need ? rank : nsel + (lane - rank);
+          const int packed = __builtin_amdgcn_ds_permute(slot * 4, lane);
+          int ka = c + __builtin_amdgcn_readlane(packed, 0);
           float4 aa = s_rec[ka].a, ab = s_rec[ka].b;
           float abl = s_rec[ka].blue;
-          for (;;) {
-            const bool mb = bits != 0;
-            const int kb = mb ? c + __builtin_ctzll(bits) : ka;
-            bits &= bits - 1;
+          for (int i = 1;; i += 2) {
+            const int kb = c + __builtin_amdgcn_readlane(packed, i & 63);
             const float4 ba = s_rec[kb].a, bb = s_rec[kb].b;
             const float bbl = s_rec[kb].blue;
-            blend_step(fx, fy, aa, ab, abl, base + ka + 1, amin, amax, tmin, T, c0, c1, c2, last);
-            if (!mb) break;
-            const bool ma = bits != 0;
-            ka = ma ? c + __builtin_ctzll(bits) : kb;
-            bits &= bits - 1;
+            blend_select(fx, fy, aa, ab, abl, base + ka + 1, amin, amax, tmin, T, c0, c1, c2, last);
+            if (i >= nsel) break;
+            ka = c + __builtin_amdgcn_readlane(packed, (i + 1) & 63);
             aa = s_rec[ka].a;
             ab = s_rec[ka].b;
             abl = s_rec[ka].blue;
-            blend_step(fx, fy, ba, bb, bbl, base + kb + 1, amin, amax, tmin, T, c0, c1, c2, last);
-            if (!ma) break;
+            blend_select(fx, fy, ba, bb, bbl, base + kb + 1, amin, amax, tmin, T, c0, c1, c2, last);
+            if (i + 1 >= nsel) break;
           }
         } else {
           // compact this wave's records of the chunk, then run the packed
