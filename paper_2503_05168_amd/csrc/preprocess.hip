@@ -179,8 +179,10 @@ __device__ __forceinline__ void project(const CamK& c, const Act& g, float lowpa
 }
 
 // NB = (sh_degree + 1)^2 is a template argument so that the coefficient
-// loads carry no per-coefficient branch and are all in flight together.
-template <int NB>
+// loads carry no per-coefficient branch and are all in flight together.  ONE
+// compiles the single-view launch without the view loop: nothing of the
+// Gaussian has to stay live across views, which halves the registers.
+template <int NB, bool ONE>
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __restrict__ means,
                                                     const float* __restrict__ log_scales,
                                                     const float* __restrict__ quats,
@@ -201,8 +203,9 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __re
   }
 
   const float inv_tile = 1.0f / (float)a.tile;
+  const int nviews = ONE ? 1 : a.n_views;
 
-  for (int v = 0; v < a.n_views; ++v) {
+  for (int v = 0; v < nviews; ++v) {
     const CamK& c = a.cam[v];
     const int64_t rec = (a.view0 + v) * n + i;
     int32_t nt = 0;
@@ -522,23 +525,29 @@ hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_s
   if (a.n == 0) return hipSuccess;
   const int block = 256;
   const int64_t grid = (a.n + block - 1) / block;
+  const dim3 g3((unsigned)grid), b3(block);
+  const bool one = a.n_views == 1;
+#define SEELE_PRE(NB)                                                                           \
+  if (one)                                                                                      \
+    hipLaunchKernelGGL((k_preprocess<NB, true>), g3, b3, 0, stream, a, g.means, g.log_scales,   \
+                       g.quats, g.opacity_logits, g.sh, splats, n_tiles);                       \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_preprocess<NB, false>), g3, b3, 0, stream, a, g.means, g.log_scales,  \
+                       g.quats, g.opacity_logits, g.sh, splats, n_tiles);
   switch (a.sh_degree) {
     case 0:
-      hipLaunchKernelGGL(k_preprocess<1>, dim3((unsigned)grid), dim3(block), 0, stream, a,
-                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      SEELE_PRE(1);
       break;
     case 1:
-      hipLaunchKernelGGL(k_preprocess<4>, dim3((unsigned)grid), dim3(block), 0, stream, a,
-                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      SEELE_PRE(4);
       break;
     case 2:
-      hipLaunchKernelGGL(k_preprocess<9>, dim3((unsigned)grid), dim3(block), 0, stream, a,
-                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      SEELE_PRE(9);
       break;
     default:
-      hipLaunchKernelGGL(k_preprocess<16>, dim3((unsigned)grid), dim3(block), 0, stream, a,
-                         g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+      SEELE_PRE(16);
   }
+#undef SEELE_PRE
   return hipGetLastError();
 }
 
