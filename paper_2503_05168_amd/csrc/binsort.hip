@@ -155,13 +155,14 @@ __global__ __launch_bounds__(B) void k_vis_count(const int32_t* __restrict__ n_t
 // exceed capacity).  3: hdr->n_seg.  4: nowhere.
 constexpr int kScanThreads = 1024;
 
-// Chunks of 4096 partials go through LDS: coalesced loads, then each thread
-// scans 4 consecutive values, then coalesced stores.
+// Chunks of 12288 partials (one chunk for a 1080p frame's 3M records) go
+// through LDS: coalesced loads, then each thread scans 12 consecutive values,
+// then coalesced stores.
 __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __restrict__ partial,
                                                                  int64_t nb, Hdr* __restrict__ hdr,
                                                                  int mode, int64_t capacity,
                                                                  int64_t* __restrict__ num_pairs) {
-  constexpr int R = 4;
+  constexpr int R = 12;
   constexpr int CH = kScanThreads * R;
   constexpr int NW = kScanThreads / 64;
   __shared__ uint64_t s_v[CH];
@@ -748,16 +749,30 @@ __global__ void k_st_tile_prefix(const int32_t* __restrict__ st_range,
   const int t = (int)(g % ST2);
   const uint32_t ns = n_segments(st_range, s);
   const uint32_t first = st_seg[s];
+  // Quarter counts of four segments at a time are loaded before any is
+  // rewritten, so sixteen loads are in flight.
+  constexpr int KS = 4, Q = KS * WAVES;
   uint32_t run = 0;
-  for (uint32_t k = 0; k < ns; ++k) {
-    uint32_t* p = seg_cnt + (int64_t)(first + k) * WAVES * ST2 + t;
+  uint32_t* p = seg_cnt + (int64_t)first * WAVES * ST2 + t;
+  uint32_t k = 0;
+  for (; k + KS <= ns; k += KS, p += Q * ST2) {
+    uint32_t c[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) c[j] = p[j * ST2];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      p[j * ST2] = run;
+      run += c[j];
+    }
+  }
+  for (; k < ns; ++k, p += WAVES * ST2) {
     uint32_t c[WAVES];
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) c[w] = p[w * ST2];
+    for (int j = 0; j < WAVES; ++j) c[j] = p[j * ST2];
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      p[w * ST2] = run;
-      run += c[w];
+    for (int j = 0; j < WAVES; ++j) {
+      p[j * ST2] = run;
+      run += c[j];
     }
   }
   const StLoc L = st_locate(views, (uint32_t)s);

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
 
   const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
   const int start = ranges[ri];
-  const float amin = rp.alpha_min, amax = rp.alpha_max;
+  const float amin = rp.alpha_min, inv_amin = rp.inv_alpha_min, amax = rp.alpha_max;
 
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
   int last = 0;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       s_e[tid].b = Bv;
       s_e[tid].c = src[2];  // blue, conic a, b, c
       s_id[tid] = id;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, Bv.y, amin, tile_x * TS,
+      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, Bv.y, inv_amin, tile_x * TS,
                                          tile_y * TS);
 #pragma unroll
       for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.0f;

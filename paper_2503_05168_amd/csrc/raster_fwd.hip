@@ -149,7 +149,8 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
 
   const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
   const int start = ranges[ri], n = ranges[ri + 1] - start;
-  const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.T_min;
+  const float amin = rp.alpha_min, inv_amin = rp.inv_alpha_min;
+  const float amax = rp.alpha_max, tmin = rp.T_min;
 
   // pixels outside the image start stopped
   float T = inside ? 1.0f : -1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
@@ -177,7 +178,7 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
       s_rec[tid].a = pa;
       s_rec[tid].b = pb;
       s_rec[tid].blue = pblue;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, amin, tile_x * TS,
+      s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, inv_amin, tile_x * TS,
                                          tile_y * TS);
     }
     __syncthreads();

@@ -73,6 +73,7 @@ struct RasterViews {
 
 struct RasterParams {
   float alpha_min, alpha_max, T_min;
+  float inv_alpha_min;  // 1 / alpha_min, for the culling bound
   float bg0, bg1, bg2;
   int group_w, group_h;
 };
@@ -183,33 +184,39 @@ __device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
 // (x0, y0).  Bit q (q = 2*row + column of the 8x8 block that wave q owns) is
 // cleared only if alpha < alpha_min at every pixel centre of block q as the
 // blending loops compute it in float32 (splat_power, fast_exp2, clamp_alpha).
-// Over the block's centres the two linear forms u = l11 dx + l21 dy and
-// w = l22 dy range over intervals; the sum of their smallest squares bounds
-// k q from below.  alpha >= alpha_min needs
-// k q <= log2(o / alpha_min), so a block is cleared when the bound exceeds
-// that by a margin covering the float32 rounding of the loop's evaluation
-// (relative to the squared magnitude S^2 of the terms it adds) and of the
-// bound itself, plus 1e-3 for the logarithm, exp2 and the product with o.
-// NaN anywhere leaves the bit set.
+// Over a block's centres the two linear forms u = l11 dx + l21 dy and
+// w = l22 dy range over intervals (l11, l22 > 0); the squared distances of
+// those intervals from zero add up to a lower bound of k q.  alpha >=
+// alpha_min needs k q <= log2(o / alpha_min), so a block is cleared when the
+// bound exceeds that by a margin covering the float32 rounding of the loop's
+// evaluation and of the bound itself (relative to the squared magnitude S^2
+// of the terms, taken over the whole tile), plus 1e-3 for the logarithm, exp2
+// and the products with o and 1 / alpha_min.  A NaN or infinite input makes
+// the margin NaN or infinite and leaves every bit set.
 template <int TS>
 __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float l11, float l21, float l22,
-                                              float opacity, float alpha_min, int x0, int y0) {
-  const float lim = __log2f(opacity / alpha_min) + 1e-3f;
+                                              float opacity, float inv_alpha_min, int x0, int y0) {
+  constexpr int NB = TS / 8;  // 8x8 blocks per tile row
+  const float X0 = ((float)x0 + 0.5f) - mx, Y0 = ((float)y0 + 0.5f) - my;
+  const float ax = __builtin_fabsf(X0) + (float)(TS - 1);
+  const float ay = __builtin_fabsf(Y0) + (float)(TS - 1);
+  const float S = l11 * ax + __builtin_fabsf(l21) * ay, Wm = l22 * ay;
+  const float thr = (__log2f(opacity * inv_alpha_min) + 1e-3f) + 4e-6f * (S * S + Wm * Wm);
+  const float ux = l11 * X0, ux7 = ux + 7.0f * l11, step = 8.0f * l11;
   uint32_t m = 0;
 #pragma unroll
-  for (int q = 0; q < (TS / 8) * (TS / 8); ++q) {
-    const float dx0 = (float)(x0 + (q & 1) * 8) + 0.5f - mx, dx1 = dx0 + 7.0f;
-    const float dy0 = (float)(y0 + (q >> 1) * 8) + 0.5f - my, dy1 = dy0 + 7.0f;
-    const float umin = l11 * dx0 + (l21 >= 0.0f ? l21 * dy0 : l21 * dy1);
-    const float umax = l11 * dx1 + (l21 >= 0.0f ? l21 * dy1 : l21 * dy0);
-    const float u2 = umin > 0.0f ? umin * umin : (umax < 0.0f ? umax * umax : 0.0f);
-    const float wy = dy0 > 0.0f ? dy0 : (dy1 < 0.0f ? dy1 : 0.0f);
-    const float w2 = (l22 * wy) * (l22 * wy);
-    const float ax = __builtin_fmaxf(__builtin_fabsf(dx0), __builtin_fabsf(dx1));
-    const float ay = __builtin_fmaxf(__builtin_fabsf(dy0), __builtin_fabsf(dy1));
-    const float S = l11 * ax + __builtin_fabsf(l21) * ay, Wm = l22 * ay;
-    const float thr = lim + 4e-6f * (S * S + Wm * Wm);
-    if (!(u2 + w2 > thr)) m |= 1u << q;
+  for (int by = 0; by < NB; ++by) {
+    const float ylo = Y0 + (float)(8 * by), yhi = ylo + 7.0f;
+    const float a = l21 * ylo, b = l21 * yhi;
+    const float lo = ux + __builtin_fminf(a, b), hi = ux7 + __builtin_fmaxf(a, b);
+    const float dw = l22 * __builtin_fmaxf(__builtin_fmaxf(ylo, -yhi), 0.0f);
+    const float w2 = dw * dw;
+#pragma unroll
+    for (int bx = 0; bx < NB; ++bx) {
+      const float ulo = bx ? lo + step : lo, uhi = bx ? hi + step : hi;
+      const float du = __builtin_fmaxf(__builtin_fmaxf(ulo, -uhi), 0.0f);
+      if (!(__builtin_fmaf(du, du, w2) > thr)) m |= 1u << (by * NB + bx);
+    }
   }
   return m;
 }
