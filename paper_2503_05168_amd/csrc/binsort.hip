@@ -69,12 +69,13 @@ struct Rect {
   uint32_t x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ Rect rect_of(const seele_splat& s, const BinView& bv) {
+// Tile rectangle from a record's packed rect_x / rect_y, clipped to its view.
+__device__ __forceinline__ Rect rect_of(uint32_t rect_x, uint32_t rect_y, const BinView& bv) {
   Rect r;
-  r.x1 = min(s.rect_x >> 16, (uint32_t)bv.grid_w);
-  r.y1 = min(s.rect_y >> 16, (uint32_t)bv.grid_h);
-  r.x0 = min(s.rect_x & 0xffffu, r.x1);
-  r.y0 = min(s.rect_y & 0xffffu, r.y1);
+  r.x1 = min(rect_x >> 16, (uint32_t)bv.grid_w);
+  r.y1 = min(rect_y >> 16, (uint32_t)bv.grid_h);
+  r.x0 = min(rect_x & 0xffffu, r.x1);
+  r.y0 = min(rect_y & 0xffffu, r.y1);
   return r;
 }
 
@@ -223,11 +224,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __rest
   }
 }
 
+// Visible records in id order: (depth key, id) at their compacted position,
+// and every record's packed tile rectangle (zero if not visible) into the
+// dense id-indexed array rid, read from the same 16 bytes of the record as
+// the depth.  The later gathers in depth order then touch 8 bytes per record
+// of a small array instead of a 64-byte record each.
 __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n_tiles, int64_t n,
                                                     const seele_splat* __restrict__ splats,
                                                     const uint64_t* __restrict__ partial,
                                                     uint32_t* __restrict__ keys,
-                                                    uint32_t* __restrict__ vals) {
+                                                    uint32_t* __restrict__ vals,
+                                                    uint2* __restrict__ rid) {
   const int w = threadIdx.x >> 6, lane = lane_id();
   const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
   if (begin >= n) return;  // per wave; no barriers below
@@ -236,13 +243,19 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
 #pragma unroll 4
   for (int it = 0; it < kWaveSpan / 64; ++it) {
     const int64_t idx = begin + it * 64 + lane;
-    const bool f = idx < n && n_tiles[idx] > 0;
+    const bool in = idx < n;
+    const bool f = in && n_tiles[idx] > 0;
     const uint64_t bal = __ballot(f);
+    uint2 rr = make_uint2(0u, 0u);
     if (f) {
+      // depth, rect_x, rect_y: the record's fourth 16-byte quarter
+      const float4 q = reinterpret_cast<const float4*>(splats + idx)[3];
       const uint32_t pos = carry + (uint32_t)__popcll(bal & lt);
-      keys[pos] = __float_as_uint(splats[idx].depth);
+      keys[pos] = __float_as_uint(q.x);
       vals[pos] = (uint32_t)idx;
+      rr = make_uint2(__float_as_uint(q.y), __float_as_uint(q.z));
     }
+    if (in) rid[idx] = rr;
     carry += (uint32_t)__popcll(bal);
   }
 }
@@ -426,7 +439,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
 // the rectangle) and entries (super-tiles it touches); per-wave sums of both
 // over the same wave spans as the compaction.
 __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ ids,
-                                                   const seele_splat* __restrict__ splats,
+                                                   const uint2* __restrict__ rid,
                                                    BinViews views, const Hdr* __restrict__ hdr,
                                                    uint32_t* __restrict__ rx_s,
                                                    uint32_t* __restrict__ ry_s,
@@ -442,7 +455,8 @@ __global__ __launch_bounds__(B) void k_pair_count(const uint32_t* __restrict__ i
       const int64_t i = begin + it * 64 + lane;
       if (i < nv) {
         const uint32_t id = ids[i];
-        const Rect r = rect_of(splats[id], views.v[view_of(id, views)]);
+        const uint2 rr = rid[id];
+        const Rect r = rect_of(rr.x, rr.y, views.v[view_of(id, views)]);
         const uint32_t m = st_count(r);
         if (m > 0) c += (uint64_t)(r.x1 - r.x0) * (r.y1 - r.y0);
         rx_s[i] = r.x0 | (r.x1 << 16);
@@ -986,6 +1000,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_svals1 = 0;  // the second value buffer is the caller's sorted_ids
   p.off_rx = take(4 * (size_t)n_records);
   p.off_ry = take(4 * (size_t)n_records);
+  p.off_rid = take(8 * (size_t)n_records);
   p.off_hist = take(4 * 256 * (size_t)nb_hist);
   p.off_digits = take(4 * 256);
   p.off_st_range = take(8 * (size_t)p.max_st);
@@ -1009,6 +1024,7 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   uint32_t* dk[2] = {at(p.off_dkeys0), at(p.off_dkeys1)};
   uint32_t* dv[2] = {at(p.off_dvals0), at(p.off_dvals1)};
   uint32_t* rx_s = at(p.off_rx);
+  uint2* rid = reinterpret_cast<uint2*>(at(p.off_rid));
   uint32_t* ry_s = at(p.off_ry);
   uint32_t* hist = at(p.off_hist);
   uint32_t* digits = at(p.off_digits);
@@ -1037,7 +1053,7 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
                        WAVES * (int64_t)nbR, hdr, 0, p.capacity, num_pairs);
     hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats, partial,
-                       dk[0], dv[0]);
+                       dk[0], dv[0], rid);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     //    stable sort by float32 depth bits (4 x 8-bit passes, ends in buffer 0)
     for (int pass = 0; pass < 4; ++pass) {
@@ -1047,7 +1063,7 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
       if (e != hipSuccess) return e;
     }
     // 2. pair and entry totals (pairs -> num_pairs)
-    hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], splats, views, hdr,
+    hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], rid, views, hdr,
                        rx_s, ry_s, partial, partial2);
   }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,

@@ -233,7 +233,7 @@ struct BinSortPlan {
   int64_t max_seg;        // bound on write segments
   // workspace carve-up (byte offsets)
   size_t off_hdr, off_partial, off_partial2, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
-  size_t off_skeys0, off_skeys1, off_svals0, off_svals1, off_rx, off_ry;
+  size_t off_skeys0, off_skeys1, off_svals0, off_svals1, off_rx, off_ry, off_rid;
   size_t off_hist, off_digits, off_st_range, off_st_seg, off_seg_st, off_seg_cnt;
   size_t off_tile_cnt, off_tile_start, total;
 };
