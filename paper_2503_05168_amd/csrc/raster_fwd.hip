@@ -158,8 +158,12 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
 
   // Staging loads are software-pipelined: while a batch is blended, each
   // staging thread already has the next batch's record and the id of the
-  // batch after in flight.
+  // batch after in flight.  Once three quarters of the tile's pixels have
+  // stopped, the tile is likely to end within the batch, so the look-ahead
+  // stops (ahead = false) and a batch that is still needed loads its records
+  // when it starts (pid then holds the current batch's id).
   const bool stager = tid < BATCH;
+  bool ahead = true;  // uniform over the block
   float4 pa = make_float4(0.0f, 0.0f, 0.0f, 0.0f), pb = pa;
   float pblue = 0.0f;
   uint32_t pid = 0;
@@ -172,8 +176,18 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   if (stager && BATCH + tid < n) pid = ids[start + BATCH + tid];
 
   for (int base = 0; base < n; base += BATCH) {
-    if (__syncthreads_count(T < 0.0f) == NT) break;
+    const int stopped = __syncthreads_count(T < 0.0f);
+    if (stopped == NT) break;
     const int j = base + tid;
+    if (!ahead) {
+      if (stager && j < n) {
+        const float4* src = reinterpret_cast<const float4*>(splats + pid);
+        pa = src[0];
+        pb = src[1];
+        pblue = src[2].x;
+      }
+      if (stager && j + BATCH < n) pid = ids[start + j + BATCH];
+    }
     if (stager && j < n) {
       s_rec[tid].a = pa;
       s_rec[tid].b = pb;
@@ -182,7 +196,8 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
                                          tile_y * TS);
     }
     __syncthreads();
-    if (stager && j + BATCH < n) {
+    ahead = 4 * stopped < 3 * NT;
+    if (ahead && stager && j + BATCH < n) {
       const float4* src = reinterpret_cast<const float4*>(splats + pid);
       pa = src[0];
       pb = src[1];
