@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=24)
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
+    ap.add_argument("--lists", choices=("super", "tile"), default="super",
+                    help="list form of the timed frame: super-tile lists read by each tile "
+                         "(default) or per-tile lists")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="first copy 256 MiB device to device (a known-size kernel that "
                          "scales hardware byte counters)")
@@ -108,7 +111,7 @@ def build_forms(names, n):
     return scene, cams, forms
 
 
-def run_form(name, form, cams, steps, warmup):
+def run_form(name, form, cams, steps, warmup, lists="super"):
     import torch
     import paper_2503_05168_amd as P
 
@@ -124,10 +127,12 @@ def run_form(name, form, cams, steps, warmup):
     dev = g.means.device
     one = [cams[0]]
     TT = P.total_tiles(one, st.tile)
+    NS = P.total_super_tiles(one, st.tile)
+    sup = lists == "super"
     npix = P.pixel_count(one)
     splats = torch.empty((n, P.pipeline.SPLAT_FLOATS), dtype=torch.float32, device=dev)
     n_tiles = torch.empty(n, dtype=torch.int32, device=dev)
-    ranges = torch.empty((TT, 2), dtype=torch.int32, device=dev)
+    ranges = torch.empty((NS if sup else TT, 2), dtype=torch.int32, device=dev)
     image = torch.empty(3 * npix, dtype=torch.float32, device=dev)
     final_T = torch.empty(npix, dtype=torch.float32, device=dev)
     n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
@@ -141,8 +146,25 @@ def run_form(name, form, cams, steps, warmup):
     ws = torch.empty(P.pipeline.bin_sort_workspace_size(n, capacity, TT), dtype=torch.uint8,
                      device=dev)
     ids = torch.empty(capacity, dtype=torch.int32, device=dev)
+    keys = torch.empty(capacity if sup else 1, dtype=torch.int32, device=dev)
     npairs_log = torch.zeros(steps, dtype=torch.int64, device=dev)
     npairs = torch.empty(1, dtype=torch.int64, device=dev)
+
+    def binning(cam):
+        if sup:
+            P.seele_bin_sort_super(splats, n_tiles, n, cam, st.tile, capacity, ws, keys, ids,
+                                   ranges, npairs)
+        else:
+            P.seele_bin_sort(splats, n_tiles, n, cam, st.tile, capacity, ws, ids, ranges, npairs)
+
+    def raster(cam, counters=None):
+        if sup:
+            P.seele_rasterize_fwd_super(splats, keys, ids, ranges, cam, st, image, final_T,
+                                        n_contrib, counters)
+        elif counters is not None:
+            counters.copy_(P.seele_rasterize_fwd_counted(splats, ids, ranges, cam, st)[3])
+        else:
+            P.seele_rasterize_fwd(splats, ids, ranges, cam, st, image, final_T, n_contrib)
 
     def step(v, ev=None):
         cam = [cams[v]]
@@ -151,10 +173,10 @@ def run_form(name, form, cams, steps, warmup):
         P.seele_preprocess(g, cam, st, segs[v], splats, n_tiles)
         if ev is not None:
             ev[1].record()
-        P.seele_bin_sort(splats, n_tiles, n, cam, st.tile, capacity, ws, ids, ranges, npairs)
+        binning(cam)
         if ev is not None:
             ev[2].record()
-        P.seele_rasterize_fwd(splats, ids, ranges, cam, st, image, final_T, n_contrib)
+        raster(cam)
         if ev is not None:
             ev[3].record()
 
@@ -177,16 +199,17 @@ def run_form(name, form, cams, steps, warmup):
     stage = {k: v / steps for k, v in stage.items()}
 
     # work counters and visible counts for the views that were timed (untimed pass)
-    vis, act, pairs, cnt = [], [], [], []
+    vis, act, pairs, ents, cnt = [], [], [], [], []
+    c = torch.zeros(6, dtype=torch.int64, device=dev)
     for i in range(min(steps, V)):
         v = i % V
         P.seele_preprocess(g, [cams[v]], st, segs[v], splats, n_tiles)
         vis.append(int((n_tiles > 0).sum().item()))
-        act.append(n if segs[v] is None else sum(c for _, c in segs[v]))
-        P.seele_bin_sort(splats, n_tiles, n, [cams[v]], st.tile, capacity, ws, ids, ranges,
-                         npairs)
+        act.append(n if segs[v] is None else sum(c_ for _, c_ in segs[v]))
+        binning([cams[v]])
         pairs.append(int(npairs.item()))
-        c = P.seele_rasterize_fwd_counted(splats, ids, ranges, [cams[v]], st)[3]
+        ents.append(int(ranges[:, 1].max().item()) if sup else 0)
+        raster([cams[v]], c)
         cnt.append([int(x) for x in c.cpu().tolist()])
     torch.cuda.synchronize()
     k = len(cnt)
@@ -196,7 +219,9 @@ def run_form(name, form, cams, steps, warmup):
     need = mean([c[4] + c[2] for c in cnt])  # evaluations left to the culled kernel
     ms = 1000.0 * wall / steps
     out = dict(fps=1000.0 / ms, ms_per_frame=ms, stage_ms=stage, capacity=capacity,
-               pairs=mean(pairs), visible=mean(vis), active=mean(act),
+               lists=lists, super_tiles=NS, tiles=TT, pairs=mean(pairs),
+               entries=mean(ents) if sup else None,
+               visible=mean(vis), active=mean(act),
                evals=evals, blends=blends, evals_needed=need,
                block_visits=mean([c[5] for c in cnt]),
                leader_tests=mean([c[2] for c in cnt]), leader_pass=mean([c[3] for c in cnt]),
@@ -431,7 +456,7 @@ def main():
     scene, cams, forms = build_forms(names, args.n)
     results = {}
     for name in names:
-        results[name] = run_form(name, forms[name], cams, args.steps, args.warmup)
+        results[name] = run_form(name, forms[name], cams, args.steps, args.warmup, args.lists)
         log(f"[bench] t+{time.time() - t_start:.0f}s form {name} done")
     fwd_bwd = None
     if not args.no_bwd:
@@ -454,7 +479,13 @@ def main():
     r_ach = r_ops / (st["raster"] * 1e-3) / 1e12
     p_bytes = 48 * head["active"] + 256 * head["visible"]
     p_ach = p_bytes / (st["preprocess"] * 1e-3) / 1e9
-    b_bytes = 16 * head["visible"] + 4 * head["pairs"] + 8 * 8160
+    # binning: 16 B per visible record (depth key, id, rectangle) plus its
+    # output -- 8 B per super-tile entry (key, id) and 8 B per super-tile
+    # range, or 4 B per pair and 8 B per tile range for per-tile lists
+    if head.get("lists") == "super":
+        b_bytes = 16 * head["visible"] + 8 * head["entries"] + 8 * head["super_tiles"]
+    else:
+        b_bytes = 16 * head["visible"] + 4 * head["pairs"] + 8 * head["tiles"]
     b_ach = b_bytes / (st["bin_sort"] * 1e-3) / 1e9
     stage_roof = {
         "raster": dict(bound="alu", achieved=r_ach, peak=PEAK_LANE_OPS / 1e12,
@@ -466,8 +497,9 @@ def main():
     }
     # the dominant single kernel: the rasterizer or the preprocessing kernel
     if st["raster"] >= st["preprocess"]:
-        roof = dict(stage_roof["raster"], kernel="raster_fwd",
-                    traffic=measured_traffic("raster_fwd_plain_c2_1080p_3M"),
+        kname = "raster_fwd_super" if head.get("lists") == "super" else "raster_fwd"
+        roof = dict(stage_roof["raster"], kernel=kname,
+                    traffic=measured_traffic(f"{kname}_plain_c2_1080p_3M"),
                     traffic_unit="bytes/launch")
     else:
         roof = dict(stage_roof["preprocess"], kernel="preprocess", traffic=None)
@@ -491,7 +523,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"outdoor-shaped scene, {args.n} Gaussians (64 clusters + 10% "
                                 f"shell, seed 2), 32-view orbit r=4, 1920x1080, 16x16 tiles, "
-                                f"plain 3DGS forward (preprocess + bin/sort + raster)"),
+                                f"plain 3DGS forward (preprocess + bin/sort + raster), "
+                                f"{args.lists} lists"),
                    "gaussians": args.n, "views": 32, "width": 1920, "height": 1080, "tile": 16},
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "fwd_bwd_ms_per_view": (None if fwd_bwd is None else

@@ -190,6 +190,35 @@ int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_
                        int64_t capacity, int32_t* tile_ranges, int64_t* num_pairs,
                        void* stream);
 
+/* Super-tiles are blocks of 4 x 4 tiles, ceil(ceil(W/tile)/4) *
+ * ceil(ceil(H/tile)/4) per view, numbered row-major per view after the
+ * previous views' ones.  This returns their number over the views (the
+ * length of the st_ranges array), or -1 on bad arguments.  cams is a host
+ * array. */
+int64_t seele_total_super_tiles(const seele_camera* cams, int32_t n_views, int32_t tile);
+
+/* The binning and depth sort of seele_bin_sort (Sec. 3.1 "Sorting"), left at
+ * super-tile granularity: every record with n_tiles > 0 yields one entry per
+ * super-tile its tile rectangle touches, and the entries are ordered by
+ * (global super-tile id, float32 depth, record id).
+ *   entry_keys device [capacity] uint32: (clip << 24) | global super-tile id,
+ *              clip = the rectangle clipped to the super-tile as local
+ *              inclusive tile coordinates x0 | x1 << 2 | y0 << 4 | y1 << 6
+ *   entry_ids  device [capacity] uint32: record ids v*n + i, same order
+ *   st_ranges  device [n_super_tiles][2] int32: [start, end) into the entries
+ *              (start = end = 0 for an empty super-tile)
+ *   num_pairs  device [1] int64: Gaussian-tile pairs the frame needs (as for
+ *              seele_bin_sort; entries never outnumber pairs).
+ * Tile t's list of seele_bin_sort is exactly the subsequence of its
+ * super-tile's entries whose clip covers t.  Workspace, capacity, overflow
+ * (every range empty, entries not written) and limits are those of
+ * seele_bin_sort; the workspace size is seele_bin_sort_workspace_size's. */
+int32_t seele_bin_sort_super(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+                             const seele_camera* cams, int32_t n_views, int32_t tile,
+                             void* workspace, size_t workspace_bytes, uint32_t* entry_keys,
+                             uint32_t* entry_ids, int64_t capacity, int32_t* st_ranges,
+                             int64_t* num_pairs, void* stream);
+
 /* Front-to-back blending of every tile of every view (Eqs. 1-2; Algorithm 1
  * when opts->mode == SEELE_RASTER_CONTRIB).
  *   image     device, per view [3][H][W] float32, views concatenated
@@ -201,6 +230,19 @@ int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_id
                             const int32_t* tile_ranges, const seele_camera* cams,
                             int32_t n_views, const seele_raster_opts* opts, float* image,
                             float* final_T, int32_t* n_contrib, void* stream);
+
+/* seele_rasterize_fwd reading the super-tile lists of seele_bin_sort_super
+ * (each tile keeps the entries whose clip covers it, in list order): the
+ * outputs are bit-identical to seele_rasterize_fwd on the per-tile lists,
+ * and n_contrib still counts positions in the tile's own list.  counters:
+ * NULL, or device [6] uint64 as for seele_rasterize_fwd_counted (then the
+ * instrumented kernel runs).  Default LDS batch (opts->lds_batch 0 or
+ * tile * tile) only; SEELE_ERR_UNSUPPORTED otherwise. */
+int32_t seele_rasterize_fwd_super(const seele_splat* splats, const uint32_t* entry_keys,
+                                  const uint32_t* entry_ids, const int32_t* st_ranges,
+                                  const seele_camera* cams, int32_t n_views,
+                                  const seele_raster_opts* opts, float* image, float* final_T,
+                                  int32_t* n_contrib, uint64_t* counters, void* stream);
 
 /* Order of the (view, tile) work queue of seele_rasterize_fwd_queue. */
 enum {

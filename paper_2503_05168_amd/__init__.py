@@ -12,7 +12,9 @@ from .pipeline import (  # noqa: F401
     CapacityError,
     seele_preprocess,
     seele_bin_sort,
+    seele_bin_sort_super,
     seele_rasterize_fwd,
+    seele_rasterize_fwd_super,
     seele_rasterize_fwd_counted,
     seele_rasterize_fwd_queue,
     seele_rasterize_bwd,
@@ -21,6 +23,7 @@ from .pipeline import (  # noqa: F401
     seele_hp_select,
     seele_hp_segments,
     total_tiles,
+    total_super_tiles,
     pixel_count,
     split_views,
 )

@@ -70,9 +70,17 @@ SIGNATURES = {
     "seele_bin_sort": (c_int32, [c_void_p, c_void_p, c_int64, POINTER(seele_camera), c_int32,
                                  c_int32, c_void_p, c_size_t, c_void_p, c_int64, c_void_p,
                                  c_void_p, c_void_p]),
+    "seele_total_super_tiles": (c_int64, [POINTER(seele_camera), c_int32, c_int32]),
+    "seele_bin_sort_super": (c_int32, [c_void_p, c_void_p, c_int64, POINTER(seele_camera),
+                                       c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
+                                       c_int64, c_void_p, c_void_p, c_void_p]),
     "seele_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
                                       c_int32, POINTER(seele_raster_opts), c_void_p, c_void_p,
                                       c_void_p, c_void_p]),
+    "seele_rasterize_fwd_super": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                            POINTER(seele_camera), c_int32,
+                                            POINTER(seele_raster_opts), c_void_p, c_void_p,
+                                            c_void_p, c_void_p, c_void_p]),
     "seele_raster_queue_workspace_size": (c_size_t, [c_int64]),
     "seele_rasterize_fwd_queue": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
                                             c_int32, POINTER(seele_raster_opts), c_int32,

@@ -36,8 +36,6 @@ constexpr int WAVES = B / 64;
 constexpr int ST = kSuperTile;
 constexpr int ST2 = ST * ST;
 constexpr int kSegLen = 1024;      // super-tile list entries per write segment
-constexpr int kClipShift = 24;     // entry key = clipped rectangle << 24 | super-tile
-constexpr uint32_t kStMask = (1u << kClipShift) - 1u;
 constexpr int kMaxGrid = 2048;     // workgroups of the loops over device-side counts
 
 struct Hdr {
@@ -119,14 +117,6 @@ __device__ __forceinline__ StLoc st_locate(const BinViews& views, uint32_t s) {
   L.nx = min(ST, bv.grid_w - sx * ST);
   L.ny = min(ST, bv.grid_h - sy * ST);
   return L;
-}
-
-// 16-bit coverage mask of an entry over its super-tile's tiles (bit 4 iy + ix).
-__device__ __forceinline__ uint32_t clip_mask(uint32_t clip) {
-  const uint32_t xm = ((2u << ((clip >> 2) & 3u)) - 1u) & ~((1u << (clip & 3u)) - 1u);
-  const uint32_t y0 = (clip >> 4) & 3u, y1 = (clip >> 6) & 3u;
-  const uint32_t rows = ((2u << (4u * y1 + 3u)) - 1u) & ~((1u << (4u * y0)) - 1u);
-  return (xm * 0x1111u) & rows;
 }
 
 // ---- visible-record compaction.  Wave w of block b owns records
@@ -1015,7 +1005,8 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
 
 hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,
                            const int32_t* n_tiles, void* ws, uint32_t* sorted_ids,
-                           int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream) {
+                           int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream,
+                           bool super, uint32_t* entry_keys) {
   char* base = static_cast<char*>(ws);
   auto at = [&](size_t o) { return reinterpret_cast<uint32_t*>(base + o); };
   Hdr* hdr = reinterpret_cast<Hdr*>(base + p.off_hdr);
@@ -1028,7 +1019,8 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   uint32_t* ry_s = at(p.off_ry);
   uint32_t* hist = at(p.off_hist);
   uint32_t* digits = at(p.off_digits);
-  int32_t* st_range = reinterpret_cast<int32_t*>(base + p.off_st_range);
+  // super-tile ranges: the caller's array for super-tile lists
+  int32_t* st_range = super ? tile_ranges : reinterpret_cast<int32_t*>(base + p.off_st_range);
   uint32_t* st_seg = at(p.off_st_seg);
   uint4* seg_meta = reinterpret_cast<uint4*>(base + p.off_seg_st);
   uint32_t* seg_cnt = at(p.off_seg_cnt);
@@ -1071,16 +1063,24 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial2,
                      WAVES * (int64_t)nbR, hdr, 2, p.capacity, num_pairs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  //    entries, then sorted by super-tile id (balanced digit widths <= 8); the
-  //    value buffers alternate between svals0 and sorted_ids so that the last
-  //    pass ends in svals0
+  //    entries, then sorted by super-tile id (balanced digit widths <= 8).
+  //    Per-tile lists: the value buffers alternate between svals0 and
+  //    sorted_ids so that the last pass ends in svals0.  Super-tile lists:
+  //    keys and values end in the caller's entry_keys and sorted_ids.
   int st_bits = 0;
   while (st_bits < 24 && ((int64_t)1 << st_bits) < n_st) ++st_bits;
   const int passes = std::max(1, (st_bits + 7) / 8);
   const int per = (st_bits + passes - 1) / passes;
+  const int fin = passes & 1;  // buffer index the last pass writes
   uint32_t* sk[2] = {at(p.off_skeys0), at(p.off_skeys1)};
   uint32_t* sv[2] = {(passes % 2 == 0) ? at(p.off_svals0) : sorted_ids,
                      (passes % 2 == 0) ? sorted_ids : at(p.off_svals0)};
+  if (super) {
+    sk[fin] = entry_keys;
+    sk[fin ^ 1] = at(p.off_skeys0);
+    sv[fin] = sorted_ids;
+    sv[fin ^ 1] = at(p.off_svals0);
+  }
   if (nbR > 0)
     hipLaunchKernelGGL(k_entry_emit, dim3(nbR), dim3(B), 0, stream, dv[0], rx_s, ry_s, views, hdr,
                        partial2, p.capacity, sk[0], sv[0]);
@@ -1093,12 +1093,13 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     if (e != hipSuccess) return e;
     shift += bits;
   }
-  const uint32_t* ekeys = sk[passes & 1];
-  const uint32_t* evals = sv[passes & 1];
+  const uint32_t* ekeys = sk[fin];
+  const uint32_t* evals = sv[fin];
   // 3. super-tile ranges, segments, per-tile counts, tile ranges, write
   if (p.capacity > 0)
     hipLaunchKernelGGL(k_st_ranges, dim3(grid_for((p.capacity + 255) / 256)), dim3(256), 0,
                        stream, ekeys, hdr, st_range);
+  if (super) return hipGetLastError();
   const int nbS = (int)nblocks_for(n_st);
   if (nbS > 0) {
     hipLaunchKernelGGL(k_seg_count, dim3(nbS), dim3(B), 0, stream, st_range, n_st, partial);

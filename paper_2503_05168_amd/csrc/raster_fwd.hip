@@ -102,11 +102,21 @@ __device__ __forceinline__ void blend_select(float fx, float fy, const float4& a
 // The tile list is consumed in LDS batches of BATCH records (<= TS*TS: threads
 // tid < BATCH stage one record each); BATCH trades barrier and early-exit
 // granularity against LDS latency and is chosen by the autotuner.
-template <int TS, int MODE, bool COUNT, int BATCH>
+//
+// SUPER: the tile reads its super-tile's depth-ordered entry list instead of
+// a list of its own (ids = entry record ids, ekeys = entry keys, ranges =
+// super-tile ranges).  Each staging thread takes two entries per batch; the
+// entries whose clipped rectangle covers the tile are compacted, in list
+// order, into the batch (so a batch holds up to 2 * BATCH records), and the
+// running count of covered entries gives each record's position in the
+// tile's own list.  Everything after staging is shared, so the outputs are
+// bit-identical to the per-tile lists'.
+template <int TS, int MODE, bool COUNT, int BATCH, bool SUPER = false>
 __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& views,
                                             const RasterParams& rp,
                                             const seele_splat* __restrict__ splats,
                                             const uint32_t* __restrict__ ids,
+                                            const uint32_t* __restrict__ ekeys,
                                             const int32_t* __restrict__ ranges,
                                             float* __restrict__ image,
                                             float* __restrict__ final_T,
@@ -115,9 +125,13 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   constexpr int NT = TS * TS;
   constexpr int NW = NT / 64;
   static_assert(BATCH <= NT && BATCH % 64 == 0 || BATCH == NT, "batch depth");
-  __shared__ LdsRec s_rec[BATCH];
-  __shared__ uint8_t s_qm[BATCH];
+  constexpr int CAP = SUPER ? 2 * BATCH : BATCH;  // records per LDS batch
+  constexpr int E = CAP;                          // list entries per batch
+  constexpr int SW = BATCH / 64;                  // staging waves
+  __shared__ LdsRec s_rec[CAP];
+  __shared__ uint8_t s_qm[CAP];
   __shared__ uint8_t s_list[NW][64];
+  __shared__ uint32_t s_wc[2][SW];
   __shared__ unsigned long long s_cnt[6];
   uint32_t c_eval = 0, c_blend = 0, c_ltest = 0, c_lpass = 0, c_need = 0, c_visit = 0;
   if (COUNT) {
@@ -147,8 +161,19 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   const float lfy = (float)(tile_y * TS + wy + (tg / gpr) * gh) + 0.5f;
   const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
 
-  const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
-  const int start = ranges[ri], n = ranges[ri + 1] - start;
+  int start, n;
+  int tloc = 0;  // SUPER: the tile's bit in an entry's coverage mask
+  if (SUPER) {
+    const int sgw = (rv.grid_w + kSuperTile - 1) / kSuperTile;
+    const int64_t s = (int64_t)rv.st_base + (tile_y / kSuperTile) * sgw + tile_x / kSuperTile;
+    start = ranges[2 * s];
+    n = ranges[2 * s + 1] - start;
+    tloc = (tile_y % kSuperTile) * kSuperTile + tile_x % kSuperTile;
+  } else {
+    const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
+    start = ranges[ri];
+    n = ranges[ri + 1] - start;
+  }
   const float amin = rp.alpha_min, inv_amin = rp.inv_alpha_min;
   const float amax = rp.alpha_max, tmin = rp.T_min;
 
@@ -167,44 +192,130 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   float4 pa = make_float4(0.0f, 0.0f, 0.0f, 0.0f), pb = pa;
   float pblue = 0.0f;
   uint32_t pid = 0;
-  if (stager && tid < n) {
-    const float4* src = reinterpret_cast<const float4*>(splats + ids[start + tid]);
-    pa = src[0];
-    pb = src[1];
-    pblue = src[2].x;
+  // SUPER state of the thread's two entries r = 0, 1 (entries base + r*BATCH
+  // + tid): covered flag and record of the batch to stage; key and id of the
+  // next batch (of the current one while ahead is false).
+  bool cv0 = false, cv1 = false;
+  float4 qa1 = pa, qb1 = pa;
+  float ql1 = 0.0f;
+  uint32_t nk0 = 0, nk1 = 0, ni1 = 0;
+  int run = 0;  // SUPER: covered entries before the batch (block-uniform)
+  auto covers = [&](uint32_t key) { return ((clip_mask(key >> kClipShift) >> tloc) & 1u) != 0u; };
+  auto load_rec = [&](uint32_t id, float4& a, float4& b, float& bl) {
+    const float4* src = reinterpret_cast<const float4*>(splats + id);
+    a = src[0];
+    b = src[1];
+    bl = src[2].x;
+  };
+  // SUPER: make (cv, q) the batch of entries j0, j0 + BATCH from (nk, ni),
+  // then load the keys and ids of the batch after into (nk, ni)
+  auto super_step = [&](int j0) {
+    const int j1 = j0 + BATCH;
+    cv0 = j0 < n && covers(nk0);
+    cv1 = j1 < n && covers(nk1);
+    if (cv0) load_rec(pid, pa, pb, pblue);
+    if (cv1) load_rec(ni1, qa1, qb1, ql1);
+    if (j0 + E < n) {
+      nk0 = ekeys[start + j0 + E];
+      pid = ids[start + j0 + E];
+    }
+    if (j1 + E < n) {
+      nk1 = ekeys[start + j1 + E];
+      ni1 = ids[start + j1 + E];
+    }
+  };
+  if (SUPER) {
+    if (stager && tid < n) {
+      nk0 = ekeys[start + tid];
+      pid = ids[start + tid];
+    }
+    if (stager && BATCH + tid < n) {
+      nk1 = ekeys[start + BATCH + tid];
+      ni1 = ids[start + BATCH + tid];
+    }
+    if (stager) super_step(tid);
+  } else {
+    if (stager && tid < n) load_rec(ids[start + tid], pa, pb, pblue);
+    if (stager && BATCH + tid < n) pid = ids[start + BATCH + tid];
   }
-  if (stager && BATCH + tid < n) pid = ids[start + BATCH + tid];
 
-  for (int base = 0; base < n; base += BATCH) {
+  for (int base = 0; base < n; base += E) {
     const int stopped = __syncthreads_count(T < 0.0f);
     if (stopped == NT) break;
     const int j = base + tid;
-    if (!ahead) {
+    int cnt;
+    if (SUPER) {
+      if (!ahead && stager) super_step(j);
+      const uint64_t b0 = __ballot(cv0), b1 = __ballot(cv1);
+      if (stager && lane == 0) {
+        s_wc[0][wave] = (uint32_t)__popcll(b0);
+        s_wc[1][wave] = (uint32_t)__popcll(b1);
+      }
+      __syncthreads();
+      uint32_t off0 = 0, off1 = 0, tot0 = 0, tot1 = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < SW; ++w2) {
+        const uint32_t c0w = s_wc[0][w2], c1w = s_wc[1][w2];
+        if (w2 < wave) {
+          off0 += c0w;
+          off1 += c1w;
+        }
+        tot0 += c0w;
+        tot1 += c1w;
+      }
+      cnt = (int)(tot0 + tot1);
+      const uint32_t r0 = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u));
+      const uint32_t r1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
+      if (cv0) {
+        const uint32_t sl = off0 + r0;
+        s_rec[sl].a = pa;
+        s_rec[sl].b = pb;
+        s_rec[sl].blue = pblue;
+        s_qm[sl] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, inv_amin,
+                                          tile_x * TS, tile_y * TS);
+      }
+      if (cv1) {
+        const uint32_t sl = tot0 + off1 + r1;
+        s_rec[sl].a = qa1;
+        s_rec[sl].b = qb1;
+        s_rec[sl].blue = ql1;
+        s_qm[sl] = (uint8_t)quad_mask<TS>(qa1.x, qa1.y, qa1.z, qa1.w, qb1.x, qb1.y, inv_amin,
+                                          tile_x * TS, tile_y * TS);
+      }
+      __syncthreads();
+      ahead = 4 * stopped < 3 * NT;
+      if (ahead && stager) super_step(j + E);
+    } else {
+      if (!ahead) {
+        if (stager && j < n) {
+          const float4* src = reinterpret_cast<const float4*>(splats + pid);
+          pa = src[0];
+          pb = src[1];
+          pblue = src[2].x;
+        }
+        if (stager && j + BATCH < n) pid = ids[start + j + BATCH];
+      }
       if (stager && j < n) {
+        s_rec[tid].a = pa;
+        s_rec[tid].b = pb;
+        s_rec[tid].blue = pblue;
+        s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, inv_amin, tile_x * TS,
+                                           tile_y * TS);
+      }
+      __syncthreads();
+      ahead = 4 * stopped < 3 * NT;
+      if (ahead && stager && j + BATCH < n) {
         const float4* src = reinterpret_cast<const float4*>(splats + pid);
         pa = src[0];
         pb = src[1];
         pblue = src[2].x;
+        if (j + 2 * BATCH < n) pid = ids[start + j + 2 * BATCH];
       }
-      if (stager && j + BATCH < n) pid = ids[start + j + BATCH];
+      cnt = min(BATCH, n - base);
     }
-    if (stager && j < n) {
-      s_rec[tid].a = pa;
-      s_rec[tid].b = pb;
-      s_rec[tid].blue = pblue;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, inv_amin, tile_x * TS,
-                                         tile_y * TS);
-    }
-    __syncthreads();
-    ahead = 4 * stopped < 3 * NT;
-    if (ahead && stager && j + BATCH < n) {
-      const float4* src = reinterpret_cast<const float4*>(splats + pid);
-      pa = src[0];
-      pb = src[1];
-      pblue = src[2].x;
-      if (j + 2 * BATCH < n) pid = ids[start + j + 2 * BATCH];
-    }
-    const int cnt = min(BATCH, n - base);
+    const int lbase = SUPER ? run : base;  // list position of the batch's first record
     if (COUNT && MODE == 0) {
       for (int k = 0; k < cnt; ++k) {
         if (__ballot(T >= 0.0f) == 0) break;
@@ -213,7 +324,7 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         if (T >= 0.0f) {
           ++c_eval;
           if (bit) ++c_need;
-          if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
+          if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, lbase + k + 1, amin,
                          amax, tmin, T, c0, c1, c2, last))
             ++c_blend;
         }
@@ -236,14 +347,14 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
           if (lane == 0) {
             c_ltest += (uint32_t)__popcll(glive);
             c_lpass += (uint32_t)__popcll(glive & gm);
-            if ((s_qm[k0 + s] >> wave) & 1u) ++c_visit;
+            if (live != 0 && ((s_qm[k0 + s] >> wave) & 1u)) ++c_visit;
           }
           if (gm == 0) continue;
           if (T >= 0.0f && ((gm >> grp) & 1ull)) {
             const int k = k0 + s;
             ++c_eval;
             ++c_need;
-            if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
+            if (blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, lbase + k + 1, amin,
                            amax, tmin, T, c0, c1, c2, last))
               ++c_blend;
           }
@@ -275,13 +386,13 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
             const int kb = c + __builtin_amdgcn_readlane(packed, i & 63);
             const float4 ba = s_rec[kb].a, bb = s_rec[kb].b;
             const float bbl = s_rec[kb].blue;
-            blend_select(fx, fy, aa, ab, abl, base + ka + 1, amin, amax, tmin, T, c0, c1, c2, last);
+            blend_select(fx, fy, aa, ab, abl, lbase + ka + 1, amin, amax, tmin, T, c0, c1, c2, last);
             if (i >= nsel) break;
             ka = c + __builtin_amdgcn_readlane(packed, (i + 1) & 63);
             aa = s_rec[ka].a;
             ab = s_rec[ka].b;
             abl = s_rec[ka].blue;
-            blend_select(fx, fy, ba, bb, bbl, base + kb + 1, amin, amax, tmin, T, c0, c1, c2, last);
+            blend_select(fx, fy, ba, bb, bbl, lbase + kb + 1, amin, amax, tmin, T, c0, c1, c2, last);
             if (i + 1 >= nsel) break;
           }
         } else {
@@ -307,7 +418,7 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
               if (gm == 0) continue;  // no leader of this wave accepts it: wave-uniform skip
               const int k = __builtin_amdgcn_readlane(kk, s * G);
               if ((gm >> grp) & 1ull)
-                blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, base + k + 1, amin,
+                blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, lbase + k + 1, amin,
                            amax, tmin, T, c0, c1, c2, last);
             }
             if (__ballot(T >= 0.0f) == 0) break;
@@ -316,6 +427,7 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         }
       }
     }
+    if (SUPER) run += cnt;
     __syncthreads();
   }
 
@@ -353,8 +465,19 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd(RasterViews views, Raster
                                                        float* __restrict__ final_T,
                                                        int32_t* __restrict__ n_contrib,
                                                        unsigned long long* __restrict__ counters) {
-  raster_tile<TS, MODE, COUNT, BATCH>(blockIdx.x, views, rp, splats, ids, ranges, image, final_T,
-                                      n_contrib, counters);
+  raster_tile<TS, MODE, COUNT, BATCH>(blockIdx.x, views, rp, splats, ids, nullptr, ranges, image,
+                                      final_T, n_contrib, counters);
+}
+
+// One workgroup per (view, tile) reading the tile's super-tile list.
+template <int TS, int MODE, bool COUNT, int BATCH>
+__global__ __launch_bounds__(TS* TS) void k_raster_fwd_super(
+    RasterViews views, RasterParams rp, const seele_splat* __restrict__ splats,
+    const uint32_t* __restrict__ entry_ids, const uint32_t* __restrict__ entry_keys,
+    const int32_t* __restrict__ st_ranges, float* __restrict__ image, float* __restrict__ final_T,
+    int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ counters) {
+  raster_tile<TS, MODE, COUNT, BATCH, true>(blockIdx.x, views, rp, splats, entry_ids, entry_keys,
+                                            st_ranges, image, final_T, n_contrib, counters);
 }
 
 // Persistent form for batches of views: a fixed grid of workgroups pulls
@@ -376,8 +499,8 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd_queue(
     __syncthreads();
     if (item >= n_items) break;
     const int t = (int)(order ? order[item] : item);
-    raster_tile<TS, MODE, false, BATCH>(t, views, rp, splats, ids, ranges, image, final_T,
-                                        n_contrib, nullptr);
+    raster_tile<TS, MODE, false, BATCH>(t, views, rp, splats, ids, nullptr, ranges, image,
+                                        final_T, n_contrib, nullptr);
   }
 }
 
@@ -435,7 +558,46 @@ void launch_queue(int mode, dim3 grid, const RasterViews& views, const RasterPar
                        splats, ids, ranges, image, final_T, n_contrib, counter, order, n_items);
 }
 
+template <int TS>
+void launch_super(int mode, bool count, dim3 grid, const RasterViews& views,
+                  const RasterParams& rp, const seele_splat* splats, const uint32_t* entry_keys,
+                  const uint32_t* entry_ids, const int32_t* st_ranges, float* image,
+                  float* final_T, int32_t* n_contrib, unsigned long long* counters,
+                  hipStream_t stream) {
+  constexpr int BT = TS * TS;
+  const dim3 block(BT);
+#define SEELE_SUPER(M, C)                                                                       \
+  hipLaunchKernelGGL((k_raster_fwd_super<TS, M, C, BT>), grid, block, 0, stream, views, rp,     \
+                     splats, entry_ids, entry_keys, st_ranges, image, final_T, n_contrib,       \
+                     counters)
+  if (mode == SEELE_RASTER_CONTRIB) {
+    if (count) SEELE_SUPER(1, true);
+    else SEELE_SUPER(1, false);
+  } else {
+    if (count) SEELE_SUPER(0, true);
+    else SEELE_SUPER(0, false);
+  }
+#undef SEELE_SUPER
+}
+
 }  // namespace
+
+hipError_t launch_raster_fwd_super(int tile, int mode, const RasterViews& views,
+                                   int n_tiles_launch, const RasterParams& rp,
+                                   const seele_splat* splats, const uint32_t* entry_keys,
+                                   const uint32_t* entry_ids, const int32_t* st_ranges,
+                                   float* image, float* final_T, int32_t* n_contrib,
+                                   unsigned long long* counters, hipStream_t stream) {
+  if (n_tiles_launch <= 0) return hipSuccess;
+  const dim3 grid(n_tiles_launch);
+  if (tile == 16)
+    launch_super<16>(mode, counters != nullptr, grid, views, rp, splats, entry_keys, entry_ids,
+                     st_ranges, image, final_T, n_contrib, counters, stream);
+  else
+    launch_super<8>(mode, counters != nullptr, grid, views, rp, splats, entry_keys, entry_ids,
+                    st_ranges, image, final_T, n_contrib, counters, stream);
+  return hipGetLastError();
+}
 
 // Batch depths offered per tile size (the default is one record per thread).
 bool raster_batch_supported(int tile, int batch) {

@@ -62,6 +62,11 @@ int32_t check_cams(const seele_camera* cams, int32_t n_views, int tile, int max_
   return SEELE_OK;
 }
 
+int64_t super_tiles_of(const seele_camera& c, int tile) {
+  const int64_t gw = (c.width + tile - 1) / tile, gh = (c.height + tile - 1) / tile;
+  return ((gw + kSuperTile - 1) / kSuperTile) * ((gh + kSuperTile - 1) / kSuperTile);
+}
+
 int64_t tiles_of(const seele_camera& c, int tile) {
   return (int64_t)((c.width + tile - 1) / tile) * ((c.height + tile - 1) / tile);
 }
@@ -196,10 +201,14 @@ RasterViews make_raster_views(const seele_camera* cams, int v0, int nv, int tile
   RasterViews rv{};
   rv.n_views = nv;
   rv.tile_base = (int32_t)tile_base;
+  int64_t st = 0;
+  for (int k = 0; k < v0; ++k) st += super_tiles_of(cams[k], tile);
   int64_t t = 0, px = 0;
   for (int k = 0; k < nv; ++k) {
     const seele_camera& c = cams[v0 + k];
     rv.v[k].tile_begin = (int32_t)t;
+    rv.v[k].st_base = (int32_t)st;
+    st += super_tiles_of(c, tile);
     rv.v[k].W = c.width;
     rv.v[k].H = c.height;
     rv.v[k].grid_w = (c.width + tile - 1) / tile;
@@ -280,11 +289,17 @@ size_t seele_bin_sort_workspace_size(int64_t n_records, int64_t capacity, int64_
   return plan_bin_sort(n_records, capacity, n_tiles_total).total;
 }
 
-int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
-                       const seele_camera* cams, int32_t n_views, int32_t tile,
-                       void* workspace, size_t workspace_bytes, uint32_t* sorted_ids,
-                       int64_t capacity, int32_t* tile_ranges, int64_t* num_pairs,
-                       void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared by both list forms: per-tile lists into (sorted_ids, ranges), or
+// (super) super-tile lists into (entry_keys, sorted_ids, ranges).
+int32_t bin_sort_impl(bool super, const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+                      const seele_camera* cams, int32_t n_views, int32_t tile, void* workspace,
+                      size_t workspace_bytes, uint32_t* entry_keys, uint32_t* sorted_ids,
+                      int64_t capacity, int32_t* ranges, int64_t* num_pairs, void* stream) {
+  int32_t* tile_ranges = ranges;
   int32_t s = check_cams(cams, n_views, tile, kMaxViewsBin);
   if (s != SEELE_OK) return s;
   if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SEELE_ERR_INVALID_ARG, "n out of range");
@@ -298,6 +313,8 @@ int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_
     return fail(SEELE_ERR_INVALID_ARG, "splats/n_tiles null or misaligned");
   if (capacity > 0 && (!sorted_ids || !aligned(sorted_ids, 4)))
     return fail(SEELE_ERR_INVALID_ARG, "sorted_ids null or misaligned");
+  if (super && capacity > 0 && (!entry_keys || !aligned(entry_keys, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "entry_keys null or misaligned");
   if (!tile_ranges || !aligned(tile_ranges, 4))
     return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
   if (!num_pairs || !aligned(num_pairs, 8))
@@ -324,10 +341,42 @@ int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_
   if (st_base > ((int64_t)1 << 24))
     return fail(SEELE_ERR_UNSUPPORTED, "more than 2^24 super-tiles (%lld)", (long long)st_base);
   bv.n_st = st_base;
-  const hipError_t e = launch_bin_sort(plan, bv, splats, n_tiles, workspace, sorted_ids,
-                                       tile_ranges, num_pairs, static_cast<hipStream_t>(stream));
+  const hipError_t e =
+      launch_bin_sort(plan, bv, splats, n_tiles, workspace, sorted_ids, tile_ranges, num_pairs,
+                      static_cast<hipStream_t>(stream), super, entry_keys);
   if (e != hipSuccess) return hip_fail(e, "bin_sort launch");
   return SEELE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+                       const seele_camera* cams, int32_t n_views, int32_t tile,
+                       void* workspace, size_t workspace_bytes, uint32_t* sorted_ids,
+                       int64_t capacity, int32_t* tile_ranges, int64_t* num_pairs,
+                       void* stream) {
+  return bin_sort_impl(false, splats, n_tiles, n, cams, n_views, tile, workspace,
+                       workspace_bytes, nullptr, sorted_ids, capacity, tile_ranges, num_pairs,
+                       stream);
+}
+
+int64_t seele_total_super_tiles(const seele_camera* cams, int32_t n_views, int32_t tile) {
+  if (seele_total_tiles(cams, n_views, tile) < 0) return -1;
+  int64_t t = 0;
+  for (int v = 0; v < n_views; ++v) t += super_tiles_of(cams[v], tile);
+  return t;
+}
+
+int32_t seele_bin_sort_super(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+                             const seele_camera* cams, int32_t n_views, int32_t tile,
+                             void* workspace, size_t workspace_bytes, uint32_t* entry_keys,
+                             uint32_t* entry_ids, int64_t capacity, int32_t* st_ranges,
+                             int64_t* num_pairs, void* stream) {
+  return bin_sort_impl(true, splats, n_tiles, n, cams, n_views, tile, workspace,
+                       workspace_bytes, entry_keys, entry_ids, capacity, st_ranges, num_pairs,
+                       stream);
 }
 
 }  // extern "C"
@@ -338,15 +387,26 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
+// super: (sorted_ids, tile_ranges) are super-tile lists (entry ids,
+// super-tile ranges) with their entry keys.
 int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
                   const int32_t* tile_ranges, const seele_camera* cams, int32_t n_views,
                   const seele_raster_opts* opts, float* image, float* final_T,
-                  int32_t* n_contrib, uint64_t* counters, void* stream) {
+                  int32_t* n_contrib, uint64_t* counters, void* stream, bool super = false,
+                  const uint32_t* entry_keys = nullptr) {
   int32_t s = check_raster_opts(opts);
   if (s != SEELE_OK) return s;
   if ((s = check_cams(cams, n_views, opts->tile, 1 << 20)) != SEELE_OK) return s;
   const int64_t TT = seele_total_tiles(cams, n_views, opts->tile);
   if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
+  if (super) {
+    if (batch_of(opts) != opts->tile * opts->tile)
+      return fail(SEELE_ERR_UNSUPPORTED, "super-tile lists take the default LDS batch only");
+    if (seele_total_super_tiles(cams, n_views, opts->tile) > ((int64_t)1 << 24))
+      return fail(SEELE_ERR_UNSUPPORTED, "more than 2^24 super-tiles");
+    if (entry_keys && !aligned(entry_keys, 4))
+      return fail(SEELE_ERR_INVALID_ARG, "entry_keys misaligned");
+  }
   if (!tile_ranges || !aligned(tile_ranges, 4))
     return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
   if (!image || !aligned(image, 4) || !final_T || !aligned(final_T, 4) || !n_contrib ||
@@ -368,9 +428,12 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
     int64_t t = 0, npx = 0;
     const RasterViews rv = make_raster_views(cams, v0, nv, opts->tile, tile_base, pix_base, t, npx);
     pix_base += npx;
-    const hipError_t e = launch_raster_fwd(opts->tile, opts->mode, batch_of(opts), rv, (int)t,
-                                           rp, splats, sorted_ids, tile_ranges, image, final_T,
-                                           n_contrib, cnt, st);
+    const hipError_t e =
+        super ? launch_raster_fwd_super(opts->tile, opts->mode, rv, (int)t, rp, splats,
+                                        entry_keys, sorted_ids, tile_ranges, image, final_T,
+                                        n_contrib, cnt, st)
+              : launch_raster_fwd(opts->tile, opts->mode, batch_of(opts), rv, (int)t, rp, splats,
+                                  sorted_ids, tile_ranges, image, final_T, n_contrib, cnt, st);
     if (e != hipSuccess) return hip_fail(e, "raster launch");
     tile_base += t;
   }
@@ -387,6 +450,15 @@ int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_id
                             float* final_T, int32_t* n_contrib, void* stream) {
   return rasterize(splats, sorted_ids, tile_ranges, cams, n_views, opts, image, final_T,
                    n_contrib, nullptr, stream);
+}
+
+int32_t seele_rasterize_fwd_super(const seele_splat* splats, const uint32_t* entry_keys,
+                                  const uint32_t* entry_ids, const int32_t* st_ranges,
+                                  const seele_camera* cams, int32_t n_views,
+                                  const seele_raster_opts* opts, float* image, float* final_T,
+                                  int32_t* n_contrib, uint64_t* counters, void* stream) {
+  return rasterize(splats, entry_ids, st_ranges, cams, n_views, opts, image, final_T, n_contrib,
+                   counters, stream, true, entry_keys);
 }
 
 size_t seele_raster_queue_workspace_size(int64_t n_tiles_total) {

@@ -43,8 +43,20 @@ struct PreArgs {
 };
 
 // Super-tiles: square blocks of kSuperTile x kSuperTile tiles (row-major per
-// view, numbered after the previous views' super-tiles).
+// view, numbered after the previous views' super-tiles).  A super-tile list
+// entry key is the record's tile rectangle clipped to the super-tile (local
+// inclusive x0, x1, y0, y1 of 2 bits each) above the global super-tile id.
 constexpr int kSuperTile = 4;
+constexpr int kClipShift = 24;
+constexpr uint32_t kStMask = (1u << kClipShift) - 1u;
+
+// 16-bit coverage mask of an entry over its super-tile's tiles (bit 4 iy + ix).
+__device__ __forceinline__ uint32_t clip_mask(uint32_t clip) {
+  const uint32_t xm = ((2u << ((clip >> 2) & 3u)) - 1u) & ~((1u << (clip & 3u)) - 1u);
+  const uint32_t y0 = (clip >> 4) & 3u, y1 = (clip >> 6) & 3u;
+  const uint32_t rows = ((2u << (4u * y1 + 3u)) - 1u) & ~((1u << (4u * y0)) - 1u);
+  return (xm * 0x1111u) & rows;
+}
 
 struct BinView {
   int32_t tile_base;  // first global tile of the view
@@ -61,6 +73,7 @@ struct BinViews {
 
 struct RasterView {
   int32_t tile_begin;  // first tile of this view, relative to the launch
+  int32_t st_base;     // global id of the view's first super-tile
   int32_t W, H, grid_w;
   int64_t pix_base;    // first pixel of this view in final_T / n_contrib
 };
@@ -238,11 +251,23 @@ struct BinSortPlan {
   size_t off_tile_cnt, off_tile_start, total;
 };
 BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_total);
+// Per-tile lists (sorted_ids, tile_ranges), or (super) the super-tile lists:
+// entry keys and ids (sorted_ids) in list order and super-tile ranges
+// (tile_ranges then holds n_st pairs).
 hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,
                            const int32_t* n_tiles, void* ws, uint32_t* sorted_ids,
-                           int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream);
+                           int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream,
+                           bool super = false, uint32_t* entry_keys = nullptr);
 
 bool raster_batch_supported(int tile, int batch);
+
+// Forward over super-tile lists (one LDS batch of two entries per thread).
+hipError_t launch_raster_fwd_super(int tile, int mode, const RasterViews& views,
+                                   int n_tiles_launch, const RasterParams& rp,
+                                   const seele_splat* splats, const uint32_t* entry_keys,
+                                   const uint32_t* entry_ids, const int32_t* st_ranges,
+                                   float* image, float* final_T, int32_t* n_contrib,
+                                   unsigned long long* counters, hipStream_t stream);
 
 hipError_t launch_raster_fwd(int tile, int mode, int batch, const RasterViews& views,
                              int n_tiles_launch, const RasterParams& rp,

@@ -173,6 +173,75 @@ def seele_bin_sort(splats, n_tiles, n: int, cams, tile: int, capacity: int,
     return sorted_ids, tile_ranges, num_pairs, workspace
 
 
+def total_super_tiles(cams, tile: int) -> int:
+    n = int(A.lib().seele_total_super_tiles(A.camera_array(cams), len(cams), tile))
+    if n < 0:
+        raise ValueError("bad cameras or tile size")
+    return n
+
+
+def seele_bin_sort_super(splats, n_tiles, n: int, cams, tile: int, capacity: int,
+                         workspace: torch.Tensor | None = None, entry_keys=None, entry_ids=None,
+                         st_ranges=None, num_pairs=None, stream=None):
+    """Super-tile lists: (entry_keys, entry_ids, st_ranges, num_pairs, workspace)."""
+    dev = splats.device
+    V = len(cams)
+    TT = total_tiles(cams, tile)
+    NS = total_super_tiles(cams, tile)
+    ws_bytes = bin_sort_workspace_size(V * n, capacity, TT)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    if entry_keys is None:
+        entry_keys = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    if entry_ids is None:
+        entry_ids = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    if st_ranges is None:
+        st_ranges = torch.empty((NS, 2), dtype=torch.int32, device=dev)
+    if num_pairs is None:
+        num_pairs = torch.empty(1, dtype=torch.int64, device=dev)
+    _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+    _need(n_tiles, V * n, torch.int32, "n_tiles")
+    _need(entry_keys, capacity, torch.int32, "entry_keys")
+    _need(entry_ids, capacity, torch.int32, "entry_ids")
+    _need(st_ranges, 2 * NS, torch.int32, "st_ranges")
+    _need(num_pairs, 1, torch.int64, "num_pairs")
+    _need(workspace, ws_bytes, torch.uint8, "workspace")
+    st = A.lib().seele_bin_sort_super(_p(splats), _p(n_tiles), n, A.camera_array(cams), V, tile,
+                                      _p(workspace), workspace.numel(), _p(entry_keys),
+                                      _p(entry_ids), capacity, _p(st_ranges), _p(num_pairs),
+                                      _stream(stream))
+    A.check(st, "seele_bin_sort_super")
+    return entry_keys, entry_ids, st_ranges, num_pairs, workspace
+
+
+def seele_rasterize_fwd_super(splats, entry_keys, entry_ids, st_ranges, cams, settings: Settings,
+                              image=None, final_T=None, n_contrib=None, counters=None,
+                              stream=None):
+    """Forward over super-tile lists; counters (device [6] int64) selects the
+    instrumented kernel.  Returns (image, final_T, n_contrib)."""
+    dev = st_ranges.device
+    npix = pixel_count(cams)
+    if image is None:
+        image = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+    if final_T is None:
+        final_T = torch.empty(npix, dtype=torch.float32, device=dev)
+    if n_contrib is None:
+        n_contrib = torch.empty(npix, dtype=torch.int32, device=dev)
+    _need(st_ranges, 2 * total_super_tiles(cams, settings.tile), torch.int32, "st_ranges")
+    _need(image, 3 * npix, torch.float32, "image")
+    _need(final_T, npix, torch.float32, "final_T")
+    _need(n_contrib, npix, torch.int32, "n_contrib")
+    if counters is not None:
+        _need(counters, 6, torch.int64, "counters")
+    opts = settings.raster_opts()
+    st = A.lib().seele_rasterize_fwd_super(_p(splats), _p(entry_keys), _p(entry_ids),
+                                           _p(st_ranges), A.camera_array(cams), len(cams),
+                                           ctypes.byref(opts), _p(image), _p(final_T),
+                                           _p(n_contrib), _p(counters), _stream(stream))
+    A.check(st, "seele_rasterize_fwd_super")
+    return image, final_T, n_contrib
+
+
 def seele_rasterize_fwd(splats, sorted_ids, tile_ranges, cams, settings: Settings, image=None,
                         final_T=None, n_contrib=None, stream=None):
     dev = tile_ranges.device
@@ -382,6 +451,9 @@ class Frame:
     tile_ranges: torch.Tensor
     num_pairs: torch.Tensor
     cams: list = field(default_factory=list)
+    # super-tile lists (Renderer(lists="super")): sorted_ids holds the entry
+    # ids, tile_ranges the super-tile ranges and entry_keys the entry keys
+    entry_keys: torch.Tensor | None = None
 
     def images(self):
         return split_views(self.image, self.cams, 3)
@@ -402,12 +474,20 @@ class Renderer:
     host read (the caller then checks ``num_pairs`` itself)."""
 
     def __init__(self, settings: Settings | None = None, capacity: int = 1 << 20,
-                 schedule: str = "grid"):
+                 schedule: str = "grid", lists: str = "tile"):
         """schedule: "grid" (one workgroup per tile), "queue" or "queue_heavy"
-        (persistent work queue in list / heaviest-first order)."""
+        (persistent work queue in list / heaviest-first order).  lists:
+        "tile" (per-tile lists) or "super" (super-tile lists, read by each
+        tile directly; grid schedule only)."""
+        if lists not in ("tile", "super"):
+            raise ValueError(f"unknown list form {lists!r}")
+        if lists == "super" and schedule != "grid":
+            raise ValueError("super-tile lists run with the grid schedule")
         self.settings = settings or Settings()
         self.capacity = int(capacity)
         self.schedule = schedule
+        self.lists = lists
+        self._ek = None
         self._ws = None
         self._qws = None
 
@@ -415,10 +495,15 @@ class Renderer:
                stream=None) -> Frame:
         s = self.settings
         splats, n_tiles = seele_preprocess(g, cams, s, segments, stream=stream)
+        keys = None
         while True:
-            ids, ranges, npairs, self._ws = seele_bin_sort(splats, n_tiles, g.n, cams, s.tile,
-                                                           self.capacity, self._ws,
-                                                           stream=stream)
+            if self.lists == "super":
+                keys, ids, ranges, npairs, self._ws = seele_bin_sort_super(
+                    splats, n_tiles, g.n, cams, s.tile, self.capacity, self._ws, stream=stream)
+            else:
+                ids, ranges, npairs, self._ws = seele_bin_sort(splats, n_tiles, g.n, cams,
+                                                               s.tile, self.capacity, self._ws,
+                                                               stream=stream)
             if not check:
                 break
             need = int(npairs.item())
@@ -428,11 +513,15 @@ class Renderer:
                 raise CapacityError(f"the frame needs {need} Gaussian-tile pairs, more than the "
                                     f"{MAX_PAIRS} one call can sort: render fewer views per call")
             self.capacity = min(int(need * 1.5) + 1024, MAX_PAIRS)
-        if self.schedule == "grid":
+        if self.lists == "super":
+            image, final_T, n_contrib = seele_rasterize_fwd_super(splats, keys, ids, ranges, cams,
+                                                                  s, stream=stream)
+        elif self.schedule == "grid":
             image, final_T, n_contrib = seele_rasterize_fwd(splats, ids, ranges, cams, s,
                                                             stream=stream)
         else:
             order = "heaviest" if self.schedule == "queue_heavy" else "list"
             image, final_T, n_contrib, self._qws = seele_rasterize_fwd_queue(
                 splats, ids, ranges, cams, s, order, self._qws, stream=stream)
-        return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs, list(cams))
+        return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs, list(cams),
+                     keys)
