@@ -27,8 +27,9 @@ namespace {
 
 struct LdsBwd {
   float4 a;  // mean_x, mean_y, l11, l21
-  float4 b;  // l22, opacity, r, g
+  float4 b;  // l22, log2(opacity), r, g
   float4 c;  // blue, conic a, conic b, conic c
+  float inv_o, pad0, pad1, pad2;  // 1 / opacity
 };
 
 // Sum of x over the 64 lanes of a wave, returned to every lane: inclusive
@@ -101,11 +102,10 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
                                            int leader_lane, int lane, float amin, float amax,
                                            float g0, float g1, float g2, float& T, float& S0,
                                            float& S1, float& S2, float* acc) {
-  const float4 a = e.a, b = e.b;
+  const float4 a = e.a, b = e.b;  // b.y = log2(opacity), as the forward stages it
   float dx, dy;
-  const float p = splat_power(fx, fy, a.x, a.y, a.z, a.w, b.x, dx, dy);
-  const float ex = fast_exp2(p);
-  const float raw = b.y * ex;
+  const float qo = splat_qo(fx, fy, a.x, a.y, a.z, a.w, b.x, b.y, dx, dy);
+  const float raw = fast_exp2(-qo);
   const float alpha = clamp_alpha(raw, amax);
   bool blended = need && alpha >= amin;
   if (MODE) {
@@ -131,7 +131,7 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
     S2 = __builtin_fmaf(ta, cc.x, S2);
     T = Tj;
     if (raw <= amax) {
-      gop = dal * ex;
+      gop = dal * raw * e.inv_o;  // d alpha / d o = alpha / o below the clamp
       const float dq = -0.5f * alpha * dal;  // dL/dq
       // q = a dx^2 + 2 b dx dy + c dy^2 with d = pixel - mean: dq/dmean = -2 A d
       gmx = -2.0f * dq * (cc.y * dx + cc.z * dy);
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
 
   const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
   const int start = ranges[ri];
-  const float amin = rp.alpha_min, inv_amin = rp.inv_alpha_min, amax = rp.alpha_max;
+  const float amin = rp.alpha_min, l2ia = rp.log2_inv_alpha_min, amax = rp.alpha_max;
 
   float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
   int last = 0;
@@ -215,11 +215,13 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       const uint32_t id = ids[start + lo + tid];
       const float4* src = reinterpret_cast<const float4*>(splats + id);
       const float4 A = src[0], Bv = src[1];
+      const float l2o = __log2f(Bv.y);
       s_e[tid].a = A;
-      s_e[tid].b = Bv;
+      s_e[tid].b = make_float4(Bv.x, l2o, Bv.z, Bv.w);
       s_e[tid].c = src[2];  // blue, conic a, b, c
+      s_e[tid].inv_o = __builtin_amdgcn_rcpf(Bv.y);
       s_id[tid] = id;
-      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, Bv.y, inv_amin, tile_x * TS,
+      s_qm[tid] = (uint8_t)quad_mask<TS>(A.x, A.y, A.z, A.w, Bv.x, l2o, l2ia, tile_x * TS,
                                          tile_y * TS);
 #pragma unroll
       for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.0f;

@@ -37,38 +37,41 @@ namespace {
 
 struct LdsRec {
   float4 a;  // mean_x, mean_y, l11, l21  (Cholesky factor of k * conic)
-  float4 b;  // l22, opacity, r, g
+  float4 b;  // l22, log2(opacity), r, g
   float blue, pad0, pad1, pad2;
 };
 
 __device__ __forceinline__ float alpha_at(float px, float py, const float4& a, const float4& b,
                                           float alpha_max) {
   float dx, dy;
-  const float p = splat_power(px, py, a.x, a.y, a.z, a.w, b.x, dx, dy);
-  return clamp_alpha(b.y * fast_exp2(p), alpha_max);
+  const float qo = splat_qo(px, py, a.x, a.y, a.z, a.w, b.x, b.y, dx, dy);
+  return clamp_alpha(fast_exp2(-qo), alpha_max);
 }
 
 // One front-to-back step of Eqs. 1-2 for one pixel, with the alpha skip, the
-// clamp and the termination rule.  A pixel's state is (T, colour, last); a
-// pixel that has stopped carries -T (T >= T_min > 0 while it runs), so every
-// later step leaves it unchanged without a separate flag.  True if blended.
+// clamp and the termination rule.  The blend weight is w = T alpha and the
+// next transmittance T - w (= T (1 - alpha)).  A pixel's state is (T,
+// colour, last); a pixel that has stopped carries -T (T >= T_min > 0 while it
+// runs): its T - w stays negative, so every later step leaves it unchanged
+// without a separate flag.  True if blended.
 __device__ __forceinline__ bool blend_step(float fx, float fy, const float4& a, const float4& b,
                                            float blue, int pos, float amin, float amax,
                                            float tmin, float& T, float& c0, float& c1, float& c2,
                                            int& last) {
   const float alpha = alpha_at(fx, fy, a, b, amax);
   const bool pass = alpha >= amin;
-  const float Tn = T * (1.0f - alpha);
-  const bool stop = Tn < tmin;
-  const bool take = pass && !stop;
+  const float wgt = T * alpha;
+  const float Tn = T - wgt;
+  const bool keep = Tn >= tmin;
+  const bool take = pass && keep;
   if (take) {
-    const float wgt = alpha * T;
     c0 = __builtin_fmaf(wgt, b.z, c0);
     c1 = __builtin_fmaf(wgt, b.w, c1);
     c2 = __builtin_fmaf(wgt, blue, c2);
     last = pos;
   }
-  T = take ? Tn : ((pass && stop) ? -__builtin_fabsf(T) : T);
+  const float Tk = keep ? Tn : -__builtin_fabsf(T);
+  T = pass ? Tk : T;
   return take;
 }
 
@@ -81,15 +84,17 @@ __device__ __forceinline__ void blend_select(float fx, float fy, const float4& a
                                              float& c2, int& last) {
   const float alpha = alpha_at(fx, fy, a, b, amax);
   const bool pass = alpha >= amin;
-  const float Tn = T * (1.0f - alpha);
-  const bool stop = Tn < tmin;
-  const bool take = pass && !stop;
-  const float wgt = take ? alpha * T : 0.0f;
+  const float w = T * alpha;
+  const float Tn = T - w;
+  const bool keep = Tn >= tmin;
+  const bool take = pass && keep;
+  const float wgt = take ? w : 0.0f;
   c0 = __builtin_fmaf(wgt, b.z, c0);
   c1 = __builtin_fmaf(wgt, b.w, c1);
   c2 = __builtin_fmaf(wgt, blue, c2);
   last = take ? pos : last;
-  T = take ? Tn : (pass ? -__builtin_fabsf(T) : T);
+  const float Tk = keep ? Tn : -__builtin_fabsf(T);
+  T = pass ? Tk : T;
 }
 
 // COUNT instantiations also accumulate the method's work counters:
@@ -162,19 +167,28 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
 
   int start, n;
-  int tloc = 0;  // SUPER: the tile's bit in an entry's coverage mask
+  // SUPER: an entry covers this tile iff its clip's x nibble (x0 | x1 << 2)
+  // has x0 <= lx <= x1 and its y nibble likewise; mx / my hold, per nibble
+  // value, whether it does (one bit each).
+  uint32_t mx = 0, my = 0;
   if (SUPER) {
     const int sgw = (rv.grid_w + kSuperTile - 1) / kSuperTile;
     const int64_t s = (int64_t)rv.st_base + (tile_y / kSuperTile) * sgw + tile_x / kSuperTile;
     start = ranges[2 * s];
     n = ranges[2 * s + 1] - start;
-    tloc = (tile_y % kSuperTile) * kSuperTile + tile_x % kSuperTile;
+    const int lx = tile_x % kSuperTile, ly = tile_y % kSuperTile;
+#pragma unroll
+    for (int v0 = 0; v0 < 16; ++v0) {
+      const int lo = v0 & 3, hi = v0 >> 2;
+      if (lo <= lx && lx <= hi) mx |= 1u << v0;
+      if (lo <= ly && ly <= hi) my |= 1u << v0;
+    }
   } else {
     const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
     start = ranges[ri];
     n = ranges[ri + 1] - start;
   }
-  const float amin = rp.alpha_min, inv_amin = rp.inv_alpha_min;
+  const float amin = rp.alpha_min, l2ia = rp.log2_inv_alpha_min;
   const float amax = rp.alpha_max, tmin = rp.T_min;
 
   // pixels outside the image start stopped
@@ -200,13 +214,17 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   float ql1 = 0.0f;
   uint32_t nk0 = 0, nk1 = 0, ni1 = 0;
   int run = 0;  // SUPER: covered entries before the batch (block-uniform)
-  auto covers = [&](uint32_t key) { return ((clip_mask(key >> kClipShift) >> tloc) & 1u) != 0u; };
+  auto covers = [&](uint32_t key) {
+    return ((mx >> ((key >> kClipShift) & 15u)) & (my >> (key >> (kClipShift + 4))) & 1u) != 0u;
+  };
   auto load_rec = [&](uint32_t id, float4& a, float4& b, float& bl) {
     const float4* src = reinterpret_cast<const float4*>(splats + id);
     a = src[0];
     b = src[1];
     bl = src[2].x;
   };
+  // staged form of a record's second quarter: opacity as log2(o)
+  auto staged_b = [](const float4& b) { return make_float4(b.x, __log2f(b.y), b.z, b.w); };
   // SUPER: make (cv, q) the batch of entries j0, j0 + BATCH from (nk, ni),
   // then load the keys and ids of the batch after into (nk, ni)
   auto super_step = [&](int j0) {
@@ -271,18 +289,23 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
       if (cv0) {
         const uint32_t sl = off0 + r0;
         s_rec[sl].a = pa;
-        s_rec[sl].b = pb;
+        s_rec[sl].b = staged_b(pb);
         s_rec[sl].blue = pblue;
-        s_qm[sl] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, inv_amin,
-                                          tile_x * TS, tile_y * TS);
       }
       if (cv1) {
         const uint32_t sl = tot0 + off1 + r1;
         s_rec[sl].a = qa1;
-        s_rec[sl].b = qb1;
+        s_rec[sl].b = staged_b(qb1);
         s_rec[sl].blue = ql1;
-        s_qm[sl] = (uint8_t)quad_mask<TS>(qa1.x, qa1.y, qa1.z, qa1.w, qb1.x, qb1.y, inv_amin,
-                                          tile_x * TS, tile_y * TS);
+      }
+      __syncthreads();
+      // culling masks over the compacted records, one per thread, so that
+      // every lane of a wave has a record to bound
+      for (int k = tid; k < cnt; k += NT) {
+        const float4 a = s_rec[k].a;
+        const float4 b = s_rec[k].b;
+        s_qm[k] = (uint8_t)quad_mask<TS>(a.x, a.y, a.z, a.w, b.x, b.y, l2ia, tile_x * TS,
+                                         tile_y * TS);
       }
       __syncthreads();
       ahead = 4 * stopped < 3 * NT;
@@ -298,10 +321,11 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         if (stager && j + BATCH < n) pid = ids[start + j + BATCH];
       }
       if (stager && j < n) {
+        const float4 sb = staged_b(pb);
         s_rec[tid].a = pa;
-        s_rec[tid].b = pb;
+        s_rec[tid].b = sb;
         s_rec[tid].blue = pblue;
-        s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, inv_amin, tile_x * TS,
+        s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, sb.x, sb.y, l2ia, tile_x * TS,
                                            tile_y * TS);
       }
       __syncthreads();

@@ -182,7 +182,7 @@ PreArgs make_pre_args(const seele_gaussians* g, const seele_preprocess_opts* opt
 RasterParams make_raster_params(const seele_raster_opts* opts) {
   RasterParams rp{};
   rp.alpha_min = opts->alpha_min;
-  rp.inv_alpha_min = 1.0f / opts->alpha_min;
+  rp.log2_inv_alpha_min = (float)std::log2(1.0 / (double)opts->alpha_min);
   rp.alpha_max = opts->alpha_max;
   rp.T_min = opts->T_min;
   rp.bg0 = opts->bg[0];

@@ -86,7 +86,7 @@ struct RasterViews {
 
 struct RasterParams {
   float alpha_min, alpha_max, T_min;
-  float inv_alpha_min;  // 1 / alpha_min, for the culling bound
+  float log2_inv_alpha_min;  // log2(1 / alpha_min), for the culling bound
   float bg0, bg1, bg2;
   int group_w, group_h;
 };
@@ -172,20 +172,22 @@ __device__ __forceinline__ Chol conic_factor(float a, float b, float c) {
   return f;
 }
 
-// Power p = -k q at pixel centre (px, py).  Shared by the forward and
-// backward kernels so that both take identical decisions: the kernels are
-// compiled with floating-point contraction off and the fused multiply-adds
-// below are explicit.
-__device__ __forceinline__ float splat_power(float px, float py, float mx, float my, float l11,
-                                             float l21, float l22, float& dx, float& dy) {
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// The exponent of the unclamped alpha in base 2 with the opacity folded in:
+// o exp2(-(u^2 + w^2)) = exp2(-qo) with qo = u^2 + w^2 - log2(o), u and w the
+// two linear forms of the pixel offset (d = pixel - mean) through the
+// Cholesky factor.  The forward, its leader tests and the backward all use
+// this one expression, so they agree on every alpha bit.
+__device__ __forceinline__ float splat_qo(float px, float py, float mx, float my, float l11,
+                                          float l21, float l22, float log2o, float& dx,
+                                          float& dy) {
   dx = px - mx;
   dy = py - my;
   const float u = __builtin_fmaf(l21, dy, l11 * dx);
   const float w = l22 * dy;
-  return -__builtin_fmaf(u, u, w * w);
+  return __builtin_fmaf(u, u, __builtin_fmaf(w, w, -log2o));
 }
-
-__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // alpha = min(alpha_max, raw) for raw = o * exp2(p) >= 0 and alpha_max > 0,
 // as one median-of-three (which needs no NaN canonicalisation of alpha_max).
@@ -196,25 +198,26 @@ __device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
 // Wave-level culling mask of one record for one tile whose top-left pixel is
 // (x0, y0).  Bit q (q = 2*row + column of the 8x8 block that wave q owns) is
 // cleared only if alpha < alpha_min at every pixel centre of block q as the
-// blending loops compute it in float32 (splat_power, fast_exp2, clamp_alpha).
+// blending loops compute it in float32 (splat_qo, fast_exp2, clamp_alpha).
 // Over a block's centres the two linear forms u = l11 dx + l21 dy and
 // w = l22 dy range over intervals (l11, l22 > 0); the squared distances of
 // those intervals from zero add up to a lower bound of k q.  alpha >=
 // alpha_min needs k q <= log2(o / alpha_min), so a block is cleared when the
 // bound exceeds that by a margin covering the float32 rounding of the loop's
 // evaluation and of the bound itself (relative to the squared magnitude S^2
-// of the terms, taken over the whole tile), plus 1e-3 for the logarithm, exp2
-// and the products with o and 1 / alpha_min.  A NaN or infinite input makes
-// the margin NaN or infinite and leaves every bit set.
+// of the terms, taken over the whole tile), plus 1e-3 for the logarithms and
+// exp2.  A NaN or infinite input makes the margin NaN or infinite and leaves
+// every bit set.  log2o = log2(o) as the loops use it; log2_inv_amin =
+// log2(1 / alpha_min).
 template <int TS>
 __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float l11, float l21, float l22,
-                                              float opacity, float inv_alpha_min, int x0, int y0) {
+                                              float log2o, float log2_inv_amin, int x0, int y0) {
   constexpr int NB = TS / 8;  // 8x8 blocks per tile row
   const float X0 = ((float)x0 + 0.5f) - mx, Y0 = ((float)y0 + 0.5f) - my;
   const float ax = __builtin_fabsf(X0) + (float)(TS - 1);
   const float ay = __builtin_fabsf(Y0) + (float)(TS - 1);
   const float S = l11 * ax + __builtin_fabsf(l21) * ay, Wm = l22 * ay;
-  const float thr = (__log2f(opacity * inv_alpha_min) + 1e-3f) + 4e-6f * (S * S + Wm * Wm);
+  const float thr = ((log2o + log2_inv_amin) + 1e-3f) + 4e-6f * (S * S + Wm * Wm);
   const float ux = l11 * X0, ux7 = ux + 7.0f * l11, step = 8.0f * l11;
   uint32_t m = 0;
 #pragma unroll
