@@ -392,32 +392,29 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         uint64_t bits = __ballot(need);
         if (bits == 0) continue;
         if (MODE == 0) {
-          // Pack the chunk indices of this wave's records into consecutive
-          // lanes (lane r < nsel holds the r-th selected index; the other
-          // lanes the unselected ones, so the mapping is a permutation and
-          // every lane holds an index inside the chunk), then walk them in
-          // depth order with a counter, two at a time: the next record's
-          // LDS reads are in flight while the current one is blended.
-          const int nsel = __popcll(bits);
-          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
-          const int slot = need ? rank : nsel + (lane - rank);
-          const int packed = __builtin_amdgcn_ds_permute(slot * 4, lane);
-          int ka = c + __builtin_amdgcn_readlane(packed, 0);
+          // Walk the wave-uniform ballot in depth order with scalar
+          // find-first-set, two records at a time: the next record's LDS
+          // reads are in flight while the current one is blended.  (When the
+          // ballot runs out, the record read ahead is a repeat of the last
+          // one and is not blended.)
+          int ka = c + __builtin_ctzll(bits);
+          bits &= bits - 1;
           float4 aa = s_rec[ka].a, ab = s_rec[ka].b;
           float abl = s_rec[ka].blue;
-          for (int i = 1;; i += 2) {
-            const int kb = c + __builtin_amdgcn_readlane(packed, i & 63);
+          for (;;) {
+            const int kb = bits ? c + __builtin_ctzll(bits) : ka;
             const float4 ba = s_rec[kb].a, bb = s_rec[kb].b;
             const float bbl = s_rec[kb].blue;
             blend_select(fx, fy, aa, ab, abl, lbase + ka + 1, amin, amax, tmin, T, c0, c1, c2, last);
-            if (i >= nsel) break;
-            ka = c + __builtin_amdgcn_readlane(packed, (i + 1) & 63);
+            if (bits == 0) break;
+            bits &= bits - 1;
+            ka = bits ? c + __builtin_ctzll(bits) : kb;
             aa = s_rec[ka].a;
             ab = s_rec[ka].b;
             abl = s_rec[ka].blue;
             blend_select(fx, fy, ba, bb, bbl, lbase + kb + 1, amin, amax, tmin, T, c0, c1, c2, last);
-            if (i + 1 >= nsel) break;
+            if (bits == 0) break;
+            bits &= bits - 1;
           }
         } else {
           // compact this wave's records of the chunk, then run the packed
