@@ -135,6 +135,10 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   constexpr int SW = BATCH / 64;                  // staging waves
   __shared__ LdsRec s_rec[CAP];
   __shared__ uint8_t s_qm[CAP];
+  // s_need[c][w]: bit i set if record 64 c + i of the batch can reach wave
+  // w's block (the ballots of the s_qm bits, taken once at staging)
+  __shared__ uint64_t s_need[CAP / 64][NW];
+  __shared__ uint32_t s_dead[NW];
   __shared__ uint8_t s_list[NW][64];
   __shared__ uint32_t s_wc[2][SW];
   __shared__ unsigned long long s_cnt[6];
@@ -258,7 +262,15 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   }
 
   for (int base = 0; base < n; base += E) {
-    const int stopped = __syncthreads_count(T < 0.0f);
+    // pixels stopped so far: per-wave ballot counts through LDS
+    {
+      const uint64_t dead = __ballot(T < 0.0f);
+      if (lane == 0) s_dead[wave] = (uint32_t)__popcll(dead);
+    }
+    __syncthreads();
+    int stopped = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) stopped += (int)s_dead[w2];
     if (stopped == NT) break;
     const int j = base + tid;
     int cnt;
@@ -301,11 +313,22 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
       __syncthreads();
       // culling masks over the compacted records, one per thread, so that
       // every lane of a wave has a record to bound
-      for (int k = tid; k < cnt; k += NT) {
-        const float4 a = s_rec[k].a;
-        const float4 b = s_rec[k].b;
-        s_qm[k] = (uint8_t)quad_mask<TS>(a.x, a.y, a.z, a.w, b.x, b.y, l2ia, tile_x * TS,
-                                         tile_y * TS);
+      for (int k0 = 0; k0 < cnt; k0 += NT) {
+        const int k = k0 + tid;
+        uint32_t qm = 0;
+        if (k < cnt) {
+          const float4 a = s_rec[k].a;
+          const float4 b = s_rec[k].b;
+          qm = quad_mask<TS>(a.x, a.y, a.z, a.w, b.x, b.y, l2ia, tile_x * TS, tile_y * TS);
+          s_qm[k] = (uint8_t)qm;
+        }
+        if (k0 + 64 * wave < cnt) {  // uniform per wave
+#pragma unroll
+          for (int q = 0; q < NW; ++q) {
+            const uint64_t bq = __ballot((qm >> q) & 1u);
+            if (lane == 0) s_need[(k0 >> 6) + wave][q] = bq;
+          }
+        }
       }
       __syncthreads();
       ahead = 4 * stopped < 3 * NT;
@@ -320,13 +343,21 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         }
         if (stager && j + BATCH < n) pid = ids[start + j + BATCH];
       }
+      uint32_t qm = 0;
       if (stager && j < n) {
         const float4 sb = staged_b(pb);
         s_rec[tid].a = pa;
         s_rec[tid].b = sb;
         s_rec[tid].blue = pblue;
-        s_qm[tid] = (uint8_t)quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, sb.x, sb.y, l2ia, tile_x * TS,
-                                           tile_y * TS);
+        qm = quad_mask<TS>(pa.x, pa.y, pa.z, pa.w, sb.x, sb.y, l2ia, tile_x * TS, tile_y * TS);
+        s_qm[tid] = (uint8_t)qm;
+      }
+      if (stager) {  // uniform per wave (BATCH is a multiple of 64)
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          const uint64_t bq = __ballot((qm >> q) & 1u);
+          if (lane == 0) s_need[wave][q] = bq;
+        }
       }
       __syncthreads();
       ahead = 4 * stopped < 3 * NT;
@@ -387,10 +418,13 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
     } else {
       for (int c = 0; c < cnt; c += 64) {
         if (__ballot(T >= 0.0f) == 0) break;
-        const int jj = c + lane;
-        const bool need = jj < cnt && ((s_qm[jj] >> wave) & 1u);
-        uint64_t bits = __ballot(need);
+        const uint64_t nb = s_need[c >> 6][wave];
+        // (readfirstlane returns int: widen through uint32_t, not by sign)
+        const uint32_t nlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nb);
+        const uint32_t nhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(nb >> 32));
+        uint64_t bits = ((uint64_t)nhi << 32) | (uint64_t)nlo;
         if (bits == 0) continue;
+        const bool need = (bits >> lane) & 1ull;
         if (MODE == 0) {
           // Walk the wave-uniform ballot in depth order with scalar
           // find-first-set, two records at a time: the next record's LDS
