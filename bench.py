@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--n", type=int, default=3_000_000, help="Gaussian count (default 3.0M)")
     ap.add_argument("--forms", default="plain,contrib,hp,hp_contrib")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-tiles", type=int, default=24)
+    ap.add_argument("--cpu-tiles", type=int, default=240,
+                    help="tiles of view 0 the CPU oracle blends (about 10-30 s of CPU work)")
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
     ap.add_argument("--lists", choices=("super", "tile"), default="super",
@@ -305,12 +306,12 @@ def run_batched(n, n_views, mode, reps=3):
     del scene
     base = P.Settings(mode=mode)
     tuned = autotune(g, cams, base, reps=reps, log=log)
-    st, sch = tuned["settings"], tuned["schedule"]
+    st, sch, lists = tuned["settings"], tuned["schedule"], tuned["lists"]
     log(f"[bench] batched {mode}: autotuned tile={st.tile} lds_batch={st.lds_batch} "
-        f"schedule={sch} ({tuned['ms']:.2f} ms/frame of {n_views} views)")
+        f"schedule={sch} lists={lists} ({tuned['ms']:.2f} ms/frame of {n_views} views)")
 
-    # sequential: one frame per camera, default settings
-    seq = P.Renderer(base, capacity=1 << 22)
+    # sequential: one frame per camera, default settings, super-tile lists
+    seq = P.Renderer(base, capacity=1 << 22, lists="super")
     for cam in cams:
         seq.render(g, [cam])
     seq.capacity = int(seq.capacity * 1.05) + 4096
@@ -323,7 +324,7 @@ def run_batched(n, n_views, mode, reps=3):
     seq_ms = 1000.0 * (time.perf_counter() - t0) / reps / n_views
 
     # batched eager, tuned
-    r = P.Renderer(st, capacity=1 << 24, schedule=sch)
+    r = P.Renderer(st, capacity=1 << 24, schedule=sch, lists=lists)
     f = r.render(g, cams)
     r.capacity = int(r.capacity * 1.05) + 4096
     torch.cuda.synchronize()
@@ -337,13 +338,16 @@ def run_batched(n, n_views, mode, reps=3):
     # batched frame in a HIP graph (static buffers, device-side counts)
     V = len(cams)
     TT = P.total_tiles(cams, st.tile)
+    NS = P.total_super_tiles(cams, st.tile)
+    sup = lists == "super"
     npix = P.pixel_count(cams)
     cap = r.capacity
     splats = torch.empty((V * n, P.pipeline.SPLAT_FLOATS), dtype=torch.float32, device="cuda")
     n_tiles = torch.empty(V * n, dtype=torch.int32, device="cuda")
     ws = torch.empty(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8, device="cuda")
     ids = torch.empty(cap, dtype=torch.int32, device="cuda")
-    ranges = torch.empty((TT, 2), dtype=torch.int32, device="cuda")
+    keys = torch.empty(cap if sup else 1, dtype=torch.int32, device="cuda")
+    ranges = torch.empty((NS if sup else TT, 2), dtype=torch.int32, device="cuda")
     npairs = torch.empty(1, dtype=torch.int64, device="cuda")
     image = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
     final_T = torch.empty(npix, dtype=torch.float32, device="cuda")
@@ -356,6 +360,12 @@ def run_batched(n, n_views, mode, reps=3):
 
     def frame():
         P.seele_preprocess(g, cams, st, None, splats, n_tiles)
+        if sup:
+            P.seele_bin_sort_super(splats, n_tiles, n, cams, st.tile, cap, ws, keys, ids, ranges,
+                                   npairs)
+            P.seele_rasterize_fwd_super(splats, keys, ids, ranges, cams, st, image, final_T,
+                                        n_contrib)
+            return
         P.seele_bin_sort(splats, n_tiles, n, cams, st.tile, cap, ws, ids, ranges, npairs)
         if sch == "grid":
             P.seele_rasterize_fwd(splats, ids, ranges, cams, st, image, final_T, n_contrib)
@@ -383,6 +393,7 @@ def run_batched(n, n_views, mode, reps=3):
     assert int(npairs.item()) <= cap, "pair buffer overflow in the graph"
     out = dict(sequential_ms_per_view=seq_ms, batched_ms_per_view=eager_ms,
                graph_ms_per_view=graph_ms, tile=st.tile, lds_batch=st.lds_batch, schedule=sch,
+               lists=lists,
                pairs=int(npairs.item()), views=n_views, gaussians=n,
                autotune=[dict(t) for t in tuned["table"]])
     log(f"[bench] batched {mode}: sequential {seq_ms:.3f} ms/view, batched {eager_ms:.3f}, "

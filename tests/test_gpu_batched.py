@@ -97,6 +97,65 @@ def test_tile8_batched_matches_oracle():
                                   ob["ids"])
 
 
+def test_super_lists_batched_eager_and_graph_replay(c5_small):
+    """The batched frame over super-tile lists (one bin sort and one raster
+    launch for all views) equals the per-tile path bit for bit, eagerly and
+    replayed from a HIP graph several times with eager work in between."""
+    from paper_2503_05168_amd import seele_bin_sort_super, seele_rasterize_fwd_super
+    from paper_2503_05168_amd.pipeline import SPLAT_FLOATS, bin_sort_workspace_size
+    from paper_2503_05168_amd import total_super_tiles
+    scene, cams = c5_small
+    for mode in ("plain", "contrib"):
+        st = Settings(mode=mode)
+        g = GaussianTensors.from_arrays(scene)
+        n, V = g.n, len(cams)
+        ref = Renderer(st).render(g, cams)
+        sup = Renderer(st, lists="super").render(g, cams)
+        torch.cuda.synchronize()
+        assert torch.equal(sup.image, ref.image) and torch.equal(sup.final_T, ref.final_T)
+        assert torch.equal(sup.n_contrib, ref.n_contrib)
+        cap = int(ref.num_pairs.item() * 1.2) + 1024
+        TT, NS = total_tiles(cams, st.tile), total_super_tiles(cams, st.tile)
+        npix = sum(c.width * c.height for c in cams)
+        splats = torch.empty((V * n, SPLAT_FLOATS), dtype=torch.float32, device="cuda")
+        n_tiles = torch.empty(V * n, dtype=torch.int32, device="cuda")
+        ws = torch.empty(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8,
+                         device="cuda")
+        keys = torch.empty(cap, dtype=torch.int32, device="cuda")
+        ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+        ranges = torch.empty((NS, 2), dtype=torch.int32, device="cuda")
+        npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+        image = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
+        final_T = torch.empty(npix, dtype=torch.float32, device="cuda")
+        n_contrib = torch.empty(npix, dtype=torch.int32, device="cuda")
+
+        def frame():
+            seele_preprocess(g, cams, st, None, splats, n_tiles)
+            seele_bin_sort_super(splats, n_tiles, n, cams, st.tile, cap, ws, keys, ids, ranges,
+                                 npairs)
+            seele_rasterize_fwd_super(splats, keys, ids, ranges, cams, st, image, final_T,
+                                      n_contrib)
+
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            frame()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            frame()
+        for rep in range(3):
+            image.zero_()
+            n_contrib.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(image, ref.image), (mode, rep)
+            assert torch.equal(final_T, ref.final_T) and torch.equal(n_contrib, ref.n_contrib)
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+
+
 def test_hip_graph_replay_matches_eager(c5_small):
     scene, cams = c5_small
     st = Settings(mode="contrib")
@@ -173,3 +232,27 @@ def test_bin_sort_super_tile_sort_passes_match_oracle(tile, n_views, passes):
     np.testing.assert_array_equal(f.sorted_ids.cpu().numpy()[:P].astype(np.int64) & 0xFFFFFFFF,
                                   ob["ids"])
     np.testing.assert_array_equal(f.tile_ranges.cpu().numpy().astype(np.int64), ob["ranges"])
+
+
+def test_autotune_covers_list_forms_and_caches(c5_small, tmp_path):
+    """The autotuner times every (tile, batch, schedule, list form) candidate
+    on the workload, returns the fastest, and answers a repeat from its
+    cache; the chosen configuration renders what the default does at the same
+    tile size."""
+    from paper_2503_05168_amd.autotune import autotune
+    scene, cams = c5_small
+    g = GaussianTensors.from_arrays(scene)
+    cache = str(tmp_path / "tune.json")
+    t = autotune(g, cams, Settings(), reps=1, cache_path=cache)
+    forms = {(r["tile"], r["lds_batch"], r["schedule"], r["lists"]) for r in t["table"]}
+    assert (16, 256, "grid", "super") in forms and (16, 256, "grid", "tile") in forms
+    assert (8, 64, "grid", "super") in forms
+    timed = [r for r in t["table"] if r["ms"] is not None]
+    assert t["ms"] == min(r["ms"] for r in timed)
+    again = autotune(g, cams, Settings(), reps=1, cache_path=cache)
+    assert again["cached"] and again["lists"] == t["lists"]
+    st = t["settings"]
+    f = Renderer(st, schedule=t["schedule"], lists=t["lists"]).render(g, cams)
+    ref = Renderer(Settings(tile=st.tile)).render(g, cams)
+    torch.cuda.synchronize()
+    assert torch.equal(f.image, ref.image) and torch.equal(f.n_contrib, ref.n_contrib)
