@@ -151,10 +151,16 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     npairs_log = torch.zeros(steps, dtype=torch.int64, device=dev)
     npairs = torch.empty(1, dtype=torch.int64, device=dev)
 
+    def preprocess(v):
+        if sup:  # the binning's first step is staged by preprocessing
+            P.seele_preprocess_staged(g, [cams[v]], st, capacity, ws, segs[v], splats, n_tiles)
+        else:
+            P.seele_preprocess(g, [cams[v]], st, segs[v], splats, n_tiles)
+
     def binning(cam):
         if sup:
-            P.seele_bin_sort_super(splats, n_tiles, n, cam, st.tile, capacity, ws, keys, ids,
-                                   ranges, npairs)
+            P.seele_bin_sort_ex(splats, n_tiles, n, cam, st.tile, capacity, ws, ids, ranges,
+                                npairs, keys, super_lists=True, staged=True)
         else:
             P.seele_bin_sort(splats, n_tiles, n, cam, st.tile, capacity, ws, ids, ranges, npairs)
 
@@ -171,7 +177,7 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
         cam = [cams[v]]
         if ev is not None:
             ev[0].record()
-        P.seele_preprocess(g, cam, st, segs[v], splats, n_tiles)
+        preprocess(v)
         if ev is not None:
             ev[1].record()
         binning(cam)
@@ -204,7 +210,7 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     c = torch.zeros(6, dtype=torch.int64, device=dev)
     for i in range(min(steps, V)):
         v = i % V
-        P.seele_preprocess(g, [cams[v]], st, segs[v], splats, n_tiles)
+        preprocess(v)
         vis.append(int((n_tiles > 0).sum().item()))
         act.append(n if segs[v] is None else sum(c_ for _, c_ in segs[v]))
         binning([cams[v]])

@@ -219,6 +219,38 @@ int32_t seele_bin_sort_super(const seele_splat* splats, const int32_t* n_tiles, 
                              uint32_t* entry_ids, int64_t capacity, int32_t* st_ranges,
                              int64_t* num_pairs, void* stream);
 
+/* seele_preprocess that also does the first step of the binning (visible
+ * records and their float32 depth keys in record order, every record's tile
+ * rectangle) and leaves it in a bin-sort workspace, for seele_bin_sort_ex
+ * with SEELE_BIN_STAGED.  Outputs (splats, n_tiles) and arguments are those
+ * of seele_preprocess; workspace / workspace_bytes / capacity are those the
+ * following seele_bin_sort_ex call will take (workspace size from
+ * seele_bin_sort_workspace_size for n_views * n records).  n_views <= 256.
+ * The staged input is valid until the workspace is used for another call;
+ * the caller orders the two calls (same stream, or synchronised). */
+int32_t seele_preprocess_staged(const seele_gaussians* g, const seele_camera* cams,
+                                int32_t n_views, const seele_preprocess_opts* opts,
+                                seele_splat* splats, int32_t* n_tiles, void* workspace,
+                                size_t workspace_bytes, int64_t capacity, void* stream);
+
+/* Flags of seele_bin_sort_ex. */
+enum {
+  SEELE_BIN_SUPER = 1,  /* super-tile lists (seele_bin_sort_super's outputs) */
+  SEELE_BIN_STAGED = 2  /* take the visible records staged in the workspace by
+                           seele_preprocess_staged (same views, n and
+                           capacity); splats and n_tiles are then not read */
+};
+
+/* seele_bin_sort (flags 0) or seele_bin_sort_super (SEELE_BIN_SUPER), either
+ * one optionally from a staged workspace (SEELE_BIN_STAGED); results are
+ * identical in every case.  entry_keys is used with SEELE_BIN_SUPER only;
+ * ids is sorted_ids / entry_ids; ranges is tile_ranges / st_ranges. */
+int32_t seele_bin_sort_ex(int32_t flags, const seele_splat* splats, const int32_t* n_tiles,
+                          int64_t n, const seele_camera* cams, int32_t n_views, int32_t tile,
+                          void* workspace, size_t workspace_bytes, uint32_t* entry_keys,
+                          uint32_t* ids, int64_t capacity, int32_t* ranges, int64_t* num_pairs,
+                          void* stream);
+
 /* Front-to-back blending of every tile of every view (Eqs. 1-2; Algorithm 1
  * when opts->mode == SEELE_RASTER_CONTRIB).
  *   image     device, per view [3][H][W] float32, views concatenated

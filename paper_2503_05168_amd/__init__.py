@@ -13,6 +13,8 @@ from .pipeline import (  # noqa: F401
     seele_preprocess,
     seele_bin_sort,
     seele_bin_sort_super,
+    seele_bin_sort_ex,
+    seele_preprocess_staged,
     seele_rasterize_fwd,
     seele_rasterize_fwd_super,
     seele_rasterize_fwd_counted,

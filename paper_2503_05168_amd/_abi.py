@@ -21,6 +21,8 @@ SEELE_EXTENT_3SIGMA = 0
 SEELE_EXTENT_OPACITY = 1
 SEELE_RASTER_PLAIN = 0
 SEELE_RASTER_CONTRIB = 1
+SEELE_BIN_SUPER = 1
+SEELE_BIN_STAGED = 2
 SEELE_QUEUE_LIST = 0
 SEELE_QUEUE_HEAVIEST_FIRST = 1
 
@@ -71,6 +73,12 @@ SIGNATURES = {
                                  c_int32, c_void_p, c_size_t, c_void_p, c_int64, c_void_p,
                                  c_void_p, c_void_p]),
     "seele_total_super_tiles": (c_int64, [POINTER(seele_camera), c_int32, c_int32]),
+    "seele_preprocess_staged": (c_int32, [POINTER(seele_gaussians), POINTER(seele_camera),
+                                          c_int32, POINTER(seele_preprocess_opts), c_void_p,
+                                          c_void_p, c_void_p, c_size_t, c_int64, c_void_p]),
+    "seele_bin_sort_ex": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, POINTER(seele_camera),
+                                    c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
+                                    c_int64, c_void_p, c_void_p, c_void_p]),
     "seele_bin_sort_super": (c_int32, [c_void_p, c_void_p, c_int64, POINTER(seele_camera),
                                        c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
                                        c_int64, c_void_p, c_void_p, c_void_p]),

@@ -250,6 +250,28 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
   }
 }
 
+static_assert(B >= 256, "one thread per stage slot of a span");
+
+// Staged compaction: span s (256 records) holds its visible records' keys
+// and ids at stage slots [256 s, 256 s + count); after the scan of the counts
+// (in place) the run goes to [off[s], off[s] + count).
+__global__ __launch_bounds__(B) void k_span_gather(const uint64_t* __restrict__ off, int64_t nspan,
+                                                    const Hdr* __restrict__ hdr,
+                                                    const uint32_t* __restrict__ skeys,
+                                                    const uint32_t* __restrict__ sids,
+                                                    uint32_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
+  const uint64_t nvis = hdr->n_vis;
+  for (int64_t s = blockIdx.x; s < nspan; s += gridDim.x) {
+    const uint64_t a = off[s];
+    const uint64_t e = s + 1 < nspan ? off[s + 1] : nvis;
+    if ((uint64_t)threadIdx.x < e - a) {
+      keys[a + threadIdx.x] = skeys[s * 256 + threadIdx.x];
+      vals[a + threadIdx.x] = sids[s * 256 + threadIdx.x];
+    }
+  }
+}
+
 // ---- stable LSD radix sort of (u32 key, u32 value) with a device-side count
 //
 // A radix block owns BLK = 256 * IT consecutive items; a fixed grid loops
@@ -980,10 +1002,13 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_hdr = take(sizeof(Hdr));
   p.off_partial = take(8 * (size_t)nb_part);
   p.off_partial2 = take(8 * WAVES * (size_t)nb_span);
+  // buffer 1 of the depth sort also holds the stage: 256 slots per span of
+  // 256 records and view, so up to n_records + 256 * kMaxViewsBin
+  const size_t stage_slots = (size_t)n_records + 256 * (size_t)kMaxViewsBin;
   p.off_dkeys0 = take(4 * (size_t)n_records);
-  p.off_dkeys1 = take(4 * (size_t)n_records);
+  p.off_dkeys1 = take(4 * stage_slots);
   p.off_dvals0 = take(4 * (size_t)n_records);
-  p.off_dvals1 = take(4 * (size_t)n_records);
+  p.off_dvals1 = take(4 * stage_slots);
   p.off_skeys0 = take(4 * (size_t)capacity);
   p.off_skeys1 = take(4 * (size_t)capacity);
   p.off_svals0 = take(4 * (size_t)capacity);
@@ -991,6 +1016,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_rx = take(4 * (size_t)n_records);
   p.off_ry = take(4 * (size_t)n_records);
   p.off_rid = take(8 * (size_t)n_records);
+  p.off_span = take(8 * ((size_t)(n_records + 255) / 256 + kMaxViewsBin));
   p.off_hist = take(4 * 256 * (size_t)nb_hist);
   p.off_digits = take(4 * 256);
   p.off_st_range = take(8 * (size_t)p.max_st);
@@ -1003,10 +1029,21 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   return p;
 }
 
+BinStage bin_stage_of(const BinSortPlan& p, void* ws, int64_t n) {
+  char* base = static_cast<char*>(ws);
+  BinStage s;
+  s.keys = reinterpret_cast<uint32_t*>(base + p.off_dkeys1);
+  s.ids = reinterpret_cast<uint32_t*>(base + p.off_dvals1);
+  s.span_count = reinterpret_cast<uint64_t*>(base + p.off_span);
+  s.rid = reinterpret_cast<uint2*>(base + p.off_rid);
+  s.n_blocks = (n + 255) / 256;
+  return s;
+}
+
 hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,
                            const int32_t* n_tiles, void* ws, uint32_t* sorted_ids,
                            int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream,
-                           bool super, uint32_t* entry_keys) {
+                           bool super, uint32_t* entry_keys, bool staged) {
   char* base = static_cast<char*>(ws);
   auto at = [&](size_t o) { return reinterpret_cast<uint32_t*>(base + o); };
   Hdr* hdr = reinterpret_cast<Hdr*>(base + p.off_hdr);
@@ -1041,11 +1078,21 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   const int nbR = (int)((R + kSpanBlock - 1) / kSpanBlock);  // record-span workgroups
   if (nbR > 0) {
     // 1. visible records (n_tiles > 0) in id order with their depth keys
-    hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
-                       WAVES * (int64_t)nbR, hdr, 0, p.capacity, num_pairs);
-    hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats, partial,
-                       dk[0], dv[0], rid);
+    if (staged) {
+      // from the stage: scan of the span counts, then each span's run copied
+      const BinStage bs = bin_stage_of(p, ws, views.n);
+      const int64_t nspan = (int64_t)views.n_views * bs.n_blocks;
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, bs.span_count,
+                         nspan, hdr, 0, p.capacity, num_pairs);
+      hipLaunchKernelGGL(k_span_gather, dim3(grid_for(nspan)), dim3(B), 0, stream,
+                         bs.span_count, nspan, hdr, bs.keys, bs.ids, dk[0], dv[0]);
+    } else {
+      hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
+                         WAVES * (int64_t)nbR, hdr, 0, p.capacity, num_pairs);
+      hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats,
+                         partial, dk[0], dv[0], rid);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     //    stable sort by float32 depth bits (4 x 8-bit passes, ends in buffer 0)
     for (int pass = 0; pass < 4; ++pass) {

@@ -182,93 +182,137 @@ __device__ __forceinline__ void project(const CamK& c, const Act& g, float lowpa
 // loads carry no per-coefficient branch and are all in flight together.  ONE
 // compiles the single-view launch without the view loop: nothing of the
 // Gaussian has to stay live across views, which halves the registers.
-template <int NB, bool ONE>
+//
+// STAGE also does the binning's first step for each view: the workgroup's
+// visible records (n_tiles > 0) are compacted in record order into their
+// span (view, workgroup) of the stage arrays -- float32 depth bits and record
+// id -- with the span's count, and every record's packed tile rectangle (zero
+// if not visible) goes to the dense id-indexed array rid.  The binning then
+// starts from a scan of the span counts instead of re-reading the records.
+template <int NB, bool ONE, bool STAGE>
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __restrict__ means,
                                                     const float* __restrict__ log_scales,
                                                     const float* __restrict__ quats,
                                                     const float* __restrict__ logits,
                                                     const float* __restrict__ sh,
                                                     seele_splat* __restrict__ splats,
-                                                    int32_t* __restrict__ n_tiles) {
+                                                    int32_t* __restrict__ n_tiles, BinStage bs) {
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const bool in = i < n;
+  if (!STAGE && !in) return;
 
-  bool active = a.n_segs == 0;
-  for (int s = 0; s < a.n_segs; ++s) active |= (i >= a.seg_begin[s]) & (i < a.seg_end[s]);
+  bool live = false;
   Act g;
-  if (!active || !activate(i, n, means, log_scales, quats, logits, g)) {
-    for (int v = 0; v < a.n_views; ++v) n_tiles[(a.view0 + v) * n + i] = 0;
-    return;
+  if (in) {
+    bool active = a.n_segs == 0;
+    for (int s = 0; s < a.n_segs; ++s) active |= (i >= a.seg_begin[s]) & (i < a.seg_end[s]);
+    live = active && activate(i, n, means, log_scales, quats, logits, g);
+  }
+  if (!live) {
+    if (in)
+      for (int v = 0; v < a.n_views; ++v) n_tiles[(a.view0 + v) * n + i] = 0;
+    if (!STAGE) return;  // (the staging below needs every thread of the block)
   }
 
   const float inv_tile = 1.0f / (float)a.tile;
   const int nviews = ONE ? 1 : a.n_views;
+  __shared__ uint32_t s_wc[4];
 
   for (int v = 0; v < nviews; ++v) {
     const CamK& c = a.cam[v];
     const int64_t rec = (a.view0 + v) * n + i;
     int32_t nt = 0;
-    Proj p;
-    project(c, g, a.lowpass, p);
-    if (p.tz > a.z_near) {
-      float ex, ey;
-      bool op_ok;
-      if (a.extent == SEELE_EXTENT_OPACITY) {
-        const float tau = fminf(2.0f * logf(g.o / a.alpha_min), 9.0f);
-        op_ok = tau > 0.0f;
-        ex = sqrtf(tau * p.ca);
-        ey = sqrtf(tau * p.cc);
-      } else {
-        // lambda_max = mid + sqrt(mid^2 - det), with mid^2 - det = ((a-c)/2)^2 + b^2
-        const float mid = 0.5f * (p.ca + p.cc), hd = 0.5f * (p.ca - p.cc);
-        const float lam = mid + sqrtf(hd * hd + p.cb * p.cb);
-        const float r = 3.0f * sqrtf(lam);
-        op_ok = g.o >= a.alpha_min;
-        ex = r;
-        ey = r;
-      }
-      const bool ok = op_ok && p.det > 0.0f && finite(p.det) && finite(p.ia) && finite(p.ib) &&
-                      finite(p.ic) && finite(p.px) && finite(p.py) && finite(ex) && finite(ey);
-      if (ok) {
-        const float gw = (float)c.gridW, gh = (float)c.gridH;
-        const int x0 = (int)fminf(fmaxf(floorf((p.px - ex) * inv_tile), 0.0f), gw);
-        const int x1 = (int)fminf(fmaxf(floorf((p.px + ex) * inv_tile) + 1.0f, 0.0f), gw);
-        const int y0 = (int)fminf(fmaxf(floorf((p.py - ey) * inv_tile), 0.0f), gh);
-        const int y1 = (int)fminf(fmaxf(floorf((p.py + ey) * inv_tile) + 1.0f, 0.0f), gh);
-        if (x1 > x0 && y1 > y0) {
-          // colour toward the camera; coefficients streamed from the SoA array
-          float dx = g.mx - c.C[0], dy = g.my - c.C[1], dz = g.mz - c.C[2];
-          const float dinv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-          dx *= dinv;
-          dy *= dinv;
-          dz *= dinv;
-          float coef[NB * 3];
-#pragma unroll
-          for (int k = 0; k < NB * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
-          float Y[16];
-          sh_basis(dx, dy, dz, Y);
-          float acc[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-          for (int k = 0; k < NB; ++k) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * coef[k * 3 + ch];
-          }
-          const float rgb[3] = {0.5f + acc[0], 0.5f + acc[1], 0.5f + acc[2]};
-          if (finite(rgb[0]) && finite(rgb[1]) && finite(rgb[2])) {
-            nt = (x1 - x0) * (y1 - y0);
-            const Chol L = conic_factor(p.ia, p.ib, p.ic);
-            float4* dst = reinterpret_cast<float4*>(splats + rec);
-            dst[0] = make_float4(p.px, p.py, L.l11, L.l21);
-            dst[1] = make_float4(L.l22, g.o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f));
-            dst[2] = make_float4(fmaxf(rgb[2], 0.0f), p.ia, p.ib, p.ic);
-            dst[3] = make_float4(p.tz, __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)),
-                                 __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)), 0.0f);
+    uint32_t dkey = 0, srx = 0, sry = 0;
+    if (live) {
+      Proj p;
+      project(c, g, a.lowpass, p);
+      if (p.tz > a.z_near) {
+        float ex, ey;
+        bool op_ok;
+        if (a.extent == SEELE_EXTENT_OPACITY) {
+          const float tau = fminf(2.0f * logf(g.o / a.alpha_min), 9.0f);
+          op_ok = tau > 0.0f;
+          ex = sqrtf(tau * p.ca);
+          ey = sqrtf(tau * p.cc);
+        } else {
+          // lambda_max = mid + sqrt(mid^2 - det), with mid^2 - det = ((a-c)/2)^2 + b^2
+          const float mid = 0.5f * (p.ca + p.cc), hd = 0.5f * (p.ca - p.cc);
+          const float lam = mid + sqrtf(hd * hd + p.cb * p.cb);
+          const float r = 3.0f * sqrtf(lam);
+          op_ok = g.o >= a.alpha_min;
+          ex = r;
+          ey = r;
+        }
+        const bool ok = op_ok && p.det > 0.0f && finite(p.det) && finite(p.ia) && finite(p.ib) &&
+                        finite(p.ic) && finite(p.px) && finite(p.py) && finite(ex) && finite(ey);
+        if (ok) {
+          const float gw = (float)c.gridW, gh = (float)c.gridH;
+          const int x0 = (int)fminf(fmaxf(floorf((p.px - ex) * inv_tile), 0.0f), gw);
+          const int x1 = (int)fminf(fmaxf(floorf((p.px + ex) * inv_tile) + 1.0f, 0.0f), gw);
+          const int y0 = (int)fminf(fmaxf(floorf((p.py - ey) * inv_tile), 0.0f), gh);
+          const int y1 = (int)fminf(fmaxf(floorf((p.py + ey) * inv_tile) + 1.0f, 0.0f), gh);
+          if (x1 > x0 && y1 > y0) {
+            // colour toward the camera; coefficients streamed from the SoA array
+            float dx = g.mx - c.C[0], dy = g.my - c.C[1], dz = g.mz - c.C[2];
+            const float dinv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= dinv;
+            dy *= dinv;
+            dz *= dinv;
+            float coef[NB * 3];
+  #pragma unroll
+            for (int k = 0; k < NB * 3; ++k) coef[k] = sh[(int64_t)k * n + i];
+            float Y[16];
+            sh_basis(dx, dy, dz, Y);
+            float acc[3] = {0.0f, 0.0f, 0.0f};
+  #pragma unroll
+            for (int k = 0; k < NB; ++k) {
+  #pragma unroll
+              for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * coef[k * 3 + ch];
+            }
+            const float rgb[3] = {0.5f + acc[0], 0.5f + acc[1], 0.5f + acc[2]};
+            if (finite(rgb[0]) && finite(rgb[1]) && finite(rgb[2])) {
+              nt = (x1 - x0) * (y1 - y0);
+              const Chol L = conic_factor(p.ia, p.ib, p.ic);
+              dkey = __float_as_uint(p.tz);
+              srx = (uint32_t)x0 | ((uint32_t)x1 << 16);
+              sry = (uint32_t)y0 | ((uint32_t)y1 << 16);
+              float4* dst = reinterpret_cast<float4*>(splats + rec);
+              dst[0] = make_float4(p.px, p.py, L.l11, L.l21);
+              dst[1] = make_float4(L.l22, g.o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f));
+              dst[2] = make_float4(fmaxf(rgb[2], 0.0f), p.ia, p.ib, p.ic);
+              dst[3] = make_float4(p.tz, __uint_as_float(srx), __uint_as_float(sry), 0.0f);
+            }
           }
         }
       }
+      n_tiles[rec] = nt;
     }
-    n_tiles[rec] = nt;
+    if (STAGE) {
+      const bool vis = nt > 0;
+      const int w = threadIdx.x >> 6;
+      const uint64_t b = __ballot(vis);
+      if ((threadIdx.x & 63) == 0) s_wc[w] = (uint32_t)__popcll(b);
+      __syncthreads();
+      uint32_t off = 0, tot = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t cw = s_wc[k];
+        off += k < w ? cw : 0u;
+        tot += cw;
+      }
+      const int64_t span = (a.view0 + v) * bs.n_blocks + blockIdx.x;
+      if (vis) {
+        const uint32_t pos =
+            off + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        bs.keys[span * 256 + pos] = dkey;
+        bs.ids[span * 256 + pos] = (uint32_t)rec;
+      }
+      if (threadIdx.x == 0) bs.span_count[span] = tot;
+      if (in) bs.rid[rec] = make_uint2(srx, sry);
+      __syncthreads();  // s_wc is rewritten for the next view
+    }
   }
 }
 
@@ -521,19 +565,26 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(
 }  // namespace
 
 hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_splat* splats,
-                             int32_t* n_tiles, hipStream_t stream) {
+                             int32_t* n_tiles, hipStream_t stream, const BinStage* stage) {
   if (a.n == 0) return hipSuccess;
   const int block = 256;
   const int64_t grid = (a.n + block - 1) / block;
   const dim3 g3((unsigned)grid), b3(block);
   const bool one = a.n_views == 1;
-#define SEELE_PRE(NB)                                                                           \
-  if (one)                                                                                      \
-    hipLaunchKernelGGL((k_preprocess<NB, true>), g3, b3, 0, stream, a, g.means, g.log_scales,   \
-                       g.quats, g.opacity_logits, g.sh, splats, n_tiles);                       \
+  const BinStage bs = stage ? *stage : BinStage{};
+#define SEELE_PRE_ONE(NB, ONE)                                                                  \
+  if (stage)                                                                                    \
+    hipLaunchKernelGGL((k_preprocess<NB, ONE, true>), g3, b3, 0, stream, a, g.means,            \
+                       g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles, bs);     \
   else                                                                                          \
-    hipLaunchKernelGGL((k_preprocess<NB, false>), g3, b3, 0, stream, a, g.means, g.log_scales,  \
-                       g.quats, g.opacity_logits, g.sh, splats, n_tiles);
+    hipLaunchKernelGGL((k_preprocess<NB, ONE, false>), g3, b3, 0, stream, a, g.means,           \
+                       g.log_scales, g.quats, g.opacity_logits, g.sh, splats, n_tiles, bs);
+#define SEELE_PRE(NB)                                                                           \
+  if (one) {                                                                                    \
+    SEELE_PRE_ONE(NB, true)                                                                     \
+  } else {                                                                                      \
+    SEELE_PRE_ONE(NB, false)                                                                    \
+  }
   switch (a.sh_degree) {
     case 0:
       SEELE_PRE(1);
@@ -548,6 +599,7 @@ hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_s
       SEELE_PRE(16);
   }
 #undef SEELE_PRE
+#undef SEELE_PRE_ONE
   return hipGetLastError();
 }
 

@@ -255,9 +255,13 @@ int64_t seele_total_tiles(const seele_camera* cams, int32_t n_views, int32_t til
   return t;
 }
 
-int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
-                         const seele_preprocess_opts* opts, seele_splat* splats,
-                         int32_t* n_tiles, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int32_t preprocess_impl(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                        const seele_preprocess_opts* opts, seele_splat* splats, int32_t* n_tiles,
+                        void* stream, const BinStage* stage) {
   int32_t s = check_gaussians(g);
   if (s != SEELE_OK) return s;
   if ((s = check_preprocess_opts(opts, g->n)) != SEELE_OK) return s;
@@ -278,10 +282,41 @@ int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int
     a.n_views = nv;
     a.view0 = v0;
     for (int k = 0; k < nv; ++k) a.cam[k] = to_camk(cams[v0 + k], opts->tile);
-    const hipError_t e = launch_preprocess(a, *g, splats, n_tiles, st);
+    const hipError_t e = launch_preprocess(a, *g, splats, n_tiles, st, stage);
     if (e != hipSuccess) return hip_fail(e, "preprocess launch");
   }
   return SEELE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_preprocess(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                         const seele_preprocess_opts* opts, seele_splat* splats,
+                         int32_t* n_tiles, void* stream) {
+  return preprocess_impl(g, cams, n_views, opts, splats, n_tiles, stream, nullptr);
+}
+
+int32_t seele_preprocess_staged(const seele_gaussians* g, const seele_camera* cams,
+                                int32_t n_views, const seele_preprocess_opts* opts,
+                                seele_splat* splats, int32_t* n_tiles, void* workspace,
+                                size_t workspace_bytes, int64_t capacity, void* stream) {
+  if (!g || !opts) return fail(SEELE_ERR_INVALID_ARG, "null gaussians or options");
+  int32_t s = check_cams(cams, n_views, opts->tile, kMaxViewsBin);
+  if (s != SEELE_OK) return s;
+  if (capacity < 0 || capacity >= ((int64_t)1 << 31))
+    return fail(SEELE_ERR_INVALID_ARG, "capacity must be in [0, 2^31)");
+  const int64_t R = (int64_t)n_views * g->n;
+  if (R >= ((int64_t)1 << 32)) return fail(SEELE_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+  const BinSortPlan plan = plan_bin_sort(R, capacity, seele_total_tiles(cams, n_views, opts->tile));
+  if (!workspace || !aligned(workspace, 256))
+    return fail(SEELE_ERR_INVALID_ARG, "workspace null or not 256-byte aligned");
+  if (workspace_bytes < plan.total)
+    return fail(SEELE_ERR_CAPACITY, "workspace %zu bytes < required %zu", workspace_bytes,
+                plan.total);
+  const BinStage bs = bin_stage_of(plan, workspace, g->n);
+  return preprocess_impl(g, cams, n_views, opts, splats, n_tiles, stream, &bs);
 }
 
 size_t seele_bin_sort_workspace_size(int64_t n_records, int64_t capacity, int64_t n_tiles_total) {
@@ -295,7 +330,8 @@ namespace {
 
 // Shared by both list forms: per-tile lists into (sorted_ids, ranges), or
 // (super) super-tile lists into (entry_keys, sorted_ids, ranges).
-int32_t bin_sort_impl(bool super, const seele_splat* splats, const int32_t* n_tiles, int64_t n,
+int32_t bin_sort_impl(bool super, bool staged, const seele_splat* splats, const int32_t* n_tiles,
+                      int64_t n,
                       const seele_camera* cams, int32_t n_views, int32_t tile, void* workspace,
                       size_t workspace_bytes, uint32_t* entry_keys, uint32_t* sorted_ids,
                       int64_t capacity, int32_t* ranges, int64_t* num_pairs, void* stream) {
@@ -309,7 +345,7 @@ int32_t bin_sort_impl(bool super, const seele_splat* splats, const int32_t* n_ti
     return fail(SEELE_ERR_INVALID_ARG, "capacity must be in [0, 2^31)");
   const int64_t TT = seele_total_tiles(cams, n_views, tile);
   if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
-  if (R > 0 && (!splats || !aligned(splats, 16) || !n_tiles || !aligned(n_tiles, 4)))
+  if (R > 0 && !staged && (!splats || !aligned(splats, 16) || !n_tiles || !aligned(n_tiles, 4)))
     return fail(SEELE_ERR_INVALID_ARG, "splats/n_tiles null or misaligned");
   if (capacity > 0 && (!sorted_ids || !aligned(sorted_ids, 4)))
     return fail(SEELE_ERR_INVALID_ARG, "sorted_ids null or misaligned");
@@ -343,7 +379,7 @@ int32_t bin_sort_impl(bool super, const seele_splat* splats, const int32_t* n_ti
   bv.n_st = st_base;
   const hipError_t e =
       launch_bin_sort(plan, bv, splats, n_tiles, workspace, sorted_ids, tile_ranges, num_pairs,
-                      static_cast<hipStream_t>(stream), super, entry_keys);
+                      static_cast<hipStream_t>(stream), super, entry_keys, staged);
   if (e != hipSuccess) return hip_fail(e, "bin_sort launch");
   return SEELE_OK;
 }
@@ -357,7 +393,7 @@ int32_t seele_bin_sort(const seele_splat* splats, const int32_t* n_tiles, int64_
                        void* workspace, size_t workspace_bytes, uint32_t* sorted_ids,
                        int64_t capacity, int32_t* tile_ranges, int64_t* num_pairs,
                        void* stream) {
-  return bin_sort_impl(false, splats, n_tiles, n, cams, n_views, tile, workspace,
+  return bin_sort_impl(false, false, splats, n_tiles, n, cams, n_views, tile, workspace,
                        workspace_bytes, nullptr, sorted_ids, capacity, tile_ranges, num_pairs,
                        stream);
 }
@@ -374,9 +410,22 @@ int32_t seele_bin_sort_super(const seele_splat* splats, const int32_t* n_tiles, 
                              void* workspace, size_t workspace_bytes, uint32_t* entry_keys,
                              uint32_t* entry_ids, int64_t capacity, int32_t* st_ranges,
                              int64_t* num_pairs, void* stream) {
-  return bin_sort_impl(true, splats, n_tiles, n, cams, n_views, tile, workspace,
+  return bin_sort_impl(true, false, splats, n_tiles, n, cams, n_views, tile, workspace,
                        workspace_bytes, entry_keys, entry_ids, capacity, st_ranges, num_pairs,
                        stream);
+}
+
+int32_t seele_bin_sort_ex(int32_t flags, const seele_splat* splats, const int32_t* n_tiles,
+                          int64_t n, const seele_camera* cams, int32_t n_views, int32_t tile,
+                          void* workspace, size_t workspace_bytes, uint32_t* entry_keys,
+                          uint32_t* ids, int64_t capacity, int32_t* ranges, int64_t* num_pairs,
+                          void* stream) {
+  if (flags & ~(SEELE_BIN_SUPER | SEELE_BIN_STAGED))
+    return fail(SEELE_ERR_INVALID_ARG, "unknown bin_sort flags 0x%x", (unsigned)flags);
+  const bool super = (flags & SEELE_BIN_SUPER) != 0;
+  return bin_sort_impl(super, (flags & SEELE_BIN_STAGED) != 0, splats, n_tiles, n, cams, n_views,
+                       tile, workspace, workspace_bytes, super ? entry_keys : nullptr, ids,
+                       capacity, ranges, num_pairs, stream);
 }
 
 }  // extern "C"

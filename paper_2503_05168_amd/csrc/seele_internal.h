@@ -237,9 +237,22 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float l11, flo
   return m;
 }
 
+// Binning input staged by preprocessing (in the bin-sort workspace): per span
+// (view v, preprocess workgroup b; span = v * n_blocks + b, 256 records) the
+// visible records' depth keys and ids compacted to the span's start, the
+// span's count, and every record's packed tile rectangle.
+struct BinStage {
+  uint32_t* keys;
+  uint32_t* ids;
+  uint64_t* span_count;
+  uint2* rid;
+  int64_t n_blocks;  // ceil(n / 256)
+};
+
 // ------------------------------------------------------------- host launchers
 hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_splat* splats,
-                             int32_t* n_tiles, hipStream_t stream);
+                             int32_t* n_tiles, hipStream_t stream,
+                             const BinStage* stage = nullptr);
 
 struct BinSortPlan {
   int64_t n_records;      // n_views * n
@@ -249,18 +262,23 @@ struct BinSortPlan {
   int64_t max_seg;        // bound on write segments
   // workspace carve-up (byte offsets)
   size_t off_hdr, off_partial, off_partial2, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
-  size_t off_skeys0, off_skeys1, off_svals0, off_svals1, off_rx, off_ry, off_rid;
+  size_t off_skeys0, off_skeys1, off_svals0, off_svals1, off_rx, off_ry, off_rid, off_span;
   size_t off_hist, off_digits, off_st_range, off_st_seg, off_seg_st, off_seg_cnt;
   size_t off_tile_cnt, off_tile_start, total;
 };
 BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_total);
 // Per-tile lists (sorted_ids, tile_ranges), or (super) the super-tile lists:
 // entry keys and ids (sorted_ids) in list order and super-tile ranges
-// (tile_ranges then holds n_st pairs).
+// (tile_ranges then holds n_st pairs).  staged: the visible records come from
+// the stage that preprocessing wrote into ws (bin_stage_of), not from
+// splats / n_tiles.
 hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const seele_splat* splats,
                            const int32_t* n_tiles, void* ws, uint32_t* sorted_ids,
                            int32_t* tile_ranges, int64_t* num_pairs, hipStream_t stream,
-                           bool super = false, uint32_t* entry_keys = nullptr);
+                           bool super = false, uint32_t* entry_keys = nullptr,
+                           bool staged = false);
+// Where preprocessing stages the binning input inside a bin-sort workspace.
+BinStage bin_stage_of(const BinSortPlan& p, void* ws, int64_t n);
 
 bool raster_batch_supported(int tile, int batch);
 

@@ -141,6 +141,60 @@ def seele_preprocess(g: GaussianTensors, cams, settings: Settings, segments=None
     return splats, n_tiles
 
 
+def seele_preprocess_staged(g: GaussianTensors, cams, settings: Settings, capacity: int,
+                            workspace: torch.Tensor, segments=None,
+                            splats: torch.Tensor | None = None,
+                            n_tiles: torch.Tensor | None = None, stream=None):
+    """seele_preprocess that also stages the binning input in `workspace` (a
+    bin-sort workspace for this capacity) for seele_bin_sort_ex(staged=True)."""
+    V, n = len(cams), g.n
+    dev = g.means.device
+    if splats is None:
+        splats = torch.empty((V * n, SPLAT_FLOATS), dtype=torch.float32, device=dev)
+    if n_tiles is None:
+        n_tiles = torch.empty(V * n, dtype=torch.int32, device=dev)
+    ws_bytes = bin_sort_workspace_size(V * n, capacity, total_tiles(cams, settings.tile))
+    _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+    _need(n_tiles, V * n, torch.int32, "n_tiles")
+    _need(workspace, ws_bytes, torch.uint8, "workspace")
+    opts, keep = settings.preprocess_opts(segments)
+    gs = g.struct()
+    st = A.lib().seele_preprocess_staged(ctypes.byref(gs), A.camera_array(cams), V,
+                                         ctypes.byref(opts), _p(splats), _p(n_tiles),
+                                         _p(workspace), workspace.numel(), capacity,
+                                         _stream(stream))
+    del keep
+    A.check(st, "seele_preprocess_staged")
+    return splats, n_tiles
+
+
+def seele_bin_sort_ex(splats, n_tiles, n: int, cams, tile: int, capacity: int,
+                      workspace: torch.Tensor, ids: torch.Tensor, ranges: torch.Tensor,
+                      num_pairs: torch.Tensor, entry_keys: torch.Tensor | None = None,
+                      super_lists: bool = False, staged: bool = False, stream=None):
+    """seele_bin_sort(_super), optionally from a workspace staged by
+    seele_preprocess_staged; every buffer is the caller's."""
+    V = len(cams)
+    TT = total_tiles(cams, tile)
+    nr = total_super_tiles(cams, tile) if super_lists else TT
+    _need(workspace, bin_sort_workspace_size(V * n, capacity, TT), torch.uint8, "workspace")
+    _need(ids, capacity, torch.int32, "ids")
+    _need(ranges, 2 * nr, torch.int32, "ranges")
+    _need(num_pairs, 1, torch.int64, "num_pairs")
+    if super_lists:
+        _need(entry_keys, capacity, torch.int32, "entry_keys")
+    if not staged:
+        _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+        _need(n_tiles, V * n, torch.int32, "n_tiles")
+    flags = (A.SEELE_BIN_SUPER if super_lists else 0) | (A.SEELE_BIN_STAGED if staged else 0)
+    st = A.lib().seele_bin_sort_ex(flags, _p(splats), _p(n_tiles), n, A.camera_array(cams), V,
+                                   tile, _p(workspace), workspace.numel(),
+                                   _p(entry_keys) if super_lists else None, _p(ids), capacity,
+                                   _p(ranges), _p(num_pairs), _stream(stream))
+    A.check(st, "seele_bin_sort_ex")
+    return ids, ranges, num_pairs
+
+
 def bin_sort_workspace_size(n_records: int, capacity: int, n_tiles_total: int) -> int:
     return int(A.lib().seele_bin_sort_workspace_size(n_records, capacity, n_tiles_total))
 
@@ -494,12 +548,29 @@ class Renderer:
     def render(self, g: GaussianTensors, cams, segments=None, check: bool = True,
                stream=None) -> Frame:
         s = self.settings
-        splats, n_tiles = seele_preprocess(g, cams, s, segments, stream=stream)
         keys = None
+        if self.lists != "super":
+            splats, n_tiles = seele_preprocess(g, cams, s, segments, stream=stream)
         while True:
             if self.lists == "super":
-                keys, ids, ranges, npairs, self._ws = seele_bin_sort_super(
-                    splats, n_tiles, g.n, cams, s.tile, self.capacity, self._ws, stream=stream)
+                # preprocessing stages the binning input in the workspace, whose
+                # layout depends on the capacity: both run again on regrowth
+                dev = g.means.device
+                V, TT = len(cams), total_tiles(cams, s.tile)
+                ws_bytes = bin_sort_workspace_size(V * g.n, self.capacity, TT)
+                if self._ws is None or self._ws.numel() < ws_bytes:
+                    self._ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+                splats, n_tiles = seele_preprocess_staged(g, cams, s, self.capacity, self._ws,
+                                                          segments, stream=stream)
+                cap = max(self.capacity, 1)
+                keys = torch.empty(cap, dtype=torch.int32, device=dev)
+                ids = torch.empty(cap, dtype=torch.int32, device=dev)
+                ranges = torch.empty((total_super_tiles(cams, s.tile), 2), dtype=torch.int32,
+                                     device=dev)
+                npairs = torch.empty(1, dtype=torch.int64, device=dev)
+                seele_bin_sort_ex(splats, n_tiles, g.n, cams, s.tile, self.capacity, self._ws,
+                                  ids, ranges, npairs, keys, super_lists=True, staged=True,
+                                  stream=stream)
             else:
                 ids, ranges, npairs, self._ws = seele_bin_sort(splats, n_tiles, g.n, cams,
                                                                s.tile, self.capacity, self._ws,

@@ -202,3 +202,99 @@ def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples():
         np.testing.assert_array_equal(ncs[0][sl][safe], r["n_contrib"][sl][safe])
         assert safe.mean() > 0.9, t
     gu.log(f"[done] super full frame, oracle tiles {tiles}")
+
+
+STAGED_CASES = [
+    ("c2shape-1080p-super", lambda: (synthetic.cluster_scene(2, 200_000),
+                                     synthetic.orbit_cameras(1, 4.0, 1920, 1080)), Settings(), True),
+    ("c5shape-mixed-12views-n-not-256-super", lambda: (synthetic.cluster_scene(5, 60_001),
+                                                       synthetic.sphere_cameras(50, 12)),
+     Settings(mode="contrib"), True),
+    ("c2shape-3views-tile8-tilelists", lambda: (synthetic.cluster_scene(2, 50_003),
+                                                synthetic.orbit_cameras(3, 4.0, 640, 480)),
+     Settings(tile=8), False),
+]
+
+
+@pytest.mark.parametrize("name,build,settings,sup", STAGED_CASES, ids=[c[0] for c in STAGED_CASES])
+def test_staged_preprocessing_bins_identically(name, build, settings, sup):
+    """seele_preprocess_staged + seele_bin_sort_ex(STAGED) write the same
+    splats, counts, lists and ranges as seele_preprocess + the unstaged sort,
+    for both list forms, several views and n not a multiple of 256."""
+    from paper_2503_05168_amd import seele_bin_sort_ex, seele_preprocess_staged
+    from paper_2503_05168_amd.pipeline import bin_sort_workspace_size
+    gu.log(f"[case] staged {name}")
+    scene, cams = build()
+    st = settings
+    g = GaussianTensors.from_arrays(scene)
+    n, V = g.n, len(cams)
+    TT = total_tiles(cams, st.tile)
+    NR = total_super_tiles(cams, st.tile) if sup else TT
+    sp0, nt0 = seele_preprocess(g, cams, st)
+    out = {}
+    for staged in (False, True):
+        cap = 1 << 22
+        for _ in range(2):  # second round with the capacity the frame reported
+            ws = torch.zeros(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8,
+                             device="cuda")
+            keys = torch.empty(cap, dtype=torch.int32, device="cuda")
+            ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+            rng = torch.empty((NR, 2), dtype=torch.int32, device="cuda")
+            npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+            if staged:
+                sp, nt = seele_preprocess_staged(g, cams, st, cap, ws)
+            else:
+                sp, nt = sp0, nt0
+            seele_bin_sort_ex(sp, nt, n, cams, st.tile, cap, ws, ids, rng, npairs, keys,
+                              super_lists=sup, staged=staged)
+            torch.cuda.synchronize()
+            need = int(npairs.item())
+            if need <= cap:
+                break
+            cap = need
+        out[staged] = (sp, nt, keys, ids, rng, need)
+    a, b = out[False], out[True]
+    assert a[5] == b[5] and a[5] > 0
+    assert torch.equal(a[1], b[1])
+    vis = (a[1] > 0).repeat_interleave(16).view(-1, 16)
+    assert torch.equal(a[0][vis], b[0][vis])  # records of visible Gaussians
+    ne = int(a[4][:, 1].max().item()) if sup else a[5]
+    assert torch.equal(a[3][:ne], b[3][:ne]) and torch.equal(a[4], b[4])
+    if sup:
+        assert torch.equal(a[2][:ne], b[2][:ne])
+    gu.log(f"[done] staged {name} pairs={a[5]}")
+
+
+def test_staged_preprocessing_with_inactive_segments():
+    """Hybrid-preprocessing segments leave most records inactive: the staged
+    path still bins exactly like the unstaged one."""
+    from paper_2503_05168_amd import seele_bin_sort_ex, seele_preprocess_staged
+    from paper_2503_05168_amd.pipeline import bin_sort_workspace_size
+    scene = synthetic.cluster_scene(3, 70_000)
+    cams = synthetic.orbit_cameras(2, 4.0, 800, 600)
+    st = Settings()
+    g = GaussianTensors.from_arrays(scene)
+    segs = [(1000, 20_000), (33_333, 5_000), (60_000, 7_777)]
+    n, V = g.n, len(cams)
+    TT, NS = total_tiles(cams, st.tile), total_super_tiles(cams, st.tile)
+    cap = 1 << 22
+    res = []
+    for staged in (False, True):
+        ws = torch.zeros(bin_sort_workspace_size(V * n, cap, TT), dtype=torch.uint8,
+                         device="cuda")
+        keys = torch.empty(cap, dtype=torch.int32, device="cuda")
+        ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+        rng = torch.empty((NS, 2), dtype=torch.int32, device="cuda")
+        npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+        if staged:
+            sp, nt = seele_preprocess_staged(g, cams, st, cap, ws, segs)
+        else:
+            sp, nt = seele_preprocess(g, cams, st, segs)
+        seele_bin_sort_ex(sp, nt, n, cams, st.tile, cap, ws, ids, rng, npairs, keys,
+                          super_lists=True, staged=staged)
+        torch.cuda.synchronize()
+        res.append((nt, keys, ids, rng, int(npairs.item())))
+    (nt0, k0, i0, r0, p0), (nt1, k1, i1, r1, p1) = res
+    assert p0 == p1 and 0 < p0 <= cap and torch.equal(nt0, nt1) and torch.equal(r0, r1)
+    ne = int(r0[:, 1].max().item())
+    assert torch.equal(k0[:ne], k1[:ne]) and torch.equal(i0[:ne], i1[:ne])
