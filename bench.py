@@ -495,6 +495,8 @@ def main():
     r_ops = head["evals_needed"] * OPS_EVAL + head["blends"] * OPS_BLEND
     r_ach = r_ops / (st["raster"] * 1e-3) / 1e12
     p_bytes = 48 * head["active"] + 256 * head["visible"]
+    if head.get("lists") == "super":  # staged: (depth key, id) per visible, rectangle per record
+        p_bytes += 8 * head["visible"] + 8 * args.n
     p_ach = p_bytes / (st["preprocess"] * 1e-3) / 1e9
     # binning: 16 B per visible record (depth key, id, rectangle) plus its
     # output -- 8 B per super-tile entry (key, id) and 8 B per super-tile

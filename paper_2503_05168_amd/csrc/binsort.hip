@@ -148,11 +148,8 @@ constexpr int kScanThreads = 1024;
 
 // Chunks of 12288 partials (one chunk for a 1080p frame's 3M records) go
 // through LDS: coalesced loads, then each thread scans 12 consecutive values,
-// then coalesced stores.
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __restrict__ partial,
-                                                                 int64_t nb, Hdr* __restrict__ hdr,
-                                                                 int mode, int64_t capacity,
-                                                                 int64_t* __restrict__ num_pairs) {
+// then coalesced stores.  In place; returns the total (to every thread).
+__device__ uint64_t scan_in_place(uint64_t* __restrict__ partial, int64_t nb) {
   constexpr int R = 12;
   constexpr int CH = kScanThreads * R;
   constexpr int NW = kScanThreads / 64;
@@ -199,6 +196,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __rest
     carry += tot;
     __syncthreads();
   }
+  return carry;
+}
+
+// One workgroup.  mode 1 with partial2 also scans the entry partials after
+// the pair partials (mode 2's result), in the same launch.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __restrict__ partial,
+                                                                 int64_t nb, Hdr* __restrict__ hdr,
+                                                                 int mode, int64_t capacity,
+                                                                 int64_t* __restrict__ num_pairs,
+                                                                 uint64_t* __restrict__ partial2 =
+                                                                     nullptr) {
+  const uint64_t carry = scan_in_place(partial, nb);
+  uint64_t carry2 = 0;
+  if (partial2) carry2 = scan_in_place(partial2, nb);
   if (threadIdx.x == 0) {
     if (mode == 0) {
       hdr->n_vis = (uint32_t)carry;
@@ -206,6 +217,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __rest
       hdr->p_total = carry;
       *num_pairs = (int64_t)carry;
       hdr->n_pairs = carry <= (uint64_t)capacity ? (uint32_t)carry : 0u;
+      if (partial2) hdr->n_ent = carry <= (uint64_t)capacity ? (uint32_t)carry2 : 0u;
     } else if (mode == 2) {
       hdr->n_ent = hdr->p_total <= (uint64_t)capacity ? (uint32_t)carry : 0u;
     } else if (mode == 3) {
@@ -214,11 +226,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __rest
   }
 }
 
-// Visible records in id order: (depth key, id) at their compacted position,
-// and every record's packed tile rectangle (zero if not visible) into the
-// dense id-indexed array rid, read from the same 16 bytes of the record as
-// the depth.  The later gathers in depth order then touch 8 bytes per record
-// of a small array instead of a 64-byte record each.
 __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n_tiles, int64_t n,
                                                     const seele_splat* __restrict__ splats,
                                                     const uint64_t* __restrict__ partial,
@@ -1105,10 +1112,10 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], rid, views, hdr,
                        rx_s, ry_s, partial, partial2);
   }
+  // pair partials, then entry partials (whose count depends on the pair
+  // total), in one launch
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
-                     WAVES * (int64_t)nbR, hdr, 1, p.capacity, num_pairs);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial2,
-                     WAVES * (int64_t)nbR, hdr, 2, p.capacity, num_pairs);
+                     WAVES * (int64_t)nbR, hdr, 1, p.capacity, num_pairs, partial2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   //    entries, then sorted by super-tile id (balanced digit widths <= 8).
   //    Per-tile lists: the value buffers alternate between svals0 and
