@@ -75,15 +75,17 @@ __device__ __forceinline__ bool blend_step(float fx, float fy, const float4& a, 
   return take;
 }
 
-// The same step without branches (selects only), for the production loop:
+// The same step without branches (selects only), for the production loops:
 // a step that does not blend adds 0 * colour (colours are finite and >= 0,
-// the sums start at +0), so it writes the same bits as blend_step.
+// the sums start at +0), so it writes the same bits as blend_step.  acc =
+// false (a group whose leader did not accept the Gaussian) leaves the pixel
+// unchanged, as if blend_step were not called.
 __device__ __forceinline__ void blend_select(float fx, float fy, const float4& a, const float4& b,
                                              float blue, int pos, float amin, float amax,
                                              float tmin, float& T, float& c0, float& c1,
-                                             float& c2, int& last) {
+                                             float& c2, int& last, bool acc = true) {
   const float alpha = alpha_at(fx, fy, a, b, amax);
-  const bool pass = alpha >= amin;
+  const bool pass = acc && alpha >= amin;
   const float w = T * alpha;
   const float Tn = T - w;
   const bool keep = Tn >= tmin;
@@ -472,9 +474,8 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
               const uint64_t gm = (bal >> (s * G)) & gmask;
               if (gm == 0) continue;  // no leader of this wave accepts it: wave-uniform skip
               const int k = __builtin_amdgcn_readlane(kk, s * G);
-              if ((gm >> grp) & 1ull)
-                blend_step(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, lbase + k + 1, amin,
-                           amax, tmin, T, c0, c1, c2, last);
+              blend_select(fx, fy, s_rec[k].a, s_rec[k].b, s_rec[k].blue, lbase + k + 1, amin,
+                           amax, tmin, T, c0, c1, c2, last, ((gm >> grp) & 1ull) != 0);
             }
             if (__ballot(T >= 0.0f) == 0) break;
           }
