@@ -72,6 +72,8 @@ def parse():
                     help="tiles of view 0 the CPU oracle blends (about 10-30 s of CPU work)")
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
+    ap.add_argument("--no-groups", action="store_true",
+                    help="skip the contribution-aware group-size sweep")
     ap.add_argument("--lists", choices=("super", "tile"), default="super",
                     help="list form of the timed frame: super-tile lists read by each tile "
                          "(default) or per-tile lists")
@@ -236,6 +238,33 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     log(f"[bench] {name}: {out['fps']:.1f} fps ({ms:.3f} ms/frame) stages="
         + ", ".join(f"{a}={b:.3f}" for a, b in stage.items())
         + f" pairs={out['pairs']:.3e} vis={out['visible']:.3e} evals={evals:.3e}")
+    return out
+
+
+def run_group_sweep(g, cams, steps, warmup, groups=((1, 1), (2, 2), (2, 4), (4, 4))):
+    """Contribution-aware form with pixel groups of several sizes (Fig. 7's
+    sweep on the synthetic 1080p scene): frames/s, and the PSNR of its image
+    against the plain form's over the first four orbit views."""
+    import torch
+    import paper_2503_05168_amd as P
+
+    views = cams[:4]
+    ref = P.Renderer(P.Settings(), capacity=1 << 26, lists="super")
+    plain = [ref.render(g, [c]).image.clone() for c in views]
+    out = []
+    for gw, gh in groups:
+        st = P.Settings(mode="contrib", group=(gw, gh))
+        res = run_form(f"contrib-{gw}x{gh}", dict(g=g, st=st, hp=None), cams, steps, warmup)
+        r = P.Renderer(st, capacity=ref.capacity, lists="super")
+        mse = 0.0
+        for c, im in zip(views, plain):
+            d = r.render(g, [c]).image - im
+            mse += float((d * d).mean().item()) / len(views)
+        psnr = float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+        out.append(dict(group=f"{gw}x{gh}", fps=res["fps"], raster_ms=res["stage_ms"]["raster"],
+                        psnr_vs_plain=psnr, leader_tests=res["leader_tests"],
+                        leader_pass=res["leader_pass"], blends=res["blends"]))
+        log(f"[bench] CR group {gw}x{gh}: {res['fps']:.1f} fps, PSNR vs plain {psnr:.2f} dB")
     return out
 
 
@@ -475,6 +504,11 @@ def main():
     for name in names:
         results[name] = run_form(name, forms[name], cams, args.steps, args.warmup, args.lists)
         log(f"[bench] t+{time.time() - t_start:.0f}s form {name} done")
+    groups = None
+    if not args.no_groups and "plain" in forms:
+        groups = run_group_sweep(forms["plain"]["g"], cams, max(8, args.steps // 2),
+                                 max(2, args.warmup // 2))
+        log(f"[bench] t+{time.time() - t_start:.0f}s group sweep done")
     fwd_bwd = None
     if not args.no_bwd:
         del forms
@@ -550,6 +584,7 @@ def main():
                                 {k: v["ms_per_view"] for k, v in fwd_bwd.items()}),
         "fwd_bwd": fwd_bwd,
         "batched_64_views": batched,
+        "contrib_group_sweep": groups,
         "roofline": roof,
         "stage_roofline": stage_roof,
         "cpu_baseline": cpu,
