@@ -276,6 +276,23 @@ int32_t seele_rasterize_fwd_super(const seele_splat* splats, const uint32_t* ent
                                   const seele_raster_opts* opts, float* image, float* final_T,
                                   int32_t* n_contrib, uint64_t* counters, void* stream);
 
+/* Offline contribution pass of the view-dependent representation (Sec. 3.3
+ * "Offline Clustering"): the plain blend of every pixel (Eqs. 1-2, exactly
+ * as seele_rasterize_fwd computes it) over the per-tile lists of
+ * seele_bin_sort, ranking each pixel's blended records by their contribution
+ * T_i alpha_i (a larger one first, equal ones toward the lower record id).
+ *   topk_mark   device [n_views * n] uint8: set to 1 for every record among
+ *               some pixel's k first (1 <= k <= 32); other entries are left
+ *               unchanged, so marks accumulate over calls (the caller clears)
+ *   contrib_sum device [n_views * n] float32: T_i alpha_i of every blend is
+ *               added to its record's entry (float atomics; summation order
+ *               unspecified)
+ * opts->mode must be SEELE_RASTER_PLAIN (SEELE_ERR_UNSUPPORTED otherwise). */
+int32_t seele_contrib_topk(const seele_splat* splats, const uint32_t* sorted_ids,
+                           const int32_t* tile_ranges, const seele_camera* cams, int32_t n_views,
+                           int64_t n, const seele_raster_opts* opts, int32_t k,
+                           uint8_t* topk_mark, float* contrib_sum, void* stream);
+
 /* Order of the (view, tile) work queue of seele_rasterize_fwd_queue. */
 enum {
   SEELE_QUEUE_LIST = 0,           /* tiles in id order                       */

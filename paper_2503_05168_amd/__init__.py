@@ -17,6 +17,7 @@ from .pipeline import (  # noqa: F401
     seele_preprocess_staged,
     seele_rasterize_fwd,
     seele_rasterize_fwd_super,
+    seele_contrib_topk,
     seele_rasterize_fwd_counted,
     seele_rasterize_fwd_queue,
     seele_rasterize_bwd,

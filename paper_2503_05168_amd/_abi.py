@@ -89,6 +89,9 @@ SIGNATURES = {
                                             POINTER(seele_camera), c_int32,
                                             POINTER(seele_raster_opts), c_void_p, c_void_p,
                                             c_void_p, c_void_p, c_void_p]),
+    "seele_contrib_topk": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera), c_int32,
+                                     c_int64, POINTER(seele_raster_opts), c_int32, c_void_p,
+                                     c_void_p, c_void_p]),
     "seele_raster_queue_workspace_size": (c_size_t, [c_int64]),
     "seele_rasterize_fwd_queue": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
                                             c_int32, POINTER(seele_raster_opts), c_int32,

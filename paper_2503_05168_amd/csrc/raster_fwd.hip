@@ -57,13 +57,14 @@ __device__ __forceinline__ float alpha_at(float px, float py, const float4& a, c
 __device__ __forceinline__ bool blend_step(float fx, float fy, const float4& a, const float4& b,
                                            float blue, int pos, float amin, float amax,
                                            float tmin, float& T, float& c0, float& c1, float& c2,
-                                           int& last) {
+                                           int& last, float* w_out = nullptr) {
   const float alpha = alpha_at(fx, fy, a, b, amax);
   const bool pass = alpha >= amin;
   const float wgt = T * alpha;
   const float Tn = T - wgt;
   const bool keep = Tn >= tmin;
   const bool take = pass && keep;
+  if (w_out) *w_out = take ? wgt : 0.0f;  // the blend weight T alpha (0 if not blended)
   if (take) {
     c0 = __builtin_fmaf(wgt, b.z, c0);
     c1 = __builtin_fmaf(wgt, b.w, c1);
@@ -560,6 +561,101 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd_queue(
   }
 }
 
+// Offline contribution pass (Sec. 3.3 "Offline Clustering"): the plain blend
+// of every pixel, exactly as the forward computes it (blend_step), keeping
+// the pixel's K largest contributions T alpha with their record ids in
+// registers; a larger contribution wins, equal ones go to the lower record
+// id.  At the end every pixel marks its top records; every blend also adds
+// its T alpha to the record's sum (one atomic per record and wave, after a
+// wave reduction).  One workgroup per (view, tile), one lane per pixel, the
+// tile list staged through LDS one record per thread.
+template <int TS, int K>
+__global__ __launch_bounds__(TS* TS) void k_contrib_topk(RasterViews views, RasterParams rp,
+                                                         const seele_splat* __restrict__ splats,
+                                                         const uint32_t* __restrict__ ids,
+                                                         const int32_t* __restrict__ ranges,
+                                                         int k_top, uint8_t* __restrict__ mark,
+                                                         float* __restrict__ contrib_sum) {
+  constexpr int NT = TS * TS;
+  __shared__ LdsRec s_rec[NT];
+  __shared__ uint32_t s_id[NT];
+  const int gt = blockIdx.x;
+  int v = 0;
+  for (int q = 1; q < views.n_views; ++q)
+    if (views.v[q].tile_begin <= gt) v = q;
+  const RasterView rv = views.v[v];
+  const int lt = gt - rv.tile_begin;
+  const int tile_x = lt % rv.grid_w, tile_y = lt / rv.grid_w;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wx = (TS == 16) ? (wave & 1) * 8 : 0, wy = (TS == 16) ? (wave >> 1) * 8 : 0;
+  const int x = tile_x * TS + wx + (lane & 7), y = tile_y * TS + wy + (lane >> 3);
+  const bool inside = x < rv.W && y < rv.H;
+  const float fx = (float)x + 0.5f, fy = (float)y + 0.5f;
+  const int64_t ri = 2 * ((int64_t)views.tile_base + gt);
+  const int start = ranges[ri], n = ranges[ri + 1] - start;
+  const float amin = rp.alpha_min, amax = rp.alpha_max, tmin = rp.T_min;
+
+  float T = inside ? 1.0f : -1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+  int last = 0;
+  float tw[K];
+  uint32_t tr[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    tw[j] = -1.0f;  // empty slot: below every contribution
+    tr[j] = 0xffffffffu;
+  }
+  for (int base = 0; base < n; base += NT) {
+    if (__syncthreads_count(T < 0.0f) == NT) break;
+    if (tid < n - base) {
+      const uint32_t id = ids[start + base + tid];
+      const float4* src = reinterpret_cast<const float4*>(splats + id);
+      const float4 b = src[1];
+      s_rec[tid].a = src[0];
+      s_rec[tid].b = make_float4(b.x, __log2f(b.y), b.z, b.w);
+      s_rec[tid].blue = src[2].x;
+      s_id[tid] = id;
+    }
+    __syncthreads();
+    const int cnt = min(NT, n - base);
+    for (int q = 0; q < cnt; ++q) {
+      if (__ballot(T >= 0.0f) == 0) break;
+      float w;
+      const bool took = blend_step(fx, fy, s_rec[q].a, s_rec[q].b, s_rec[q].blue, base + q + 1,
+                                   amin, amax, tmin, T, c0, c1, c2, last, &w);
+      const uint32_t rid = s_id[q];
+      if (took) {
+        // replace the worst kept entry (smallest weight, then largest id) if w beats it
+        int wj = 0;
+#pragma unroll
+        for (int j = 1; j < K; ++j) {
+          const bool worse = tw[j] < tw[wj] || (tw[j] == tw[wj] && tr[j] > tr[wj]);
+          wj = (j < k_top && worse) ? j : wj;
+        }
+        float ww = 0.0f;
+        uint32_t wr = 0u;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          ww = j == wj ? tw[j] : ww;
+          wr = j == wj ? tr[j] : wr;
+        }
+        if (w > ww || (w == ww && rid < wr)) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            tw[j] = j == wj ? w : tw[j];
+            tr[j] = j == wj ? rid : tr[j];
+          }
+        }
+      }
+      const float ws = wave_sum(w);
+      if (lane == 0 && ws != 0.0f) atomicAdd(contrib_sum + rid, ws);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j < k_top && tr[j] != 0xffffffffu) mark[tr[j]] = 1;
+}
+
 // Sort keys for heaviest-first scheduling: ~(list length) so an ascending
 // stable sort puts long lists first (ties in tile order).
 __global__ void k_tile_len_keys(const int32_t* __restrict__ ranges, int32_t tile_base,
@@ -652,6 +748,21 @@ hipError_t launch_raster_fwd_super(int tile, int mode, const RasterViews& views,
   else
     launch_super<8>(mode, counters != nullptr, grid, views, rp, splats, entry_keys, entry_ids,
                     st_ranges, image, final_T, n_contrib, counters, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_contrib_topk(int tile, const RasterViews& views, int n_tiles_launch,
+                               const RasterParams& rp, const seele_splat* splats,
+                               const uint32_t* sorted_ids, const int32_t* tile_ranges, int k_top,
+                               uint8_t* mark, float* contrib_sum, hipStream_t stream) {
+  if (n_tiles_launch <= 0) return hipSuccess;
+  const dim3 grid(n_tiles_launch);
+  if (tile == 16)
+    hipLaunchKernelGGL((k_contrib_topk<16, 32>), grid, dim3(256), 0, stream, views, rp, splats,
+                       sorted_ids, tile_ranges, k_top, mark, contrib_sum);
+  else
+    hipLaunchKernelGGL((k_contrib_topk<8, 32>), grid, dim3(64), 0, stream, views, rp, splats,
+                       sorted_ids, tile_ranges, k_top, mark, contrib_sum);
   return hipGetLastError();
 }
 

@@ -501,6 +501,42 @@ int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_id
                    n_contrib, nullptr, stream);
 }
 
+int32_t seele_contrib_topk(const seele_splat* splats, const uint32_t* sorted_ids,
+                           const int32_t* tile_ranges, const seele_camera* cams, int32_t n_views,
+                           int64_t n, const seele_raster_opts* opts, int32_t k,
+                           uint8_t* topk_mark, float* contrib_sum, void* stream) {
+  int32_t s = check_raster_opts(opts);
+  if (s != SEELE_OK) return s;
+  if (opts->mode != SEELE_RASTER_PLAIN)
+    return fail(SEELE_ERR_UNSUPPORTED, "the contribution pass blends in the plain form");
+  if (k < 1 || k > 32) return fail(SEELE_ERR_INVALID_ARG, "k must be in [1, 32]");
+  if ((s = check_cams(cams, n_views, opts->tile, 1 << 20)) != SEELE_OK) return s;
+  if (n < 0 || (int64_t)n_views * n >= ((int64_t)1 << 32))
+    return fail(SEELE_ERR_INVALID_ARG, "n out of range");
+  const int64_t TT = seele_total_tiles(cams, n_views, opts->tile);
+  if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
+  if (!tile_ranges || !aligned(tile_ranges, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
+  if (n > 0 && (!topk_mark || !contrib_sum || !aligned(contrib_sum, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "topk_mark / contrib_sum null or misaligned");
+  if ((splats && !aligned(splats, 16)) || (sorted_ids && !aligned(sorted_ids, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "splats/sorted_ids misaligned");
+  const RasterParams rp = make_raster_params(opts);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t tile_base = 0, pix_base = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsRaster) {
+    const int nv = std::min(kMaxViewsRaster, n_views - v0);
+    int64_t t = 0, npx = 0;
+    const RasterViews rv = make_raster_views(cams, v0, nv, opts->tile, tile_base, pix_base, t, npx);
+    pix_base += npx;
+    const hipError_t e = launch_contrib_topk(opts->tile, rv, (int)t, rp, splats, sorted_ids,
+                                             tile_ranges, k, topk_mark, contrib_sum, st);
+    if (e != hipSuccess) return hip_fail(e, "contribution pass launch");
+    tile_base += t;
+  }
+  return SEELE_OK;
+}
+
 int32_t seele_rasterize_fwd_super(const seele_splat* splats, const uint32_t* entry_keys,
                                   const uint32_t* entry_ids, const int32_t* st_ranges,
                                   const seele_camera* cams, int32_t n_views,

@@ -282,6 +282,12 @@ BinStage bin_stage_of(const BinSortPlan& p, void* ws, int64_t n);
 
 bool raster_batch_supported(int tile, int batch);
 
+// Offline contribution pass: per-pixel top-k (k <= 32) marks and sums.
+hipError_t launch_contrib_topk(int tile, const RasterViews& views, int n_tiles_launch,
+                               const RasterParams& rp, const seele_splat* splats,
+                               const uint32_t* sorted_ids, const int32_t* tile_ranges, int k_top,
+                               uint8_t* mark, float* contrib_sum, hipStream_t stream);
+
 // Forward over super-tile lists (one LDS batch of two entries per thread).
 hipError_t launch_raster_fwd_super(int tile, int mode, const RasterViews& views,
                                    int n_tiles_launch, const RasterParams& rp,

@@ -296,6 +296,29 @@ def seele_rasterize_fwd_super(splats, entry_keys, entry_ids, st_ranges, cams, se
     return image, final_T, n_contrib
 
 
+def seele_contrib_topk(splats, sorted_ids, tile_ranges, cams, settings: Settings, n: int,
+                       k: int = 32, topk_mark=None, contrib_sum=None, stream=None):
+    """Offline contribution pass over per-tile lists (plain blend): marks
+    every record among some pixel's k largest contributions T alpha and adds
+    every blend's T alpha per record.  Marks and sums accumulate into the
+    given tensors (zero-initialised when not given).  Returns (mark, sum)."""
+    dev = tile_ranges.device
+    R = len(cams) * n
+    if topk_mark is None:
+        topk_mark = torch.zeros(max(R, 1), dtype=torch.uint8, device=dev)
+    if contrib_sum is None:
+        contrib_sum = torch.zeros(max(R, 1), dtype=torch.float32, device=dev)
+    _need(tile_ranges, 2 * total_tiles(cams, settings.tile), torch.int32, "tile_ranges")
+    _need(topk_mark, R, torch.uint8, "topk_mark")
+    _need(contrib_sum, R, torch.float32, "contrib_sum")
+    opts = settings.raster_opts()
+    st = A.lib().seele_contrib_topk(_p(splats), _p(sorted_ids), _p(tile_ranges),
+                                    A.camera_array(cams), len(cams), n, ctypes.byref(opts), k,
+                                    _p(topk_mark), _p(contrib_sum), _stream(stream))
+    A.check(st, "seele_contrib_topk")
+    return topk_mark, contrib_sum
+
+
 def seele_rasterize_fwd(splats, sorted_ids, tile_ranges, cams, settings: Settings, image=None,
                         final_T=None, n_contrib=None, stream=None):
     dev = tile_ranges.device
