@@ -44,3 +44,71 @@ def active_mask(n: int, segments) -> np.ndarray:
     for b, c in segments:
         m[b:b + c] = True
     return m
+
+
+# ---------------------------------------------------------------------------
+# Offline construction (Sec. 3.3 "Offline Clustering")
+#
+# Readings: the sampled poses are clustered with k-means on the same camera
+# feature the runtime selection uses; seeding is farthest-point (pose 0, then
+# repeatedly the pose whose distance to its nearest chosen centroid is
+# largest, the lowest index on ties), then Lloyd iterations (assign to the
+# nearest centroid, lowest index on ties; move each centroid to its members'
+# mean, an empty cluster keeping its centroid) until no label changes or
+# `iters` updates were made.  Per cluster, the union over its views' pixels
+# of their top-k contributors (contrib.marks_and_sums) is its important set;
+# the shared set is the union of the clusters' important sets.  Every other
+# Gaussian with a positive summed contribution in some cluster is exclusive
+# to the cluster where that sum is largest (the earlier cluster on ties);
+# Gaussians that never blend belong to no segment and are placed last.
+
+def kmeans(features: np.ndarray, K: int, iters: int = 100):
+    """(centroids [K, 6] float64, labels [n] int) of the poses' features."""
+    f = np.asarray(features, dtype=np.float64)
+    n = len(f)
+    if not 1 <= K <= n:
+        raise ValueError("need 1 <= K <= number of poses")
+    chosen = [0]
+    for _ in range(1, K):
+        d_near = np.array([min(((f[p] - f[c]) ** 2).sum() for c in chosen) for p in range(n)])
+        chosen.append(int(np.flatnonzero(d_near == d_near.max())[0]))
+    cent = f[chosen].copy()
+    labels = None
+    for it in range(iters + 1):
+        d = ((f[:, None, :] - cent[None, :, :]) ** 2).sum(-1)
+        new = np.array([int(np.flatnonzero(d[p] == d[p].min())[0]) for p in range(n)])
+        if labels is not None and (new == labels).all():
+            break
+        labels = new
+        if it == iters:
+            break
+        for k in range(K):
+            if (labels == k).any():
+                cent[k] = f[labels == k].mean(0)
+    return cent, labels
+
+
+def partition(cluster_marks, cluster_sums, n: int):
+    """Segment layout from each cluster's top-k marks (bool [n]) and summed
+    contributions ([n]): (perm, seg_begin [1 + K], seg_count [1 + K]) with
+    perm[new position] = original index over [shared | excl_0 | ... |
+    excl_{K-1} | unused], the original order kept inside each segment."""
+    K = len(cluster_marks)
+    shared = np.zeros(n, dtype=bool)
+    for m in cluster_marks:
+        shared |= np.asarray(m, dtype=bool)
+    seg = np.full(n, K + 1)
+    for i in range(n):
+        if shared[i]:
+            seg[i] = 0
+            continue
+        best, best_c = 0.0, -1
+        for c in range(K):
+            if cluster_sums[c][i] > best:
+                best, best_c = cluster_sums[c][i], c
+        if best_c >= 0:
+            seg[i] = 1 + best_c
+    perm = np.concatenate([np.flatnonzero(seg == s) for s in range(K + 2)]).astype(np.int64)
+    count = np.array([(seg == s).sum() for s in range(K + 1)], dtype=np.int64)
+    begin = np.concatenate([[0], np.cumsum(count)[:-1]]).astype(np.int64)
+    return perm, begin, count
