@@ -355,6 +355,48 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
                             const float* dL_dimage, float* grad2d,
                             const seele_gaussian_grads* grads, void* stream);
 
+/* Offline view-dependent representation (Sec. 3.3 "Offline Clustering").
+ *
+ * seele_hp_kmeans clusters n_cams sampled poses (host array) into K groups
+ * by the pose feature (camera centre / pos_scale, beta * view direction),
+ * the one seele_hp_select uses: farthest-point seeding (pose 0 first, then
+ * the pose farthest from every chosen centroid, lowest index on ties), then
+ * Lloyd iterations (nearest centroid, lowest index on ties; member means; an
+ * empty cluster keeps its centroid) until no label changes or `iters` updates.
+ * Host only: centroids host [K][6], labels host [n_cams]. */
+int32_t seele_hp_kmeans(const seele_camera* cams, int32_t n_cams, float pos_scale, float beta,
+                        int32_t K, int32_t iters, float* centroids, int32_t* labels);
+
+/* Folds one cluster's seele_contrib_topk results (records v*n + i of its
+ * n_views views) into per-Gaussian state, on the device: shared[i] |= any
+ * view's top-k mark; if the cluster's summed contribution exceeds best_sum[i]
+ * (strictly), best_sum[i] and best_cluster[i] = cluster.  The caller starts
+ * from shared = 0, best_sum = 0, best_cluster = -1 and calls once per
+ * cluster in index order (so ties keep the earlier cluster).
+ *   topk_mark [n_views * n] uint8, contrib_sum [n_views * n] float32,
+ *   shared [n] uint8, best_sum [n] float32, best_cluster [n] int32. */
+int32_t seele_hp_accumulate(const uint8_t* topk_mark, const float* contrib_sum, int32_t n_views,
+                            int64_t n, int32_t cluster, uint8_t* shared, float* best_sum,
+                            int32_t* best_cluster, void* stream);
+
+/* The segment layout (host): Gaussians with shared[i] form the shared
+ * segment; the others with best_sum[i] > 0 form cluster best_cluster[i]'s
+ * exclusive segment; the rest (never blended in any sampled view) go last
+ * and belong to no segment.  Within a segment the original order is kept.
+ *   perm          host [n] int64: perm[new position] = original index
+ *   layout_begin  host [1 + K] int64: shared segment, then clusters 0..K-1
+ *   layout_count  host [1 + K] int64   (the layout seele_hp_segments reads) */
+int32_t seele_hp_partition(const uint8_t* shared, const float* best_sum,
+                           const int32_t* best_cluster, int64_t n, int32_t K, int64_t* perm,
+                           int64_t* layout_begin, int64_t* layout_count);
+
+/* dst[c] = src[perm[c]] for every attribute, c < n_out (perm device int64);
+ * dst holds device arrays in the seele_gaussians layout for n_out Gaussians
+ * (the writable struct seele_gaussian_grads describes them); the SH rows
+ * src->sh_degree uses are copied. */
+int32_t seele_gather_gaussians(const seele_gaussians* src, const int64_t* perm, int64_t n_out,
+                               const seele_gaussian_grads* dst, void* stream);
+
 /* Hybrid preprocessing, runtime cluster choice (Sec. 3.3 "Algorithm").  The
  * camera feature is (centre / pos_scale, beta * view direction); the nearest
  * of the K centroids (host [K][6]) is chosen, then the M centroids nearest to

@@ -30,3 +30,11 @@ from .pipeline import (  # noqa: F401
     pixel_count,
     split_views,
 )
+from .hp_build import (  # noqa: F401
+    ViewDependentScene,
+    build_view_dependent,
+    seele_gather_gaussians,
+    seele_hp_accumulate,
+    seele_hp_kmeans,
+    seele_hp_partition,
+)

@@ -105,6 +105,14 @@ SIGNATURES = {
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, POINTER(seele_gaussian_grads),
                                       c_void_p]),
+    "seele_hp_kmeans": (c_int32, [POINTER(seele_camera), c_int32, c_float, c_float, c_int32,
+                                  c_int32, POINTER(c_float), POINTER(c_int32)]),
+    "seele_hp_accumulate": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_int32, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]),
+    "seele_hp_partition": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32,
+                                     POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
+    "seele_gather_gaussians": (c_int32, [POINTER(seele_gaussians), c_void_p, c_int64,
+                                         POINTER(seele_gaussian_grads), c_void_p]),
     "seele_hp_select": (c_int32, [POINTER(c_float), c_int32, POINTER(seele_camera), c_float,
                                   c_float, c_int32, POINTER(c_int32)]),
     "seele_hp_segments": (c_int32, [POINTER(c_int64), POINTER(c_int64), c_int32, POINTER(c_int32),

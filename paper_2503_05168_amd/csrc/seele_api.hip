@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "seele_internal.h"
 
@@ -219,6 +221,45 @@ RasterViews make_raster_views(const seele_camera* cams, int v0, int nv, int tile
   n_tiles_out = t;
   n_pix_out = px;
   return rv;
+}
+
+// Per Gaussian i, over the n_views records v*n + i of one cluster's views:
+// shared |= any top-k mark; the summed contribution replaces best_sum (and
+// the cluster best_cluster) if strictly larger, so ties keep the earlier
+// cluster.
+__global__ void k_hp_accumulate(const uint8_t* __restrict__ mark, const float* __restrict__ sums,
+                                int32_t n_views, int64_t n, int32_t cluster,
+                                uint8_t* __restrict__ shared, float* __restrict__ best_sum,
+                                int32_t* __restrict__ best_cluster) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint8_t any = 0;
+  float s = 0.0f;
+  for (int v = 0; v < n_views; ++v) {
+    any |= mark[(int64_t)v * n + i];
+    s += sums[(int64_t)v * n + i];
+  }
+  if (any) shared[i] = 1;
+  if (s > best_sum[i]) {
+    best_sum[i] = s;
+    best_cluster[i] = cluster;
+  }
+}
+
+// dst[c] = src[perm[c]] for every attribute (SoA: component-major arrays).
+__global__ void k_gather_gaussians(seele_gaussians src, const int64_t* __restrict__ perm,
+                                   int64_t n_out, seele_gaussian_grads dst, int n_sh) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_out) return;
+  const int64_t i = perm[c];
+  const int64_t ns = src.n, nd = n_out;
+  for (int k = 0; k < 3; ++k) {
+    dst.means[k * nd + c] = src.means[k * ns + i];
+    dst.log_scales[k * nd + c] = src.log_scales[k * ns + i];
+  }
+  for (int k = 0; k < 4; ++k) dst.quats[k * nd + c] = src.quats[k * ns + i];
+  dst.opacity_logits[c] = src.opacity_logits[i];
+  for (int k = 0; k < n_sh; ++k) dst.sh[k * nd + c] = src.sh[k * ns + i];
 }
 
 __global__ void k_fill_f32(float* p, int64_t n) {
@@ -702,6 +743,148 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
   return SEELE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Pose feature of Sec. 3.3 "Offline Clustering": the camera centre divided
+// by pos_scale, then beta times the viewing direction (camera +z in world
+// coordinates).
+void pose_feature(const seele_camera* cam, float pos_scale, float beta, double* f) {
+  for (int i = 0; i < 3; ++i) {
+    double c = 0.0;
+    for (int j = 0; j < 3; ++j) c -= (double)cam->R[j * 3 + i] * (double)cam->t[j];
+    f[i] = c / (double)pos_scale;
+    f[3 + i] = (double)beta * (double)cam->R[6 + i];
+  }
+}
+
+double dist2_6(const double* a, const double* b) {
+  double s = 0.0;
+  for (int i = 0; i < 6; ++i) s += (a[i] - b[i]) * (a[i] - b[i]);
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_hp_kmeans(const seele_camera* cams, int32_t n_cams, float pos_scale, float beta,
+                        int32_t K, int32_t iters, float* centroids, int32_t* labels) {
+  if (!cams || !centroids || !labels) return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (n_cams < 1 || K < 1 || K > n_cams || iters < 0)
+    return fail(SEELE_ERR_INVALID_ARG, "need 1 <= K <= n_cams and iters >= 0");
+  if (!(pos_scale > 0.0f) || !is_finite(pos_scale) || !is_finite(beta))
+    return fail(SEELE_ERR_INVALID_ARG, "bad pos_scale/beta");
+  std::vector<double> f((size_t)n_cams * 6), c((size_t)K * 6), dmin((size_t)n_cams);
+  for (int p = 0; p < n_cams; ++p) pose_feature(&cams[p], pos_scale, beta, &f[(size_t)p * 6]);
+  // farthest-point seeding: pose 0, then each time the pose farthest from
+  // every chosen centroid (the lowest index on ties)
+  for (int i = 0; i < 6; ++i) c[i] = f[i];
+  for (int p = 0; p < n_cams; ++p) dmin[p] = dist2_6(&f[(size_t)p * 6], &c[0]);
+  for (int k = 1; k < K; ++k) {
+    int far = 0;
+    for (int p = 1; p < n_cams; ++p)
+      if (dmin[p] > dmin[far]) far = p;
+    for (int i = 0; i < 6; ++i) c[(size_t)k * 6 + i] = f[(size_t)far * 6 + i];
+    for (int p = 0; p < n_cams; ++p)
+      dmin[p] = std::min(dmin[p], dist2_6(&f[(size_t)p * 6], &c[(size_t)k * 6]));
+  }
+  // Lloyd: nearest centroid (lowest index on ties), then member means; an
+  // empty cluster keeps its centroid; stops when no label changes
+  std::vector<int> lab((size_t)n_cams, -1);
+  for (int it = 0; it <= iters; ++it) {
+    bool changed = false;
+    for (int p = 0; p < n_cams; ++p) {
+      int best = 0;
+      double bd = dist2_6(&f[(size_t)p * 6], &c[0]);
+      for (int k = 1; k < K; ++k) {
+        const double d = dist2_6(&f[(size_t)p * 6], &c[(size_t)k * 6]);
+        if (d < bd) {
+          bd = d;
+          best = k;
+        }
+      }
+      changed |= lab[p] != best;
+      lab[p] = best;
+    }
+    if (!changed || it == iters) break;
+    std::vector<double> sum((size_t)K * 6, 0.0);
+    std::vector<int> cnt((size_t)K, 0);
+    for (int p = 0; p < n_cams; ++p) {
+      ++cnt[lab[p]];
+      for (int i = 0; i < 6; ++i) sum[(size_t)lab[p] * 6 + i] += f[(size_t)p * 6 + i];
+    }
+    for (int k = 0; k < K; ++k)
+      if (cnt[k] > 0)
+        for (int i = 0; i < 6; ++i) c[(size_t)k * 6 + i] = sum[(size_t)k * 6 + i] / cnt[k];
+  }
+  for (int k = 0; k < K * 6; ++k) centroids[k] = (float)c[k];
+  for (int p = 0; p < n_cams; ++p) labels[p] = lab[p];
+  return SEELE_OK;
+}
+
+int32_t seele_hp_accumulate(const uint8_t* topk_mark, const float* contrib_sum, int32_t n_views,
+                            int64_t n, int32_t cluster, uint8_t* shared, float* best_sum,
+                            int32_t* best_cluster, void* stream) {
+  if (n_views < 1 || n < 0 || cluster < 0)
+    return fail(SEELE_ERR_INVALID_ARG, "need n_views >= 1, n >= 0, cluster >= 0");
+  if (n == 0) return SEELE_OK;
+  if (!topk_mark || !contrib_sum || !shared || !best_sum || !best_cluster ||
+      !aligned(contrib_sum, 4) || !aligned(best_sum, 4) || !aligned(best_cluster, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "null or misaligned argument");
+  hipLaunchKernelGGL(k_hp_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), topk_mark, contrib_sum, n_views, n, cluster,
+                     shared, best_sum, best_cluster);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SEELE_OK : hip_fail(e, "hp accumulate launch");
+}
+
+int32_t seele_gather_gaussians(const seele_gaussians* src, const int64_t* perm, int64_t n_out,
+                               const seele_gaussian_grads* dst, void* stream) {
+  int32_t s = check_gaussians(src);
+  if (s != SEELE_OK) return s;
+  if (n_out < 0 || n_out >= ((int64_t)1 << 31) || !dst)
+    return fail(SEELE_ERR_INVALID_ARG, "bad n_out or null dst");
+  if (n_out == 0) return SEELE_OK;
+  if (src->n == 0) return fail(SEELE_ERR_INVALID_ARG, "gather from an empty set");
+  if (!perm || !aligned(perm, 8)) return fail(SEELE_ERR_INVALID_ARG, "perm null or misaligned");
+  const void* p[5] = {dst->means, dst->log_scales, dst->quats, dst->opacity_logits, dst->sh};
+  for (int k = 0; k < 5; ++k)
+    if (!p[k] || !aligned(p[k], 4)) return fail(SEELE_ERR_INVALID_ARG, "dst array null/misaligned");
+  const int n_sh = 3 * (src->sh_degree + 1) * (src->sh_degree + 1);
+  hipLaunchKernelGGL(k_gather_gaussians, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), *src, perm, n_out, *dst, n_sh);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SEELE_OK : hip_fail(e, "gather launch");
+}
+
+int32_t seele_hp_partition(const uint8_t* shared, const float* best_sum,
+                           const int32_t* best_cluster, int64_t n, int32_t K, int64_t* perm,
+                           int64_t* layout_begin, int64_t* layout_count) {
+  if (n < 0 || K < 1) return fail(SEELE_ERR_INVALID_ARG, "need n >= 0 and K >= 1");
+  if (n > 0 && (!shared || !best_sum || !best_cluster || !perm))
+    return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (!layout_begin || !layout_count) return fail(SEELE_ERR_INVALID_ARG, "null layout");
+  // segment of each Gaussian: 0 shared, 1 + c exclusive to cluster c, K + 1 discarded
+  auto seg_of = [&](int64_t i) -> int64_t {
+    if (shared[i]) return 0;
+    const int32_t c = best_cluster[i];
+    if (best_sum[i] > 0.0f && c >= 0 && c < K) return 1 + c;
+    return (int64_t)K + 1;
+  };
+  std::vector<int64_t> cnt((size_t)K + 2, 0);
+  for (int64_t i = 0; i < n; ++i) ++cnt[(size_t)seg_of(i)];
+  std::vector<int64_t> next((size_t)K + 2, 0);
+  for (int s = 1; s < K + 2; ++s) next[(size_t)s] = next[(size_t)s - 1] + cnt[(size_t)s - 1];
+  for (int s = 0; s < K + 1; ++s) {
+    layout_begin[s] = next[(size_t)s];
+    layout_count[s] = cnt[(size_t)s];
+  }
+  for (int64_t i = 0; i < n; ++i) perm[next[(size_t)seg_of(i)]++] = i;
+  return SEELE_OK;
+}
+
 int32_t seele_hp_select(const float* centroids, int32_t K, const seele_camera* cam,
                         float pos_scale, float beta, int32_t M, int32_t* clusters) {
   if (!centroids || !cam || !clusters) return fail(SEELE_ERR_INVALID_ARG, "null argument");
@@ -709,12 +892,7 @@ int32_t seele_hp_select(const float* centroids, int32_t K, const seele_camera* c
   if (!(pos_scale > 0.0f) || !is_finite(pos_scale) || !is_finite(beta))
     return fail(SEELE_ERR_INVALID_ARG, "bad pos_scale/beta");
   double f[6];
-  for (int i = 0; i < 3; ++i) {
-    double c = 0.0;
-    for (int j = 0; j < 3; ++j) c -= (double)cam->R[j * 3 + i] * (double)cam->t[j];
-    f[i] = c / (double)pos_scale;
-    f[3 + i] = (double)beta * (double)cam->R[6 + i];  // camera +z axis in world coordinates
-  }
+  pose_feature(cam, pos_scale, beta, f);
   auto dist2 = [&](int k, const double* p) {
     double s = 0.0;
     for (int i = 0; i < 6; ++i) {

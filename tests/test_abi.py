@@ -226,3 +226,53 @@ def test_bindings_refuse_undersized_buffers():
                 torch.empty(128, dtype=torch.float32)[::2]):
         with pytest.raises(ValueError):
             pl._need(bad, 64, torch.float32, "x")
+
+
+def test_hp_kmeans_matches_oracle():
+    # host routine: labels exactly, centroids to float32 rounding
+    from paper_2503_05168_amd.hp_build import seele_hp_kmeans
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        n = int(rng.integers(5, 60))
+        cams = []
+        for _ in range(n):
+            d = rng.normal(size=3)
+            cams.append(synthetic.look_at(d / np.linalg.norm(d) * rng.uniform(2, 6)))
+        cams += synthetic.orbit_cameras(int(rng.integers(1, 12)), 4.0, 64, 64)
+        K = int(rng.integers(1, min(8, len(cams)) + 1))
+        beta = float(rng.choice([0.5, 1.0, 2.0]))
+        cents, lab = seele_hp_kmeans(cams, 6.0, beta, K, 50)
+        f = np.stack([ohp.camera_feature(c, 6.0, beta) for c in cams])
+        oc, ol = ohp.kmeans(f, K, 50)
+        assert lab.tolist() == ol.tolist()
+        np.testing.assert_allclose(cents, oc, rtol=0, atol=1e-6)
+
+
+def test_hp_kmeans_rejects_bad_args():
+    L = A.lib()
+    cams = A.camera_array([synthetic.look_at((0, 0, -4))] * 3)
+    c = (ctypes.c_float * 24)()
+    lab = (ctypes.c_int32 * 3)()
+    for K, ps in ((0, 1.0), (4, 1.0), (2, 0.0), (2, float("nan"))):
+        assert L.seele_hp_kmeans(cams, 3, ps, 1.0, K, 10, c, lab) == A.SEELE_ERR_INVALID_ARG
+
+
+def test_hp_partition_matches_oracle():
+    from paper_2503_05168_amd.hp_build import seele_hp_partition
+    rng = np.random.default_rng(12)
+    for n, K in ((0, 1), (1, 1), (37, 3), (2000, 8)):
+        marks = [rng.random(n) < 0.1 for _ in range(K)]
+        # dyadic sums with many ties and zeros
+        sums = [np.where(rng.random(n) < 0.6, rng.integers(0, 5, n) / 8.0, 0.0).astype(np.float32)
+                for _ in range(K)]
+        # the fold the device performs cluster by cluster (strictly larger wins)
+        shared = np.any(marks, axis=0).astype(np.uint8) if n else np.zeros(0, np.uint8)
+        best = np.zeros(n, np.float32)
+        bc = np.full(n, -1, np.int32)
+        for c in range(K):
+            up = sums[c] > best
+            best[up], bc[up] = sums[c][up], c
+        perm, begin, count = seele_hp_partition(shared, best, bc, K)
+        op, ob, oc = ohp.partition(marks, [s.astype(np.float64) for s in sums], n)
+        assert perm.tolist() == op.tolist()
+        assert begin.tolist() == ob.tolist() and count.tolist() == oc.tolist()
