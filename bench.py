@@ -12,6 +12,11 @@ forms are reported beside it:
   hp          hybrid preprocessing: nearest view cluster (8 clusters, each
               ~60% of the Gaussians incl. the shared set) + opacity-aware extent
   hp_contrib  both.
+  hp_built    hybrid preprocessing over a representation built by the
+              offline construction of Sec. 3.3 from 128 sampled poses around
+              the orbit (24 pose clusters, top-32 contributors, nearest
+              cluster + 3 neighbours) + opacity-aware extent; its PSNR against
+              the plain full-scene image is reported beside its speed.
 Per-stage times come from HIP events recorded on the launch stream.  The
 roofline object covers the dominant kernel of the plain form; its work counts
 come from the library's instrumented rasterizer (run once per view, untimed).
@@ -66,7 +71,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--n", type=int, default=3_000_000, help="Gaussian count (default 3.0M)")
-    ap.add_argument("--forms", default="plain,contrib,hp,hp_contrib")
+    ap.add_argument("--forms", default="plain,contrib,hp,hp_contrib,hp_built")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=240,
                     help="tiles of view 0 the CPU oracle blends (about 10-30 s of CPU work)")
@@ -111,7 +116,39 @@ def build_forms(names, n):
         if "hp_contrib" in names:
             forms["hp_contrib"] = dict(g=g3, st=Settings(extent="opacity", mode="contrib"),
                                        hp=lay)
+    if "hp_built" in names:
+        import torch
+        from paper_2503_05168_amd import build_view_dependent
+        poses = synthetic.sampled_orbit_poses(6, 128, 1920, 1080)
+        t = time.time()
+        vd = build_view_dependent(g, poses, 24, k=32, settings=Settings(), views_per_call=8)
+        torch.cuda.synchronize()
+        build_s = time.time() - t
+        log(f"[bench] view-dependent representation built in {build_s:.1f}s: {vd.stats}")
+        forms["hp_built"] = dict(g=vd.gaussians, st=Settings(extent="opacity"), hp=vd, M=3,
+                                 full_g=g,
+                                 extra=dict(build_s=build_s, sampled_poses=len(poses),
+                                            clusters=24, M=3, k=32, shared=vd.stats["shared"],
+                                            exclusive_total=sum(vd.stats["exclusive"]),
+                                            unused=vd.stats["unused"]))
     return scene, cams, forms
+
+
+def hp_quality(full_g, form, cams):
+    """PSNR of a hybrid-preprocessing form's image against the plain
+    full-scene image over the first four orbit views."""
+    import paper_2503_05168_amd as P
+    lay = form["hp"]
+    ref = P.Renderer(P.Settings(), capacity=1 << 26, lists="super")
+    r = P.Renderer(form["st"], capacity=1 << 26, lists="super")
+    mse = 0.0
+    views = cams[:4]
+    for c in views:
+        cl = P.seele_hp_select(lay.centroids, c, lay.pos_scale, lay.beta, form.get("M", 0))
+        segs = P.seele_hp_segments(lay.seg_begin, lay.seg_count, cl)
+        d = r.render(form["g"], [c], segs).image - ref.render(full_g, [c]).image
+        mse += float((d * d).mean().item()) / len(views)
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
 
 
 def run_form(name, form, cams, steps, warmup, lists="super"):
@@ -125,7 +162,8 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     segs = [None] * V
     if lay is not None:
         for v, cam in enumerate(cams):
-            cl = P.seele_hp_select(lay.centroids, cam, lay.pos_scale, lay.beta, 0)
+            cl = P.seele_hp_select(lay.centroids, cam, lay.pos_scale, lay.beta,
+                                   form.get("M", 0))
             segs[v] = P.seele_hp_segments(lay.seg_begin, lay.seg_count, cl)
     dev = g.means.device
     one = [cams[0]]
@@ -503,6 +541,12 @@ def main():
     results = {}
     for name in names:
         results[name] = run_form(name, forms[name], cams, args.steps, args.warmup, args.lists)
+        if "extra" in forms[name]:
+            results[name].update(forms[name]["extra"])
+            results[name]["psnr_vs_plain_full"] = hp_quality(forms[name]["full_g"], forms[name],
+                                                             cams)
+            log(f"[bench] {name}: PSNR vs the plain full-scene image "
+                f"{results[name]['psnr_vs_plain_full']:.2f} dB")
         log(f"[bench] t+{time.time() - t_start:.0f}s form {name} done")
     groups = None
     if not args.no_groups and "plain" in forms:

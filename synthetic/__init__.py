@@ -11,6 +11,7 @@ from .scenes import (  # noqa: F401
     cluster_scene,
     look_at,
     orbit_cameras,
+    sampled_orbit_poses,
     perturbed_scene,
     sphere_cameras,
     hp_membership,

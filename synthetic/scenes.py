@@ -194,6 +194,22 @@ def orbit_cameras(n_views: int, radius: float, width: int, height: int, hfov_deg
     return cams
 
 
+def sampled_orbit_poses(seed: int, n_views: int, width: int, height: int, r_lo=3.5, r_hi=4.5,
+                        y_max=0.5, hfov_deg=60.0):
+    """Random poses around an orbit: angle uniform on the circle, radius
+    uniform in [r_lo, r_hi], height uniform in [-y_max, y_max], looking at
+    the origin (draw order per pose: angle, radius, height)."""
+    rng = np.random.default_rng(seed)
+    cams = []
+    for _ in range(n_views):
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        r = rng.uniform(r_lo, r_hi)
+        y = rng.uniform(-y_max, y_max)
+        cams.append(look_at((r * math.sin(th), y, -r * math.cos(th)), width=width, height=height,
+                            hfov_deg=hfov_deg))
+    return cams
+
+
 def sphere_cameras(seed: int, n_views: int, r_lo=3.0, r_hi=6.0,
                    resolutions=((640, 480), (1280, 720), (1920, 1080)), hfov_deg=60.0,
                    max_abs_y=0.9):
