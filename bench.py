@@ -77,6 +77,8 @@ def parse():
                     help="tiles of view 0 the CPU oracle blends (about 10-30 s of CPU work)")
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
+    ap.add_argument("--no-prefetch", action="store_true",
+                    help="skip the scene-prefetching measurement (needs the hp_built form)")
     ap.add_argument("--no-groups", action="store_true",
                     help="skip the contribution-aware group-size sweep")
     ap.add_argument("--lists", choices=("super", "tile"), default="super",
@@ -276,6 +278,92 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     log(f"[bench] {name}: {out['fps']:.1f} fps ({ms:.3f} ms/frame) stages="
         + ", ".join(f"{a}={b:.3f}" for a, b in stage.items())
         + f" pairs={out['pairs']:.3e} vis={out['visible']:.3e} evals={evals:.3e}")
+    return out
+
+
+def run_prefetch(vd, frames=240, slots=8, M=3):
+    """Scene prefetching (Sec. 3.3) over the built representation along a
+    smooth 1080p camera path (an orbit of radius 4 with a vertical wobble of
+    0.3, `frames` frames, none of them a sampled pose): ms/frame with every
+    cluster resident (one preloaded slot per cluster, the same code path),
+    with `slots` cluster slots and prediction one frame
+    ahead, and with the same slots but demand loads only; resident bytes and
+    copies.  Each is timed over the whole path after an untimed pass, in two
+    modes: streaming (the host runs ahead of the GPU) and interactive (each
+    frame waits for the previous one, so a copy the frame needs is not
+    hidden behind earlier frames); three interleaved rounds, the best
+    counts.  The pair capacity is sized on an all-resident
+    pass over the path and checked on the device after every timed run."""
+    import torch
+    import synthetic
+    import paper_2503_05168_amd as P
+    from paper_2503_05168_amd.prefetch import ROWS, PrefetchingRenderer
+
+    path = []
+    for k in range(frames):
+        th = 2.0 * math.pi * k / frames
+        path.append(synthetic.look_at((4.0 * math.sin(th), 0.3 * math.sin(3 * th),
+                                       -4.0 * math.cos(th)), width=1920, height=1080))
+    st = P.Settings(extent="opacity")
+    ref = P.Renderer(st, capacity=1 << 24, lists="super")
+    for c in path:  # sizes the pair buffer
+        ref.render(vd.gaussians, [c], P.seele_hp_segments(
+            vd.seg_begin, vd.seg_count, P.seele_hp_select(vd.centroids, c, vd.pos_scale, vd.beta,
+                                                          M)))
+    cap = int(ref.capacity * 1.05) + 4096
+    del ref
+
+    def timed(fn, interactive):
+        for i in range(len(path)):
+            fn(i)
+        torch.cuda.synchronize()
+        mx = torch.zeros(1, dtype=torch.int64, device="cuda")
+        t0 = time.perf_counter()
+        for i in range(len(path)):
+            torch.maximum(mx, fn(i).num_pairs, out=mx)
+            if interactive:
+                torch.cuda.current_stream().synchronize()
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / len(path)
+        assert int(mx.item()) <= cap, "pair buffer overflow in the timed region"
+        return ms
+
+    K = len(vd.seg_begin) - 1
+    cfgs = {"all_resident": dict(n_slots=K, lookahead=None, preload=True),
+            "prefetch": dict(n_slots=slots, lookahead=1.0),
+            "demand_only": dict(n_slots=slots, lookahead=None)}
+    prs, host = {}, None
+    for name, kw in cfgs.items():
+        prs[name] = PrefetchingRenderer(vd, st, M=M, capacity=cap, lists="super", host=host,
+                                        **kw)
+        host = prs[name].host
+    # three interleaved rounds of every configuration; the best round counts
+    ms = {name: {"streaming": [], "interactive": []} for name in cfgs}
+    for _ in range(3):
+        for mode in ("streaming", "interactive"):
+            for name, pr in prs.items():
+                ms[name][mode].append(timed(lambda i: pr.render(path[i], check=False),
+                                            mode == "interactive"))
+    best = {name: {m: min(v) for m, v in d.items()} for name, d in ms.items()}
+    out = dict(frames=frames, slots=slots, M=M, rounds=3,
+               model_bytes=ROWS * 4 * int(vd.gaussians.n),
+               all_clusters_bytes=ROWS * 4 * int(vd.seg_count.sum()))
+    assert prs["all_resident"].stats["loads"] == 0
+    for name, pr in prs.items():
+        n = pr.stats["frames"]
+        out[name] = dict(ms=best[name], resident_bytes=pr.resident_bytes,
+                         loads_per_frame=pr.stats["loads"] / n,
+                         demand_loads_per_frame=pr.stats["demand_loads"] / n,
+                         mb_loaded_per_frame=pr.stats["bytes_loaded"] / n / 1e6)
+        if name != "all_resident":
+            out[name]["overhead"] = {m: best[name][m] / best["all_resident"][m] - 1.0
+                                     for m in best[name]}
+        log(f"[bench] {name}: {best[name]['streaming']:.3f} / {best[name]['interactive']:.3f} "
+            f"ms/frame streaming / interactive, resident {pr.resident_bytes / 1e6:.0f} MB "
+            f"(all clusters {out['all_clusters_bytes'] / 1e6:.0f} MB), "
+            f"{out[name]['loads_per_frame']:.2f} loads/frame "
+            f"({out[name]['demand_loads_per_frame']:.2f} demand)")
+    del prs, host
     return out
 
 
@@ -548,6 +636,10 @@ def main():
             log(f"[bench] {name}: PSNR vs the plain full-scene image "
                 f"{results[name]['psnr_vs_plain_full']:.2f} dB")
         log(f"[bench] t+{time.time() - t_start:.0f}s form {name} done")
+    prefetch = None
+    if not args.no_prefetch and "hp_built" in forms:
+        prefetch = run_prefetch(forms["hp_built"]["hp"])
+        log(f"[bench] t+{time.time() - t_start:.0f}s prefetch done")
     groups = None
     if not args.no_groups and "plain" in forms:
         groups = run_group_sweep(forms["plain"]["g"], cams, max(8, args.steps // 2),
@@ -629,6 +721,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batched_64_views": batched,
         "contrib_group_sweep": groups,
+        "scene_prefetch": prefetch,
         "roofline": roof,
         "stage_roofline": stage_roof,
         "cpu_baseline": cpu,

@@ -415,6 +415,59 @@ int32_t seele_hp_segments(const int64_t* layout_begin, const int64_t* layout_cou
                           const int32_t* clusters, int32_t n_sel, int64_t* out_begin,
                           int64_t* out_count, int32_t* n_out);
 
+/* Scene prefetching (Sec. 3.3 "Scene Prefetching"): clusters predicted for
+ * coming frames are copied to the GPU ahead of time on a dedicated stream,
+ * the future pose predicted by linear extrapolation of the camera pose.
+ *
+ * seele_pose_extrapolate: the pose s frames after `cur`, given the frame
+ * before it: camera centre c_cur + s (c_cur - c_prev) and rotation
+ * (R_cur R_prev^T)^s R_cur, the power taken on the relative rotation's
+ * rotation vector (angle scaled by s about the same axis); intrinsics and
+ * image size from `cur`.  s = 0 gives cur, s = -1 prev.  Host only. */
+int32_t seele_pose_extrapolate(const seele_camera* prev, const seele_camera* cur, float s,
+                               seele_camera* out);
+
+/* Resident-set planning for a device pool that holds the shared segment and
+ * n_slots slots of slot_cap Gaussians each.  slot_cluster[n_slots] (cluster
+ * held by each slot, -1 empty) and slot_stamp[n_slots] (frame of its last
+ * use or load) are host arrays updated in place; cluster_count[K] gives each
+ * cluster's exclusive-segment size.
+ *   1. Every needed cluster (need[n_need], this frame's selection) that is
+ *      resident is held and stamped with `frame`.
+ *   2. Each needed cluster that is not resident is loaded (a demand load)
+ *      into the lowest empty slot, else into the slot that is not held with
+ *      the oldest stamp, slots whose cluster is not in `want` first, the
+ *      lowest index on ties.
+ *   3. Each predicted cluster (want[n_want], in priority order) that is not
+ *      resident is loaded into the lowest empty slot, else into the oldest
+ *      slot (lowest index on ties) that is not held, not predicted and
+ *      stamped before `frame`; planning stops at the first one with no such
+ *      slot.  Loaded slots are stamped with `frame` and held.
+ * load_cluster / load_slot (host, capacity n_slots) receive the loads in
+ * order, *n_loads their number and *n_demand how many lead (the demand
+ * loads).  Errors: a cluster outside 0..K-1 or larger than slot_cap, more
+ * distinct needed clusters than slots, an inconsistent slot table.  The
+ * caller copies each load (seele_load_segments) after the last reader of the
+ * evicted cluster is done.  Host only. */
+int32_t seele_resident_plan(int32_t* slot_cluster, int64_t* slot_stamp, int32_t n_slots,
+                            const int64_t* cluster_count, int32_t K, int64_t slot_cap,
+                            const int32_t* need, int32_t n_need, const int32_t* want,
+                            int32_t n_want, int64_t frame, int32_t* load_cluster,
+                            int32_t* load_slot, int32_t* n_loads, int32_t* n_demand);
+
+/* Host-to-device segment copies of a row-major attribute table: for each
+ * load j, columns [src_begin[j], src_begin[j] + count[j]) of all `rows`
+ * rows of host_src (row stride src_stride floats) go to columns starting at
+ * dst_begin[j] of dev_pool (row stride dst_stride floats), one 2D copy per
+ * load enqueued on `stream`.  host_src must be pinned host memory for the
+ * copies to run asynchronously; both tables stay owned by the caller and
+ * must live until the copies complete.  Errors: a load out of either
+ * table's bounds (nothing is enqueued). */
+int32_t seele_load_segments(const float* host_src, int64_t src_stride, float* dev_pool,
+                            int64_t dst_stride, int32_t rows, const int64_t* src_begin,
+                            const int64_t* dst_begin, const int64_t* count, int32_t n_loads,
+                            void* stream);
+
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* seele_last_error(void);
 /* Static name of a status code. */

@@ -38,3 +38,9 @@ from .hp_build import (  # noqa: F401
     seele_hp_kmeans,
     seele_hp_partition,
 )
+from .prefetch import (  # noqa: F401
+    PrefetchingRenderer,
+    seele_load_segments,
+    seele_pose_extrapolate,
+    seele_resident_plan,
+)

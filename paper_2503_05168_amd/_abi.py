@@ -113,6 +113,13 @@ SIGNATURES = {
                                      POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "seele_gather_gaussians": (c_int32, [POINTER(seele_gaussians), c_void_p, c_int64,
                                          POINTER(seele_gaussian_grads), c_void_p]),
+    "seele_pose_extrapolate": (c_int32, [POINTER(seele_camera), POINTER(seele_camera), c_float,
+                                         POINTER(seele_camera)]),
+    "seele_resident_plan": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64,
+                                      c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p,
+                                      c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "seele_load_segments": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                                      c_void_p, c_void_p, c_int32, c_void_p]),
     "seele_hp_select": (c_int32, [POINTER(c_float), c_int32, POINTER(seele_camera), c_float,
                                   c_float, c_int32, POINTER(c_int32)]),
     "seele_hp_segments": (c_int32, [POINTER(c_int64), POINTER(c_int64), c_int32, POINTER(c_int32),

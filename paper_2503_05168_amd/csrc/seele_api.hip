@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -961,6 +962,235 @@ int32_t seele_hp_segments(const int64_t* layout_begin, const int64_t* layout_cou
       std::swap(out_count[j], out_count[j - 1]);
     }
   *n_out = cnt;
+  return SEELE_OK;
+}
+
+}  // extern "C"
+
+// ---- scene prefetching (Sec. 3.3 "Scene Prefetching")
+
+namespace {
+
+using M3 = std::array<double, 9>;  // row-major
+
+M3 mat_of(const float* r) {
+  M3 m;
+  for (int k = 0; k < 9; ++k) m[k] = (double)r[k];
+  return m;
+}
+
+M3 mul(const M3& a, const M3& b) {
+  M3 c{};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) c[i * 3 + j] += a[i * 3 + k] * b[k * 3 + j];
+  return c;
+}
+
+M3 transpose(const M3& a) {
+  M3 t;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) t[i * 3 + j] = a[j * 3 + i];
+  return t;
+}
+
+// Rotation vector (axis times angle) of a rotation matrix.
+void rot_log(const M3& r, double* w) {
+  const double v[3] = {r[7] - r[5], r[2] - r[6], r[3] - r[1]};  // 2 sin(theta) axis
+  const double c = std::min(1.0, std::max(-1.0, 0.5 * (r[0] + r[4] + r[8] - 1.0)));
+  const double th = std::acos(c);
+  if (th < 1e-6) {  // theta / (2 sin theta) -> 1/2
+    for (int i = 0; i < 3; ++i) w[i] = 0.5 * v[i];
+    return;
+  }
+  if (th < 3.14159) {
+    const double f = th / (2.0 * std::sin(th));
+    for (int i = 0; i < 3; ++i) w[i] = f * v[i];
+    return;
+  }
+  // near pi: the axis from the symmetric part (R + I) / 2 = a a^T (+ O(pi - theta))
+  int k = 0;
+  for (int i = 1; i < 3; ++i)
+    if (r[i * 4] > r[k * 4]) k = i;
+  double a[3];
+  const double akk = std::sqrt(std::max(0.0, 0.5 * (r[k * 4] + 1.0)));
+  for (int i = 0; i < 3; ++i)
+    a[i] = i == k ? akk : 0.25 * (r[i * 3 + k] + r[k * 3 + i]) / akk;
+  const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  const double sg = (a[0] * v[0] + a[1] * v[1] + a[2] * v[2]) < 0.0 ? -1.0 : 1.0;
+  for (int i = 0; i < 3; ++i) w[i] = sg * th * a[i] / nrm;
+}
+
+// Rotation matrix of a rotation vector (Rodrigues' formula).
+M3 rot_exp(const double* w) {
+  const double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  M3 r{1, 0, 0, 0, 1, 0, 0, 0, 1};
+  if (th == 0.0) return r;
+  const double x = w[0] / th, y = w[1] / th, z = w[2] / th;
+  const M3 k{0, -z, y, z, 0, -x, -y, x, 0};
+  const M3 k2 = mul(k, k);
+  const double s = std::sin(th), c1 = 1.0 - std::cos(th);
+  for (int i = 0; i < 9; ++i) r[i] += s * k[i] + c1 * k2[i];
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_pose_extrapolate(const seele_camera* prev, const seele_camera* cur, float s,
+                               seele_camera* out) {
+  if (!prev || !cur || !out) return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (!is_finite(s)) return fail(SEELE_ERR_INVALID_ARG, "non-finite step");
+  int32_t st = check_camera(*prev, 0, 16);
+  if (st == SEELE_OK) st = check_camera(*cur, 1, 16);
+  if (st != SEELE_OK) return st;
+  const M3 rp = mat_of(prev->R), rc = mat_of(cur->R);
+  double cp[3], cc[3], co[3];
+  for (int i = 0; i < 3; ++i) {
+    cp[i] = cc[i] = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      cp[i] -= rp[j * 3 + i] * (double)prev->t[j];
+      cc[i] -= rc[j * 3 + i] * (double)cur->t[j];
+    }
+    co[i] = cc[i] + (double)s * (cc[i] - cp[i]);
+  }
+  double w[3];
+  rot_log(mul(rc, transpose(rp)), w);
+  for (int i = 0; i < 3; ++i) w[i] *= (double)s;
+  const M3 ro = mul(rot_exp(w), rc);
+  seele_camera o = *cur;
+  for (int k = 0; k < 9; ++k) o.R[k] = (float)ro[k];
+  for (int i = 0; i < 3; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < 3; ++j) t -= ro[i * 3 + j] * co[j];
+    o.t[i] = (float)t;
+  }
+  *out = o;
+  return SEELE_OK;
+}
+
+int32_t seele_resident_plan(int32_t* slot_cluster, int64_t* slot_stamp, int32_t n_slots,
+                            const int64_t* cluster_count, int32_t K, int64_t slot_cap,
+                            const int32_t* need, int32_t n_need, const int32_t* want,
+                            int32_t n_want, int64_t frame, int32_t* load_cluster,
+                            int32_t* load_slot, int32_t* n_loads, int32_t* n_demand) {
+  if (!slot_cluster || !slot_stamp || !cluster_count || !load_cluster || !load_slot || !n_loads ||
+      !n_demand || (n_need > 0 && !need) || (n_want > 0 && !want))
+    return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (n_slots < 1 || K < 1 || slot_cap < 0 || n_need < 0 || n_want < 0)
+    return fail(SEELE_ERR_INVALID_ARG, "need n_slots >= 1, K >= 1, sizes >= 0");
+  std::vector<int> slot_of((size_t)K, -1);
+  for (int s = 0; s < n_slots; ++s) {
+    const int c = slot_cluster[s];
+    if (c < -1 || c >= K) return fail(SEELE_ERR_INVALID_ARG, "slot %d holds cluster %d", s, c);
+    if (c >= 0) {
+      if (slot_of[c] >= 0) return fail(SEELE_ERR_INVALID_ARG, "cluster %d in two slots", c);
+      slot_of[c] = s;
+    }
+  }
+  auto check_c = [&](int c) -> int32_t {
+    if (c < 0 || c >= K) return fail(SEELE_ERR_INVALID_ARG, "cluster %d not in 0..%d", c, K - 1);
+    if (cluster_count[c] > slot_cap)
+      return fail(SEELE_ERR_CAPACITY, "cluster %d (%lld Gaussians) exceeds the slot size %lld", c,
+                  (long long)cluster_count[c], (long long)slot_cap);
+    return SEELE_OK;
+  };
+  std::vector<char> needed((size_t)K, 0), wanted((size_t)K, 0), held((size_t)n_slots, 0);
+  int distinct = 0;
+  for (int i = 0; i < n_need; ++i) {
+    const int32_t st = check_c(need[i]);
+    if (st != SEELE_OK) return st;
+    distinct += !needed[need[i]];
+    needed[need[i]] = 1;
+  }
+  if (distinct > n_slots)
+    return fail(SEELE_ERR_CAPACITY, "%d clusters needed at once, %d slots", distinct, n_slots);
+  for (int i = 0; i < n_want; ++i) {
+    const int32_t st = check_c(want[i]);
+    if (st != SEELE_OK) return st;
+    wanted[want[i]] = 1;
+  }
+  int nl = 0;
+  // a slot for cluster c: the lowest empty slot, else the least recently
+  // stamped slot that is not held (lowest index on ties), preferring slots
+  // whose cluster is not wanted; for a predicted load only unwanted, older
+  // slots qualify
+  auto pick = [&](bool demand) -> int {
+    for (int s = 0; s < n_slots; ++s)
+      if (slot_cluster[s] < 0) return s;
+    int best = -1;
+    for (int s = 0; s < n_slots; ++s) {
+      if (held[s]) continue;
+      const bool w = wanted[slot_cluster[s]] != 0;
+      if (!demand && (w || slot_stamp[s] >= frame)) continue;
+      if (best < 0) {
+        best = s;
+        continue;
+      }
+      const bool wb = wanted[slot_cluster[best]] != 0;
+      if (w != wb ? !w : slot_stamp[s] < slot_stamp[best]) best = s;
+    }
+    return best;
+  };
+  auto load = [&](int c, int s) {
+    if (slot_cluster[s] >= 0) slot_of[slot_cluster[s]] = -1;
+    slot_cluster[s] = c;
+    slot_of[c] = s;
+    slot_stamp[s] = frame;
+    held[s] = 1;
+    load_cluster[nl] = c;
+    load_slot[nl] = s;
+    ++nl;
+  };
+  for (int i = 0; i < n_need; ++i) {  // resident needed clusters are held
+    const int s = slot_of[need[i]];
+    if (s >= 0) {
+      held[s] = 1;
+      slot_stamp[s] = frame;
+    }
+  }
+  for (int i = 0; i < n_need; ++i) {  // demand loads
+    const int c = need[i];
+    if (slot_of[c] >= 0) continue;
+    load(c, pick(true));  // a slot exists: distinct needs <= n_slots
+  }
+  *n_demand = nl;
+  for (int i = 0; i < n_want; ++i) {  // predicted loads
+    const int c = want[i];
+    if (slot_of[c] >= 0) {
+      held[slot_of[c]] = 1;
+      continue;
+    }
+    const int s = pick(false);
+    if (s < 0) break;
+    load(c, s);
+  }
+  *n_loads = nl;
+  return SEELE_OK;
+}
+
+int32_t seele_load_segments(const float* host_src, int64_t src_stride, float* dev_pool,
+                            int64_t dst_stride, int32_t rows, const int64_t* src_begin,
+                            const int64_t* dst_begin, const int64_t* count, int32_t n_loads,
+                            void* stream) {
+  if (n_loads < 0 || rows < 0 || src_stride < 0 || dst_stride < 0)
+    return fail(SEELE_ERR_INVALID_ARG, "negative size");
+  if (n_loads == 0 || rows == 0) return SEELE_OK;
+  if (!host_src || !dev_pool || !src_begin || !dst_begin || !count)
+    return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  for (int j = 0; j < n_loads; ++j)
+    if (count[j] < 0 || src_begin[j] < 0 || dst_begin[j] < 0 ||
+        src_begin[j] + count[j] > src_stride || dst_begin[j] + count[j] > dst_stride)
+      return fail(SEELE_ERR_INVALID_ARG, "load %d out of bounds", j);
+  for (int j = 0; j < n_loads; ++j) {
+    if (count[j] == 0) continue;
+    const hipError_t e = hipMemcpy2DAsync(
+        dev_pool + dst_begin[j], (size_t)dst_stride * sizeof(float), host_src + src_begin[j],
+        (size_t)src_stride * sizeof(float), (size_t)count[j] * sizeof(float), (size_t)rows,
+        hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "segment copy");
+  }
   return SEELE_OK;
 }
 

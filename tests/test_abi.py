@@ -276,3 +276,69 @@ def test_hp_partition_matches_oracle():
         op, ob, oc = ohp.partition(marks, [s.astype(np.float64) for s in sums], n)
         assert perm.tolist() == op.tolist()
         assert begin.tolist() == ob.tolist() and count.tolist() == oc.tolist()
+
+
+def test_pose_extrapolate_matches_oracle():
+    from oracle import prefetch as opf
+    from paper_2503_05168_amd.prefetch import seele_pose_extrapolate
+    rng = np.random.default_rng(21)
+    cams = synthetic.sampled_orbit_poses(4, 30, 64, 48)
+    cams += synthetic.orbit_cameras(8, 4.0, 64, 48)
+    for i in range(len(cams) - 1):
+        a, b = cams[i], cams[i + 1]
+        for s in (0.0, 1.0, 2.5, -1.0, float(rng.uniform(-3, 3))):
+            got = seele_pose_extrapolate(a, b, s)
+            R, t = opf.extrapolate_pose(a.R, a.t, b.R, b.t, s)
+            np.testing.assert_allclose(got.R, R, atol=2e-6)
+            np.testing.assert_allclose(got.t, t, atol=2e-5 * max(1.0, abs(s)))
+            assert (got.width, got.height, got.fx) == (b.width, b.height, np.float32(b.fx))
+    # half a turn between the frames (the near-pi branch of the rotation log)
+    a = synthetic.look_at((0.0, 0.0, -4.0))
+    b = synthetic.look_at((0.0, 0.0, 4.0))
+    got = seele_pose_extrapolate(a, b, 1.0)
+    R, t = opf.extrapolate_pose(a.R, a.t, b.R, b.t, 1.0)
+    np.testing.assert_allclose(got.R, R, atol=2e-6)
+
+
+def test_resident_plan_matches_oracle():
+    from oracle import prefetch as opf
+    from paper_2503_05168_amd.prefetch import seele_resident_plan
+    rng = np.random.default_rng(22)
+    for K, S in ((6, 4), (24, 8), (3, 3)):
+        cnt = rng.integers(0, 50, K).astype(np.int64)
+        sc = np.full(S, -1, np.int32)
+        ss = np.zeros(S, np.int64)
+        osc, oss = list(sc), list(ss)
+        for frame in range(1, 300):
+            need = [int(x) for x in rng.choice(K, size=int(rng.integers(1, min(S, 4) + 1)),
+                                                replace=False)]
+            want = [int(x) for x in rng.choice(K, size=int(rng.integers(0, min(K, 6) + 1)),
+                                                replace=False)]
+            loads, nd = seele_resident_plan(sc, ss, cnt, 50, need, want, frame)
+            osc, oss, oloads, ond = opf.plan(osc, oss, cnt, 50, need, want, frame)
+            assert loads == oloads and nd == ond, frame
+            assert sc.tolist() == osc and ss.tolist() == oss
+
+
+def test_resident_plan_and_load_reject_bad_args():
+    from paper_2503_05168_amd import SeeleError
+    from paper_2503_05168_amd.prefetch import seele_resident_plan
+    cnt = np.array([5, 60], np.int64)
+    sc = np.full(2, -1, np.int32)
+    ss = np.zeros(2, np.int64)
+    with pytest.raises(SeeleError):
+        seele_resident_plan(sc, ss, cnt, 50, [1], [], 1)  # larger than a slot
+    with pytest.raises(SeeleError):
+        seele_resident_plan(np.full(1, -1, np.int32), np.zeros(1, np.int64), cnt[:1] * 0, 50,
+                            [0, 1], [], 1)  # two clusters, one slot
+    with pytest.raises(SeeleError):
+        seele_resident_plan(np.array([0, 0], np.int32), ss, cnt, 50, [0], [], 1)  # duplicate
+    L = A.lib()
+    b = (ctypes.c_int64 * 1)(5)
+    d = (ctypes.c_int64 * 1)(0)
+    c = (ctypes.c_int64 * 1)(10)
+    # columns 5..15 of a 12-column table: refused before anything is enqueued
+    assert L.seele_load_segments(FAKE, 12, FAKE, 100, 59, b, d, c, 1, None) == \
+        A.SEELE_ERR_INVALID_ARG
+    assert L.seele_load_segments(FAKE, 100, FAKE, 8, 59, b, d, c, 1, None) == \
+        A.SEELE_ERR_INVALID_ARG
