@@ -468,6 +468,43 @@ int32_t seele_load_segments(const float* host_src, int64_t src_stride, float* de
                             const int64_t* dst_begin, const int64_t* count, int32_t n_loads,
                             void* stream);
 
+/* Fine-tuning (Sec. 3.5): the pipeline trains through its unchanged
+ * backward; these are the loss and optimizer steps around it.
+ *
+ * Photometric loss of 3DGS training (the L_3DGS term): per view
+ *   L_v = (1 - lambda) mean|x - y| + lambda (1 - SSIM(x, y))
+ * over the [3][H][W] render x and target y, SSIM being the mean over pixels
+ * and channels of the SSIM map with an 11 x 11 Gaussian window (sigma 1.5,
+ * normalised, zero padding), C1 = 0.01^2, C2 = 0.03^2.  loss (device,
+ * [n_views]) receives L_v; dL_dimage (device, the image layout) the
+ * gradient of the mean of L_v over the views (at x = y the L1 term
+ * contributes 0).  image and target: device, views concatenated as the
+ * rasterizer writes them.  workspace: device, 256-byte aligned, at least
+ * seele_photometric_loss_workspace_size bytes; contents undefined after. */
+size_t seele_photometric_loss_workspace_size(const seele_camera* cams, int32_t n_views);
+int32_t seele_photometric_loss(const float* image, const float* target, const seele_camera* cams,
+                               int32_t n_views, float lambda, void* workspace,
+                               size_t workspace_bytes, float* loss, float* dL_dimage,
+                               void* stream);
+
+typedef struct seele_adam_opts {
+  float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
+  float beta1, beta2, eps;
+} seele_adam_opts;
+
+/* One Adam step over every attribute element of n Gaussians (the optimizer
+ * of 3DGS training): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr * (m / (1 - b1^step)) / (sqrt(v) / sqrt(1 - b2^step) + eps), with
+ * the learning rate of the element's attribute (SH degree-0 rows and the
+ * higher rows separately).  params (written in place), grads, m and v are
+ * device arrays in the seele_gaussians layout (the writable descriptor
+ * seele_gaussian_grads describes each); m and v start at zero; step counts
+ * from 1.  SH rows beyond 3 (sh_degree + 1)^2 are not touched. */
+int32_t seele_adam_step(const seele_gaussian_grads* params, const seele_gaussian_grads* grads,
+                        const seele_gaussian_grads* m, const seele_gaussian_grads* v, int64_t n,
+                        int32_t sh_degree, const seele_adam_opts* opts, int64_t step,
+                        void* stream);
+
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* seele_last_error(void);
 /* Static name of a status code. */

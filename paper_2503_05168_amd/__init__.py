@@ -44,3 +44,9 @@ from .prefetch import (  # noqa: F401
     seele_pose_extrapolate,
     seele_resident_plan,
 )
+from .finetune import (  # noqa: F401
+    AdamOpts,
+    FineTuner,
+    seele_adam_step,
+    seele_photometric_loss,
+)

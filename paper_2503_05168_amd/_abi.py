@@ -38,6 +38,12 @@ class seele_gaussian_grads(ctypes.Structure):
                 ("opacity_logits", c_void_p), ("sh", c_void_p)]
 
 
+class seele_adam_opts(ctypes.Structure):
+    _fields_ = [("lr_means", c_float), ("lr_log_scales", c_float), ("lr_quats", c_float),
+                ("lr_opacity", c_float), ("lr_sh_dc", c_float), ("lr_sh_rest", c_float),
+                ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+
+
 class seele_camera(ctypes.Structure):
     _fields_ = [("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float),
                 ("cx", c_float), ("cy", c_float), ("width", c_int32), ("height", c_int32)]
@@ -120,6 +126,13 @@ SIGNATURES = {
                                       c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "seele_load_segments": (c_int32, [c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                                       c_void_p, c_void_p, c_int32, c_void_p]),
+    "seele_photometric_loss_workspace_size": (c_size_t, [POINTER(seele_camera), c_int32]),
+    "seele_photometric_loss": (c_int32, [c_void_p, c_void_p, POINTER(seele_camera), c_int32,
+                                         c_float, c_void_p, c_size_t, c_void_p, c_void_p,
+                                         c_void_p]),
+    "seele_adam_step": (c_int32, [POINTER(seele_gaussian_grads), POINTER(seele_gaussian_grads),
+                                  POINTER(seele_gaussian_grads), POINTER(seele_gaussian_grads),
+                                  c_int64, c_int32, POINTER(seele_adam_opts), c_int64, c_void_p]),
     "seele_hp_select": (c_int32, [POINTER(c_float), c_int32, POINTER(seele_camera), c_float,
                                   c_float, c_int32, POINTER(c_int32)]),
     "seele_hp_segments": (c_int32, [POINTER(c_int64), POINTER(c_int64), c_int32, POINTER(c_int32),

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "finetune_internal.h"
 #include "seele_internal.h"
 
 using namespace seele;
@@ -1192,6 +1193,117 @@ int32_t seele_load_segments(const float* host_src, int64_t src_stride, float* de
     if (e != hipSuccess) return hip_fail(e, "segment copy");
   }
   return SEELE_OK;
+}
+
+}  // extern "C"
+
+// ---- fine-tuning (Sec. 3.5)
+
+namespace {
+
+struct LossPlan {
+  int64_t elems = 0, blocks = 0;
+  size_t bytes = 0;
+};
+
+LossPlan loss_plan(const seele_camera* cams, int32_t n_views) {
+  LossPlan p;
+  for (int v = 0; v < n_views; ++v) {
+    p.elems += 3 * (int64_t)cams[v].width * cams[v].height;
+    p.blocks += loss_blocks(cams[v].width, cams[v].height);
+  }
+  // 3 maps of all elements + 2 floats per block (each chunk of views reuses it)
+  p.bytes = (size_t)(3 * p.elems + 2 * p.blocks) * sizeof(float) + 256;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t seele_photometric_loss_workspace_size(const seele_camera* cams, int32_t n_views) {
+  if (!cams || n_views < 1) return 0;
+  return loss_plan(cams, n_views).bytes;
+}
+
+int32_t seele_photometric_loss(const float* image, const float* target, const seele_camera* cams,
+                               int32_t n_views, float lambda, void* workspace,
+                               size_t workspace_bytes, float* loss, float* dL_dimage,
+                               void* stream) {
+  if (!cams || n_views < 1) return fail(SEELE_ERR_INVALID_ARG, "need cameras, n_views >= 1");
+  for (int v = 0; v < n_views; ++v) {
+    const int32_t st = check_camera(cams[v], v, 16);
+    if (st != SEELE_OK) return st;
+  }
+  if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(SEELE_ERR_INVALID_ARG, "lambda not in [0, 1]");
+  if (!image || !target || !loss || !dL_dimage || !aligned(image, 4) || !aligned(target, 4) ||
+      !aligned(loss, 4) || !aligned(dL_dimage, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "null or misaligned array");
+  const LossPlan plan = loss_plan(cams, n_views);
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < plan.bytes)
+    return fail(SEELE_ERR_CAPACITY, "workspace needs %zu bytes", plan.bytes);
+  if (plan.blocks >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "images too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* maps = static_cast<float*>(workspace);
+  int64_t e0 = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsLoss) {
+    const int nv = std::min(kMaxViewsLoss, n_views - v0);
+    LossViews lv{};
+    lv.n_views = nv;
+    int64_t e = 0, b = 0;
+    for (int k = 0; k < nv; ++k) {
+      const seele_camera& c = cams[v0 + k];
+      lv.elem_off[k] = e;
+      lv.blk_off[k] = (int32_t)b;
+      lv.w[k] = c.width;
+      lv.h[k] = c.height;
+      e += 3 * (int64_t)c.width * c.height;
+      b += loss_blocks(c.width, c.height);
+    }
+    lv.elem_off[nv] = e;
+    lv.blk_off[nv] = (int32_t)b;
+    float* blk = maps + 3 * e;
+    const hipError_t err = launch_photometric_loss(
+        lv, (int)b, image + e0, target + e0, lambda, 1.0f / (float)n_views, maps, e, blk,
+        loss + v0, dL_dimage + e0, s);
+    if (err != hipSuccess) return hip_fail(err, "photometric loss launch");
+    e0 += e;
+  }
+  return SEELE_OK;
+}
+
+int32_t seele_adam_step(const seele_gaussian_grads* params, const seele_gaussian_grads* grads,
+                        const seele_gaussian_grads* m, const seele_gaussian_grads* v, int64_t n,
+                        int32_t sh_degree, const seele_adam_opts* opts, int64_t step,
+                        void* stream) {
+  if (!params || !grads || !m || !v || !opts) return fail(SEELE_ERR_INVALID_ARG, "null argument");
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || step < 1)
+    return fail(SEELE_ERR_INVALID_ARG, "need n >= 0, 0 <= sh_degree <= 3, step >= 1");
+  const float lrs[6] = {opts->lr_means, opts->lr_log_scales, opts->lr_quats,
+                        opts->lr_opacity, opts->lr_sh_dc, opts->lr_sh_rest};
+  for (float x : lrs)
+    if (!(x >= 0.0f) || !is_finite(x)) return fail(SEELE_ERR_INVALID_ARG, "bad learning rate");
+  if (!(opts->beta1 >= 0.0f && opts->beta1 < 1.0f) || !(opts->beta2 >= 0.0f && opts->beta2 < 1.0f) ||
+      !(opts->eps > 0.0f))
+    return fail(SEELE_ERR_INVALID_ARG, "bad beta1/beta2/eps");
+  if (n == 0) return SEELE_OK;
+  const int n_sh = 3 * (sh_degree + 1) * (sh_degree + 1);
+  const int64_t len[6] = {3 * n, 3 * n, 4 * n, n, 3 * n, (int64_t)(n_sh - 3) * n};
+  const seele_gaussian_grads* t[4] = {params, grads, m, v};
+  float* ptr[4][6];
+  for (int k = 0; k < 4; ++k) {
+    const seele_gaussian_grads& a = *t[k];
+    float* base[6] = {a.means, a.log_scales, a.quats, a.opacity_logits, a.sh,
+                      a.sh ? a.sh + 3 * n : nullptr};
+    for (int s = 0; s < 6; ++s) {
+      if (len[s] > 0 && (!base[s] || !aligned(base[s], 4)))
+        return fail(SEELE_ERR_INVALID_ARG, "null or misaligned attribute array");
+      ptr[k][s] = base[s];
+    }
+  }
+  const hipError_t e = launch_adam(ptr[0], ptr[1], ptr[2], ptr[3], len, lrs, opts->beta1,
+                                   opts->beta2, opts->eps, step, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEELE_OK : hip_fail(e, "adam launch");
 }
 
 }  // extern "C"
