@@ -396,9 +396,9 @@ def run_group_sweep(g, cams, steps, warmup, groups=((1, 1), (2, 2), (2, 4), (4, 
 
 def run_fwd_bwd(n, n_views, steps, warmup, mode):
     """Fine-tuning step of the paper's Sec. 3.5 on the 1.0M-Gaussian workload:
-    the 8 views rendered in one batched call, the 3DGS photometric loss
-    (0.8 L1 + 0.2 D-SSIM) against images of a perturbed copy of the scene,
-    the batched backward to every raw parameter, then one Adam step.
+    the 8 views rendered in one batched call, the loss L_3DGS (0.8 L1 + 0.2
+    D-SSIM) + 0.1 FLIP against images of a perturbed copy of the scene, the
+    batched backward to every raw parameter, then one Adam step.
     Returns ms per view: forward, loss, backward, Adam (stream time from
     events), forward + loss + backward, and the whole step (wall clock)."""
     import torch
@@ -443,7 +443,7 @@ def run_fwd_bwd(n, n_views, steps, warmup, mode):
                finetune_step_ms_per_view=1000.0 * wall / steps / n_views,
                loss_first=float(losses[0].mean().item()), loss_last=float(losses[-1].mean().item()),
                gaussians=n, views=n_views, width=1280, height=720)
-    log(f"[bench] fwd+bwd {mode}: {out['ms_per_view']:.3f} ms/view (fwd {ph[0]:.3f}, loss "
+    log(f"[bench] fwd+bwd {mode}: {out['ms_per_view']:.3f} ms/view (fwd {ph[0]:.3f}, loss+FLIP "
         f"{ph[1]:.3f}, bwd {ph[2]:.3f}); Adam {ph[3]:.3f}; whole step "
         f"{out['finetune_step_ms_per_view']:.3f} ms/view; loss {out['loss_first']:.5f} -> "
         f"{out['loss_last']:.5f}")

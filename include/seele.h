@@ -505,6 +505,22 @@ int32_t seele_adam_step(const seele_gaussian_grads* params, const seele_gaussian
                         int32_t sh_degree, const seele_adam_opts* opts, int64_t step,
                         void* stream);
 
+/* View-consistency term of the fine-tuning loss (Sec. 3.5): FLIP (LDR)
+ * between each view's render (`image`, sRGB [3][H][W] per view, clamped to
+ * [0, 1]) and its `reference`, for a viewer at `ppd` pixels per degree
+ * (FLIP's default 67.02: 0.7 m from a 0.7 m wide 3840-pixel screen).  flip
+ * (device [n_views]) receives each view's mean FLIP; dL_dimage receives
+ * scale * d(mean over views of the per-view means)/d image, written, or
+ * added to its contents when accumulate != 0 (so the photometric loss's
+ * gradient and gamma * this one sum in place).  workspace: device, 256-byte
+ * aligned, at least seele_flip_loss_workspace_size bytes.  Errors: ppd
+ * whose filters exceed 24-pixel radii (ppd above about 177). */
+size_t seele_flip_loss_workspace_size(const seele_camera* cams, int32_t n_views);
+int32_t seele_flip_loss(const float* image, const float* reference, const seele_camera* cams,
+                        int32_t n_views, float ppd, float scale, int32_t accumulate,
+                        void* workspace, size_t workspace_bytes, float* flip, float* dL_dimage,
+                        void* stream);
+
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* seele_last_error(void);
 /* Static name of a status code. */

@@ -48,5 +48,6 @@ from .finetune import (  # noqa: F401
     AdamOpts,
     FineTuner,
     seele_adam_step,
+    seele_flip_loss,
     seele_photometric_loss,
 )

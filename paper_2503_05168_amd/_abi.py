@@ -133,6 +133,10 @@ SIGNATURES = {
     "seele_adam_step": (c_int32, [POINTER(seele_gaussian_grads), POINTER(seele_gaussian_grads),
                                   POINTER(seele_gaussian_grads), POINTER(seele_gaussian_grads),
                                   c_int64, c_int32, POINTER(seele_adam_opts), c_int64, c_void_p]),
+    "seele_flip_loss_workspace_size": (c_size_t, [POINTER(seele_camera), c_int32]),
+    "seele_flip_loss": (c_int32, [c_void_p, c_void_p, POINTER(seele_camera), c_int32, c_float,
+                                  c_float, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
+                                  c_void_p]),
     "seele_hp_select": (c_int32, [POINTER(c_float), c_int32, POINTER(seele_camera), c_float,
                                   c_float, c_int32, POINTER(c_int32)]),
     "seele_hp_segments": (c_int32, [POINTER(c_int64), POINTER(c_int64), c_int32, POINTER(c_int32),

@@ -26,4 +26,34 @@ hipError_t launch_adam(float* const* p, const float* const* g, float* const* m, 
                        const int64_t* len, const float* lr, float b1, float b2, float eps,
                        int64_t step, hipStream_t stream);
 
+// FLIP (view-consistency term): pixel blocks of 256 never straddle a view.
+constexpr int kMaxViewsFlip = 64;
+constexpr int kMaxFlipRadius = 24;
+struct FlipViews {
+  int n_views;
+  int64_t pix_off[kMaxViewsFlip + 1];  // first pixel of view v in the maps
+  int32_t blk_off[kMaxViewsFlip + 1];
+  int32_t w[kMaxViewsFlip], h[kMaxViewsFlip];
+};
+// separable filters: CSF (radius rc) for Y (gA), Cx (gRG) and Cz
+// (c1 u1 + c2 u2 in both axes); feature (radius rf): normalised Gaussian gn,
+// edge fe and point fp profiles
+struct FlipFilt {
+  int rc, rf;
+  float c1, c2;
+  float gA[2 * kMaxFlipRadius + 1], gRG[2 * kMaxFlipRadius + 1];
+  float u1[2 * kMaxFlipRadius + 1], u2[2 * kMaxFlipRadius + 1];
+  float gn[2 * kMaxFlipRadius + 1], fe[2 * kMaxFlipRadius + 1], fp[2 * kMaxFlipRadius + 1];
+};
+struct FlipConst {
+  float m[3][3], mi[3][3], white[3];
+  float qc, qf, pc, pt, eps, cmax;
+};
+
+int64_t flip_blocks(int w, int h);
+hipError_t launch_flip(const FlipViews& fv, int n_blocks, const FlipFilt& f, const FlipConst& k,
+                       const float* test, const float* ref, float* maps, int64_t P, float* blk,
+                       float scale, bool accumulate, float* out, float* grad,
+                       hipStream_t stream);
+
 }  // namespace seele

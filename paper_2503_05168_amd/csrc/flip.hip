@@ -1,0 +1,393 @@
+// FLIP (LDR) image difference and its gradient with respect to the test
+// image, for the view-consistency term of the fine-tuning loss (Sec. 3.5).
+//
+// Per pixel of each view ([3][H][W] sRGB, clamped to [0, 1]):
+//   colour: sRGB -> linear -> XYZ -> YCxCz; each opponent channel filtered
+//     with its contrast-sensitivity kernel (separable: one Gaussian for Y
+//     and Cx, two for Cz), edges replicated; -> linear RGB clamped to
+//     [0, 1] -> CIELAB -> Hunt-adjusted; HyAB distance to the reference's,
+//     to the power qc, mapped piecewise linearly onto [0, 1] (cmax: the
+//     same for green against blue);
+//   features: edge and point detectors (separable derivative-of-Gaussian
+//     kernels, positive and negative weights normalised to +-1) along x and
+//     y on the normalised luminance; dF = (max of the magnitude
+//     differences, floored at eps, / sqrt 2)^qf;
+//   value dE_c^(1 - dF); a view's score is its mean.
+// The gradient runs the same chain backwards: per-pixel seeds for the
+// filtered channels and the four feature responses, the adjoints of the
+// vertical and horizontal passes (edge replication adds the weights of
+// every padded tap to the border pixel), then the colour transforms.
+#include <cmath>
+
+#include "finetune_internal.h"
+
+namespace seele {
+
+namespace {
+
+constexpr int kFB = 256;
+
+__device__ __forceinline__ int flip_view(const FlipViews& fv) {
+  int v = 0;
+  for (int q = 1; q < fv.n_views; ++q)
+    if (fv.blk_off[q] <= (int)blockIdx.x) v = q;
+  return v;
+}
+
+struct Px {
+  int v, x, y, W, H;
+  int64_t p;     // pixel index (view offset + y W + x) in the maps
+  int64_t e0;    // element index of channel 0 of this pixel in the images
+  int64_t plane;
+  bool ok;
+};
+
+__device__ __forceinline__ Px px_of(const FlipViews& fv) {
+  Px q{};
+  const int v = flip_view(fv);
+  const int W = fv.w[v], H = fv.h[v];
+  const int64_t i = (int64_t)(blockIdx.x - fv.blk_off[v]) * kFB + threadIdx.x;
+  q.plane = (int64_t)W * H;
+  q.ok = i < q.plane;
+  const int64_t ii = q.ok ? i : 0;
+  q.v = v;
+  q.y = (int)(ii / W);
+  q.x = (int)(ii - (int64_t)q.y * W);
+  q.W = W;
+  q.H = H;
+  q.p = fv.pix_off[v] + ii;
+  q.e0 = 3 * fv.pix_off[v] + ii;
+  return q;
+}
+
+__device__ __forceinline__ float srgb_lin(float c) {
+  return c > 0.04045f ? powf((c + 0.055f) / 1.055f, 2.4f) : c / 12.92f;
+}
+__device__ __forceinline__ float srgb_lin_d(float c) {
+  return c > 0.04045f ? (2.4f / 1.055f) * powf((c + 0.055f) / 1.055f, 1.4f) : 1.0f / 12.92f;
+}
+
+// sRGB (clamped) -> YCxCz
+__device__ __forceinline__ void to_ycxcz(const FlipConst& k, const float* rgb, float* o) {
+  float l[3];
+  for (int c = 0; c < 3; ++c) l[c] = srgb_lin(fminf(fmaxf(rgb[c], 0.f), 1.f));
+  float n[3];
+  for (int i = 0; i < 3; ++i)
+    n[i] = (k.m[i][0] * l[0] + k.m[i][1] * l[1] + k.m[i][2] * l[2]) / k.white[i];
+  o[0] = 116.f * n[1] - 16.f;
+  o[1] = 500.f * (n[0] - n[1]);
+  o[2] = 200.f * (n[1] - n[2]);
+}
+
+__global__ __launch_bounds__(kFB) void k_flip_prep(FlipViews fv, FlipConst k,
+                                                    const float* __restrict__ test,
+                                                    const float* __restrict__ ref,
+                                                    float* __restrict__ o, int64_t P) {
+  const Px q = px_of(fv);
+  if (!q.ok) return;
+  float a[3], b[3], ot[3], orf[3];
+  for (int c = 0; c < 3; ++c) {
+    a[c] = test[q.e0 + c * q.plane];
+    b[c] = ref[q.e0 + c * q.plane];
+  }
+  to_ycxcz(k, a, ot);
+  to_ycxcz(k, b, orf);
+  for (int c = 0; c < 3; ++c) {
+    o[c * P + q.p] = ot[c];
+    o[(3 + c) * P + q.p] = orf[c];
+  }
+}
+
+// horizontal passes (x clamped to the row) of both images:
+// maps per image: Y*gA, Cx*gRG, Cz*u1, Cz*u2, yn*fe, yn*gn, yn*fp
+__global__ __launch_bounds__(kFB) void k_flip_h(FlipViews fv, FlipFilt f,
+                                                 const float* __restrict__ o, int64_t P,
+                                                 float* __restrict__ h) {
+  const Px q = px_of(fv);
+  if (!q.ok) return;
+  const int64_t row = q.p - q.x;
+  for (int im = 0; im < 2; ++im) {
+    const float* Y = o + (3 * im) * P + row;
+    const float* Cx = Y + P;
+    const float* Cz = Y + 2 * P;
+    float s[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int t = -f.rc; t <= f.rc; ++t) {
+      const int xx = min(max(q.x + t, 0), q.W - 1);
+      const int j = t + f.rc;
+      s[0] += f.gA[j] * Y[xx];
+      s[1] += f.gRG[j] * Cx[xx];
+      s[2] += f.u1[j] * Cz[xx];
+      s[3] += f.u2[j] * Cz[xx];
+    }
+    for (int t = -f.rf; t <= f.rf; ++t) {
+      const int xx = min(max(q.x + t, 0), q.W - 1);
+      const int j = t + f.rf;
+      const float yn = (Y[xx] + 16.f) * (1.f / 116.f);
+      s[4] += f.fe[j] * yn;
+      s[5] += f.gn[j] * yn;
+      s[6] += f.fp[j] * yn;
+    }
+    for (int m = 0; m < 7; ++m) h[(7 * im + m) * P + q.p] = s[m];
+  }
+}
+
+// vertical pass of map `src` (column of pixel q, y clamped) with weights w[2r+1]
+__device__ __forceinline__ float vpass(const float* src, const Px& q, const float* w, int r) {
+  const int64_t col = q.p - (int64_t)q.y * q.W;
+  float s = 0.f;
+  for (int t = -r; t <= r; ++t) {
+    const int yy = min(max(q.y + t, 0), q.H - 1);
+    s += w[t + r] * src[col + (int64_t)yy * q.W];
+  }
+  return s;
+}
+
+struct Colour {
+  float L, a, b;     // Hunt-adjusted CIELAB
+  float Lr, ar, br;  // CIELAB before the Hunt adjustment
+  float rgb[3];      // linear RGB before the clamp
+  float n[3];        // XYZ / white after the clamp
+};
+
+__device__ __forceinline__ float lab_f(float t) {
+  const float d = 6.f / 29.f;
+  return t > d * d * d ? cbrtf(t) : t / (3.f * d * d) + 4.f / 29.f;
+}
+__device__ __forceinline__ float lab_fd(float t) {
+  const float d = 6.f / 29.f;
+  return t > d * d * d ? (1.f / 3.f) / (cbrtf(t) * cbrtf(t)) : 1.f / (3.f * d * d);
+}
+
+__device__ __forceinline__ Colour colour_of(const FlipConst& k, float Y, float Cx, float Cz) {
+  Colour c{};
+  const float yy = (Y + 16.f) / 116.f;
+  const float xyz[3] = {k.white[0] * (Cx / 500.f + yy), k.white[1] * yy,
+                        k.white[2] * (yy - Cz / 200.f)};
+  float l[3];
+  for (int i = 0; i < 3; ++i) {
+    c.rgb[i] = k.mi[i][0] * xyz[0] + k.mi[i][1] * xyz[1] + k.mi[i][2] * xyz[2];
+    l[i] = fminf(fmaxf(c.rgb[i], 0.f), 1.f);
+  }
+  for (int i = 0; i < 3; ++i)
+    c.n[i] = (k.m[i][0] * l[0] + k.m[i][1] * l[1] + k.m[i][2] * l[2]) / k.white[i];
+  const float fx = lab_f(c.n[0]), fy = lab_f(c.n[1]), fz = lab_f(c.n[2]);
+  c.Lr = 116.f * fy - 16.f;
+  c.ar = 500.f * (fx - fy);
+  c.br = 200.f * (fy - fz);
+  c.L = c.Lr;
+  c.a = 0.01f * c.Lr * c.ar;
+  c.b = 0.01f * c.Lr * c.br;
+  return c;
+}
+
+// vertical passes -> per-pixel FLIP and the seeds of its gradient
+__global__ __launch_bounds__(kFB) void k_flip_eval(FlipViews fv, FlipFilt f, FlipConst k,
+                                                    const float* __restrict__ h, int64_t P,
+                                                    float* __restrict__ seed,
+                                                    float* __restrict__ blk) {
+  __shared__ float s_red[kFB / 64];
+  const Px q = px_of(fv);
+  float val = 0.f;
+  if (q.ok) {
+    float cf[2][3], fe[2][4];
+    for (int im = 0; im < 2; ++im) {
+      const float* hm = h + (int64_t)(7 * im) * P;
+      cf[im][0] = vpass(hm, q, f.gA, f.rc);
+      cf[im][1] = vpass(hm + P, q, f.gRG, f.rc);
+      cf[im][2] = f.c1 * vpass(hm + 2 * P, q, f.u1, f.rc) + f.c2 * vpass(hm + 3 * P, q, f.u2, f.rc);
+      fe[im][0] = vpass(hm + 4 * P, q, f.gn, f.rf);  // edge x
+      fe[im][1] = vpass(hm + 5 * P, q, f.fe, f.rf);  // edge y
+      fe[im][2] = vpass(hm + 6 * P, q, f.gn, f.rf);  // point x
+      fe[im][3] = vpass(hm + 5 * P, q, f.fp, f.rf);  // point y
+    }
+    // colour error
+    const Colour t = colour_of(k, cf[0][0], cf[0][1], cf[0][2]);
+    const Colour r = colour_of(k, cf[1][0], cf[1][1], cf[1][2]);
+    const float dL = r.L - t.L, da = r.a - t.a, db = r.b - t.b;
+    const float rr = da * da + db * db;
+    const float root = sqrtf(fmaxf(rr, k.eps));
+    const float hy = fabsf(dL) + root;
+    const float e = powf(hy, k.qc);
+    const float pcc = k.pc * k.cmax;
+    const bool low = e < pcc;
+    const float dEc = low ? (k.pt / pcc) * e : k.pt + ((e - pcc) / (k.cmax - pcc)) * (1.f - k.pt);
+    // feature error
+    const float et = sqrtf(fe[0][0] * fe[0][0] + fe[0][1] * fe[0][1]);
+    const float er = sqrtf(fe[1][0] * fe[1][0] + fe[1][1] * fe[1][1]);
+    const float pt = sqrtf(fe[0][2] * fe[0][2] + fe[0][3] * fe[0][3]);
+    const float pr = sqrtf(fe[1][2] * fe[1][2] + fe[1][3] * fe[1][3]);
+    const float d1 = fabsf(er - et), d2 = fabsf(pr - pt);
+    const float mraw = fmaxf(d1, d2);
+    const float m = fmaxf(mraw, k.eps);
+    const float dF = powf(m * 0.70710678118654752f, k.qf);
+    val = powf(dEc, 1.f - dF);
+    // seeds: dval/d(filtered Y, Cx, Cz of the test), dval/d(ex, ey, px, py)
+    const float g_dEc = (1.f - dF) * powf(dEc, -dF);
+    const float g_dF = -val * logf(dEc);
+    const float g_e = g_dEc * (low ? k.pt / pcc : (1.f - k.pt) / (k.cmax - pcc));
+    const float g_hy = g_e * k.qc * powf(hy, k.qc - 1.f);
+    // d hy / d (test L, a, b) (Hunt-adjusted); the root is floored at eps
+    const float sgn = dL > 0.f ? 1.f : (dL < 0.f ? -1.f : 0.f);
+    float gL = -g_hy * sgn;
+    float ga = rr > k.eps ? -g_hy * da / root : 0.f;
+    float gb = rr > k.eps ? -g_hy * db / root : 0.f;
+    // Hunt: a' = L a / 100, b' = L b / 100
+    const float gLr = gL + 0.01f * (t.ar * ga + t.br * gb);
+    const float gar = 0.01f * t.Lr * ga, gbr = 0.01f * t.Lr * gb;
+    // CIELAB from XYZ / white
+    const float gfx = 500.f * gar, gfy = 116.f * gLr - 500.f * gar + 200.f * gbr,
+                gfz = -200.f * gbr;
+    const float gn[3] = {gfx * lab_fd(t.n[0]), gfy * lab_fd(t.n[1]), gfz * lab_fd(t.n[2])};
+    // XYZ = M clamp(rgb); n = XYZ / white
+    float grgb[3];
+    for (int j = 0; j < 3; ++j) {
+      float s = 0.f;
+      for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+      grgb[j] = (t.rgb[j] >= 0.f && t.rgb[j] <= 1.f) ? s : 0.f;
+    }
+    // rgb = Mi xyz(Y, Cx, Cz)
+    float gxyz[3];
+    for (int j = 0; j < 3; ++j)
+      gxyz[j] = k.mi[0][j] * grgb[0] + k.mi[1][j] * grgb[1] + k.mi[2][j] * grgb[2];
+    // xyz = white * (Cx/500 + yy, yy, yy - Cz/200), yy = (Y + 16)/116
+    const float gyy = k.white[0] * gxyz[0] + k.white[1] * gxyz[1] + k.white[2] * gxyz[2];
+    const int64_t o = q.p;
+    seed[o] = gyy / 116.f;
+    seed[P + o] = k.white[0] * gxyz[0] / 500.f;
+    seed[2 * P + o] = -k.white[2] * gxyz[2] / 200.f;
+    // features
+    const float g_m = mraw > k.eps ? g_dF * k.qf * dF / m : 0.f;
+    float gex = 0.f, gey = 0.f, gpx = 0.f, gpy = 0.f;
+    if (d1 >= d2) {
+      const float g_et = -g_m * ((er - et) > 0.f ? 1.f : ((er - et) < 0.f ? -1.f : 0.f));
+      if (et > 0.f) {
+        gex = g_et * fe[0][0] / et;
+        gey = g_et * fe[0][1] / et;
+      }
+    } else {
+      const float g_pt = -g_m * ((pr - pt) > 0.f ? 1.f : ((pr - pt) < 0.f ? -1.f : 0.f));
+      if (pt > 0.f) {
+        gpx = g_pt * fe[0][2] / pt;
+        gpy = g_pt * fe[0][3] / pt;
+      }
+    }
+    seed[3 * P + o] = gex;
+    seed[4 * P + o] = gey;
+    seed[5 * P + o] = gpx;
+    seed[6 * P + o] = gpy;
+  }
+  const float ws = wave_sum(val);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = 0.f;
+    for (int i = 0; i < kFB / 64; ++i) a += s_red[i];
+    blk[blockIdx.x] = a;
+  }
+}
+
+// adjoint of an edge-replicated correlation along one axis: the weight that
+// carries output position p onto input position i (0 <= i < n)
+__device__ __forceinline__ float adj_weight(const float* w, int r, int i, int p, int n) {
+  const bool lo = i == 0, hi = i == n - 1;
+  if (!lo && !hi) return w[i - p + r];
+  float s = 0.f;
+  for (int t = -r; t <= r; ++t) {
+    const int j = p + t;
+    const int c = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+    if (c == i) s += w[t + r];
+  }
+  return s;
+}
+
+__device__ __forceinline__ float vadj(const float* src, const Px& q, const float* w, int r) {
+  const int64_t col = q.p - (int64_t)q.y * q.W;
+  float s = 0.f;
+  const int p0 = max(q.y - r, 0), p1 = min(q.y + r, q.H - 1);
+  for (int p = p0; p <= p1; ++p) s += adj_weight(w, r, q.y, p, q.H) * src[col + (int64_t)p * q.W];
+  return s;
+}
+
+__device__ __forceinline__ float hadj(const float* src, const Px& q, const float* w, int r) {
+  const int64_t row = q.p - q.x;
+  float s = 0.f;
+  const int p0 = max(q.x - r, 0), p1 = min(q.x + r, q.W - 1);
+  for (int p = p0; p <= p1; ++p) s += adj_weight(w, r, q.x, p, q.W) * src[row + p];
+  return s;
+}
+
+// adjoint vertical passes of the seeds
+__global__ __launch_bounds__(kFB) void k_flip_vadj(FlipViews fv, FlipFilt f,
+                                                    const float* __restrict__ seed, int64_t P,
+                                                    float* __restrict__ t) {
+  const Px q = px_of(fv);
+  if (!q.ok) return;
+  const int64_t o = q.p;
+  t[o] = vadj(seed, q, f.gA, f.rc);
+  t[P + o] = vadj(seed + P, q, f.gRG, f.rc);
+  t[2 * P + o] = f.c1 * vadj(seed + 2 * P, q, f.u1, f.rc);
+  t[3 * P + o] = f.c2 * vadj(seed + 2 * P, q, f.u2, f.rc);
+  t[4 * P + o] = vadj(seed + 3 * P, q, f.gn, f.rf);                                   // -> fe
+  t[5 * P + o] = vadj(seed + 4 * P, q, f.fe, f.rf) + vadj(seed + 6 * P, q, f.fp, f.rf);  // -> gn
+  t[6 * P + o] = vadj(seed + 5 * P, q, f.gn, f.rf);                                   // -> fp
+}
+
+// adjoint horizontal passes, then the colour transforms of the test back to
+// its sRGB values
+__global__ __launch_bounds__(kFB) void k_flip_grad(FlipViews fv, FlipFilt f, FlipConst k,
+                                                    const float* __restrict__ test,
+                                                    const float* __restrict__ t, int64_t P,
+                                                    float scale, int accumulate,
+                                                    float* __restrict__ grad) {
+  const Px q = px_of(fv);
+  if (!q.ok) return;
+  const float gY = hadj(t, q, f.gA, f.rc) +
+                   (hadj(t + 4 * P, q, f.fe, f.rf) + hadj(t + 5 * P, q, f.gn, f.rf) +
+                    hadj(t + 6 * P, q, f.fp, f.rf)) * (1.f / 116.f);
+  const float gCx = hadj(t + P, q, f.gRG, f.rc);
+  const float gCz = hadj(t + 2 * P, q, f.u1, f.rc) + hadj(t + 3 * P, q, f.u2, f.rc);
+  // YCxCz = (116 ny - 16, 500 (nx - ny), 200 (ny - nz)), n = M lin / white
+  const float gn[3] = {500.f * gCx, 116.f * gY - 500.f * gCx + 200.f * gCz, -200.f * gCz};
+  const float sc = scale / (float)q.plane;
+  for (int j = 0; j < 3; ++j) {
+    float s = 0.f;
+    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+    const int64_t e = q.e0 + j * q.plane;
+    const float x = test[e];
+    const float g = (x >= 0.f && x <= 1.f) ? s * srgb_lin_d(x) : 0.f;
+    grad[e] = accumulate ? grad[e] + sc * g : sc * g;
+  }
+}
+
+__global__ void k_flip_reduce(FlipViews fv, const float* __restrict__ blk,
+                              float* __restrict__ out) {
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = fv.blk_off[v] + (int)threadIdx.x; b < fv.blk_off[v + 1]; b += 64) s += blk[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[v] = (float)(s / ((double)fv.w[v] * (double)fv.h[v]));
+}
+
+}  // namespace
+
+int64_t flip_blocks(int w, int h) { return ((int64_t)w * h + kFB - 1) / kFB; }
+
+hipError_t launch_flip(const FlipViews& fv, int n_blocks, const FlipFilt& f, const FlipConst& k,
+                       const float* test, const float* ref, float* maps, int64_t P, float* blk,
+                       float scale, bool accumulate, float* out, float* grad,
+                       hipStream_t stream) {
+  float* o = maps;            // 6 maps: YCxCz of test and reference
+  float* h = maps + 6 * P;    // 14 maps: horizontal passes; later 7 adjoint maps
+  float* seed = maps + 20 * P;  // 7 maps
+  const dim3 grid((unsigned)n_blocks), block(kFB);
+  hipLaunchKernelGGL(k_flip_prep, grid, block, 0, stream, fv, k, test, ref, o, P);
+  hipLaunchKernelGGL(k_flip_h, grid, block, 0, stream, fv, f, o, P, h);
+  hipLaunchKernelGGL(k_flip_eval, grid, block, 0, stream, fv, f, k, h, P, seed, blk);
+  hipLaunchKernelGGL(k_flip_vadj, grid, block, 0, stream, fv, f, seed, P, h);
+  hipLaunchKernelGGL(k_flip_grad, grid, block, 0, stream, fv, f, k, test, h, P, scale,
+                     accumulate ? 1 : 0, grad);
+  hipLaunchKernelGGL(k_flip_reduce, dim3((unsigned)fv.n_views), dim3(64), 0, stream, fv, blk, out);
+  return hipGetLastError();
+}
+
+}  // namespace seele

@@ -1307,3 +1307,184 @@ int32_t seele_adam_step(const seele_gaussian_grads* params, const seele_gaussian
 }
 
 }  // extern "C"
+
+// ---- FLIP view-consistency term (Sec. 3.5)
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct FlipHost {
+  FlipFilt f;
+  FlipConst k;
+};
+
+void flip_lab(const double* m, const double* white, const double* lin, double* lab) {
+  double n[3];
+  for (int i = 0; i < 3; ++i)
+    n[i] = (m[i * 3] * lin[0] + m[i * 3 + 1] * lin[1] + m[i * 3 + 2] * lin[2]) / white[i];
+  const double d = 6.0 / 29.0;
+  double f[3];
+  for (int i = 0; i < 3; ++i) f[i] = n[i] > d * d * d ? std::cbrt(n[i]) : n[i] / (3 * d * d) + 4.0 / 29.0;
+  lab[0] = 116 * f[1] - 16;
+  lab[1] = 0.01 * lab[0] * 500 * (f[0] - f[1]);  // Hunt-adjusted
+  lab[2] = 0.01 * lab[0] * 200 * (f[1] - f[2]);
+}
+
+int32_t flip_setup(float ppd, FlipHost& h) {
+  if (!(ppd > 0.0f) || !is_finite(ppd)) return fail(SEELE_ERR_INVALID_ARG, "bad pixels per degree");
+  const double P = ppd;
+  const double bA = 0.0047, bRG = 0.0053, a1 = 34.1, b1 = 0.04, a2 = 13.5, b2 = 0.025;
+  const int rc = (int)std::ceil(3.0 * std::sqrt(0.04 / (2 * kPi * kPi)) * P);
+  const double sd = 0.5 * 0.082 * P;
+  const int rf = (int)std::ceil(3.0 * sd);
+  if (rc > kMaxFlipRadius || rf > kMaxFlipRadius)
+    return fail(SEELE_ERR_UNSUPPORTED, "pixels per degree above %d-pixel filter radii",
+                kMaxFlipRadius);
+  FlipFilt& f = h.f;
+  f = FlipFilt{};
+  f.rc = rc;
+  f.rf = rf;
+  auto gauss = [&](double b, int t) { return std::exp(-kPi * kPi * (t / P) * (t / P) / b); };
+  double sA = 0, sRG = 0, s1 = 0, s2 = 0;
+  for (int t = -rc; t <= rc; ++t) {
+    sA += gauss(bA, t);
+    sRG += gauss(bRG, t);
+    s1 += gauss(b1, t);
+    s2 += gauss(b2, t);
+  }
+  const double w1 = a1 * std::sqrt(kPi / b1), w2 = a2 * std::sqrt(kPi / b2);
+  const double S = w1 * s1 * s1 + w2 * s2 * s2;
+  f.c1 = (float)(w1 / S);
+  f.c2 = (float)(w2 / S);
+  for (int t = -rc; t <= rc; ++t) {
+    f.gA[t + rc] = (float)(gauss(bA, t) / sA);
+    f.gRG[t + rc] = (float)(gauss(bRG, t) / sRG);
+    f.u1[t + rc] = (float)gauss(b1, t);
+    f.u2[t + rc] = (float)gauss(b2, t);
+  }
+  double G = 0, ep = 0, en = 0, pp = 0, pn = 0;
+  for (int t = -rf; t <= rf; ++t) {
+    const double g = std::exp(-(double)t * t / (2 * sd * sd));
+    const double e = -t * g, q = ((double)t * t / (sd * sd) - 1) * g;
+    G += g;
+    if (e > 0) ep += e; else en -= e;
+    if (q > 0) pp += q; else pn -= q;
+  }
+  for (int t = -rf; t <= rf; ++t) {
+    const double g = std::exp(-(double)t * t / (2 * sd * sd));
+    const double e = -t * g, q = ((double)t * t / (sd * sd) - 1) * g;
+    f.gn[t + rf] = (float)(g / G);
+    f.fe[t + rf] = (float)(e > 0 ? e / ep : e / en);
+    f.fp[t + rf] = (float)(q > 0 ? q / pp : q / pn);
+  }
+  // colour constants: linear sRGB -> XYZ (D65) and its inverse
+  const double m[9] = {10135552.0 / 24577794, 8788810.0 / 24577794, 4435075.0 / 24577794,
+                       2613072.0 / 12288897,  8788810.0 / 12288897, 887015.0 / 12288897,
+                       1425312.0 / 73733382,  8788810.0 / 73733382, 70074185.0 / 73733382};
+  const double det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                     m[2] * (m[3] * m[7] - m[4] * m[6]);
+  const double mi[9] = {(m[4] * m[8] - m[5] * m[7]) / det, (m[2] * m[7] - m[1] * m[8]) / det,
+                        (m[1] * m[5] - m[2] * m[4]) / det, (m[5] * m[6] - m[3] * m[8]) / det,
+                        (m[0] * m[8] - m[2] * m[6]) / det, (m[2] * m[3] - m[0] * m[5]) / det,
+                        (m[3] * m[7] - m[4] * m[6]) / det, (m[1] * m[6] - m[0] * m[7]) / det,
+                        (m[0] * m[4] - m[1] * m[3]) / det};
+  double white[3];
+  for (int i = 0; i < 3; ++i) white[i] = m[i * 3] + m[i * 3 + 1] + m[i * 3 + 2];
+  FlipConst& k = h.k;
+  for (int i = 0; i < 3; ++i) {
+    k.white[i] = (float)white[i];
+    for (int j = 0; j < 3; ++j) {
+      k.m[i][j] = (float)m[i * 3 + j];
+      k.mi[i][j] = (float)mi[i * 3 + j];
+    }
+  }
+  k.qc = 0.7f;
+  k.qf = 0.5f;
+  k.pc = 0.4f;
+  k.pt = 0.95f;
+  k.eps = 1e-15f;
+  const double green[3] = {0, 1, 0}, blue[3] = {0, 0, 1};
+  double lg[3], lb[3];
+  flip_lab(m, white, green, lg);
+  flip_lab(m, white, blue, lb);
+  const double hy = std::fabs(lg[0] - lb[0]) +
+                    std::sqrt(std::max((lg[1] - lb[1]) * (lg[1] - lb[1]) +
+                                       (lg[2] - lb[2]) * (lg[2] - lb[2]), 1e-15));
+  k.cmax = (float)std::pow(hy, 0.7);
+  return SEELE_OK;
+}
+
+struct FlipPlan {
+  int64_t pix = 0, blocks = 0;
+  size_t bytes = 0;
+};
+
+FlipPlan flip_plan(const seele_camera* cams, int32_t n_views) {
+  FlipPlan p;
+  for (int v = 0; v < n_views; ++v) {
+    p.pix += (int64_t)cams[v].width * cams[v].height;
+    p.blocks += flip_blocks(cams[v].width, cams[v].height);
+  }
+  p.bytes = (size_t)(27 * p.pix + p.blocks) * sizeof(float) + 256;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t seele_flip_loss_workspace_size(const seele_camera* cams, int32_t n_views) {
+  if (!cams || n_views < 1) return 0;
+  return flip_plan(cams, n_views).bytes;
+}
+
+int32_t seele_flip_loss(const float* image, const float* reference, const seele_camera* cams,
+                        int32_t n_views, float ppd, float scale, int32_t accumulate,
+                        void* workspace, size_t workspace_bytes, float* flip, float* dL_dimage,
+                        void* stream) {
+  if (!cams || n_views < 1) return fail(SEELE_ERR_INVALID_ARG, "need cameras, n_views >= 1");
+  for (int v = 0; v < n_views; ++v) {
+    const int32_t st = check_camera(cams[v], v, 16);
+    if (st != SEELE_OK) return st;
+  }
+  if (!is_finite(scale)) return fail(SEELE_ERR_INVALID_ARG, "non-finite scale");
+  if (!image || !reference || !flip || !dL_dimage || !aligned(image, 4) ||
+      !aligned(reference, 4) || !aligned(flip, 4) || !aligned(dL_dimage, 4))
+    return fail(SEELE_ERR_INVALID_ARG, "null or misaligned array");
+  FlipHost h;
+  int32_t st = flip_setup(ppd, h);
+  if (st != SEELE_OK) return st;
+  const FlipPlan plan = flip_plan(cams, n_views);
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < plan.bytes)
+    return fail(SEELE_ERR_CAPACITY, "workspace needs %zu bytes", plan.bytes);
+  if (plan.blocks >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "images too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* maps = static_cast<float*>(workspace);
+  int64_t p0 = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsFlip) {
+    const int nv = std::min(kMaxViewsFlip, n_views - v0);
+    FlipViews fv{};
+    fv.n_views = nv;
+    int64_t P = 0, b = 0;
+    for (int k = 0; k < nv; ++k) {
+      const seele_camera& c = cams[v0 + k];
+      fv.pix_off[k] = P;
+      fv.blk_off[k] = (int32_t)b;
+      fv.w[k] = c.width;
+      fv.h[k] = c.height;
+      P += (int64_t)c.width * c.height;
+      b += flip_blocks(c.width, c.height);
+    }
+    fv.pix_off[nv] = P;
+    fv.blk_off[nv] = (int32_t)b;
+    const hipError_t e = launch_flip(fv, (int)b, h.f, h.k, image + 3 * p0, reference + 3 * p0,
+                                     maps, P, maps + 27 * P, scale / (float)n_views,
+                                     accumulate != 0, flip + v0, dL_dimage + 3 * p0, s);
+    if (e != hipSuccess) return hip_fail(e, "flip launch");
+    p0 += P;
+  }
+  return SEELE_OK;
+}
+
+}  // extern "C"

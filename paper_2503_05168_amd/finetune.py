@@ -85,15 +85,20 @@ def seele_adam_step(params: GaussianTensors, grads: GaussianTensors, m: Gaussian
 
 
 class FineTuner:
-    """Fine-tunes a scene (in place) against target images: each step renders
-    the given views (optionally with active segments), takes the photometric
-    loss, runs the backward and one Adam step."""
+    """Fine-tunes a scene (in place) against target images with the loss of
+    Sec. 3.5, L_3DGS + gamma * FLIP over the step's views (gamma = 0.1; the
+    paper's steps take 7 consecutive frames): each step renders the views
+    (optionally with active segments), takes both loss terms with their
+    image gradients, runs the backward and one Adam step."""
 
     def __init__(self, g: GaussianTensors, settings: Settings | None = None, lam: float = 0.2,
-                 opts: AdamOpts | None = None, extent: float = 1.0, capacity: int = 1 << 22):
+                 opts: AdamOpts | None = None, extent: float = 1.0, capacity: int = 1 << 22,
+                 gamma: float = 0.1, ppd: float | None = None):
         self.g = g
         self.settings = settings or Settings()
         self.lam = lam
+        self.gamma = gamma
+        self.ppd = ppd
         self.opts = opts or AdamOpts()
         self.extent = extent
         self.m = zeros_like_gaussians(g)
@@ -102,8 +107,10 @@ class FineTuner:
         self.renderer = Renderer(self.settings, capacity=capacity, lists="tile")
         self.t = 0
         self._ws = None
+        self._fws = None
         self._grad2d = None
         self._pairs = None
+        self.last_flip = None
 
     def renderer_last_pairs(self):
         """Device count of Gaussian-tile pairs of the last step's render (to
@@ -111,13 +118,17 @@ class FineTuner:
         return self._pairs
 
     def step(self, cams, target, segments=None, check: bool = True, events=None):
-        """One step; returns the per-view losses (device).  events, if given,
-        are four CUDA events recorded after render, loss, backward, Adam."""
+        """One step; returns the per-view photometric losses (device; the
+        per-view FLIP is kept in last_flip).  events, if given, are four CUDA
+        events recorded after render, loss (both terms), backward, Adam."""
         f = self.renderer.render(self.g, cams, segments, check=check)
         self._pairs = f.num_pairs
         if events is not None:
             events[0].record()
         loss, dL, self._ws = seele_photometric_loss(f.image, target, cams, self.lam, self._ws)
+        if self.gamma:
+            self.last_flip, _, self._fws = seele_flip_loss(
+                f.image, target, cams, self.ppd or FLIP_PPD, self.gamma, True, dL, self._fws)
         if events is not None:
             events[1].record()
         n_rec = len(cams) * self.g.n
@@ -133,3 +144,33 @@ class FineTuner:
         if events is not None:
             events[3].record()
         return loss
+
+
+FLIP_PPD = 0.7 * (3840 / 0.7) * 3.141592653589793 / 180.0  # FLIP's default viewer
+
+
+def seele_flip_loss(image, reference, cams, ppd: float = FLIP_PPD, scale: float = 1.0,
+                    accumulate: bool = False, grad=None, workspace=None, flip=None,
+                    stream=None):
+    """(per-view mean FLIP [V], gradient buffer, workspace): the gradient of
+    scale * (mean over views) is written into `grad`, or added to it with
+    accumulate=True."""
+    cam_arr = A.camera_array(cams)
+    V = len(cams)
+    need = A.lib().seele_flip_loss_workspace_size(cam_arr, V)
+    dev = image.device
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    if flip is None:
+        flip = torch.empty(V, dtype=torch.float32, device=dev)
+    if grad is None:
+        if accumulate:
+            raise ValueError("accumulate needs a gradient buffer")
+        grad = torch.empty_like(image)
+    assert image.is_contiguous() and reference.is_contiguous()
+    assert image.numel() == reference.numel() == grad.numel()
+    st = A.lib().seele_flip_loss(_p(image), _p(reference), cam_arr, V, float(ppd), float(scale),
+                                 int(bool(accumulate)), _p(workspace), workspace.numel(), _p(flip),
+                                 _p(grad), _stream(stream))
+    A.check(st, "seele_flip_loss")
+    return flip, grad, workspace

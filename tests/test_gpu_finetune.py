@@ -111,7 +111,7 @@ def test_finetune_reduces_loss_and_composes():
     target = Renderer(st).render(GaussianTensors.from_arrays(target_scene), cams).image.clone()
     g = GaussianTensors.from_arrays(scene)
     opts = AdamOpts(lr_means=2e-4, eps=1e-8)
-    ft = FineTuner(g, st, opts=opts, extent=1.0)
+    ft = FineTuner(g, st, opts=opts, extent=1.0, gamma=0.0)
     losses = []
     for it in range(40):
         before = {k: getattr(g, k).clone() for k in ("means", "opacity_logits")}
@@ -130,3 +130,22 @@ def test_finetune_reduces_loss_and_composes():
                         ).all(), (k, err.max())
     gu.log(f"[done] finetune loss {losses[0]:.5f} -> {losses[-1]:.5f}")
     assert losses[-1] < 0.8 * losses[0]
+
+
+def test_finetune_with_flip_term_sums_gradients():
+    """With the FLIP term (gamma = 0.1, 7 consecutive views per step) a run's
+    photometric loss and FLIP both fall."""
+    gu.log("[case] finetune with FLIP term")
+    scene = synthetic.ball_scene(4, 3000, log_scale_mu=-3.0)
+    target_scene = synthetic.perturbed_scene(scene, 41, mean_sigma=0.02, logit_sigma=0.3)
+    cams = synthetic.orbit_cameras(7, 3.0, 64, 48)
+    st = Settings()
+    target = Renderer(st).render(GaussianTensors.from_arrays(target_scene), cams).image.clone()
+    g = GaussianTensors.from_arrays(scene)
+    ft = FineTuner(g, st, opts=AdamOpts(lr_means=2e-4, eps=1e-8), gamma=0.1)
+    losses, flips = [], []
+    for it in range(30):
+        losses.append(float(ft.step(cams, target).mean().item()))
+        flips.append(float(ft.last_flip.mean().item()))
+    gu.log(f"[done] loss {losses[0]:.5f} -> {losses[-1]:.5f}, FLIP {flips[0]:.4f} -> {flips[-1]:.4f}")
+    assert losses[-1] < 0.8 * losses[0] and flips[-1] < flips[0]

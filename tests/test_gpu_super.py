@@ -172,6 +172,18 @@ def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples():
     gu.log("[case] super full frame 3.0M 1080p")
     f, P = check_against_tile_path(scene, cams, st, counters=False)
     gu.log(f"[step] full frame lists and bits equal, pairs={P}")
+    # the staged path the benchmark times gives the same lists and bits
+    _, _, _, keys, eids, rng, _, img, T, nc = super_frame(scene, cams, st)
+    fs = Renderer(st, capacity=1 << 22, lists="super").render(GaussianTensors.from_arrays(scene),
+                                                               cams)
+    torch.cuda.synchronize()
+    E = int(rng[:, 1].max().item())
+    assert torch.equal(fs.entry_keys[:E], keys[:E]) and torch.equal(fs.sorted_ids[:E], eids[:E])
+    assert torch.equal(fs.tile_ranges, rng)
+    assert torch.equal(fs.image, img) and torch.equal(fs.final_T, T)
+    assert torch.equal(fs.n_contrib, nc)
+    del fs
+    gu.log("[step] staged full frame equal")
     sp = gu.splats_np(f)
     ids = f.sorted_ids.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
     ranges = f.tile_ranges.cpu().numpy().astype(np.int64)
