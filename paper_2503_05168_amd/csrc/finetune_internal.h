@@ -51,6 +51,13 @@ struct FlipConst {
 };
 
 int64_t flip_blocks(int w, int h);
+// tiled path: filter radii up to flip_tile_halo(), one block per 32 x 8 tile
+int flip_tile_halo();
+int64_t flip_tile_blocks(int w, int h);
+hipError_t launch_flip_tiled(const FlipViews& fv, int n_blocks, const FlipFilt& f,
+                             const FlipConst& k, const float* test, const float* ref,
+                             float* maps, int64_t P, float* blk, float scale, bool accumulate,
+                             float* out, float* grad, hipStream_t stream);
 hipError_t launch_flip(const FlipViews& fv, int n_blocks, const FlipFilt& f, const FlipConst& k,
                        const float* test, const float* ref, float* maps, int64_t P, float* blk,
                        float scale, bool accumulate, float* out, float* grad,

@@ -180,6 +180,89 @@ __device__ __forceinline__ Colour colour_of(const FlipConst& k, float Y, float C
   return c;
 }
 
+// Per-pixel FLIP from the filtered colour (cf[image][Y, Cx, Cz]) and the
+// feature responses (fe[image][ex, ey, px, py]) of test (0) and reference
+// (1); sd receives the value's derivatives with respect to the test's
+// filtered Y, Cx, Cz and its ex, ey, px, py.
+__device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf)[3],
+                                            const float (*fe)[4], float* sd) {
+  // colour error
+  const Colour t = colour_of(k, cf[0][0], cf[0][1], cf[0][2]);
+  const Colour r = colour_of(k, cf[1][0], cf[1][1], cf[1][2]);
+  const float dL = r.L - t.L, da = r.a - t.a, db = r.b - t.b;
+  const float rr = da * da + db * db;
+  const float root = sqrtf(fmaxf(rr, k.eps));
+  const float hy = fabsf(dL) + root;
+  const float e = powf(hy, k.qc);
+  const float pcc = k.pc * k.cmax;
+  const bool low = e < pcc;
+  const float dEc = low ? (k.pt / pcc) * e : k.pt + ((e - pcc) / (k.cmax - pcc)) * (1.f - k.pt);
+  // feature error
+  const float et = sqrtf(fe[0][0] * fe[0][0] + fe[0][1] * fe[0][1]);
+  const float er = sqrtf(fe[1][0] * fe[1][0] + fe[1][1] * fe[1][1]);
+  const float pt = sqrtf(fe[0][2] * fe[0][2] + fe[0][3] * fe[0][3]);
+  const float pr = sqrtf(fe[1][2] * fe[1][2] + fe[1][3] * fe[1][3]);
+  const float d1 = fabsf(er - et), d2 = fabsf(pr - pt);
+  const float mraw = fmaxf(d1, d2);
+  const float m = fmaxf(mraw, k.eps);
+  const float dF = powf(m * 0.70710678118654752f, k.qf);
+  const float val = powf(dEc, 1.f - dF);
+  // seeds: dval/d(filtered Y, Cx, Cz of the test), dval/d(ex, ey, px, py)
+  const float g_dEc = (1.f - dF) * powf(dEc, -dF);
+  const float g_dF = -val * logf(dEc);
+  const float g_e = g_dEc * (low ? k.pt / pcc : (1.f - k.pt) / (k.cmax - pcc));
+  const float g_hy = g_e * k.qc * powf(hy, k.qc - 1.f);
+  // d hy / d (test L, a, b) (Hunt-adjusted); the root is floored at eps
+  const float sgn = dL > 0.f ? 1.f : (dL < 0.f ? -1.f : 0.f);
+  float gL = -g_hy * sgn;
+  float ga = rr > k.eps ? -g_hy * da / root : 0.f;
+  float gb = rr > k.eps ? -g_hy * db / root : 0.f;
+  // Hunt: a' = L a / 100, b' = L b / 100
+  const float gLr = gL + 0.01f * (t.ar * ga + t.br * gb);
+  const float gar = 0.01f * t.Lr * ga, gbr = 0.01f * t.Lr * gb;
+  // CIELAB from XYZ / white
+  const float gfx = 500.f * gar, gfy = 116.f * gLr - 500.f * gar + 200.f * gbr,
+              gfz = -200.f * gbr;
+  const float gn[3] = {gfx * lab_fd(t.n[0]), gfy * lab_fd(t.n[1]), gfz * lab_fd(t.n[2])};
+  // XYZ = M clamp(rgb); n = XYZ / white
+  float grgb[3];
+  for (int j = 0; j < 3; ++j) {
+    float s = 0.f;
+    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+    grgb[j] = (t.rgb[j] >= 0.f && t.rgb[j] <= 1.f) ? s : 0.f;
+  }
+  // rgb = Mi xyz(Y, Cx, Cz)
+  float gxyz[3];
+  for (int j = 0; j < 3; ++j)
+    gxyz[j] = k.mi[0][j] * grgb[0] + k.mi[1][j] * grgb[1] + k.mi[2][j] * grgb[2];
+  // xyz = white * (Cx/500 + yy, yy, yy - Cz/200), yy = (Y + 16)/116
+  const float gyy = k.white[0] * gxyz[0] + k.white[1] * gxyz[1] + k.white[2] * gxyz[2];
+  sd[0] = gyy / 116.f;
+  sd[1] = k.white[0] * gxyz[0] / 500.f;
+  sd[2] = -k.white[2] * gxyz[2] / 200.f;
+  // features
+  const float g_m = mraw > k.eps ? g_dF * k.qf * dF / m : 0.f;
+  float gex = 0.f, gey = 0.f, gpx = 0.f, gpy = 0.f;
+  if (d1 >= d2) {
+    const float g_et = -g_m * ((er - et) > 0.f ? 1.f : ((er - et) < 0.f ? -1.f : 0.f));
+    if (et > 0.f) {
+      gex = g_et * fe[0][0] / et;
+      gey = g_et * fe[0][1] / et;
+    }
+  } else {
+    const float g_pt = -g_m * ((pr - pt) > 0.f ? 1.f : ((pr - pt) < 0.f ? -1.f : 0.f));
+    if (pt > 0.f) {
+      gpx = g_pt * fe[0][2] / pt;
+      gpy = g_pt * fe[0][3] / pt;
+    }
+  }
+  sd[3] = gex;
+  sd[4] = gey;
+  sd[5] = gpx;
+  sd[6] = gpy;
+  return val;
+}
+
 // vertical passes -> per-pixel FLIP and the seeds of its gradient
 __global__ __launch_bounds__(kFB) void k_flip_eval(FlipViews fv, FlipFilt f, FlipConst k,
                                                     const float* __restrict__ h, int64_t P,
@@ -200,81 +283,9 @@ __global__ __launch_bounds__(kFB) void k_flip_eval(FlipViews fv, FlipFilt f, Fli
       fe[im][2] = vpass(hm + 6 * P, q, f.gn, f.rf);  // point x
       fe[im][3] = vpass(hm + 5 * P, q, f.fp, f.rf);  // point y
     }
-    // colour error
-    const Colour t = colour_of(k, cf[0][0], cf[0][1], cf[0][2]);
-    const Colour r = colour_of(k, cf[1][0], cf[1][1], cf[1][2]);
-    const float dL = r.L - t.L, da = r.a - t.a, db = r.b - t.b;
-    const float rr = da * da + db * db;
-    const float root = sqrtf(fmaxf(rr, k.eps));
-    const float hy = fabsf(dL) + root;
-    const float e = powf(hy, k.qc);
-    const float pcc = k.pc * k.cmax;
-    const bool low = e < pcc;
-    const float dEc = low ? (k.pt / pcc) * e : k.pt + ((e - pcc) / (k.cmax - pcc)) * (1.f - k.pt);
-    // feature error
-    const float et = sqrtf(fe[0][0] * fe[0][0] + fe[0][1] * fe[0][1]);
-    const float er = sqrtf(fe[1][0] * fe[1][0] + fe[1][1] * fe[1][1]);
-    const float pt = sqrtf(fe[0][2] * fe[0][2] + fe[0][3] * fe[0][3]);
-    const float pr = sqrtf(fe[1][2] * fe[1][2] + fe[1][3] * fe[1][3]);
-    const float d1 = fabsf(er - et), d2 = fabsf(pr - pt);
-    const float mraw = fmaxf(d1, d2);
-    const float m = fmaxf(mraw, k.eps);
-    const float dF = powf(m * 0.70710678118654752f, k.qf);
-    val = powf(dEc, 1.f - dF);
-    // seeds: dval/d(filtered Y, Cx, Cz of the test), dval/d(ex, ey, px, py)
-    const float g_dEc = (1.f - dF) * powf(dEc, -dF);
-    const float g_dF = -val * logf(dEc);
-    const float g_e = g_dEc * (low ? k.pt / pcc : (1.f - k.pt) / (k.cmax - pcc));
-    const float g_hy = g_e * k.qc * powf(hy, k.qc - 1.f);
-    // d hy / d (test L, a, b) (Hunt-adjusted); the root is floored at eps
-    const float sgn = dL > 0.f ? 1.f : (dL < 0.f ? -1.f : 0.f);
-    float gL = -g_hy * sgn;
-    float ga = rr > k.eps ? -g_hy * da / root : 0.f;
-    float gb = rr > k.eps ? -g_hy * db / root : 0.f;
-    // Hunt: a' = L a / 100, b' = L b / 100
-    const float gLr = gL + 0.01f * (t.ar * ga + t.br * gb);
-    const float gar = 0.01f * t.Lr * ga, gbr = 0.01f * t.Lr * gb;
-    // CIELAB from XYZ / white
-    const float gfx = 500.f * gar, gfy = 116.f * gLr - 500.f * gar + 200.f * gbr,
-                gfz = -200.f * gbr;
-    const float gn[3] = {gfx * lab_fd(t.n[0]), gfy * lab_fd(t.n[1]), gfz * lab_fd(t.n[2])};
-    // XYZ = M clamp(rgb); n = XYZ / white
-    float grgb[3];
-    for (int j = 0; j < 3; ++j) {
-      float s = 0.f;
-      for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
-      grgb[j] = (t.rgb[j] >= 0.f && t.rgb[j] <= 1.f) ? s : 0.f;
-    }
-    // rgb = Mi xyz(Y, Cx, Cz)
-    float gxyz[3];
-    for (int j = 0; j < 3; ++j)
-      gxyz[j] = k.mi[0][j] * grgb[0] + k.mi[1][j] * grgb[1] + k.mi[2][j] * grgb[2];
-    // xyz = white * (Cx/500 + yy, yy, yy - Cz/200), yy = (Y + 16)/116
-    const float gyy = k.white[0] * gxyz[0] + k.white[1] * gxyz[1] + k.white[2] * gxyz[2];
-    const int64_t o = q.p;
-    seed[o] = gyy / 116.f;
-    seed[P + o] = k.white[0] * gxyz[0] / 500.f;
-    seed[2 * P + o] = -k.white[2] * gxyz[2] / 200.f;
-    // features
-    const float g_m = mraw > k.eps ? g_dF * k.qf * dF / m : 0.f;
-    float gex = 0.f, gey = 0.f, gpx = 0.f, gpy = 0.f;
-    if (d1 >= d2) {
-      const float g_et = -g_m * ((er - et) > 0.f ? 1.f : ((er - et) < 0.f ? -1.f : 0.f));
-      if (et > 0.f) {
-        gex = g_et * fe[0][0] / et;
-        gey = g_et * fe[0][1] / et;
-      }
-    } else {
-      const float g_pt = -g_m * ((pr - pt) > 0.f ? 1.f : ((pr - pt) < 0.f ? -1.f : 0.f));
-      if (pt > 0.f) {
-        gpx = g_pt * fe[0][2] / pt;
-        gpy = g_pt * fe[0][3] / pt;
-      }
-    }
-    seed[3 * P + o] = gex;
-    seed[4 * P + o] = gey;
-    seed[5 * P + o] = gpx;
-    seed[6 * P + o] = gpy;
+    float sd[7];
+    val = flip_pixel(k, cf, fe, sd);
+    for (int m = 0; m < 7; ++m) seed[m * P + q.p] = sd[m];
   }
   const float ws = wave_sum(val);
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = ws;
@@ -368,9 +379,258 @@ __global__ void k_flip_reduce(FlipViews fv, const float* __restrict__ blk,
   if (threadIdx.x == 0) out[v] = (float)(s / ((double)fv.w[v] * (double)fv.h[v]));
 }
 
+// ---- tiled path (filter radii <= kFlipHalo): one workgroup per 32 x 8
+// output tile of one view; the tile and its halo are staged in LDS, both
+// window passes run there
+
+constexpr int kFTX = 32, kFTY = 8, kFlipHalo = 10;
+constexpr int kFRX = kFTX + 2 * kFlipHalo, kFRY = kFTY + 2 * kFlipHalo;
+
+struct FTile {
+  int v, x0, y0, W, H;
+  int64_t pix0;  // first pixel of the view in the maps
+};
+
+__device__ __forceinline__ FTile ftile(const FlipViews& fv) {
+  FTile t{};
+  const int v = flip_view(fv);
+  const int W = fv.w[v], H = fv.h[v];
+  const int gx = (W + kFTX - 1) / kFTX;
+  const int b = (int)blockIdx.x - fv.blk_off[v];
+  t.v = v;
+  t.W = W;
+  t.H = H;
+  t.x0 = (b % gx) * kFTX;
+  t.y0 = (b / gx) * kFTY;
+  t.pix0 = fv.pix_off[v];
+  return t;
+}
+
+constexpr int kFTap = 2 * kFlipHalo + 1;
+
+// the seven 1D filters, zero-padded to kFTap taps (centre at kFlipHalo):
+// 0 gA, 1 gRG, 2 u1, 3 u2 (radius rc); 4 gn, 5 fe, 6 fp (radius rf)
+__device__ __forceinline__ void load_weights(const FlipFilt& f, float (*w)[kFTap]) {
+  for (int i = threadIdx.x; i < 7 * kFTap; i += kFB) {
+    const int m = i / kFTap, t = i - m * kFTap - kFlipHalo;
+    const int r = m < 4 ? f.rc : f.rf;
+    const float* src = m == 0 ? f.gA : m == 1 ? f.gRG : m == 2 ? f.u1 : m == 3 ? f.u2
+                     : m == 4 ? f.gn : m == 5 ? f.fe : f.fp;
+    w[m][t + kFlipHalo] = (t >= -r && t <= r) ? src[t + r] : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f, FlipConst k,
+                                                        const float* __restrict__ o,
+                                                        float* __restrict__ seed, int64_t P,
+                                                        float* __restrict__ blk) {
+  __shared__ float s_w[7][kFTap];
+  __shared__ float s_in[3][kFRY][kFRX];
+  __shared__ float s_h[7][kFRY][kFTX];
+  __shared__ float s_red[kFB / 64];
+  const FTile T = ftile(fv);
+  load_weights(f, s_w);
+  const int oy = threadIdx.x / kFTX, ox = threadIdx.x % kFTX;
+  const int x = T.x0 + ox, y = T.y0 + oy;
+  float cf[2][3], fe[2][4];
+  for (int im = 1; im >= 0; --im) {  // reference first, then the test
+    const float* src = o + (int64_t)(3 * im) * P + T.pix0;
+    for (int i = threadIdx.x; i < kFRY * kFRX; i += kFB) {
+      const int r = i / kFRX, c = i - r * kFRX;
+      const int yy = min(max(T.y0 + r - kFlipHalo, 0), T.H - 1);
+      const int xx = min(max(T.x0 + c - kFlipHalo, 0), T.W - 1);
+      const int64_t e = (int64_t)yy * T.W + xx;
+      s_in[0][r][c] = src[e];
+      s_in[1][r][c] = src[P + e];
+      s_in[2][r][c] = src[2 * P + e];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kFRY * kFTX; i += kFB) {
+      const int r = i / kFTX, c = i - r * kFTX;
+      float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < kFTap; ++j) {
+        const float Y = s_in[0][r][c + j], cz = s_in[2][r][c + j];
+        const float yn = (Y + 16.f) * (1.f / 116.f);
+        a[0] += s_w[0][j] * Y;
+        a[1] += s_w[1][j] * s_in[1][r][c + j];
+        a[2] += s_w[2][j] * cz;
+        a[3] += s_w[3][j] * cz;
+        a[4] += s_w[5][j] * yn;  // edge profile along x
+        a[5] += s_w[4][j] * yn;  // Gaussian along x
+        a[6] += s_w[6][j] * yn;  // point profile along x
+      }
+#pragma unroll
+      for (int m = 0; m < 7; ++m) s_h[m][r][c] = a[m];
+    }
+    __syncthreads();
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < kFTap; ++j) {
+      const int ry = oy + j;
+      v[0] += s_w[0][j] * s_h[0][ry][ox];
+      v[1] += s_w[1][j] * s_h[1][ry][ox];
+      v[2] += s_w[2][j] * s_h[2][ry][ox];
+      v[3] += s_w[3][j] * s_h[3][ry][ox];
+      v[4] += s_w[4][j] * s_h[4][ry][ox];  // ex: edge along x, Gaussian along y
+      v[5] += s_w[5][j] * s_h[5][ry][ox];  // ey: Gaussian along x, edge along y
+      v[6] += s_w[4][j] * s_h[6][ry][ox];  // px
+      v[7] += s_w[6][j] * s_h[5][ry][ox];  // py
+    }
+    cf[im][0] = v[0];
+    cf[im][1] = v[1];
+    cf[im][2] = f.c1 * v[2] + f.c2 * v[3];
+    fe[im][0] = v[4];
+    fe[im][1] = v[5];
+    fe[im][2] = v[6];
+    fe[im][3] = v[7];
+    __syncthreads();
+  }
+  float val = 0.f;
+  if (x < T.W && y < T.H) {
+    float sd[7];
+    val = flip_pixel(k, cf, fe, sd);
+    const int64_t oo = T.pix0 + (int64_t)y * T.W + x;
+    for (int m = 0; m < 7; ++m) seed[m * P + oo] = sd[m];
+  }
+  const float ws = wave_sum(val);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = 0.f;
+    for (int i = 0; i < kFB / 64; ++i) a += s_red[i];
+    blk[blockIdx.x] = a;
+  }
+}
+
+// Adjoint of an edge-replicated 1D correlation at input position i of n,
+// from the outputs g(p) at LDS positions base + p * stride: interior
+// positions take sum_t w[t] g(i - t); the two border positions also take the
+// weights of every tap that the replication folded onto them.
+__device__ __forceinline__ float adj1d(const float* w, int i, int n, const float* g, int base,
+                                       int stride) {
+  float s = 0.f;
+  if (i > 0 && i < n - 1) {
+#pragma unroll
+    for (int j = 0; j < kFTap; ++j) {
+      const int p = i - (j - kFlipHalo);
+      if (p >= 0 && p < n) s += w[j] * g[(base + p) * stride];
+    }
+    return s;
+  }
+  const int p0 = max(i - kFlipHalo, 0), p1 = min(i + kFlipHalo, n - 1);
+  for (int p = p0; p <= p1; ++p) {
+    float wt = 0.f;
+    for (int j = 0; j < kFTap; ++j) {
+      const int q = p + j - kFlipHalo;
+      const int c = q < 0 ? 0 : (q > n - 1 ? n - 1 : q);
+      if (c == i) wt += w[j];
+    }
+    s += wt * g[(base + p) * stride];
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f, FlipConst k,
+                                                        const float* __restrict__ test,
+                                                        const float* __restrict__ seed, int64_t P,
+                                                        float scale, int accumulate,
+                                                        float* __restrict__ grad) {
+  __shared__ float s_w[7][kFTap];
+  __shared__ float s_s[7][kFRY][kFRX];
+  __shared__ float s_v[7][kFTY][kFRX];
+  const FTile T = ftile(fv);
+  load_weights(f, s_w);
+  // seeds of the tile and its halo (zero outside the image)
+  for (int i = threadIdx.x; i < kFRY * kFRX; i += kFB) {
+    const int r = i / kFRX, c = i - r * kFRX;
+    const int yy = T.y0 + r - kFlipHalo, xx = T.x0 + c - kFlipHalo;
+    float val[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (yy >= 0 && yy < T.H && xx >= 0 && xx < T.W) {
+      const int64_t oo = T.pix0 + (int64_t)yy * T.W + xx;
+      for (int m = 0; m < 7; ++m) val[m] = seed[m * P + oo];
+    }
+    for (int m = 0; m < 7; ++m) s_s[m][r][c] = val[m];
+  }
+  __syncthreads();
+  // adjoint vertical passes at the tile's rows, every in-image halo column;
+  // row p of the image sits at LDS row p - y0 + halo
+  const int rbase = kFlipHalo - T.y0;
+  for (int i = threadIdx.x; i < kFTY * kFRX; i += kFB) {
+    const int oy = i / kFRX, c = i - oy * kFRX;
+    const int y = T.y0 + oy, xx = T.x0 + c - kFlipHalo;
+    float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (y < T.H && xx >= 0 && xx < T.W) {
+      a[0] = adj1d(s_w[0], y, T.H, &s_s[0][0][c], rbase, kFRX);
+      a[1] = adj1d(s_w[1], y, T.H, &s_s[1][0][c], rbase, kFRX);
+      a[2] = f.c1 * adj1d(s_w[2], y, T.H, &s_s[2][0][c], rbase, kFRX);
+      a[3] = f.c2 * adj1d(s_w[3], y, T.H, &s_s[2][0][c], rbase, kFRX);
+      a[4] = adj1d(s_w[4], y, T.H, &s_s[3][0][c], rbase, kFRX);   // ex -> edge along x
+      a[5] = adj1d(s_w[5], y, T.H, &s_s[4][0][c], rbase, kFRX) +  // ey, py -> Gaussian along x
+             adj1d(s_w[6], y, T.H, &s_s[6][0][c], rbase, kFRX);
+      a[6] = adj1d(s_w[4], y, T.H, &s_s[5][0][c], rbase, kFRX);   // px -> point along x
+    }
+    for (int m = 0; m < 7; ++m) s_v[m][oy][c] = a[m];
+  }
+  __syncthreads();
+  const int oy = threadIdx.x / kFTX, ox = threadIdx.x % kFTX;
+  const int x = T.x0 + ox, y = T.y0 + oy;
+  if (x >= T.W || y >= T.H) return;
+  const int cbase = kFlipHalo - T.x0;
+  const float gA = adj1d(s_w[0], x, T.W, s_v[0][oy], cbase, 1);
+  const float gRG = adj1d(s_w[1], x, T.W, s_v[1][oy], cbase, 1);
+  const float gB = adj1d(s_w[2], x, T.W, s_v[2][oy], cbase, 1) +
+                   adj1d(s_w[3], x, T.W, s_v[3][oy], cbase, 1);
+  const float gF = adj1d(s_w[5], x, T.W, s_v[4][oy], cbase, 1) +
+                   adj1d(s_w[4], x, T.W, s_v[5][oy], cbase, 1) +
+                   adj1d(s_w[6], x, T.W, s_v[6][oy], cbase, 1);
+  const float gY = gA + gF * (1.f / 116.f);
+  const float gn[3] = {500.f * gRG, 116.f * gY - 500.f * gRG + 200.f * gB, -200.f * gB};
+  const int64_t plane = (int64_t)T.W * T.H;
+  const float sc = scale / (float)plane;
+  const int64_t e0 = 3 * T.pix0 + (int64_t)y * T.W + x;
+  for (int j = 0; j < 3; ++j) {
+    float s = 0.f;
+    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+    const int64_t e = e0 + j * plane;
+    const float xv = test[e];
+    const float g = (xv >= 0.f && xv <= 1.f) ? s * srgb_lin_d(xv) : 0.f;
+    grad[e] = accumulate ? grad[e] + sc * g : sc * g;
+  }
+}
+
 }  // namespace
 
 int64_t flip_blocks(int w, int h) { return ((int64_t)w * h + kFB - 1) / kFB; }
+
+int flip_tile_halo() { return kFlipHalo; }
+
+int64_t flip_tile_blocks(int w, int h) {
+  return (int64_t)((w + kFTX - 1) / kFTX) * ((h + kFTY - 1) / kFTY);
+}
+
+hipError_t launch_flip_tiled(const FlipViews& fv, int n_blocks, const FlipFilt& f,
+                             const FlipConst& k, const float* test, const float* ref,
+                             float* maps, int64_t P, float* blk, float scale, bool accumulate,
+                             float* out, float* grad, hipStream_t stream) {
+  // YCxCz of both images once per pixel (6 maps), then the tiles
+  float* o = maps;
+  float* seed = maps + 6 * P;
+  unsigned pix_blocks = 0;
+  for (int v = 0; v < fv.n_views; ++v) pix_blocks += (unsigned)flip_blocks(fv.w[v], fv.h[v]);
+  FlipViews pv = fv;
+  for (int v = 0, b = 0; v <= fv.n_views; ++v) {
+    pv.blk_off[v] = b;
+    if (v < fv.n_views) b += (int)flip_blocks(fv.w[v], fv.h[v]);
+  }
+  hipLaunchKernelGGL(k_flip_prep, dim3(pix_blocks), dim3(kFB), 0, stream, pv, k, test, ref, o, P);
+  const dim3 grid((unsigned)n_blocks), block(kFB);
+  hipLaunchKernelGGL(k_flip_fwd_tile, grid, block, 0, stream, fv, f, k, o, seed, P, blk);
+  hipLaunchKernelGGL(k_flip_bwd_tile, grid, block, 0, stream, fv, f, k, test, seed, P, scale,
+                     accumulate ? 1 : 0, grad);
+  hipLaunchKernelGGL(k_flip_reduce, dim3((unsigned)fv.n_views), dim3(64), 0, stream, fv, blk, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_flip(const FlipViews& fv, int n_blocks, const FlipFilt& f, const FlipConst& k,
                        const float* test, const float* ref, float* maps, int64_t P, float* blk,

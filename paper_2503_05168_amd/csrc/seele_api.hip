@@ -1424,8 +1424,10 @@ FlipPlan flip_plan(const seele_camera* cams, int32_t n_views) {
   FlipPlan p;
   for (int v = 0; v < n_views; ++v) {
     p.pix += (int64_t)cams[v].width * cams[v].height;
-    p.blocks += flip_blocks(cams[v].width, cams[v].height);
+    p.blocks += std::max(flip_blocks(cams[v].width, cams[v].height),
+                         flip_tile_blocks(cams[v].width, cams[v].height));
   }
+  // 27 maps for the untiled path (7 for the tiled one) + a float per block
   p.bytes = (size_t)(27 * p.pix + p.blocks) * sizeof(float) + 256;
   return p;
 }
@@ -1461,6 +1463,8 @@ int32_t seele_flip_loss(const float* image, const float* reference, const seele_
   if (plan.blocks >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "images too large");
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* maps = static_cast<float*>(workspace);
+  // LDS-tiled kernels when both filter radii fit their halo
+  const bool tiled = std::max(h.f.rc, h.f.rf) <= flip_tile_halo();
   int64_t p0 = 0;
   for (int v0 = 0; v0 < n_views; v0 += kMaxViewsFlip) {
     const int nv = std::min(kMaxViewsFlip, n_views - v0);
@@ -1474,13 +1478,17 @@ int32_t seele_flip_loss(const float* image, const float* reference, const seele_
       fv.w[k] = c.width;
       fv.h[k] = c.height;
       P += (int64_t)c.width * c.height;
-      b += flip_blocks(c.width, c.height);
+      b += tiled ? flip_tile_blocks(c.width, c.height) : flip_blocks(c.width, c.height);
     }
     fv.pix_off[nv] = P;
     fv.blk_off[nv] = (int32_t)b;
-    const hipError_t e = launch_flip(fv, (int)b, h.f, h.k, image + 3 * p0, reference + 3 * p0,
-                                     maps, P, maps + 27 * P, scale / (float)n_views,
-                                     accumulate != 0, flip + v0, dL_dimage + 3 * p0, s);
+    const hipError_t e =
+        tiled ? launch_flip_tiled(fv, (int)b, h.f, h.k, image + 3 * p0, reference + 3 * p0,
+                                  maps, P, maps + 27 * P, scale / (float)n_views,
+                                  accumulate != 0, flip + v0, dL_dimage + 3 * p0, s)
+              : launch_flip(fv, (int)b, h.f, h.k, image + 3 * p0, reference + 3 * p0, maps, P,
+                            maps + 27 * P, scale / (float)n_views, accumulate != 0, flip + v0,
+                            dL_dimage + 3 * p0, s);
     if (e != hipSuccess) return hip_fail(e, "flip launch");
     p0 += P;
   }

@@ -119,18 +119,21 @@ class FineTuner:
 
     def step(self, cams, target, segments=None, check: bool = True, events=None):
         """One step; returns the per-view photometric losses (device; the
-        per-view FLIP is kept in last_flip).  events, if given, are four CUDA
-        events recorded after render, loss (both terms), backward, Adam."""
+        per-view FLIP is kept in last_flip).  events, if given, are five CUDA
+        events recorded after render, photometric loss, FLIP, backward,
+        Adam."""
         f = self.renderer.render(self.g, cams, segments, check=check)
         self._pairs = f.num_pairs
         if events is not None:
             events[0].record()
         loss, dL, self._ws = seele_photometric_loss(f.image, target, cams, self.lam, self._ws)
+        if events is not None:
+            events[1].record()
         if self.gamma:
             self.last_flip, _, self._fws = seele_flip_loss(
                 f.image, target, cams, self.ppd or FLIP_PPD, self.gamma, True, dL, self._fws)
         if events is not None:
-            events[1].record()
+            events[2].record()
         n_rec = len(cams) * self.g.n
         if self._grad2d is None or self._grad2d.shape[0] < n_rec:
             self._grad2d = torch.empty((n_rec, 9), dtype=torch.float32, device=self.g.means.device)
@@ -138,11 +141,11 @@ class FineTuner:
                             f.tile_ranges, f.final_T, f.n_contrib, dL, segments,
                             self._grad2d[:n_rec], self.grads)
         if events is not None:
-            events[2].record()
+            events[3].record()
         self.t += 1
         seele_adam_step(self.g, self.grads, self.m, self.v, self.t, self.opts, self.extent)
         if events is not None:
-            events[3].record()
+            events[4].record()
         return loss
 
 

@@ -20,15 +20,18 @@ def _cams(sizes):
 
 
 CASES = {
-    "ragged": [(40, 30), (23, 17), (5, 4)],
+    "ragged": [(40, 30), (23, 17), (5, 4), (70, 9)],
     "single-64": [(64, 48)],
 }
 
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("kind", ["near", "random"])
-def test_flip_matches_oracle(name, kind):
-    gu.log(f"[case] flip {name} {kind}")
+@pytest.mark.parametrize("ppd", [oflip.PPD, 120.0])
+def test_flip_matches_oracle(name, kind, ppd):
+    """ppd 67 runs the LDS-tiled kernels (radii 10 and 9), ppd 120 the
+    untiled ones (radii 17 and 15)."""
+    gu.log(f"[case] flip {name} {kind} ppd={ppd:.1f}")
     cams = _cams(CASES[name])
     rng = np.random.default_rng(3 + len(cams))
     ref = [rng.uniform(0.0, 1.0, (3, c.height, c.width)) for c in cams]
@@ -40,9 +43,9 @@ def test_flip_matches_oracle(name, kind):
     ref = [r.astype(np.float32) for r in ref]
     img = torch.from_numpy(np.concatenate([a.ravel() for a in test])).cuda()
     rf = torch.from_numpy(np.concatenate([a.ravel() for a in ref])).cuda()
-    val, grad, _ = seele_flip_loss(img, rf, cams, scale=0.1)
+    val, grad, _ = seele_flip_loss(img, rf, cams, ppd=ppd, scale=0.1)
     torch.cuda.synchronize()
-    ov, og = oflip.flip_and_grad(test, ref)
+    ov, og = oflip.flip_and_grad(test, ref, ppd)
     np.testing.assert_allclose(val.cpu().numpy(), ov, rtol=2e-4)
     g = grad.cpu().numpy()
     off = 0
@@ -58,7 +61,7 @@ def test_flip_matches_oracle(name, kind):
         off += n
     # accumulate adds onto what the buffer holds
     base = torch.ones_like(grad)
-    _, g2, _ = seele_flip_loss(img, rf, cams, scale=0.1, accumulate=True, grad=base)
+    _, g2, _ = seele_flip_loss(img, rf, cams, ppd=ppd, scale=0.1, accumulate=True, grad=base)
     torch.cuda.synchronize()
     torch.testing.assert_close(g2, grad + 1.0, rtol=0, atol=1e-6)
 
