@@ -504,18 +504,17 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
 }
 
 // Adjoint of an edge-replicated 1D correlation at input position i of n,
-// from the outputs g(p) at LDS positions base + p * stride: interior
-// positions take sum_t w[t] g(i - t); the two border positions also take the
+// from the outputs g(p) at LDS positions (base + p) * stride, which hold
+// zero for p outside the image: interior positions take sum_t w[t] g(i - t)
+// over the whole staged window; the two border positions also take the
 // weights of every tap that the replication folded onto them.
 __device__ __forceinline__ float adj1d(const float* w, int i, int n, const float* g, int base,
                                        int stride) {
   float s = 0.f;
   if (i > 0 && i < n - 1) {
+    const float* gi = g + (base + i + kFlipHalo) * stride;
 #pragma unroll
-    for (int j = 0; j < kFTap; ++j) {
-      const int p = i - (j - kFlipHalo);
-      if (p >= 0 && p < n) s += w[j] * g[(base + p) * stride];
-    }
+    for (int j = 0; j < kFTap; ++j) s += w[j] * gi[-j * stride];
     return s;
   }
   const int p0 = max(i - kFlipHalo, 0), p1 = min(i + kFlipHalo, n - 1);
