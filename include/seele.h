@@ -521,6 +521,21 @@ int32_t seele_flip_loss(const float* image, const float* reference, const seele_
                         void* workspace, size_t workspace_bytes, float* flip, float* dL_dimage,
                         void* stream);
 
+/* Storage order of a scene (a layout choice, not a step of the method):
+ * the permutation that sorts the Gaussians by the 30-bit Morton code of
+ * their means, bit 3k + a holding bit k of axis a's quantised coordinate
+ * q_a = min(1023, floor((x_a - lo_a) * (1024 / (hi_a - lo_a)))) computed in
+ * float32 over the box [lo, hi] of the finite coordinates (q_a = 1023 for a
+ * non-finite coordinate, 0 on a flat axis); equal codes keep their original
+ * order.  Gathering the scene in this order (seele_gather_gaussians) lets a
+ * view's culled and visible Gaussians, and a tile's list, occupy contiguous
+ * runs of memory.  perm: device int64 [n], new position -> original index.
+ * workspace: device, 256-byte aligned, seele_spatial_order_workspace_size
+ * bytes. */
+size_t seele_spatial_order_workspace_size(int64_t n);
+int32_t seele_spatial_order(const seele_gaussians* g, void* workspace, size_t workspace_bytes,
+                            int64_t* perm, void* stream);
+
 /* Thread-local message describing the last non-OK status on this thread. */
 const char* seele_last_error(void);
 /* Static name of a status code. */

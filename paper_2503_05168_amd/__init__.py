@@ -37,6 +37,8 @@ from .hp_build import (  # noqa: F401
     seele_hp_accumulate,
     seele_hp_kmeans,
     seele_hp_partition,
+    seele_spatial_order,
+    spatially_ordered,
 )
 from .prefetch import (  # noqa: F401
     PrefetchingRenderer,

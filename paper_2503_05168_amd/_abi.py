@@ -137,6 +137,9 @@ SIGNATURES = {
     "seele_flip_loss": (c_int32, [c_void_p, c_void_p, POINTER(seele_camera), c_int32, c_float,
                                   c_float, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
                                   c_void_p]),
+    "seele_spatial_order_workspace_size": (c_size_t, [c_int64]),
+    "seele_spatial_order": (c_int32, [POINTER(seele_gaussians), c_void_p, c_size_t, c_void_p,
+                                      c_void_p]),
     "seele_hp_select": (c_int32, [POINTER(c_float), c_int32, POINTER(seele_camera), c_float,
                                   c_float, c_int32, POINTER(c_int32)]),
     "seele_hp_segments": (c_int32, [POINTER(c_int64), POINTER(c_int64), c_int32, POINTER(c_int32),

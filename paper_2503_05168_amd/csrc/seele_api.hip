@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "finetune_internal.h"
+#include "layout_internal.h"
 #include "seele_internal.h"
 
 using namespace seele;
@@ -1493,6 +1494,31 @@ int32_t seele_flip_loss(const float* image, const float* reference, const seele_
     p0 += P;
   }
   return SEELE_OK;
+}
+
+}  // extern "C"
+
+// ---- scene storage order
+
+extern "C" {
+
+size_t seele_spatial_order_workspace_size(int64_t n) {
+  return n < 0 ? 0 : spatial_order_workspace_size(n);
+}
+
+int32_t seele_spatial_order(const seele_gaussians* g, void* workspace, size_t workspace_bytes,
+                            int64_t* perm, void* stream) {
+  const int32_t st = check_gaussians(g);
+  if (st != SEELE_OK) return st;
+  if (g->n >= ((int64_t)1 << 32)) return fail(SEELE_ERR_UNSUPPORTED, "more than 2^32 Gaussians");
+  if (g->n == 0) return SEELE_OK;
+  if (!perm || !aligned(perm, 8)) return fail(SEELE_ERR_INVALID_ARG, "perm null or misaligned");
+  const size_t need = spatial_order_workspace_size(g->n);
+  if (!workspace || !aligned(workspace, 256) || workspace_bytes < need)
+    return fail(SEELE_ERR_CAPACITY, "workspace needs %zu bytes", need);
+  const hipError_t e = launch_spatial_order(g->means, g->n, workspace, perm,
+                                            static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEELE_OK : hip_fail(e, "spatial order launch");
 }
 
 }  // extern "C"

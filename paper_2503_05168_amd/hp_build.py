@@ -110,6 +110,27 @@ def _sorted_lists(g: GaussianTensors, cams, settings: Settings, capacity: int, w
         capacity = min(int(need * 1.5) + 1024, MAX_PAIRS)
 
 
+def seele_spatial_order(g: GaussianTensors, workspace=None, stream=None):
+    """(perm int64 [n] on the device: new position -> original index, workspace)."""
+    n = g.n
+    dev = g.means.device
+    perm = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    need = A.lib().seele_spatial_order_workspace_size(n)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    src = g.struct()
+    st = A.lib().seele_spatial_order(ctypes.byref(src), _p(workspace), workspace.numel(),
+                                     _p(perm), _stream(stream))
+    A.check(st, "seele_spatial_order")
+    return perm[:n], workspace
+
+
+def spatially_ordered(g: GaussianTensors):
+    """(the scene gathered in Morton order of its means, perm)."""
+    perm, _ = seele_spatial_order(g)
+    return seele_gather_gaussians(g, perm), perm
+
+
 def build_view_dependent(g: GaussianTensors, poses, n_clusters: int, k: int = 32,
                          beta: float = 1.0, pos_scale: float | None = None,
                          settings: Settings | None = None, iters: int = 100,

@@ -12,6 +12,7 @@ import torch
 import synthetic
 from oracle import blend as oblend
 from paper_2503_05168_amd import (GaussianTensors, Renderer, Settings, seele_bin_sort_super,
+                                  seele_spatial_order,
                                   seele_preprocess, seele_rasterize_fwd_counted,
                                   seele_rasterize_fwd_super, total_super_tiles, total_tiles)
 
@@ -162,14 +163,20 @@ def test_super_default_batch_only():
         Renderer(Settings(), lists="super", schedule="queue")
 
 
-def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples():
+@pytest.mark.parametrize("order", ["morton", "generated"])
+def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples(order):
     """The benchmark's frame (3.0M Gaussians, 1920x1080, 16x16 tiles) in the
-    launch configuration it times: bit-identical to the per-tile path, and
-    sampled tiles against the float64 oracle over the GPU's own splats."""
+    launch configuration it times, in the storage order it uses (Morton order
+    of the means) and in the generator's order: bit-identical to the per-tile
+    path, and sampled tiles against the float64 oracle over the GPU's own
+    splats."""
     cfg = synthetic.config(2, n_views=1)
     scene, cams = cfg["scene"], cfg["cams"]
+    if order == "morton":
+        perm, _ = seele_spatial_order(GaussianTensors.from_arrays(scene))
+        scene = scene.subset(perm.cpu().numpy())
     st = Settings()
-    gu.log("[case] super full frame 3.0M 1080p")
+    gu.log(f"[case] super full frame 3.0M 1080p, {order} order")
     f, P = check_against_tile_path(scene, cams, st, counters=False)
     gu.log(f"[step] full frame lists and bits equal, pairs={P}")
     # the staged path the benchmark times gives the same lists and bits
