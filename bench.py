@@ -80,6 +80,12 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
     ap.add_argument("--no-prefetch", action="store_true",
                     help="skip the scene-prefetching measurement (needs the hp_built form)")
+    ap.add_argument("--ft-steps", type=int, default=1000,
+                    help="steps of the integrated fine-tuning run (0 skips it; needs hp_built)")
+    ap.add_argument("--ft-gamma", type=float, default=0.1,
+                    help="weight of the FLIP term in the integrated fine-tuning run")
+    ap.add_argument("--ft-lr-scale", type=float, default=1.0,
+                    help="scale of the 3DGS learning rates in the integrated fine-tuning run")
     ap.add_argument("--no-groups", action="store_true",
                     help="skip the contribution-aware group-size sweep")
     ap.add_argument("--lists", choices=("super", "tile"), default="super",
@@ -380,6 +386,81 @@ def run_prefetch(vd, frames=240, slots=8, M=3):
     return out
 
 
+def run_integrated_finetune(vd, full_g, start_g, steps=1000, window=7, M=3, frames=240,
+                            lr_scale=1.0, gamma=0.1):
+    """The integrated fine-tuning of Sec. 3.5 in the built representation's
+    layout: a model to fine-tune (start_g: the scene with perturbed means
+    and opacities, standing in for a converted model that lost quality) is
+    trained towards the plain full-scene renders of the scene.  Each step
+    renders `window` consecutive 1080p frames of a camera path (orbit radius
+    4, vertical wobble 0.3) with Seele's pipeline (hybrid preprocessing over
+    the union of the frames' selected clusters, opacity-aware extent,
+    contribution-aware rasterization), takes L_3DGS + gamma FLIP, the
+    backward and Adam.  Reports ms per step and the PSNR of Seele's render
+    against the plain full-scene image on 8 orbit views (not on the path)
+    before and after."""
+    import torch
+    import synthetic
+    import paper_2503_05168_amd as P
+
+    path = []
+    for k in range(frames):
+        th = 2.0 * math.pi * k / frames
+        path.append(synthetic.look_at((4.0 * math.sin(th), 0.3 * math.sin(3 * th),
+                                       -4.0 * math.cos(th)), width=1920, height=1080))
+    held = synthetic.orbit_cameras(32, 4.0, 1920, 1080)
+    plain = P.Renderer(P.Settings(), capacity=1 << 26, lists="super")
+    npx = 3 * 1920 * 1080
+    targets = torch.empty((frames, npx), dtype=torch.float32, device="cuda")
+    for i, c in enumerate(path):
+        targets[i].copy_(plain.render(full_g, [c]).image)
+    held_ref = [plain.render(full_g, [c]).image.clone() for c in held[::4]]
+    g = start_g
+    st = P.Settings(mode="contrib", extent="opacity")
+
+    def segs(cams):
+        cl = sorted({c for cam in cams for c in P.seele_hp_select(vd.centroids, cam, vd.pos_scale,
+                                                                  vd.beta, M)})
+        return P.seele_hp_segments(vd.seg_begin, vd.seg_count, cl)
+
+    def psnr_held():
+        r = P.Renderer(st, capacity=1 << 26, lists="super")
+        mse = 0.0
+        for c, ref in zip(held[::4], held_ref):
+            d = r.render(g, [c], segs([c])).image - ref
+            mse += float((d * d).mean().item()) / len(held_ref)
+        return 10.0 * math.log10(1.0 / mse)
+
+    before = psnr_held()
+    o = P.AdamOpts()
+    opts = P.AdamOpts(*(lr_scale * getattr(o, k) for k in
+                        ("lr_means", "lr_log_scales", "lr_quats", "lr_opacity", "lr_sh_dc",
+                         "lr_sh_rest")))
+    ft = P.FineTuner(g, st, gamma=gamma, opts=opts, extent=vd.pos_scale, capacity=1 << 26)
+    starts = [(s_ * window) % (frames - window + 1) for s_ in range(steps)]
+    loss0 = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, s0 in enumerate(starts):
+        cams = path[s0:s0 + window]
+        l = ft.step(cams, targets[s0:s0 + window].reshape(-1), segs(cams))
+        if i == 0:
+            loss0 = float(l.mean().item())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    loss1 = float(l.mean().item())
+    after = psnr_held()
+    out = dict(steps=steps, window=window, lr_scale=lr_scale, gamma=gamma,
+               ms_per_step=1000.0 * wall / max(steps, 1),
+               ms_per_view=1000.0 * wall / max(steps * window, 1), loss_first=loss0,
+               loss_last=loss1, psnr_before=before, psnr_after=after)
+    log(f"[bench] integrated fine-tuning: {steps} steps x {window} frames, "
+        f"{out['ms_per_step']:.2f} ms/step; loss {loss0:.5f} -> {loss1:.5f}; PSNR vs the plain "
+        f"full scene {before:.2f} -> {after:.2f} dB")
+    del ft, targets
+    return out
+
+
 def run_group_sweep(g, cams, steps, warmup, groups=((1, 1), (2, 2), (2, 4), (4, 4))):
     """Contribution-aware form with pixel groups of several sizes (Fig. 7's
     sweep on the synthetic 1080p scene): frames/s, and the PSNR of its image
@@ -654,6 +735,17 @@ def main():
     if not args.no_prefetch and "hp_built" in forms:
         prefetch = run_prefetch(forms["hp_built"]["hp"])
         log(f"[bench] t+{time.time() - t_start:.0f}s prefetch done")
+    finetune = None
+    if args.ft_steps > 0 and "hp_built" in forms:
+        import synthetic
+        vd = forms["hp_built"]["hp"]
+        start = P.seele_gather_gaussians(
+            P.GaussianTensors.from_arrays(synthetic.perturbed_scene(scene, 40)), vd.perm)
+        finetune = run_integrated_finetune(vd, forms["hp_built"]["full_g"], start,
+                                           args.ft_steps, lr_scale=args.ft_lr_scale,
+                                           gamma=args.ft_gamma)
+        del start
+        log(f"[bench] t+{time.time() - t_start:.0f}s integrated fine-tuning done")
     groups = None
     if not args.no_groups and "plain" in forms:
         groups = run_group_sweep(forms["plain"]["g"], cams, max(8, args.steps // 2),
@@ -736,6 +828,7 @@ def main():
         "batched_64_views": batched,
         "contrib_group_sweep": groups,
         "scene_prefetch": prefetch,
+        "integrated_finetune": finetune,
         "roofline": roof,
         "stage_roofline": stage_roof,
         "cpu_baseline": cpu,
