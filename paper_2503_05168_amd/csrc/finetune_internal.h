@@ -46,7 +46,7 @@ struct FlipFilt {
   float gn[2 * kMaxFlipRadius + 1], fe[2 * kMaxFlipRadius + 1], fp[2 * kMaxFlipRadius + 1];
 };
 struct FlipConst {
-  float m[3][3], mi[3][3], white[3];
+  float m[3][3], mi[3][3], white[3], inv_white[3];
   float qc, qf, pc, pt, eps, cmax;
 };
 

@@ -27,6 +27,12 @@ namespace {
 
 constexpr int kFB = 256;
 
+// x^y for x > 0 through the hardware base-2 logarithm and exponential
+// (about 1 ulp each); x = 0 gives 0 for y > 0
+__device__ __forceinline__ float fpow(float x, float y) {
+  return x > 0.0f ? __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x)) : 0.0f;
+}
+
 __device__ __forceinline__ int flip_view(const FlipViews& fv) {
   int v = 0;
   for (int q = 1; q < fv.n_views; ++q)
@@ -61,10 +67,11 @@ __device__ __forceinline__ Px px_of(const FlipViews& fv) {
 }
 
 __device__ __forceinline__ float srgb_lin(float c) {
-  return c > 0.04045f ? powf((c + 0.055f) / 1.055f, 2.4f) : c / 12.92f;
+  return c > 0.04045f ? fpow((c + 0.055f) * (1.0f / 1.055f), 2.4f) : c * (1.0f / 12.92f);
 }
 __device__ __forceinline__ float srgb_lin_d(float c) {
-  return c > 0.04045f ? (2.4f / 1.055f) * powf((c + 0.055f) / 1.055f, 1.4f) : 1.0f / 12.92f;
+  return c > 0.04045f ? (2.4f / 1.055f) * fpow((c + 0.055f) * (1.0f / 1.055f), 1.4f)
+                      : 1.0f / 12.92f;
 }
 
 // sRGB (clamped) -> YCxCz
@@ -73,7 +80,7 @@ __device__ __forceinline__ void to_ycxcz(const FlipConst& k, const float* rgb, f
   for (int c = 0; c < 3; ++c) l[c] = srgb_lin(fminf(fmaxf(rgb[c], 0.f), 1.f));
   float n[3];
   for (int i = 0; i < 3; ++i)
-    n[i] = (k.m[i][0] * l[0] + k.m[i][1] * l[1] + k.m[i][2] * l[2]) / k.white[i];
+    n[i] = (k.m[i][0] * l[0] + k.m[i][1] * l[1] + k.m[i][2] * l[2]) * k.inv_white[i];
   o[0] = 116.f * n[1] - 16.f;
   o[1] = 500.f * (n[0] - n[1]);
   o[2] = 200.f * (n[1] - n[2]);
@@ -151,11 +158,11 @@ struct Colour {
 
 __device__ __forceinline__ float lab_f(float t) {
   const float d = 6.f / 29.f;
-  return t > d * d * d ? cbrtf(t) : t / (3.f * d * d) + 4.f / 29.f;
+  return t > d * d * d ? fpow(t, 1.f / 3.f) : t * (1.f / (3.f * d * d)) + 4.f / 29.f;
 }
 __device__ __forceinline__ float lab_fd(float t) {
   const float d = 6.f / 29.f;
-  return t > d * d * d ? (1.f / 3.f) / (cbrtf(t) * cbrtf(t)) : 1.f / (3.f * d * d);
+  return t > d * d * d ? (1.f / 3.f) * fpow(t, -2.f / 3.f) : 1.f / (3.f * d * d);
 }
 
 __device__ __forceinline__ Colour colour_of(const FlipConst& k, float Y, float Cx, float Cz) {
@@ -169,7 +176,7 @@ __device__ __forceinline__ Colour colour_of(const FlipConst& k, float Y, float C
     l[i] = fminf(fmaxf(c.rgb[i], 0.f), 1.f);
   }
   for (int i = 0; i < 3; ++i)
-    c.n[i] = (k.m[i][0] * l[0] + k.m[i][1] * l[1] + k.m[i][2] * l[2]) / k.white[i];
+    c.n[i] = (k.m[i][0] * l[0] + k.m[i][1] * l[1] + k.m[i][2] * l[2]) * k.inv_white[i];
   const float fx = lab_f(c.n[0]), fy = lab_f(c.n[1]), fz = lab_f(c.n[2]);
   c.Lr = 116.f * fy - 16.f;
   c.ar = 500.f * (fx - fy);
@@ -193,7 +200,7 @@ __device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf
   const float rr = da * da + db * db;
   const float root = sqrtf(fmaxf(rr, k.eps));
   const float hy = fabsf(dL) + root;
-  const float e = powf(hy, k.qc);
+  const float e = fpow(hy, k.qc);
   const float pcc = k.pc * k.cmax;
   const bool low = e < pcc;
   const float dEc = low ? (k.pt / pcc) * e : k.pt + ((e - pcc) / (k.cmax - pcc)) * (1.f - k.pt);
@@ -205,13 +212,13 @@ __device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf
   const float d1 = fabsf(er - et), d2 = fabsf(pr - pt);
   const float mraw = fmaxf(d1, d2);
   const float m = fmaxf(mraw, k.eps);
-  const float dF = powf(m * 0.70710678118654752f, k.qf);
-  const float val = powf(dEc, 1.f - dF);
+  const float dF = fpow(m * 0.70710678118654752f, k.qf);
+  const float val = fpow(dEc, 1.f - dF);
   // seeds: dval/d(filtered Y, Cx, Cz of the test), dval/d(ex, ey, px, py)
-  const float g_dEc = (1.f - dF) * powf(dEc, -dF);
-  const float g_dF = -val * logf(dEc);
+  const float g_dEc = (1.f - dF) * fpow(dEc, -dF);
+  const float g_dF = -val * (0.69314718055994531f * __builtin_amdgcn_logf(dEc));
   const float g_e = g_dEc * (low ? k.pt / pcc : (1.f - k.pt) / (k.cmax - pcc));
-  const float g_hy = g_e * k.qc * powf(hy, k.qc - 1.f);
+  const float g_hy = g_e * k.qc * fpow(hy, k.qc - 1.f);
   // d hy / d (test L, a, b) (Hunt-adjusted); the root is floored at eps
   const float sgn = dL > 0.f ? 1.f : (dL < 0.f ? -1.f : 0.f);
   float gL = -g_hy * sgn;
@@ -228,7 +235,7 @@ __device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf
   float grgb[3];
   for (int j = 0; j < 3; ++j) {
     float s = 0.f;
-    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] * k.inv_white[i];
     grgb[j] = (t.rgb[j] >= 0.f && t.rgb[j] <= 1.f) ? s : 0.f;
   }
   // rgb = Mi xyz(Y, Cx, Cz)
@@ -362,7 +369,7 @@ __global__ __launch_bounds__(kFB) void k_flip_grad(FlipViews fv, FlipFilt f, Fli
   const float sc = scale / (float)q.plane;
   for (int j = 0; j < 3; ++j) {
     float s = 0.f;
-    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] * k.inv_white[i];
     const int64_t e = q.e0 + j * q.plane;
     const float x = test[e];
     const float g = (x >= 0.f && x <= 1.f) ? s * srgb_lin_d(x) : 0.f;
@@ -385,6 +392,9 @@ __global__ void k_flip_reduce(FlipViews fv, const float* __restrict__ blk,
 
 constexpr int kFTX = 32, kFTY = 8, kFlipHalo = 10;
 constexpr int kFRX = kFTX + 2 * kFlipHalo, kFRY = kFTY + 2 * kFlipHalo;
+// row pitch of the staged forward input: = 1 mod 4, so the horizontal
+// pass's items (four adjacent columns each, eight per row) hit distinct banks
+constexpr int kFRXP = kFRX + 1;
 
 struct FTile {
   int v, x0, y0, W, H;
@@ -425,7 +435,7 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
                                                         float* __restrict__ seed, int64_t P,
                                                         float* __restrict__ blk) {
   __shared__ float s_w[7][kFTap];
-  __shared__ float s_in[3][kFRY][kFRX];
+  __shared__ float s_in[3][kFRY][kFRXP];
   __shared__ float s_h[7][kFRY][kFTX];
   __shared__ float s_red[kFB / 64];
   const FTile T = ftile(fv);
@@ -445,23 +455,44 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
       s_in[2][r][c] = src[2 * P + e];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kFRY * kFTX; i += kFB) {
-      const int r = i / kFTX, c = i - r * kFTX;
-      float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // horizontal passes, four adjacent outputs per item sharing their taps
+    for (int i = threadIdx.x; i < kFRY * (kFTX / 4); i += kFB) {
+      const int r = i / (kFTX / 4), c0 = (i - r * (kFTX / 4)) * 4;
+      float dY[kFTap + 3], dX[kFTap + 3], dZ[kFTap + 3];
+#pragma unroll
+      for (int j = 0; j < kFTap + 3; ++j) {
+        dY[j] = s_in[0][r][c0 + j];
+        dX[j] = s_in[1][r][c0 + j];
+        dZ[j] = s_in[2][r][c0 + j];
+      }
+      float a[4][7];
+#pragma unroll
+      for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) a[o][m] = 0.f;
 #pragma unroll
       for (int j = 0; j < kFTap; ++j) {
-        const float Y = s_in[0][r][c + j], cz = s_in[2][r][c + j];
-        const float yn = (Y + 16.f) * (1.f / 116.f);
-        a[0] += s_w[0][j] * Y;
-        a[1] += s_w[1][j] * s_in[1][r][c + j];
-        a[2] += s_w[2][j] * cz;
-        a[3] += s_w[3][j] * cz;
-        a[4] += s_w[5][j] * yn;  // edge profile along x
-        a[5] += s_w[4][j] * yn;  // Gaussian along x
-        a[6] += s_w[6][j] * yn;  // point profile along x
+        const float w0 = s_w[0][j], w1 = s_w[1][j], w2 = s_w[2][j], w3 = s_w[3][j];
+        const float w4 = s_w[4][j], w5 = s_w[5][j], w6 = s_w[6][j];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          // the feature passes run on Y: every feature kernel sums to zero,
+          // so on the normalised luminance (Y + 16) / 116 they give the
+          // same responses divided by 116 (applied after the vertical pass)
+          const float Y = dY[j + o], cz = dZ[j + o];
+          a[o][0] += w0 * Y;
+          a[o][1] += w1 * dX[j + o];
+          a[o][2] += w2 * cz;
+          a[o][3] += w3 * cz;
+          a[o][4] += w5 * Y;  // edge profile along x
+          a[o][5] += w4 * Y;  // Gaussian along x
+          a[o][6] += w6 * Y;  // point profile along x
+        }
       }
 #pragma unroll
-      for (int m = 0; m < 7; ++m) s_h[m][r][c] = a[m];
+      for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) s_h[m][r][c0 + o] = a[o][m];
     }
     __syncthreads();
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -480,10 +511,10 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
     cf[im][0] = v[0];
     cf[im][1] = v[1];
     cf[im][2] = f.c1 * v[2] + f.c2 * v[3];
-    fe[im][0] = v[4];
-    fe[im][1] = v[5];
-    fe[im][2] = v[6];
-    fe[im][3] = v[7];
+    fe[im][0] = v[4] * (1.f / 116.f);
+    fe[im][1] = v[5] * (1.f / 116.f);
+    fe[im][2] = v[6] * (1.f / 116.f);
+    fe[im][3] = v[7] * (1.f / 116.f);
     __syncthreads();
   }
   float val = 0.f;
@@ -590,7 +621,7 @@ __global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f,
   const int64_t e0 = 3 * T.pix0 + (int64_t)y * T.W + x;
   for (int j = 0; j < 3; ++j) {
     float s = 0.f;
-    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] / k.white[i];
+    for (int i = 0; i < 3; ++i) s += k.m[i][j] * gn[i] * k.inv_white[i];
     const int64_t e = e0 + j * plane;
     const float xv = test[e];
     const float g = (xv >= 0.f && xv <= 1.f) ? s * srgb_lin_d(xv) : 0.f;

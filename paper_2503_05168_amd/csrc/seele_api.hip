@@ -1395,6 +1395,7 @@ int32_t flip_setup(float ppd, FlipHost& h) {
   FlipConst& k = h.k;
   for (int i = 0; i < 3; ++i) {
     k.white[i] = (float)white[i];
+    k.inv_white[i] = (float)(1.0 / white[i]);
     for (int j = 0; j < 3; ++j) {
       k.m[i][j] = (float)m[i * 3 + j];
       k.mi[i][j] = (float)mi[i * 3 + j];
