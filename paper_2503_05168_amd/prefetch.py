@@ -138,8 +138,11 @@ class PrefetchingRenderer:
         assert host.shape == (ROWS, n) and host.is_pinned()
         self.host = host
         self.n_pool = self.n_shared + self.S * self.slot_cap
-        self.pool = torch.zeros((ROWS, max(self.n_pool, 1)), dtype=torch.float32, device=dev)
+        # only loaded columns are ever read (segments cover loaded clusters)
+        self.pool = torch.empty((ROWS, max(self.n_pool, 1)), dtype=torch.float32, device=dev)
         self.copy_stream = torch.cuda.Stream(device=dev)
+        # the copies follow everything already queued on the caller's stream
+        self.copy_stream.wait_stream(torch.cuda.current_stream(dev))
         if self.n_shared:
             seele_load_segments(self.host, self.pool, [0], [0], [self.n_shared], self.copy_stream)
         self.g = table_gaussians(self.pool, g.sh_degree)
