@@ -129,11 +129,13 @@ __global__ __launch_bounds__(kLossBlock) void k_ssim_fwd(LossViews lv, Win win,
     const float sx = m[2] - mx * mx, sy = m[3] - my * my, sxy = m[4] - mx * my;
     const float a1 = 2.f * mx * my + C1, a2 = 2.f * sxy + C2;
     const float b1 = mx * mx + my * my + C1, b2 = sx + sy + C2;
-    const float inv = 1.f / (b1 * b2);
+    // hardware reciprocals (about 1 ulp)
+    const float ib1 = __builtin_amdgcn_rcpf(b1), ib2 = __builtin_amdgcn_rcpf(b2);
+    const float inv = ib1 * ib2;
     const float S = a1 * a2 * inv;
     const int64_t o = j.base + (int64_t)y * j.W + x;
-    part[o] = 2.f * my * (a2 - a1) * inv - 2.f * mx * S * (1.f / b1 - 1.f / b2);
-    part[stride + o] = -S / b2;
+    part[o] = 2.f * my * (a2 - a1) * inv - 2.f * mx * S * (ib1 - ib2);
+    part[stride + o] = -S * ib2;
     part[2 * stride + o] = 2.f * a1 * inv;
     ssum += S;
     lsum += fabsf(s_in[0][oy + kHalf][ox + kHalf] - s_in[1][oy + kHalf][ox + kHalf]);

@@ -48,6 +48,7 @@ struct FlipFilt {
 struct FlipConst {
   float m[3][3], mi[3][3], white[3], inv_white[3];
   float qc, qf, pc, pt, eps, cmax;
+  float lo_slope, hi_slope;  // pt / (pc cmax) and (1 - pt) / (cmax - pc cmax)
 };
 
 int64_t flip_blocks(int w, int h);

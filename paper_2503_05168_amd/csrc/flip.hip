@@ -33,6 +33,9 @@ __device__ __forceinline__ float fpow(float x, float y) {
   return x > 0.0f ? __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x)) : 0.0f;
 }
 
+// 1 / x through the hardware reciprocal (about 1 ulp)
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ int flip_view(const FlipViews& fv) {
   int v = 0;
   for (int q = 1; q < fv.n_views; ++q)
@@ -167,9 +170,9 @@ __device__ __forceinline__ float lab_fd(float t) {
 
 __device__ __forceinline__ Colour colour_of(const FlipConst& k, float Y, float Cx, float Cz) {
   Colour c{};
-  const float yy = (Y + 16.f) / 116.f;
-  const float xyz[3] = {k.white[0] * (Cx / 500.f + yy), k.white[1] * yy,
-                        k.white[2] * (yy - Cz / 200.f)};
+  const float yy = (Y + 16.f) * (1.f / 116.f);
+  const float xyz[3] = {k.white[0] * (Cx * (1.f / 500.f) + yy), k.white[1] * yy,
+                        k.white[2] * (yy - Cz * (1.f / 200.f))};
   float l[3];
   for (int i = 0; i < 3; ++i) {
     c.rgb[i] = k.mi[i][0] * xyz[0] + k.mi[i][1] * xyz[1] + k.mi[i][2] * xyz[2];
@@ -203,7 +206,7 @@ __device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf
   const float e = fpow(hy, k.qc);
   const float pcc = k.pc * k.cmax;
   const bool low = e < pcc;
-  const float dEc = low ? (k.pt / pcc) * e : k.pt + ((e - pcc) / (k.cmax - pcc)) * (1.f - k.pt);
+  const float dEc = low ? k.lo_slope * e : k.pt + (e - pcc) * k.hi_slope;
   // feature error
   const float et = sqrtf(fe[0][0] * fe[0][0] + fe[0][1] * fe[0][1]);
   const float er = sqrtf(fe[1][0] * fe[1][0] + fe[1][1] * fe[1][1]);
@@ -217,13 +220,14 @@ __device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf
   // seeds: dval/d(filtered Y, Cx, Cz of the test), dval/d(ex, ey, px, py)
   const float g_dEc = (1.f - dF) * fpow(dEc, -dF);
   const float g_dF = -val * (0.69314718055994531f * __builtin_amdgcn_logf(dEc));
-  const float g_e = g_dEc * (low ? k.pt / pcc : (1.f - k.pt) / (k.cmax - pcc));
+  const float g_e = g_dEc * (low ? k.lo_slope : k.hi_slope);
   const float g_hy = g_e * k.qc * fpow(hy, k.qc - 1.f);
   // d hy / d (test L, a, b) (Hunt-adjusted); the root is floored at eps
   const float sgn = dL > 0.f ? 1.f : (dL < 0.f ? -1.f : 0.f);
   float gL = -g_hy * sgn;
-  float ga = rr > k.eps ? -g_hy * da / root : 0.f;
-  float gb = rr > k.eps ? -g_hy * db / root : 0.f;
+  const float ir = frcp(root);
+  float ga = rr > k.eps ? -g_hy * da * ir : 0.f;
+  float gb = rr > k.eps ? -g_hy * db * ir : 0.f;
   // Hunt: a' = L a / 100, b' = L b / 100
   const float gLr = gL + 0.01f * (t.ar * ga + t.br * gb);
   const float gar = 0.01f * t.Lr * ga, gbr = 0.01f * t.Lr * gb;
@@ -244,23 +248,25 @@ __device__ __forceinline__ float flip_pixel(const FlipConst& k, const float (*cf
     gxyz[j] = k.mi[0][j] * grgb[0] + k.mi[1][j] * grgb[1] + k.mi[2][j] * grgb[2];
   // xyz = white * (Cx/500 + yy, yy, yy - Cz/200), yy = (Y + 16)/116
   const float gyy = k.white[0] * gxyz[0] + k.white[1] * gxyz[1] + k.white[2] * gxyz[2];
-  sd[0] = gyy / 116.f;
-  sd[1] = k.white[0] * gxyz[0] / 500.f;
-  sd[2] = -k.white[2] * gxyz[2] / 200.f;
+  sd[0] = gyy * (1.f / 116.f);
+  sd[1] = k.white[0] * gxyz[0] * (1.f / 500.f);
+  sd[2] = -k.white[2] * gxyz[2] * (1.f / 200.f);
   // features
-  const float g_m = mraw > k.eps ? g_dF * k.qf * dF / m : 0.f;
+  const float g_m = mraw > k.eps ? g_dF * k.qf * dF * frcp(m) : 0.f;
   float gex = 0.f, gey = 0.f, gpx = 0.f, gpy = 0.f;
   if (d1 >= d2) {
     const float g_et = -g_m * ((er - et) > 0.f ? 1.f : ((er - et) < 0.f ? -1.f : 0.f));
     if (et > 0.f) {
-      gex = g_et * fe[0][0] / et;
-      gey = g_et * fe[0][1] / et;
+      const float ie = frcp(et);
+      gex = g_et * fe[0][0] * ie;
+      gey = g_et * fe[0][1] * ie;
     }
   } else {
     const float g_pt = -g_m * ((pr - pt) > 0.f ? 1.f : ((pr - pt) < 0.f ? -1.f : 0.f));
     if (pt > 0.f) {
-      gpx = g_pt * fe[0][2] / pt;
-      gpy = g_pt * fe[0][3] / pt;
+      const float ip = frcp(pt);
+      gpx = g_pt * fe[0][2] * ip;
+      gpy = g_pt * fe[0][3] * ip;
     }
   }
   sd[3] = gex;

@@ -1414,6 +1414,8 @@ int32_t flip_setup(float ppd, FlipHost& h) {
                     std::sqrt(std::max((lg[1] - lb[1]) * (lg[1] - lb[1]) +
                                        (lg[2] - lb[2]) * (lg[2] - lb[2]), 1e-15));
   k.cmax = (float)std::pow(hy, 0.7);
+  k.lo_slope = (float)(0.95 / (0.4 * (double)k.cmax));
+  k.hi_slope = (float)((1.0 - 0.95) / ((double)k.cmax - 0.4 * (double)k.cmax));
   return SEELE_OK;
 }
 
