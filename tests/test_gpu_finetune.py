@@ -56,10 +56,11 @@ def test_photometric_loss_matches_oracle(name, kind):
             off += n
 
 
-def test_adam_matches_oracle():
-    gu.log("[case] adam")
+@pytest.mark.parametrize("n", [1003, 1024])
+def test_adam_matches_oracle(n):
+    """n = 1003 runs the scalar kernel, n = 1024 the four-wide one."""
+    gu.log(f"[case] adam n={n}")
     rng = np.random.default_rng(9)
-    n = 1003
     for deg in (3, 1):
         p = GaussianTensors.from_arrays(synthetic.ball_scene(3, n, sh_degree=deg))
         p0 = {k: getattr(p, k).clone() for k in ("means", "log_scales", "quats", "opacity_logits",
