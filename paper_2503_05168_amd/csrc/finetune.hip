@@ -207,17 +207,31 @@ __global__ __launch_bounds__(kLossBlock) void k_ssim_bwd(LossViews lv, Win win,
 
 // per view: loss = (1 - lambda) mean|x - y| + lambda (1 - mean S), the block
 // sums added in block order
-__global__ void k_loss_reduce(LossViews lv, const float* __restrict__ blk, float lambda,
-                              float* __restrict__ loss) {
+__global__ __launch_bounds__(kLossBlock) void k_loss_reduce(LossViews lv,
+                                                             const float* __restrict__ blk,
+                                                             float lambda,
+                                                             float* __restrict__ loss) {
+  __shared__ double s_r[2][kLossBlock / 64];
   const int v = blockIdx.x;
   double s = 0.0, l = 0.0;
-  for (int b = lv.blk_off[v] + (int)threadIdx.x; b < lv.blk_off[v + 1]; b += 64) {
+  for (int b = lv.blk_off[v] + (int)threadIdx.x; b < lv.blk_off[v + 1]; b += kLossBlock) {
     s += (double)blk[2 * b];
     l += (double)blk[2 * b + 1];
   }
   s = wave_sum(s);
   l = wave_sum(l);
+  if ((threadIdx.x & 63) == 0) {
+    s_r[0][threadIdx.x >> 6] = s;
+    s_r[1][threadIdx.x >> 6] = l;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    s = 0.0;
+    l = 0.0;
+    for (int w = 0; w < kLossBlock / 64; ++w) {
+      s += s_r[0][w];
+      l += s_r[1][w];
+    }
     const double n = 3.0 * (double)lv.w[v] * (double)lv.h[v];
     loss[v] = (float)((1.0 - (double)lambda) * l / n + (double)lambda * (1.0 - s / n));
   }
@@ -304,8 +318,8 @@ hipError_t launch_photometric_loss(const LossViews& lv, int n_blocks, const floa
   hipLaunchKernelGGL(k_ssim_fwd, grid, block, 0, stream, lv, win, img, tgt, maps, stride, blk);
   hipLaunchKernelGGL(k_ssim_bwd, grid, block, 0, stream, lv, win, img, tgt, maps, stride, lambda,
                      inv_views, grad);
-  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)lv.n_views), dim3(64), 0, stream, lv, blk,
-                     lambda, loss);
+  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)lv.n_views), dim3(kLossBlock), 0, stream, lv,
+                     blk, lambda, loss);
   return hipGetLastError();
 }
 

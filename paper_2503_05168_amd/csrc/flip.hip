@@ -383,13 +383,20 @@ __global__ __launch_bounds__(kFB) void k_flip_grad(FlipViews fv, FlipFilt f, Fli
   }
 }
 
-__global__ void k_flip_reduce(FlipViews fv, const float* __restrict__ blk,
-                              float* __restrict__ out) {
+__global__ __launch_bounds__(kFB) void k_flip_reduce(FlipViews fv, const float* __restrict__ blk,
+                                                      float* __restrict__ out) {
+  __shared__ double s_r[kFB / 64];
   const int v = blockIdx.x;
   double s = 0.0;
-  for (int b = fv.blk_off[v] + (int)threadIdx.x; b < fv.blk_off[v + 1]; b += 64) s += blk[b];
+  for (int b = fv.blk_off[v] + (int)threadIdx.x; b < fv.blk_off[v + 1]; b += kFB) s += blk[b];
   s = wave_sum(s);
-  if (threadIdx.x == 0) out[v] = (float)(s / ((double)fv.w[v] * (double)fv.h[v]));
+  if ((threadIdx.x & 63) == 0) s_r[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s = 0.0;
+    for (int w = 0; w < kFB / 64; ++w) s += s_r[w];
+    out[v] = (float)(s / ((double)fv.w[v] * (double)fv.h[v]));
+  }
 }
 
 // ---- tiled path (filter radii <= kFlipHalo): one workgroup per 32 x 8
@@ -664,7 +671,7 @@ hipError_t launch_flip_tiled(const FlipViews& fv, int n_blocks, const FlipFilt& 
   hipLaunchKernelGGL(k_flip_fwd_tile, grid, block, 0, stream, fv, f, k, o, seed, P, blk);
   hipLaunchKernelGGL(k_flip_bwd_tile, grid, block, 0, stream, fv, f, k, test, seed, P, scale,
                      accumulate ? 1 : 0, grad);
-  hipLaunchKernelGGL(k_flip_reduce, dim3((unsigned)fv.n_views), dim3(64), 0, stream, fv, blk, out);
+  hipLaunchKernelGGL(k_flip_reduce, dim3((unsigned)fv.n_views), dim3(kFB), 0, stream, fv, blk, out);
   return hipGetLastError();
 }
 
@@ -682,7 +689,7 @@ hipError_t launch_flip(const FlipViews& fv, int n_blocks, const FlipFilt& f, con
   hipLaunchKernelGGL(k_flip_vadj, grid, block, 0, stream, fv, f, seed, P, h);
   hipLaunchKernelGGL(k_flip_grad, grid, block, 0, stream, fv, f, k, test, h, P, scale,
                      accumulate ? 1 : 0, grad);
-  hipLaunchKernelGGL(k_flip_reduce, dim3((unsigned)fv.n_views), dim3(64), 0, stream, fv, blk, out);
+  hipLaunchKernelGGL(k_flip_reduce, dim3((unsigned)fv.n_views), dim3(kFB), 0, stream, fv, blk, out);
   return hipGetLastError();
 }
 
