@@ -99,11 +99,11 @@ __global__ __launch_bounds__(kLossBlock) void k_ssim_fwd(LossViews lv, Win win,
 #pragma unroll
     for (int t = 0; t < kTap; ++t) {
       const float a = s_in[0][r][c + t], b = s_in[1][r][c + t], w = win.w[t];
-      h0 += w * a;
-      h1 += w * b;
-      h2 += w * (a * a);
-      h3 += w * (b * b);
-      h4 += w * (a * b);
+      h0 = __builtin_fmaf(w, a, h0);
+      h1 = __builtin_fmaf(w, b, h1);
+      h2 = __builtin_fmaf(w, a * a, h2);
+      h3 = __builtin_fmaf(w, b * b, h3);
+      h4 = __builtin_fmaf(w, a * b, h4);
     }
     s_h[0][r][c] = h0;
     s_h[1][r][c] = h1;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kLossBlock) void k_ssim_fwd(LossViews lv, Win win,
     for (int t = 0; t < kTap; ++t) {
       const float w = win.w[t];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) m[k] += w * s_h[k][oy + t][ox];
+      for (int k = 0; k < 5; ++k) m[k] = __builtin_fmaf(w, s_h[k][oy + t][ox], m[k]);
     }
     const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
     const float mx = m[0], my = m[1];
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kLossBlock) void k_ssim_bwd(LossViews lv, Win win,
     for (int t = 0; t < kTap; ++t) {
       const float w = win.w[t];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) h[k] += w * s_in[k][r][c + t];
+      for (int k = 0; k < 3; ++k) h[k] = __builtin_fmaf(w, s_in[k][r][c + t], h[k]);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) s_h[k][r][c] = h[k];
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kLossBlock) void k_ssim_bwd(LossViews lv, Win win,
     for (int t = 0; t < kTap; ++t) {
       const float w = win.w[t];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) g[k] += w * s_h[k][oy + t][ox];
+      for (int k = 0; k < 3; ++k) g[k] = __builtin_fmaf(w, s_h[k][oy + t][ox], g[k]);
     }
     const int64_t o = j.base + (int64_t)y * j.W + x;
     const float xv = img[o], yv = tgt[o];

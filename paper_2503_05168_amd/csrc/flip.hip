@@ -493,13 +493,13 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
           // so on the normalised luminance (Y + 16) / 116 they give the
           // same responses divided by 116 (applied after the vertical pass)
           const float Y = dY[j + o], cz = dZ[j + o];
-          a[o][0] += w0 * Y;
-          a[o][1] += w1 * dX[j + o];
-          a[o][2] += w2 * cz;
-          a[o][3] += w3 * cz;
-          a[o][4] += w5 * Y;  // edge profile along x
-          a[o][5] += w4 * Y;  // Gaussian along x
-          a[o][6] += w6 * Y;  // point profile along x
+          a[o][0] = __builtin_fmaf(w0, Y, a[o][0]);
+          a[o][1] = __builtin_fmaf(w1, dX[j + o], a[o][1]);
+          a[o][2] = __builtin_fmaf(w2, cz, a[o][2]);
+          a[o][3] = __builtin_fmaf(w3, cz, a[o][3]);
+          a[o][4] = __builtin_fmaf(w5, Y, a[o][4]);  // edge profile along x
+          a[o][5] = __builtin_fmaf(w4, Y, a[o][5]);  // Gaussian along x
+          a[o][6] = __builtin_fmaf(w6, Y, a[o][6]);  // point profile along x
         }
       }
 #pragma unroll
@@ -512,14 +512,14 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
 #pragma unroll
     for (int j = 0; j < kFTap; ++j) {
       const int ry = oy + j;
-      v[0] += s_w[0][j] * s_h[0][ry][ox];
-      v[1] += s_w[1][j] * s_h[1][ry][ox];
-      v[2] += s_w[2][j] * s_h[2][ry][ox];
-      v[3] += s_w[3][j] * s_h[3][ry][ox];
-      v[4] += s_w[4][j] * s_h[4][ry][ox];  // ex: edge along x, Gaussian along y
-      v[5] += s_w[5][j] * s_h[5][ry][ox];  // ey: Gaussian along x, edge along y
-      v[6] += s_w[4][j] * s_h[6][ry][ox];  // px
-      v[7] += s_w[6][j] * s_h[5][ry][ox];  // py
+      v[0] = __builtin_fmaf(s_w[0][j], s_h[0][ry][ox], v[0]);
+      v[1] = __builtin_fmaf(s_w[1][j], s_h[1][ry][ox], v[1]);
+      v[2] = __builtin_fmaf(s_w[2][j], s_h[2][ry][ox], v[2]);
+      v[3] = __builtin_fmaf(s_w[3][j], s_h[3][ry][ox], v[3]);
+      v[4] = __builtin_fmaf(s_w[4][j], s_h[4][ry][ox], v[4]);  // ex: edge x, Gaussian y
+      v[5] = __builtin_fmaf(s_w[5][j], s_h[5][ry][ox], v[5]);  // ey: Gaussian x, edge y
+      v[6] = __builtin_fmaf(s_w[4][j], s_h[6][ry][ox], v[6]);  // px
+      v[7] = __builtin_fmaf(s_w[6][j], s_h[5][ry][ox], v[7]);  // py
     }
     cf[im][0] = v[0];
     cf[im][1] = v[1];
@@ -558,7 +558,7 @@ __device__ __forceinline__ float adj1d(const float* w, int i, int n, const float
   if (i > 0 && i < n - 1) {
     const float* gi = g + (base + i + kFlipHalo) * stride;
 #pragma unroll
-    for (int j = 0; j < kFTap; ++j) s += w[j] * gi[-j * stride];
+    for (int j = 0; j < kFTap; ++j) s = __builtin_fmaf(w[j], gi[-j * stride], s);
     return s;
   }
   const int p0 = max(i - kFlipHalo, 0), p1 = min(i + kFlipHalo, n - 1);
