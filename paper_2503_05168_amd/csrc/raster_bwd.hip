@@ -121,8 +121,12 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
     const float rom = __builtin_amdgcn_rcpf(om);  // 1 - alpha >= 1 - alpha_max > 0
     const float Tj = T * rom;
     const float ta = Tj * alpha;
-    const float dal = g0 * (Tj * b.z - S0 * rom) + g1 * (Tj * b.w - S1 * rom) +
-                      g2 * (Tj * cc.x - S2 * rom);
+    // fused multiply-adds from here on: the gradient chain needs no
+    // bit-identity with the forward (only alpha and the decisions do)
+    const float dal = __builtin_fmaf(
+        g2, __builtin_fmaf(Tj, cc.x, -S2 * rom),
+        __builtin_fmaf(g1, __builtin_fmaf(Tj, b.w, -S1 * rom),
+                       g0 * __builtin_fmaf(Tj, b.z, -S0 * rom)));
     gr = ta * g0;
     gg = ta * g1;
     gbl = ta * g2;
@@ -134,8 +138,8 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
       gop = dal * raw * e.inv_o;  // d alpha / d o = alpha / o below the clamp
       const float dq = -0.5f * alpha * dal;  // dL/dq
       // q = a dx^2 + 2 b dx dy + c dy^2 with d = pixel - mean: dq/dmean = -2 A d
-      gmx = -2.0f * dq * (cc.y * dx + cc.z * dy);
-      gmy = -2.0f * dq * (cc.z * dx + cc.w * dy);
+      gmx = -2.0f * dq * __builtin_fmaf(cc.y, dx, cc.z * dy);
+      gmy = -2.0f * dq * __builtin_fmaf(cc.z, dx, cc.w * dy);
       gca = dq * dx * dx;
       gcb = dq * 2.0f * dx * dy;
       gcc = dq * dy * dy;
