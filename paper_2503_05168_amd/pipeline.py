@@ -572,32 +572,25 @@ class Renderer:
                stream=None) -> Frame:
         s = self.settings
         keys = None
-        if self.lists != "super":
-            splats, n_tiles = seele_preprocess(g, cams, s, segments, stream=stream)
+        sup = self.lists == "super"
         while True:
-            if self.lists == "super":
-                # preprocessing stages the binning input in the workspace, whose
-                # layout depends on the capacity: both run again on regrowth
-                dev = g.means.device
-                V, TT = len(cams), total_tiles(cams, s.tile)
-                ws_bytes = bin_sort_workspace_size(V * g.n, self.capacity, TT)
-                if self._ws is None or self._ws.numel() < ws_bytes:
-                    self._ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
-                splats, n_tiles = seele_preprocess_staged(g, cams, s, self.capacity, self._ws,
-                                                          segments, stream=stream)
-                cap = max(self.capacity, 1)
-                keys = torch.empty(cap, dtype=torch.int32, device=dev)
-                ids = torch.empty(cap, dtype=torch.int32, device=dev)
-                ranges = torch.empty((total_super_tiles(cams, s.tile), 2), dtype=torch.int32,
-                                     device=dev)
-                npairs = torch.empty(1, dtype=torch.int64, device=dev)
-                seele_bin_sort_ex(splats, n_tiles, g.n, cams, s.tile, self.capacity, self._ws,
-                                  ids, ranges, npairs, keys, super_lists=True, staged=True,
-                                  stream=stream)
-            else:
-                ids, ranges, npairs, self._ws = seele_bin_sort(splats, n_tiles, g.n, cams,
-                                                               s.tile, self.capacity, self._ws,
-                                                               stream=stream)
+            # preprocessing stages the binning input in the workspace, whose
+            # layout depends on the capacity: both run again on regrowth
+            dev = g.means.device
+            V, TT = len(cams), total_tiles(cams, s.tile)
+            ws_bytes = bin_sort_workspace_size(V * g.n, self.capacity, TT)
+            if self._ws is None or self._ws.numel() < ws_bytes:
+                self._ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+            splats, n_tiles = seele_preprocess_staged(g, cams, s, self.capacity, self._ws,
+                                                      segments, stream=stream)
+            cap = max(self.capacity, 1)
+            keys = torch.empty(cap, dtype=torch.int32, device=dev) if sup else None
+            ids = torch.empty(cap, dtype=torch.int32, device=dev)
+            ranges = torch.empty((total_super_tiles(cams, s.tile) if sup else TT, 2),
+                                 dtype=torch.int32, device=dev)
+            npairs = torch.empty(1, dtype=torch.int64, device=dev)
+            seele_bin_sort_ex(splats, n_tiles, g.n, cams, s.tile, self.capacity, self._ws, ids,
+                              ranges, npairs, keys, super_lists=sup, staged=True, stream=stream)
             if not check:
                 break
             need = int(npairs.item())
