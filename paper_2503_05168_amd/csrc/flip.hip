@@ -443,7 +443,30 @@ __device__ __forceinline__ void load_weights(const FlipFilt& f, float (*w)[kFTap
   }
 }
 
-__global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f, FlipConst k,
+// Per filter, the sums of its zero-padded taps up to and from each index:
+// cs[m][0][t] = w[0] + ... + w[t] and cs[m][1][t] = w[t] + ... + w[kFTap-1],
+// both added in increasing tap order.
+__device__ __forceinline__ void load_tap_sums(const FlipFilt& f, float (*cs)[2][kFTap]) {
+  for (int i = threadIdx.x; i < 7 * kFTap; i += kFB) {
+    const int m = i / kFTap, t = i - m * kFTap;
+    const int r = m < 4 ? f.rc : f.rf;
+    const float* src = m == 0 ? f.gA : m == 1 ? f.gRG : m == 2 ? f.u1 : m == 3 ? f.u2
+                     : m == 4 ? f.gn : m == 5 ? f.fe : f.fp;
+    float pre = 0.f, suf = 0.f;
+    for (int j = 0; j < kFTap; ++j) {
+      const int d = j - kFlipHalo;
+      const float wj = (d >= -r && d <= r) ? src[d + r] : 0.0f;
+      if (j <= t) pre += wj;
+      if (j >= t) suf += wj;
+    }
+    cs[m][0][t] = pre;
+    cs[m][1][t] = suf;
+  }
+}
+
+// At most 168 VGPRs (3 waves per SIMD), the occupancy the kernel's LDS
+// allows; without the bound the compiler takes 182 and runs 2.
+__global__ __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(3))) void k_flip_fwd_tile(FlipViews fv, FlipFilt f, FlipConst k,
                                                         const float* __restrict__ o,
                                                         float* __restrict__ seed, int64_t P,
                                                         float* __restrict__ blk) {
@@ -550,10 +573,13 @@ __global__ __launch_bounds__(kFB) void k_flip_fwd_tile(FlipViews fv, FlipFilt f,
 // Adjoint of an edge-replicated 1D correlation at input position i of n,
 // from the outputs g(p) at LDS positions (base + p) * stride, which hold
 // zero for p outside the image: interior positions take sum_t w[t] g(i - t)
-// over the whole staged window; the two border positions also take the
-// weights of every tap that the replication folded onto them.
-__device__ __forceinline__ float adj1d(const float* w, int i, int n, const float* g, int base,
-                                       int stride) {
+// over the whole staged window.  A border position also takes every tap that
+// the replication folded onto it: output p reaches input 0 through its taps
+// t <= halo - p and input n - 1 through its taps t >= halo + n - 1 - p (a
+// one-pixel line: all taps), so its weight is a prefix or suffix sum `cs` of
+// the filter's taps.
+__device__ __forceinline__ float adj1d(const float* w, const float (*cs)[kFTap], int i, int n,
+                                       const float* g, int base, int stride) {
   float s = 0.f;
   if (i > 0 && i < n - 1) {
     const float* gi = g + (base + i + kFlipHalo) * stride;
@@ -563,12 +589,9 @@ __device__ __forceinline__ float adj1d(const float* w, int i, int n, const float
   }
   const int p0 = max(i - kFlipHalo, 0), p1 = min(i + kFlipHalo, n - 1);
   for (int p = p0; p <= p1; ++p) {
-    float wt = 0.f;
-    for (int j = 0; j < kFTap; ++j) {
-      const int q = p + j - kFlipHalo;
-      const int c = q < 0 ? 0 : (q > n - 1 ? n - 1 : q);
-      if (c == i) wt += w[j];
-    }
+    const float wt = n == 1   ? cs[0][kFTap - 1]
+                     : i == 0 ? cs[0][kFlipHalo - p]
+                              : cs[1][kFlipHalo + n - 1 - p];
     s += wt * g[(base + p) * stride];
   }
   return s;
@@ -580,10 +603,12 @@ __global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f,
                                                         float scale, int accumulate,
                                                         float* __restrict__ grad) {
   __shared__ float s_w[7][kFTap];
+  __shared__ float s_cs[7][2][kFTap];
   __shared__ float s_s[7][kFRY][kFRX];
   __shared__ float s_v[7][kFTY][kFRX];
   const FTile T = ftile(fv);
   load_weights(f, s_w);
+  load_tap_sums(f, s_cs);
   // seeds of the tile and its halo (zero outside the image)
   for (int i = threadIdx.x; i < kFRY * kFRX; i += kFB) {
     const int r = i / kFRX, c = i - r * kFRX;
@@ -604,14 +629,14 @@ __global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f,
     const int y = T.y0 + oy, xx = T.x0 + c - kFlipHalo;
     float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (y < T.H && xx >= 0 && xx < T.W) {
-      a[0] = adj1d(s_w[0], y, T.H, &s_s[0][0][c], rbase, kFRX);
-      a[1] = adj1d(s_w[1], y, T.H, &s_s[1][0][c], rbase, kFRX);
-      a[2] = f.c1 * adj1d(s_w[2], y, T.H, &s_s[2][0][c], rbase, kFRX);
-      a[3] = f.c2 * adj1d(s_w[3], y, T.H, &s_s[2][0][c], rbase, kFRX);
-      a[4] = adj1d(s_w[4], y, T.H, &s_s[3][0][c], rbase, kFRX);   // ex -> edge along x
-      a[5] = adj1d(s_w[5], y, T.H, &s_s[4][0][c], rbase, kFRX) +  // ey, py -> Gaussian along x
-             adj1d(s_w[6], y, T.H, &s_s[6][0][c], rbase, kFRX);
-      a[6] = adj1d(s_w[4], y, T.H, &s_s[5][0][c], rbase, kFRX);   // px -> point along x
+      a[0] = adj1d(s_w[0], s_cs[0], y, T.H, &s_s[0][0][c], rbase, kFRX);
+      a[1] = adj1d(s_w[1], s_cs[1], y, T.H, &s_s[1][0][c], rbase, kFRX);
+      a[2] = f.c1 * adj1d(s_w[2], s_cs[2], y, T.H, &s_s[2][0][c], rbase, kFRX);
+      a[3] = f.c2 * adj1d(s_w[3], s_cs[3], y, T.H, &s_s[2][0][c], rbase, kFRX);
+      a[4] = adj1d(s_w[4], s_cs[4], y, T.H, &s_s[3][0][c], rbase, kFRX);   // ex -> edge along x
+      a[5] = adj1d(s_w[5], s_cs[5], y, T.H, &s_s[4][0][c], rbase, kFRX) +  // ey, py -> Gaussian along x
+             adj1d(s_w[6], s_cs[6], y, T.H, &s_s[6][0][c], rbase, kFRX);
+      a[6] = adj1d(s_w[4], s_cs[4], y, T.H, &s_s[5][0][c], rbase, kFRX);   // px -> point along x
     }
     for (int m = 0; m < 7; ++m) s_v[m][oy][c] = a[m];
   }
@@ -620,13 +645,13 @@ __global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f,
   const int x = T.x0 + ox, y = T.y0 + oy;
   if (x >= T.W || y >= T.H) return;
   const int cbase = kFlipHalo - T.x0;
-  const float gA = adj1d(s_w[0], x, T.W, s_v[0][oy], cbase, 1);
-  const float gRG = adj1d(s_w[1], x, T.W, s_v[1][oy], cbase, 1);
-  const float gB = adj1d(s_w[2], x, T.W, s_v[2][oy], cbase, 1) +
-                   adj1d(s_w[3], x, T.W, s_v[3][oy], cbase, 1);
-  const float gF = adj1d(s_w[5], x, T.W, s_v[4][oy], cbase, 1) +
-                   adj1d(s_w[4], x, T.W, s_v[5][oy], cbase, 1) +
-                   adj1d(s_w[6], x, T.W, s_v[6][oy], cbase, 1);
+  const float gA = adj1d(s_w[0], s_cs[0], x, T.W, s_v[0][oy], cbase, 1);
+  const float gRG = adj1d(s_w[1], s_cs[1], x, T.W, s_v[1][oy], cbase, 1);
+  const float gB = adj1d(s_w[2], s_cs[2], x, T.W, s_v[2][oy], cbase, 1) +
+                   adj1d(s_w[3], s_cs[3], x, T.W, s_v[3][oy], cbase, 1);
+  const float gF = adj1d(s_w[5], s_cs[5], x, T.W, s_v[4][oy], cbase, 1) +
+                   adj1d(s_w[4], s_cs[4], x, T.W, s_v[5][oy], cbase, 1) +
+                   adj1d(s_w[6], s_cs[6], x, T.W, s_v[6][oy], cbase, 1);
   const float gY = gA + gF * (1.f / 116.f);
   const float gn[3] = {500.f * gRG, 116.f * gY - 500.f * gRG + 200.f * gB, -200.f * gB};
   const int64_t plane = (int64_t)T.W * T.H;
