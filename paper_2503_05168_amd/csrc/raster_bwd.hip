@@ -161,10 +161,14 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
                                                        const float* __restrict__ dL_dimage,
                                                        float* __restrict__ grad2d) {
   constexpr int NT = TS * TS;
-  __shared__ LdsBwd s_e[NT];
-  __shared__ uint32_t s_id[NT];
-  __shared__ uint8_t s_qm[NT];
-  __shared__ float s_g[NT][9];  // per staged record: the block's 2D gradient sum
+  // records staged per batch: half the block for 16 x 16 tiles keeps the LDS
+  // at 13 KB, so the VGPR budget (9 waves per SIMD), not the LDS, bounds the
+  // occupancy
+  constexpr int NBATCH = NT > 64 ? NT / 2 : NT;
+  __shared__ LdsBwd s_e[NBATCH];
+  __shared__ uint32_t s_id[NBATCH];
+  __shared__ uint8_t s_qm[NBATCH];
+  __shared__ float s_g[NBATCH][9];  // per staged record: the block's 2D gradient sum
   __shared__ int s_max;
 
   const int gt = blockIdx.x;
@@ -213,8 +217,8 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
   int wave_last = last;
   for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
 
-  for (int hi = jmax; hi > 0; hi -= NT) {
-    const int lo = hi > NT ? hi - NT : 0;
+  for (int hi = jmax; hi > 0; hi -= NBATCH) {
+    const int lo = hi > NBATCH ? hi - NBATCH : 0;
     if (tid < hi - lo) {
       const uint32_t id = ids[start + lo + tid];
       const float4* src = reinterpret_cast<const float4*>(splats + id);
