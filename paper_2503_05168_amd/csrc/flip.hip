@@ -622,23 +622,63 @@ __global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f,
   }
   __syncthreads();
   // adjoint vertical passes at the tile's rows, every in-image halo column;
-  // row p of the image sits at LDS row p - y0 + halo
+  // row p of the image sits at LDS row p - y0 + halo.  One item per (output
+  // map, column): when every tile row is an interior row of the image, the
+  // column's kFRY staged seeds are read once into registers and give all
+  // kFTY rows (taps added in the order adj1d adds them); otherwise each row
+  // takes adj1d.  Output map 5 sums two filters (ey and py).
   const int rbase = kFlipHalo - T.y0;
-  for (int i = threadIdx.x; i < kFTY * kFRX; i += kFB) {
-    const int oy = i / kFRX, c = i - oy * kFRX;
-    const int y = T.y0 + oy, xx = T.x0 + c - kFlipHalo;
-    float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (y < T.H && xx >= 0 && xx < T.W) {
-      a[0] = adj1d(s_w[0], s_cs[0], y, T.H, &s_s[0][0][c], rbase, kFRX);
-      a[1] = adj1d(s_w[1], s_cs[1], y, T.H, &s_s[1][0][c], rbase, kFRX);
-      a[2] = f.c1 * adj1d(s_w[2], s_cs[2], y, T.H, &s_s[2][0][c], rbase, kFRX);
-      a[3] = f.c2 * adj1d(s_w[3], s_cs[3], y, T.H, &s_s[2][0][c], rbase, kFRX);
-      a[4] = adj1d(s_w[4], s_cs[4], y, T.H, &s_s[3][0][c], rbase, kFRX);   // ex -> edge along x
-      a[5] = adj1d(s_w[5], s_cs[5], y, T.H, &s_s[4][0][c], rbase, kFRX) +  // ey, py -> Gaussian along x
-             adj1d(s_w[6], s_cs[6], y, T.H, &s_s[6][0][c], rbase, kFRX);
-      a[6] = adj1d(s_w[4], s_cs[4], y, T.H, &s_s[5][0][c], rbase, kFRX);   // px -> point along x
+  const bool rows_inside = T.y0 > 0 && T.y0 + kFTY < T.H;  // 0 < y < H - 1 for every row
+  for (int i = threadIdx.x; i < 7 * kFRX; i += kFB) {
+    const int dm = i / kFRX, c = i - dm * kFRX;
+    const int xx = T.x0 + c - kFlipHalo;
+    // (filter, seed map) of the output map's terms and its colour weight
+    const int wk = dm == 6 ? 4 : dm, sm = dm <= 2 ? dm : dm - 1;
+    const float sc = dm == 2 ? f.c1 : dm == 3 ? f.c2 : 1.f;
+    const int sm2 = dm == 3 ? 2 : sm;
+    float acc[kFTY];
+#pragma unroll
+    for (int oy = 0; oy < kFTY; ++oy) acc[oy] = 0.f;
+    if (xx >= 0 && xx < T.W) {
+      if (rows_inside) {
+        float wv[kFTap], col[kFRY];
+#pragma unroll
+        for (int j = 0; j < kFTap; ++j) wv[j] = s_w[wk][j];
+#pragma unroll
+        for (int r = 0; r < kFRY; ++r) col[r] = s_s[sm2][r][c];
+#pragma unroll
+        for (int oy = 0; oy < kFTY; ++oy) {
+          float s = 0.f;
+#pragma unroll
+          for (int j = 0; j < kFTap; ++j) s = __builtin_fmaf(wv[j], col[oy + 2 * kFlipHalo - j], s);
+          acc[oy] = s;
+        }
+        if (dm == 5) {
+#pragma unroll
+          for (int j = 0; j < kFTap; ++j) wv[j] = s_w[6][j];
+#pragma unroll
+          for (int r = 0; r < kFRY; ++r) col[r] = s_s[6][r][c];
+#pragma unroll
+          for (int oy = 0; oy < kFTY; ++oy) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < kFTap; ++j)
+              s = __builtin_fmaf(wv[j], col[oy + 2 * kFlipHalo - j], s);
+            acc[oy] = acc[oy] + s;
+          }
+        }
+      } else {
+        for (int oy = 0; oy < kFTY; ++oy) {
+          const int y = T.y0 + oy;
+          if (y >= T.H) break;
+          float s = adj1d(s_w[wk], s_cs[wk], y, T.H, &s_s[sm2][0][c], rbase, kFRX);
+          if (dm == 5) s = s + adj1d(s_w[6], s_cs[6], y, T.H, &s_s[6][0][c], rbase, kFRX);
+          acc[oy] = s;
+        }
+      }
     }
-    for (int m = 0; m < 7; ++m) s_v[m][oy][c] = a[m];
+#pragma unroll
+    for (int oy = 0; oy < kFTY; ++oy) s_v[dm][oy][c] = sc * acc[oy];
   }
   __syncthreads();
   const int oy = threadIdx.x / kFTX, ox = threadIdx.x % kFTX;
