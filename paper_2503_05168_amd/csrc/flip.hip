@@ -465,7 +465,8 @@ __device__ __forceinline__ void load_tap_sums(const FlipFilt& f, float (*cs)[2][
 }
 
 // At most 168 VGPRs (3 waves per SIMD), the occupancy the kernel's LDS
-// allows; without the bound the compiler takes 182 and runs 2.
+// allows; without the bound the compiler takes 182 and runs 2 (with it, a
+// few values of the horizontal pass spill, which costs less).
 __global__ __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(3))) void k_flip_fwd_tile(FlipViews fv, FlipFilt f, FlipConst k,
                                                         const float* __restrict__ o,
                                                         float* __restrict__ seed, int64_t P,
@@ -531,19 +532,34 @@ __global__ __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int m = 0; m < 7; ++m) s_h[m][r][c0 + o] = a[o][m];
     }
     __syncthreads();
-    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // vertical passes: thread (k, column) gives filter output k of all kFTY
+    // rows of its column from a register window of the column (taps in
+    // increasing order, as per pixel); the outputs go through LDS (the staged
+    // input is dead by now) to their pixels' threads
+    static_assert(8 * kFTX == kFB && 8 * kFTY * kFTX <= 3 * kFRY * kFRXP, "vertical items");
+    {
+      const int vk = threadIdx.x / kFTX, vc = threadIdx.x % kFTX;
+      // (filter, horizontal map) of output k: 0..5 as is, 6 = px, 7 = py
+      const int wk = vk == 6 ? 4 : vk == 7 ? 6 : vk;
+      const int hm = vk == 7 ? 5 : vk;
+      float acc[kFTY];
 #pragma unroll
-    for (int j = 0; j < kFTap; ++j) {
-      const int ry = oy + j;
-      v[0] = __builtin_fmaf(s_w[0][j], s_h[0][ry][ox], v[0]);
-      v[1] = __builtin_fmaf(s_w[1][j], s_h[1][ry][ox], v[1]);
-      v[2] = __builtin_fmaf(s_w[2][j], s_h[2][ry][ox], v[2]);
-      v[3] = __builtin_fmaf(s_w[3][j], s_h[3][ry][ox], v[3]);
-      v[4] = __builtin_fmaf(s_w[4][j], s_h[4][ry][ox], v[4]);  // ex: edge x, Gaussian y
-      v[5] = __builtin_fmaf(s_w[5][j], s_h[5][ry][ox], v[5]);  // ey: Gaussian x, edge y
-      v[6] = __builtin_fmaf(s_w[4][j], s_h[6][ry][ox], v[6]);  // px
-      v[7] = __builtin_fmaf(s_w[6][j], s_h[5][ry][ox], v[7]);  // py
+      for (int oy2 = 0; oy2 < kFTY; ++oy2) acc[oy2] = 0.f;
+#pragma unroll
+      for (int j = 0; j < kFTap; ++j) {
+        const float w = s_w[wk][j];
+#pragma unroll
+        for (int oy2 = 0; oy2 < kFTY; ++oy2)
+          acc[oy2] = __builtin_fmaf(w, s_h[hm][oy2 + j][vc], acc[oy2]);
+      }
+      float* s_vo = &s_in[0][0][0];  // [8][kFTY][kFTX]
+#pragma unroll
+      for (int oy2 = 0; oy2 < kFTY; ++oy2) s_vo[(vk * kFTY + oy2) * kFTX + vc] = acc[oy2];
     }
+    __syncthreads();
+    float v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = (&s_in[0][0][0])[(m * kFTY + oy) * kFTX + ox];
     cf[im][0] = v[0];
     cf[im][1] = v[1];
     cf[im][2] = f.c1 * v[2] + f.c2 * v[3];
