@@ -697,17 +697,50 @@ __global__ __launch_bounds__(kFB) void k_flip_bwd_tile(FlipViews fv, FlipFilt f,
     for (int oy = 0; oy < kFTY; ++oy) s_v[dm][oy][c] = sc * acc[oy];
   }
   __syncthreads();
+  // adjoint horizontal passes: item (filter term, row, 4 adjacent columns)
+  // gives its 4 outputs from one register window of the row when all 4 are
+  // interior columns of the image (taps in the order adj1d adds them), else
+  // per column through adj1d; the terms go through LDS (the staged seeds are
+  // dead by now) and each pixel sums its own
+  const int cbase = kFlipHalo - T.x0;
+  float* s_p = &s_s[0][0][0];  // [7][kFTY][kFTX]
+  static_assert(7 * kFTY * kFTX <= 7 * kFRY * kFRX, "horizontal terms");
+  for (int i = threadIdx.x; i < 7 * kFTY * (kFTX / 4); i += kFB) {
+    const int hk = i / (kFTY * (kFTX / 4));
+    const int rem = i - hk * (kFTY * (kFTX / 4));
+    const int hy = rem / (kFTX / 4), c0 = (rem - hy * (kFTX / 4)) * 4;
+    // (filter, vertical map) of term hk: A, RG, B1, B2, ex, px, py
+    const int wk = hk == 4 ? 5 : hk == 5 ? 4 : hk;
+    const float* row = s_v[hk][hy];
+    float out[4];
+    const int xa = T.x0 + c0;
+    if (xa > 0 && xa + 3 < T.W - 1) {
+      float win[kFTap + 3];
+#pragma unroll
+      for (int j = 0; j < kFTap + 3; ++j) win[j] = row[c0 + j];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < kFTap; ++j) s = __builtin_fmaf(s_w[wk][j], win[o + 2 * kFlipHalo - j], s);
+        out[o] = s;
+      }
+    } else {
+      for (int o = 0; o < 4; ++o)
+        out[o] = xa + o < T.W ? adj1d(s_w[wk], s_cs[wk], xa + o, T.W, row, cbase, 1) : 0.f;
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) s_p[(hk * kFTY + hy) * kFTX + c0 + o] = out[o];
+  }
+  __syncthreads();
   const int oy = threadIdx.x / kFTX, ox = threadIdx.x % kFTX;
   const int x = T.x0 + ox, y = T.y0 + oy;
   if (x >= T.W || y >= T.H) return;
-  const int cbase = kFlipHalo - T.x0;
-  const float gA = adj1d(s_w[0], s_cs[0], x, T.W, s_v[0][oy], cbase, 1);
-  const float gRG = adj1d(s_w[1], s_cs[1], x, T.W, s_v[1][oy], cbase, 1);
-  const float gB = adj1d(s_w[2], s_cs[2], x, T.W, s_v[2][oy], cbase, 1) +
-                   adj1d(s_w[3], s_cs[3], x, T.W, s_v[3][oy], cbase, 1);
-  const float gF = adj1d(s_w[5], s_cs[5], x, T.W, s_v[4][oy], cbase, 1) +
-                   adj1d(s_w[4], s_cs[4], x, T.W, s_v[5][oy], cbase, 1) +
-                   adj1d(s_w[6], s_cs[6], x, T.W, s_v[6][oy], cbase, 1);
+  const int pp = oy * kFTX + ox, ps = kFTY * kFTX;
+  const float gA = s_p[pp];
+  const float gRG = s_p[ps + pp];
+  const float gB = s_p[2 * ps + pp] + s_p[3 * ps + pp];
+  const float gF = s_p[4 * ps + pp] + s_p[5 * ps + pp] + s_p[6 * ps + pp];
   const float gY = gA + gF * (1.f / 116.f);
   const float gn[3] = {500.f * gRG, 116.f * gY - 500.f * gRG + 200.f * gB, -200.f * gB};
   const int64_t plane = (int64_t)T.W * T.H;
