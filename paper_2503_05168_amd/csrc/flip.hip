@@ -465,8 +465,8 @@ __device__ __forceinline__ void load_tap_sums(const FlipFilt& f, float (*cs)[2][
 }
 
 // At most 168 VGPRs (3 waves per SIMD), the occupancy the kernel's LDS
-// allows; without the bound the compiler takes 182 and runs 2 (with it, a
-// few values of the horizontal pass spill, which costs less).
+// allows; without the bound the compiler takes 182 and runs 2 (with it, 6
+// VGPRs spill, which costs less).
 __global__ __launch_bounds__(kFB) __attribute__((amdgpu_waves_per_eu(3))) void k_flip_fwd_tile(FlipViews fv, FlipFilt f, FlipConst k,
                                                         const float* __restrict__ o,
                                                         float* __restrict__ seed, int64_t P,
