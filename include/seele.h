@@ -363,9 +363,18 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
  * the pose farthest from every chosen centroid, lowest index on ties), then
  * Lloyd iterations (nearest centroid, lowest index on ties; member means; an
  * empty cluster keeps its centroid) until no label changes or `iters` updates.
+ * pos_scale <= 0 takes seele_hp_pos_scale(cams, n_cams) (an error if every
+ * centre is at the origin); a non-finite pos_scale or beta is an error.
  * Host only: centroids host [K][6], labels host [n_cams]. */
 int32_t seele_hp_kmeans(const seele_camera* cams, int32_t n_cams, float pos_scale, float beta,
                         int32_t K, int32_t iters, float* centroids, int32_t* labels);
+
+/* Default position normaliser of the pose feature (Sec. 3.3 "Offline
+ * Clustering" normalises the camera position without saying by what): the
+ * largest distance of a camera centre from the world origin over the n_cams
+ * sampled poses (host array), as float32.  Returns -1 (and sets the last
+ * error) on a null array, n_cams < 1 or a non-finite centre.  Host only. */
+float seele_hp_pos_scale(const seele_camera* cams, int32_t n_cams);
 
 /* Folds one cluster's seele_contrib_topk results (records v*n + i of its
  * n_views views) into per-Gaussian state, on the device: shared[i] |= any

@@ -62,6 +62,14 @@ def active_mask(n: int, segments) -> np.ndarray:
 # to the cluster where that sum is largest (the earlier cluster on ties);
 # Gaussians that never blend belong to no segment and are placed last.
 
+def default_pos_scale(cams) -> float:
+    """The position normaliser when none is given (a reading: the paper
+    normalises the camera position without naming the divisor): the largest
+    distance of a sampled camera centre from the world origin."""
+    return max(float(np.linalg.norm(-np.asarray(c.R, dtype=np.float64).T
+                                     @ np.asarray(c.t, dtype=np.float64))) for c in cams)
+
+
 def kmeans(features: np.ndarray, K: int, iters: int = 100):
     """(centroids [K, 6] float64, labels [n] int) of the poses' features."""
     f = np.asarray(features, dtype=np.float64)

@@ -113,6 +113,7 @@ SIGNATURES = {
                                       c_void_p]),
     "seele_hp_kmeans": (c_int32, [POINTER(seele_camera), c_int32, c_float, c_float, c_int32,
                                   c_int32, POINTER(c_float), POINTER(c_int32)]),
+    "seele_hp_pos_scale": (c_float, [POINTER(seele_camera), c_int32]),
     "seele_hp_accumulate": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_int32, c_void_p,
                                       c_void_p, c_void_p, c_void_p]),
     "seele_hp_partition": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32,

@@ -772,13 +772,37 @@ double dist2_6(const double* a, const double* b) {
 
 extern "C" {
 
+float seele_hp_pos_scale(const seele_camera* cams, int32_t n_cams) {
+  if (!cams || n_cams < 1) {
+    fail(SEELE_ERR_INVALID_ARG, "need at least one camera");
+    return -1.0f;
+  }
+  double best = 0.0;
+  for (int p = 0; p < n_cams; ++p) {
+    double f[6];
+    pose_feature(&cams[p], 1.0f, 0.0f, f);
+    const double r = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!std::isfinite(r)) {
+      fail(SEELE_ERR_INVALID_ARG, "non-finite camera centre");
+      return -1.0f;
+    }
+    best = std::max(best, r);
+  }
+  return (float)best;
+}
+
 int32_t seele_hp_kmeans(const seele_camera* cams, int32_t n_cams, float pos_scale, float beta,
                         int32_t K, int32_t iters, float* centroids, int32_t* labels) {
   if (!cams || !centroids || !labels) return fail(SEELE_ERR_INVALID_ARG, "null argument");
   if (n_cams < 1 || K < 1 || K > n_cams || iters < 0)
     return fail(SEELE_ERR_INVALID_ARG, "need 1 <= K <= n_cams and iters >= 0");
-  if (!(pos_scale > 0.0f) || !is_finite(pos_scale) || !is_finite(beta))
+  if (!is_finite(pos_scale) || !is_finite(beta))
     return fail(SEELE_ERR_INVALID_ARG, "bad pos_scale/beta");
+  if (pos_scale <= 0.0f) {
+    pos_scale = seele_hp_pos_scale(cams, n_cams);
+    if (!(pos_scale > 0.0f))
+      return fail(SEELE_ERR_INVALID_ARG, "every sampled camera centre is at the origin");
+  }
   std::vector<double> f((size_t)n_cams * 6), c((size_t)K * 6), dmin((size_t)n_cams);
   for (int p = 0; p < n_cams; ++p) pose_feature(&cams[p], pos_scale, beta, &f[(size_t)p * 6]);
   // farthest-point seeding: pose 0, then each time the pose farthest from

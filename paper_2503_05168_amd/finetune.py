@@ -12,7 +12,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _abi as A
-from .pipeline import (GaussianTensors, Renderer, Settings, _p, _stream, seele_rasterize_bwd)
+from .pipeline import (GaussianTensors, Renderer, Settings, _need, _p, _stream, pixel_count,
+                       seele_rasterize_bwd)
 
 
 def seele_photometric_loss(image, target, cams, lam: float = 0.2, workspace=None, loss=None,
@@ -28,7 +29,12 @@ def seele_photometric_loss(image, target, cams, lam: float = 0.2, workspace=None
         loss = torch.empty(V, dtype=torch.float32, device=dev)
     if grad is None:
         grad = torch.empty_like(image)
-    assert image.is_contiguous() and target.is_contiguous() and image.numel() == target.numel()
+    npx = 3 * pixel_count(cams)
+    _need(image, npx, torch.float32, "image")
+    _need(target, npx, torch.float32, "target")
+    _need(grad, npx, torch.float32, "grad")
+    _need(loss, V, torch.float32, "loss")
+    _need(workspace, need, torch.uint8, "workspace")
     st = A.lib().seele_photometric_loss(_p(image), _p(target), cam_arr, V, float(lam),
                                         _p(workspace), workspace.numel(), _p(loss), _p(grad),
                                         _stream(stream))
@@ -59,12 +65,13 @@ class AdamOpts:
         return o
 
 
-def _desc(t: GaussianTensors) -> A.seele_gaussian_grads:
+def _desc(t: GaussianTensors, n: int, name: str) -> A.seele_gaussian_grads:
+    """Descriptor of n Gaussians' attribute arrays (sizes checked)."""
+    t.check(n, name)
     d = A.seele_gaussian_grads()
-    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
-        x = getattr(t, name)
-        assert x.is_contiguous() and x.dtype == torch.float32
-        setattr(d, name, x.data_ptr() if x.numel() else None)
+    for attr in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        x = getattr(t, attr)
+        setattr(d, attr, x.data_ptr() if x.numel() else None)
     return d
 
 
@@ -78,8 +85,10 @@ def seele_adam_step(params: GaussianTensors, grads: GaussianTensors, m: Gaussian
                     v: GaussianTensors, step: int, opts: AdamOpts | None = None,
                     extent: float = 1.0, stream=None):
     o = (opts or AdamOpts()).struct(extent)
-    st = A.lib().seele_adam_step(ctypes.byref(_desc(params)), ctypes.byref(_desc(grads)),
-                                 ctypes.byref(_desc(m)), ctypes.byref(_desc(v)), params.n,
+    n = params.n
+    st = A.lib().seele_adam_step(ctypes.byref(_desc(params, n, "params")),
+                                 ctypes.byref(_desc(grads, n, "grads")),
+                                 ctypes.byref(_desc(m, n, "m")), ctypes.byref(_desc(v, n, "v")), n,
                                  params.sh_degree, ctypes.byref(o), int(step), _stream(stream))
     A.check(st, "seele_adam_step")
 
@@ -170,8 +179,12 @@ def seele_flip_loss(image, reference, cams, ppd: float = FLIP_PPD, scale: float 
         if accumulate:
             raise ValueError("accumulate needs a gradient buffer")
         grad = torch.empty_like(image)
-    assert image.is_contiguous() and reference.is_contiguous()
-    assert image.numel() == reference.numel() == grad.numel()
+    npx = 3 * pixel_count(cams)
+    _need(image, npx, torch.float32, "image")
+    _need(reference, npx, torch.float32, "reference")
+    _need(grad, npx, torch.float32, "grad")
+    _need(flip, V, torch.float32, "flip")
+    _need(workspace, need, torch.uint8, "workspace")
     st = A.lib().seele_flip_loss(_p(image), _p(reference), cam_arr, V, float(ppd), float(scale),
                                  int(bool(accumulate)), _p(workspace), workspace.numel(), _p(flip),
                                  _p(grad), _stream(stream))

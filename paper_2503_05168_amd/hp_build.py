@@ -19,7 +19,7 @@ import numpy as np
 import torch
 
 from . import _abi as A
-from .pipeline import (MAX_PAIRS, CapacityError, GaussianTensors, Settings, _p, _stream,
+from .pipeline import (MAX_PAIRS, CapacityError, GaussianTensors, Settings, _need, _p, _stream,
                        seele_bin_sort, seele_contrib_topk, seele_preprocess)
 
 
@@ -41,8 +41,17 @@ class ViewDependentScene:
     stats: dict = field(default_factory=dict)
 
 
+def seele_hp_pos_scale(cams) -> float:
+    """The library's default position normaliser of the pose feature."""
+    v = float(A.lib().seele_hp_pos_scale(A.camera_array(cams), len(cams)))
+    if not v > 0.0:
+        A.check(A.SEELE_ERR_INVALID_ARG, "seele_hp_pos_scale")
+    return v
+
+
 def seele_hp_kmeans(cams, pos_scale: float, beta: float, K: int, iters: int = 100):
-    """(centroids float32 [K, 6], labels int32 [len(cams)])."""
+    """(centroids float32 [K, 6], labels int32 [len(cams)]); pos_scale <= 0
+    lets the library take its default (seele_hp_pos_scale)."""
     cents = np.zeros((K, 6), dtype=np.float32)
     labels = np.zeros(len(cams), dtype=np.int32)
     st = A.lib().seele_hp_kmeans(A.camera_array(cams), len(cams), pos_scale, beta, K, iters,
@@ -54,6 +63,11 @@ def seele_hp_kmeans(cams, pos_scale: float, beta: float, K: int, iters: int = 10
 
 def seele_hp_accumulate(mark, sums, n_views: int, n: int, cluster: int, shared, best_sum,
                         best_cluster, stream=None):
+    _need(mark, n_views * n, torch.uint8, "mark")
+    _need(sums, n_views * n, torch.float32, "sums")
+    _need(shared, n, torch.uint8, "shared")
+    _need(best_sum, n, torch.float32, "best_sum")
+    _need(best_cluster, n, torch.int32, "best_cluster")
     st = A.lib().seele_hp_accumulate(_p(mark), _p(sums), n_views, n, cluster, _p(shared),
                                      _p(best_sum), _p(best_cluster), _stream(stream))
     A.check(st, "seele_hp_accumulate")
@@ -85,11 +99,12 @@ def seele_gather_gaussians(g: GaussianTensors, perm: torch.Tensor, stream=None) 
                           torch.empty((n_out,), device=g.means.device),
                           torch.zeros((16, 3, n_out), device=g.means.device), g.sh_degree)
     dst = A.seele_gaussian_grads()
+    out.check(n_out, "gathered")
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         ten = getattr(out, name)
         setattr(dst, name, ten.data_ptr() if ten.numel() else None)
     src = g.struct()
-    perm = perm.to(dtype=torch.int64).contiguous()
+    perm = _need(perm.to(dtype=torch.int64).contiguous(), n_out, torch.int64, "perm")
     st = A.lib().seele_gather_gaussians(ctypes.byref(src), _p(perm), n_out, ctypes.byref(dst),
                                         _stream(stream))
     A.check(st, "seele_gather_gaussians")
@@ -144,8 +159,7 @@ def build_view_dependent(g: GaussianTensors, poses, n_clusters: int, k: int = 32
     if settings.mode != "plain":
         raise ValueError("the contribution pass blends in the plain form")
     if pos_scale is None:
-        pos_scale = float(max(np.linalg.norm(-(np.asarray(c.R).T @ np.asarray(c.t)))
-                              for c in poses))
+        pos_scale = seele_hp_pos_scale(poses)
     cents, labels = seele_hp_kmeans(poses, pos_scale, beta, n_clusters, iters)
     n = g.n
     dev = g.means.device

@@ -40,13 +40,24 @@ class GaussianTensors:
         return cls(t(scene.means), t(scene.log_scales), t(scene.quats), t(scene.opacity_logits),
                    t(scene.sh), int(getattr(scene, "sh_degree", 3)))
 
+    # float32 elements per Gaussian of each attribute array
+    PER_GAUSSIAN = (("means", 3), ("log_scales", 3), ("quats", 4), ("opacity_logits", 1),
+                    ("sh", 48))
+
+    def check(self, n: int | None = None, name: str = "gaussians") -> "GaussianTensors":
+        """Every attribute array holds at least n Gaussians (default: self.n)."""
+        n = self.n if n is None else n
+        for attr, k in self.PER_GAUSSIAN:
+            _need(getattr(self, attr), k * n, torch.float32, f"{name}.{attr}")
+        return self
+
     def struct(self) -> A.seele_gaussians:
+        self.check()
         g = A.seele_gaussians()
         g.n = self.n
         g.sh_degree = self.sh_degree
         for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
             ten = getattr(self, name)
-            assert ten.is_contiguous() and ten.dtype == torch.float32
             setattr(g, name, ten.data_ptr() if ten.numel() else None)
         return g
 

@@ -9,6 +9,7 @@ from .scenes import (  # noqa: F401
     Scene,
     ball_scene,
     cluster_scene,
+    crop_camera,
     look_at,
     orbit_cameras,
     sampled_orbit_poses,

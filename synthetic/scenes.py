@@ -185,6 +185,16 @@ def look_at(center, target=(0.0, 0.0, 0.0), width=256, height=256, hfov_deg=60.0
     return Camera(R, t, fl, fl, width / 2.0, height / 2.0, int(width), int(height))
 
 
+def crop_camera(cam: Camera, x0: int, y0: int, width: int, height: int) -> Camera:
+    """The same pinhole camera restricted to the pixel window [x0, x0 + width)
+    x [y0, y0 + height) of its image: the principal point moves by the
+    window's origin.  A window whose origin is a multiple of the tile size
+    (and of the pixel-group size) renders exactly the same pixels as the full
+    view, since every tile list and pixel group is unchanged."""
+    return Camera(cam.R.copy(), cam.t.copy(), cam.fx, cam.fy, cam.cx - x0, cam.cy - y0,
+                  int(width), int(height))
+
+
 def orbit_cameras(n_views: int, radius: float, width: int, height: int, hfov_deg=60.0):
     cams = []
     for k in range(n_views):

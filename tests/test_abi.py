@@ -228,6 +228,51 @@ def test_bindings_refuse_undersized_buffers():
             pl._need(bad, 64, torch.float32, "x")
 
 
+def test_loss_optimizer_and_builder_bindings_refuse_undersized_buffers():
+    # CPU tensors: every check runs before the library is handed a pointer
+    import torch
+    from paper_2503_05168_amd import finetune as ft
+    from paper_2503_05168_amd import hp_build as hb
+    from paper_2503_05168_amd.pipeline import GaussianTensors
+    cams = [synthetic.look_at((0, 0, -3), width=8, height=6),
+            synthetic.look_at((0, 0, -3), width=5, height=4)]
+    npx = 3 * (48 + 20)
+    f = lambda k, dt=torch.float32: torch.zeros(k, dtype=dt)
+    for args in ((f(npx - 1), f(npx), {}), (f(npx), f(npx - 1), {}),
+                 (f(npx), f(npx), dict(grad=f(npx - 1))), (f(npx), f(npx), dict(loss=f(1)))):
+        with pytest.raises(ValueError):
+            ft.seele_photometric_loss(args[0], args[1], cams, 0.2, **args[2])
+        with pytest.raises(ValueError):
+            kw = dict(args[2])
+            if "loss" in kw:
+                kw["flip"] = kw.pop("loss")
+            ft.seele_flip_loss(args[0], args[1], cams, **kw)
+    n = 10
+    g = lambda m: GaussianTensors(f(3 * m).reshape(3, m), f(3 * m).reshape(3, m),
+                                  f(4 * m).reshape(4, m), f(m), f(48 * m).reshape(16, 3, m))
+    short = g(n)
+    short.sh = f(48 * n - 1)
+    for bad in ("grads", "m", "v"):
+        ts = dict(grads=g(n), m=g(n), v=g(n))
+        ts[bad] = g(n - 1)
+        with pytest.raises(ValueError):
+            ft.seele_adam_step(g(n), ts["grads"], ts["m"], ts["v"], 1)
+    with pytest.raises(ValueError):
+        ft.seele_adam_step(g(n), short, g(n), g(n), 1)
+    u8 = lambda k: f(k, torch.uint8)
+    ok = dict(mark=u8(2 * n), sums=f(2 * n), shared=u8(n), best_sum=f(n),
+              best_cluster=f(n, torch.int32))
+    for k, small in (("mark", u8(2 * n - 1)), ("sums", f(2 * n - 1)), ("shared", u8(n - 1)),
+                     ("best_sum", f(n - 1)), ("best_cluster", f(n - 1, torch.int32))):
+        a = dict(ok)
+        a[k] = small
+        with pytest.raises(ValueError):
+            hb.seele_hp_accumulate(a["mark"], a["sums"], 2, n, 0, a["shared"], a["best_sum"],
+                                   a["best_cluster"])
+    with pytest.raises(ValueError):
+        hb.seele_gather_gaussians(short, torch.arange(n, dtype=torch.int64))
+
+
 def test_hp_kmeans_matches_oracle():
     # host routine: labels exactly, centroids to float32 rounding
     from paper_2503_05168_amd.hp_build import seele_hp_kmeans
@@ -253,8 +298,33 @@ def test_hp_kmeans_rejects_bad_args():
     cams = A.camera_array([synthetic.look_at((0, 0, -4))] * 3)
     c = (ctypes.c_float * 24)()
     lab = (ctypes.c_int32 * 3)()
-    for K, ps in ((0, 1.0), (4, 1.0), (2, 0.0), (2, float("nan"))):
+    for K, ps in ((0, 1.0), (4, 1.0), (2, float("nan")), (2, float("inf"))):
         assert L.seele_hp_kmeans(cams, 3, ps, 1.0, K, 10, c, lab) == A.SEELE_ERR_INVALID_ARG
+    # pos_scale <= 0 takes the library default, which needs a centre away from the origin
+    origin = A.camera_array([synthetic.look_at((0, 0, -4))])
+    origin[0].t[0] = origin[0].t[1] = origin[0].t[2] = 0.0
+    assert L.seele_hp_kmeans(origin, 1, 0.0, 1.0, 1, 10, c, lab) == A.SEELE_ERR_INVALID_ARG
+    assert L.seele_hp_pos_scale(origin, 0) < 0 and L.seele_hp_pos_scale(None, 1) < 0
+
+
+def test_hp_kmeans_default_pos_scale_matches_oracle():
+    from paper_2503_05168_amd.hp_build import seele_hp_kmeans, seele_hp_pos_scale
+    rng = np.random.default_rng(12)
+    cams = []
+    for _ in range(40):
+        d = rng.normal(size=3)
+        cams.append(synthetic.look_at(d / np.linalg.norm(d) * rng.uniform(2, 7)))
+    ps = ohp.default_pos_scale(cams)
+    assert abs(seele_hp_pos_scale(cams) - ps) <= 1e-6 * ps
+    for p_in in (0.0, -3.0):
+        cents, lab = seele_hp_kmeans(cams, p_in, 1.0, 5, 50)
+        cents2, lab2 = seele_hp_kmeans(cams, seele_hp_pos_scale(cams), 1.0, 5, 50)
+        assert lab.tolist() == lab2.tolist()
+        np.testing.assert_array_equal(cents, cents2)
+    f = np.stack([ohp.camera_feature(c, ps, 1.0) for c in cams])
+    oc, ol = ohp.kmeans(f, 5, 50)
+    assert lab.tolist() == ol.tolist()
+    np.testing.assert_allclose(cents, oc, rtol=0, atol=1e-6)
 
 
 def test_hp_partition_matches_oracle():

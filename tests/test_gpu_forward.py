@@ -153,6 +153,18 @@ CASES = [
     ("c2shape-cr-tile8", lambda: (synthetic.cluster_scene(2, 40_000),
                                   [synthetic.look_at((2, 1, -3.5), width=480, height=270)]),
      Settings(mode="contrib", tile=8)),
+    ("c1-cr-4x4", lambda: (synthetic.config(1)["scene"], synthetic.config(1)["cams"]),
+     Settings(mode="contrib", group=(4, 4))),
+    ("c1-cr-2x4-tile16", lambda: (synthetic.config(1)["scene"], synthetic.config(1)["cams"]),
+     Settings(mode="contrib", group=(2, 4))),
+    ("c2shape-cr-4x4-tile8-ragged", lambda: (synthetic.cluster_scene(2, 40_000),
+                                             [synthetic.look_at((1, -1, -3.5), width=333,
+                                                                height=201)]),
+     Settings(mode="contrib", group=(4, 4), tile=8)),
+    ("c2shape-cr-2x4-tile16-ragged", lambda: (synthetic.cluster_scene(2, 40_000),
+                                              [synthetic.look_at((-1, 0.5, -3.5), width=301,
+                                                                 height=187)]),
+     Settings(mode="contrib", group=(2, 4), extent="opacity")),
 ]
 
 

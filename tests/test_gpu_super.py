@@ -62,9 +62,9 @@ def expand_super(keys, ids, st_ranges, cams, tile):
     return out_ids, ranges
 
 
-def super_frame(scene, cams, st, capacity=1 << 22):
+def super_frame(scene, cams, st, capacity=1 << 22, segments=None):
     g = GaussianTensors.from_arrays(scene)
-    splats, n_tiles = seele_preprocess(g, cams, st)
+    splats, n_tiles = seele_preprocess(g, cams, st, segments)
     keys, ids, rng, npairs, ws = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile,
                                                       capacity)
     need = int(npairs.item())
@@ -76,9 +76,10 @@ def super_frame(scene, cams, st, capacity=1 << 22):
     return g, splats, n_tiles, keys, ids, rng, npairs, img, T, nc
 
 
-def check_against_tile_path(scene, cams, st, counters=True):
-    g, splats, n_tiles, keys, ids, rng, npairs, img, T, nc = super_frame(scene, cams, st)
-    f = gu.run(scene, cams, st, capacity=1 << 22)
+def check_against_tile_path(scene, cams, st, counters=True, segments=None):
+    g, splats, n_tiles, keys, ids, rng, npairs, img, T, nc = super_frame(scene, cams, st,
+                                                                         segments=segments)
+    f = gu.run(scene, cams, st, capacity=1 << 22, segments=segments)
     P = int(f.num_pairs.item())
     assert int(npairs.item()) == P
     assert rng.shape == (total_super_tiles(cams, st.tile), 2)
@@ -119,6 +120,11 @@ CASES = [
     ("c2shape-tile8-plain-1080p", lambda: (synthetic.cluster_scene(2, 200_000),
                                            synthetic.orbit_cameras(2, 4.0, 1920, 1080)),
      Settings(tile=8)),
+    ("c1-cr-4x4", lambda: (synthetic.config(1)["scene"], synthetic.config(1)["cams"]),
+     Settings(mode="contrib", group=(4, 4))),
+    ("c2shape-cr-2x4-tile16-2views", lambda: (synthetic.cluster_scene(2, 60_000),
+                                              synthetic.orbit_cameras(2, 4.0, 640, 360)),
+     Settings(mode="contrib", group=(2, 4))),
 ]
 
 
@@ -163,26 +169,44 @@ def test_super_default_batch_only():
         Renderer(Settings(), lists="super", schedule="queue")
 
 
-@pytest.mark.parametrize("order", ["morton", "generated"])
-def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples(order):
-    """The benchmark's frame (3.0M Gaussians, 1920x1080, 16x16 tiles) in the
-    launch configuration it times, in the storage order it uses (Morton order
-    of the means) and in the generator's order: bit-identical to the per-tile
-    path, and sampled tiles against the float64 oracle over the GPU's own
-    splats."""
-    cfg = synthetic.config(2, n_views=1)
-    scene, cams = cfg["scene"], cfg["cams"]
+FULL_FRAMES = [("morton", "plain"), ("generated", "plain"), ("morton", "contrib"),
+               ("c3-segments", "hp_contrib")]
+
+
+@pytest.mark.parametrize("order,form", FULL_FRAMES, ids=[f"{a}-{b}" for a, b in FULL_FRAMES])
+def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples(order, form):
+    """The benchmark's frames (3.0M Gaussians, 1920x1080, 16x16 tiles) in the
+    launch configuration it times: the plain form in the storage order it
+    uses (Morton order of the means) and in the generator's order, the
+    contribution-aware form (2x2 groups), and hybrid preprocessing (the c3
+    layout's nearest cluster, opacity-aware extent) with contribution-aware
+    rasterization.  Each is bit-identical to the per-tile path, the
+    instrumented kernel (which visits every listed record) writes the same
+    bits as the culled ones, and sampled tiles match the float64 oracle over
+    the GPU's own splats."""
+    segs = None
+    if order == "c3-segments":
+        from oracle import hp as ohp
+        cfg = synthetic.config(3)
+        lay, scene, cams = cfg["hp"], cfg["scene"], cfg["cams"][:1]
+        sel = ohp.select_clusters(lay.centroids, ohp.camera_feature(cams[0], lay.pos_scale),
+                                  cfg["M"])
+        segs = ohp.active_segments(lay.seg_begin, lay.seg_count, sel)
+    else:
+        cfg = synthetic.config(2, n_views=1)
+        scene, cams = cfg["scene"], cfg["cams"]
     if order == "morton":
         perm, _ = seele_spatial_order(GaussianTensors.from_arrays(scene))
         scene = scene.subset(perm.cpu().numpy())
-    st = Settings()
-    gu.log(f"[case] super full frame 3.0M 1080p, {order} order")
-    f, P = check_against_tile_path(scene, cams, st, counters=False)
-    gu.log(f"[step] full frame lists and bits equal, pairs={P}")
+    st = {"plain": Settings(), "contrib": Settings(mode="contrib"),
+          "hp_contrib": Settings(mode="contrib", extent="opacity")}[form]
+    gu.log(f"[case] super full frame 3.0M 1080p, {order} order, {form}")
+    f, P = check_against_tile_path(scene, cams, st, counters=True, segments=segs)
+    gu.log(f"[step] full frame lists, bits and counters equal, pairs={P}")
     # the staged path the benchmark times gives the same lists and bits
-    _, _, _, keys, eids, rng, _, img, T, nc = super_frame(scene, cams, st)
+    _, _, _, keys, eids, rng, _, img, T, nc = super_frame(scene, cams, st, segments=segs)
     fs = Renderer(st, capacity=1 << 22, lists="super").render(GaussianTensors.from_arrays(scene),
-                                                               cams)
+                                                               cams, segs)
     torch.cuda.synchronize()
     E = int(rng[:, 1].max().item())
     assert torch.equal(fs.entry_keys[:E], keys[:E]) and torch.equal(fs.sorted_ids[:E], eids[:E])
@@ -209,7 +233,8 @@ def test_full_frame_3m_1080p_super_matches_tile_path_and_oracle_samples(order):
                          (ty < rect[:, 3]))[0]
         want = cov[np.lexsort((cov, depth[cov]))]
         np.testing.assert_array_equal(ids[ranges[t, 0]:ranges[t, 1]], want)
-    r = oblend.render_tiles(sp, ranges, ids, cam.width, cam.height, 16, 0, "plain", st.group,
+    mode = "plain" if st.mode == "plain" else "cr"
+    r = oblend.render_tiles(sp, ranges, ids, cam.width, cam.height, 16, 0, mode, st.group,
                             st.bg, st.alpha_min, st.alpha_max, st.T_min, tiles=tiles)
     imgs, Ts, ncs = gu.outputs_np(f)
     for t in tiles:

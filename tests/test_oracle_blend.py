@@ -237,3 +237,72 @@ def test_binning_multi_view_tile_bases():
     assert b["ranges"].shape == (8 + 9, 2)
     first = b["ids"][b["tiles"] < 8]
     assert (first < 50).all() and (b["ids"][b["tiles"] >= 8] >= 50).all()
+
+
+def test_plain_counters_by_hand_count():
+    # one 16x16 tile, five entries; the narrow entry (sigma = 0.2 px, centred on pixel (3, 4))
+    # reaches alpha_theta at that pixel only: a neighbour one pixel away sees
+    # 0.99 exp(-1 / (2 * 0.04)) ~ 4e-6 < 1/255
+    s = 0.2
+    mean = [[8, 8], [8, 8], [3.5, 4.5], [8, 8], [8, 8]]
+    conic = [[0, 0, 0], [0, 0, 0], [1 / s ** 2, 0, 1 / s ** 2], [0, 0, 0], [0, 0, 0]]
+    r = _one_tile(mean, conic, [0.98, 0.98, 0.995, 0.5, 0.6], [[1, 1, 1]] * 5)
+    # per pixel, T: 1 -> 0.02 -> 4e-4; entry 2 stops pixel (3, 4) (4e-4 * 0.01 < 1e-4) and is
+    # skipped (alpha < alpha_theta) everywhere else; entry 3 blends (T = 2e-4) at the 255 live
+    # pixels; entry 4 stops them all (2e-4 * 0.4 < 1e-4)
+    # evaluations are counted for live pixels only: 256 + 256 + 256 + 255 + 255
+    assert r["counters"]["evals"] == 1278
+    # blends: 256 + 256 + 0 + 255 + 0
+    assert r["counters"]["blends"] == 767
+    assert r["n_contrib"][4, 3] == 2 and r["n_contrib"][0, 0] == 4
+    assert r["counters"]["leader_tests"] == 0 and r["counters"]["pass_evals"] == 0
+
+
+def test_skip_and_termination_counters_by_hand_count():
+    # the five flat layers of test_alpha_skip_and_termination: every pixel evaluates the
+    # sub-threshold layer, blends two, evaluates the third 0.98 layer and stops there; the
+    # last layer is never evaluated -> 4 evaluations and 2 blends per pixel
+    r = _one_tile([[8, 8]] * 5, [[0, 0, 0]] * 5, [A_T * 0.999, 0.98, 0.98, 0.98, 0.5],
+                  [[1, 0, 0]] * 5)
+    assert r["counters"]["evals"] == 4 * 256
+    assert r["counters"]["blends"] == 2 * 256
+
+
+def test_cr_counters_by_hand_count():
+    # a 4x4 image in one 4x4 tile, 2x2 groups: leaders (0,0), (2,0), (0,2), (2,2)
+    s = 0.2
+    mean = [[2, 2], [2.5, 2.5], [1.5, 0.5], [2, 2], [2, 2], [2, 2]]
+    conic = [[0, 0, 0], [1 / s ** 2, 0, 1 / s ** 2], [1 / s ** 2, 0, 1 / s ** 2],
+             [0, 0, 0], [0, 0, 0], [0, 0, 0]]
+    r = _one_tile(mean, conic, [0.5, 0.9, 0.9, 0.98, 0.98, 0.6], [[1, 1, 1]] * 6, size=4,
+                  tile=4, mode="cr")
+    c = r["counters"]
+    # entry: live groups tested / accepted, live pixels of accepted groups, blends
+    #  0 flat 0.5            4 / 4, 16, 16        (T = 0.5)
+    #  1 narrow on leader (2,2)   4 / 1, 4, 1     (only that pixel: T = 0.05)
+    #  2 narrow on follower (1,0) 4 / 0, 0, 0     (its leader sees alpha ~ 1e-11)
+    #  3 flat 0.98           4 / 4, 16, 16        (T = 0.01; pixel (2,2): 1e-3)
+    #  4 flat 0.98           4 / 4, 16, 15        (T = 2e-4; pixel (2,2) stops: 2e-5 < 1e-4)
+    #  5 flat 0.6            4 / 4, 15, 0         (2e-4 * 0.4 < 1e-4: every live pixel stops;
+    #                                              group (2,2) still counts, its followers live)
+    assert c["leader_tests"] == 24
+    assert c["leader_pass"] == 17
+    assert c["pass_evals"] == 67
+    assert c["blends"] == 48
+    assert r["n_contrib"][2, 2] == 4 and r["n_contrib"][0, 1] == 5
+    assert c["evals"] == 0
+
+
+def test_tile_aligned_crop_renders_the_same_pixels():
+    # a camera restricted to a window whose origin is a multiple of the tile (and group) size
+    # sees every tile list and pixel group of that window unchanged (x' moves by the window
+    # origin, up to the rounding of one float64 addition)
+    scene = synthetic.ball_scene(13, 300, log_scale_mu=-3.0)
+    full = synthetic.look_at((0.3, -0.2, -3.0), width=80, height=64)
+    crop = synthetic.crop_camera(full, 16, 32, 48, 32)
+    for mode in ("plain", "cr"):
+        a = blend.render_view(project.project_view(scene, full, tile=16), mode=mode)
+        b = blend.render_view(project.project_view(scene, crop, tile=16), mode=mode)
+        np.testing.assert_allclose(b["image"], a["image"][:, 32:64, 16:64], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(b["final_T"], a["final_T"][32:64, 16:64], rtol=0, atol=1e-12)
+        np.testing.assert_array_equal(b["n_contrib"], a["n_contrib"][32:64, 16:64])

@@ -117,3 +117,12 @@ def test_partition_invariants():
                 assert (S[:s - 1, i] < S[s - 1, i]).all()
     rest = perm[begin[-1] + count[-1]:]
     assert all(not shared[i] and S[:, i].max() == 0 for i in rest)
+
+
+def test_default_pos_scale_is_the_farthest_camera_centre():
+    # orbit cameras all sit at radius 4; a camera placed at (3, 4, 12) is 13 from the origin
+    cams = synthetic.orbit_cameras(8, 4.0, 64, 64)
+    assert abs(hp.default_pos_scale(cams) - 4.0) < 1e-6
+    far = synthetic.look_at((3.0, 4.0, 12.0))
+    assert abs(hp.default_pos_scale(cams + [far]) - 13.0) < 1e-5
+    assert abs(hp.default_pos_scale([far]) - 13.0) < 1e-5
