@@ -38,10 +38,14 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz FP32 lane-ops (packed FP32 not used)
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
-# algorithmic FP32 lane operations per alpha evaluation / per blend, as written
-# in the kernels (2 sub, 2 mul, 2 fma, 1 neg-fma for q; exp2; o*G; min; compare)
-OPS_EVAL = 11
-OPS_BLEND = 7
+# algorithmic FP32 lane operations per alpha evaluation (the quadratic form,
+# opacity and clamp: 12, plus the exp) and per blend (weight, transmittance,
+# three colour FMAs, termination test: 9)
+OPS_EVAL = 13
+OPS_BLEND = 9
+# backward: lane-ops per blended (pixel, Gaussian) and per visible record
+OPS_BWD_BLEND = 40
+OPS_BWD_RECORD = 300
 
 
 def measured_traffic(kernel_key):
@@ -72,7 +76,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--n", type=int, default=3_000_000, help="Gaussian count (default 3.0M)")
-    ap.add_argument("--forms", default="plain,contrib,hp,hp_contrib,hp_built")
+    ap.add_argument("--forms",
+                    default="plain,contrib,hp,hp_contrib,hp_built,plain_generator_order")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=240,
                     help="tiles of view 0 the CPU oracle blends (about 10-30 s of CPU work)")
@@ -121,11 +126,16 @@ def build_forms(names, n):
     cams = synthetic.orbit_cameras(32, 4.0, 1920, 1080)
     log(f"[bench] scene ready in {time.time() - t:.1f}s")
     forms = {}
+    if "plain_generator_order" in names:
+        g0 = GaussianTensors.from_arrays(scene)
+        forms["plain_generator_order"] = dict(g=g0, st=Settings(), hp=None)
     scene, g = load_scene(scene)
+    if "plain_generator_order" in forms:  # differs from the stored order's image by tie swaps
+        forms["plain_generator_order"]["full_g"] = g
     if "plain" in names:
         forms["plain"] = dict(g=g, st=Settings(), hp=None)
     if "contrib" in names:
-        forms["contrib"] = dict(g=g, st=Settings(mode="contrib"), hp=None)
+        forms["contrib"] = dict(g=g, st=Settings(mode="contrib"), hp=None, full_g=g)
     if "hp" in names or "hp_contrib" in names:
         labels = synthetic.hp_membership(3, scene.n, n_clusters=8)
         cents = _orbit_centroids(8, 32, 4.0)
@@ -133,10 +143,10 @@ def build_forms(names, n):
         g3 = GaussianTensors.from_arrays(scene_r)
         del scene_r
         if "hp" in names:
-            forms["hp"] = dict(g=g3, st=Settings(extent="opacity"), hp=lay)
+            forms["hp"] = dict(g=g3, st=Settings(extent="opacity"), hp=lay, full_g=g)
         if "hp_contrib" in names:
             forms["hp_contrib"] = dict(g=g3, st=Settings(extent="opacity", mode="contrib"),
-                                       hp=lay)
+                                       hp=lay, full_g=g)
     if "hp_built" in names:
         import torch
         from paper_2503_05168_amd import build_view_dependent
@@ -155,21 +165,26 @@ def build_forms(names, n):
     return scene, cams, forms
 
 
-def hp_quality(full_g, form, cams):
-    """PSNR of a hybrid-preprocessing form's image against the plain
-    full-scene image over the first four orbit views."""
+def form_quality(full_g, form, cams):
+    """Image error of a form against the plain full-scene image over the
+    first four orbit views: PSNR and max abs per channel (the plain GPU image
+    equals the float64 oracle's within 1e-5, checked by the tests)."""
     import paper_2503_05168_amd as P
     lay = form["hp"]
     ref = P.Renderer(P.Settings(), capacity=1 << 26, lists="super")
     r = P.Renderer(form["st"], capacity=1 << 26, lists="super")
-    mse = 0.0
+    mse, mx = 0.0, 0.0
     views = cams[:4]
     for c in views:
-        cl = P.seele_hp_select(lay.centroids, c, lay.pos_scale, lay.beta, form.get("M", 0))
-        segs = P.seele_hp_segments(lay.seg_begin, lay.seg_count, cl)
+        segs = None
+        if lay is not None:
+            cl = P.seele_hp_select(lay.centroids, c, lay.pos_scale, lay.beta, form.get("M", 0))
+            segs = P.seele_hp_segments(lay.seg_begin, lay.seg_count, cl)
         d = r.render(form["g"], [c], segs).image - ref.render(full_g, [c]).image
         mse += float((d * d).mean().item()) / len(views)
-    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+        mx = max(mx, float(d.abs().max().item()))
+    psnr = float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+    return dict(psnr_vs_plain_full=psnr, max_abs_vs_plain_full=mx, quality_views=len(views))
 
 
 def run_form(name, form, cams, steps, warmup, lists="super"):
@@ -210,7 +225,7 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     ids = torch.empty(capacity, dtype=torch.int32, device=dev)
     keys = torch.empty(capacity if sup else 1, dtype=torch.int32, device=dev)
     npairs_log = torch.zeros(steps, dtype=torch.int64, device=dev)
-    npairs = torch.empty(1, dtype=torch.int64, device=dev)
+    npairs = torch.empty(2 if sup else 1, dtype=torch.int64, device=dev)
 
     def preprocess(v):
         if sup:  # the binning's first step is staged by preprocessing
@@ -255,7 +270,8 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     t0 = time.perf_counter()
     for i in range(steps):
         step(i % V, evs[i])
-        npairs_log[i:i + 1].copy_(npairs, non_blocking=True)
+        # the stored list length (super-tile entries, or pairs)
+        npairs_log[i:i + 1].copy_(npairs[-1:], non_blocking=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert int(npairs_log.max().item()) <= capacity, "pair buffer overflow in the timed region"
@@ -275,7 +291,7 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
         vis.append(int((n_tiles > 0).sum().item()))
         act.append(n if segs[v] is None else sum(c_ for _, c_ in segs[v]))
         binning([cams[v]])
-        pairs.append(int(npairs.item()))
+        pairs.append(int(npairs[0].item()))
         ents.append(int(ranges[:, 1].max().item()) if sup else 0)
         raster([cams[v]], c)
         cnt.append([int(x) for x in c.cpu().tolist()])
@@ -332,19 +348,22 @@ def run_prefetch(vd, frames=240, slots=8, M=3):
     cap = int(ref.capacity * 1.05) + 4096
     del ref
 
+    def listed(f):  # stored list length: super-tile entries
+        return f.num_entries if f.num_entries is not None else f.num_pairs
+
     def timed(fn, interactive):
         mx = torch.zeros(1, dtype=torch.int64, device="cuda")
         for i in range(len(path)):  # the same host work as the timed pass
-            torch.maximum(mx, fn(i).num_pairs, out=mx)
+            torch.maximum(mx, listed(fn(i)), out=mx)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(len(path)):
-            torch.maximum(mx, fn(i).num_pairs, out=mx)
+            torch.maximum(mx, listed(fn(i)), out=mx)
             if interactive:
                 torch.cuda.current_stream().synchronize()
         torch.cuda.synchronize()
         ms = 1000.0 * (time.perf_counter() - t0) / len(path)
-        assert int(mx.item()) <= cap, "pair buffer overflow in the timed region"
+        assert int(mx.item()) <= cap, "list buffer overflow in the timed region"
         return ms
 
     K = len(vd.seg_begin) - 1
@@ -533,11 +552,19 @@ def run_fwd_bwd(n, n_views, steps, warmup, mode):
     wall = time.perf_counter() - t0
     assert int(npairs.item()) <= ft.renderer.capacity, "pair buffer overflow"
     ph = [sum(e[k].elapsed_time(e[k + 1]) for e in evs) / steps / n_views for k in range(5)]
+    # work of the backward (untimed): blends of the 8 views from the
+    # instrumented forward, and the visible records
+    f = ft.renderer.render(g, cams)
+    cnt = P.seele_rasterize_fwd_counted(f.splats, f.sorted_ids, f.tile_ranges, cams, st)[3]
+    blends = int(cnt[1].item())
+    n_vis = int((f.n_tiles > 0).sum().item())
+    del f
     out = dict(ms_per_view=ph[0] + ph[3], fwd_ms_per_view=ph[0], loss_ms_per_view=ph[1],
                flip_ms_per_view=ph[2], bwd_ms_per_view=ph[3], adam_ms_per_view=ph[4],
                finetune_step_ms_per_view=1000.0 * wall / steps / n_views,
                loss_first=float(losses[0].mean().item()), loss_last=float(losses[-1].mean().item()),
-               gaussians=n, views=n_views, width=1280, height=720)
+               gaussians=n, views=n_views, width=1280, height=720, blends=blends,
+               visible_records=n_vis)
     log(f"[bench] fwd+bwd {mode}: {out['ms_per_view']:.3f} ms/view (fwd {ph[0]:.3f}, bwd "
         f"{ph[3]:.3f}); loss {ph[1]:.3f}, FLIP {ph[2]:.3f}, Adam {ph[4]:.3f}; whole step "
         f"{out['finetune_step_ms_per_view']:.3f} ms/view; loss {out['loss_first']:.5f} -> "
@@ -589,7 +616,7 @@ def run_batched(n, n_views, mode, reps=3):
         f = r.render(g, cams, check=False)
     torch.cuda.synchronize()
     eager_ms = 1000.0 * (time.perf_counter() - t0) / reps / n_views
-    assert int(f.num_pairs.item()) <= r.capacity
+    assert f.list_need() <= r.capacity
 
     # batched frame in a HIP graph (static buffers, device-side counts)
     V = len(cams)
@@ -604,7 +631,7 @@ def run_batched(n, n_views, mode, reps=3):
     ids = torch.empty(cap, dtype=torch.int32, device="cuda")
     keys = torch.empty(cap if sup else 1, dtype=torch.int32, device="cuda")
     ranges = torch.empty((NS if sup else TT, 2), dtype=torch.int32, device="cuda")
-    npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+    npairs = torch.empty(2 if sup else 1, dtype=torch.int64, device="cuda")
     image = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
     final_T = torch.empty(npix, dtype=torch.float32, device="cuda")
     n_contrib = torch.empty(npix, dtype=torch.int32, device="cuda")
@@ -646,11 +673,12 @@ def run_batched(n, n_views, mode, reps=3):
         graph.replay()
     torch.cuda.synchronize()
     graph_ms = 1000.0 * (time.perf_counter() - t0) / reps / n_views
-    assert int(npairs.item()) <= cap, "pair buffer overflow in the graph"
+    assert int(npairs[-1].item()) <= cap, "list buffer overflow in the graph"
     out = dict(sequential_ms_per_view=seq_ms, batched_ms_per_view=eager_ms,
                graph_ms_per_view=graph_ms, tile=st.tile, lds_batch=st.lds_batch, schedule=sch,
                lists=lists,
-               pairs=int(npairs.item()), views=n_views, gaussians=n,
+               pairs=int(npairs[0].item()),
+               entries=int(npairs[1].item()) if sup else None, views=n_views, gaussians=n,
                autotune=[dict(t) for t in tuned["table"]])
     log(f"[bench] batched {mode}: sequential {seq_ms:.3f} ms/view, batched {eager_ms:.3f}, "
         f"graph {graph_ms:.3f}")
@@ -726,10 +754,11 @@ def main():
         results[name] = run_form(name, forms[name], cams, args.steps, args.warmup, args.lists)
         if "extra" in forms[name]:
             results[name].update(forms[name]["extra"])
-            results[name]["psnr_vs_plain_full"] = hp_quality(forms[name]["full_g"], forms[name],
-                                                             cams)
-            log(f"[bench] {name}: PSNR vs the plain full-scene image "
-                f"{results[name]['psnr_vs_plain_full']:.2f} dB")
+        if "full_g" in forms[name]:
+            results[name].update(form_quality(forms[name]["full_g"], forms[name], cams))
+            log(f"[bench] {name}: vs the plain full-scene image PSNR "
+                f"{results[name]['psnr_vs_plain_full']:.2f} dB, max abs "
+                f"{results[name]['max_abs_vs_plain_full']:.3e}")
         log(f"[bench] t+{time.time() - t_start:.0f}s form {name} done")
     prefetch = None
     if not args.no_prefetch and "hp_built" in forms:
@@ -790,6 +819,18 @@ def main():
         "bin_sort": dict(bound="hbm", achieved=b_ach, peak=PEAK_HBM / 1e9, unit="GB/s",
                          frac=b_ach / (PEAK_HBM / 1e9)),
     }
+    if fwd_bwd is not None:
+        # backward of the 8-view 720p fine-tuning frame: per blend ~40 lane-ops,
+        # per visible record ~300 (the preprocessing chain), per Gaussian 236 B
+        # of gradients written; priced against the VALU peak
+        fb = fwd_bwd["plain"]
+        b_ops = OPS_BWD_BLEND * fb["blends"] + OPS_BWD_RECORD * fb["visible_records"]
+        b_s = fb["bwd_ms_per_view"] * fb["views"] * 1e-3
+        stage_roof["raster_bwd"] = dict(
+            bound="alu", achieved=b_ops / b_s / 1e12, peak=PEAK_LANE_OPS / 1e12,
+            unit="Tlane-op/s", frac=b_ops / b_s / PEAK_LANE_OPS,
+            grad_bytes_GBps=236 * fb["gaussians"] / b_s / 1e9,
+            workload="1.0M Gaussians, 8 x 1280x720, plain")
     # the dominant single kernel: the rasterizer or the preprocessing kernel
     if st["raster"] >= st["preprocess"]:
         kname = "raster_fwd_super" if head.get("lists") == "super" else "raster_fwd"

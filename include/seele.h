@@ -207,12 +207,16 @@ int64_t seele_total_super_tiles(const seele_camera* cams, int32_t n_views, int32
  *   entry_ids  device [capacity] uint32: record ids v*n + i, same order
  *   st_ranges  device [n_super_tiles][2] int32: [start, end) into the entries
  *              (start = end = 0 for an empty super-tile)
- *   num_pairs  device [1] int64: Gaussian-tile pairs the frame needs (as for
- *              seele_bin_sort; entries never outnumber pairs).
- * Tile t's list of seele_bin_sort is exactly the subsequence of its
- * super-tile's entries whose clip covers t.  Workspace, capacity, overflow
- * (every range empty, entries not written) and limits are those of
- * seele_bin_sort; the workspace size is seele_bin_sort_workspace_size's. */
+ *   num_pairs  device [2] int64: the Gaussian-tile pairs of the frame (as
+ *              for seele_bin_sort), then the entries it needs (never more
+ *              than the pairs).
+ * Here `capacity` bounds the entries: a frame overflows when its entries
+ * exceed it (every range written empty, entries not written), however many
+ * pairs it has; the caller reads num_pairs[1], grows both buffers and calls
+ * again.  Tile t's list of seele_bin_sort is exactly the subsequence of its
+ * super-tile's entries whose clip covers t.  Workspace and other limits are
+ * those of seele_bin_sort; the workspace size is
+ * seele_bin_sort_workspace_size's. */
 int32_t seele_bin_sort_super(const seele_splat* splats, const int32_t* n_tiles, int64_t n,
                              const seele_camera* cams, int32_t n_views, int32_t tile,
                              void* workspace, size_t workspace_bytes, uint32_t* entry_keys,
@@ -244,7 +248,9 @@ enum {
 /* seele_bin_sort (flags 0) or seele_bin_sort_super (SEELE_BIN_SUPER), either
  * one optionally from a staged workspace (SEELE_BIN_STAGED); results are
  * identical in every case.  entry_keys is used with SEELE_BIN_SUPER only;
- * ids is sorted_ids / entry_ids; ranges is tile_ranges / st_ranges. */
+ * ids is sorted_ids / entry_ids; ranges is tile_ranges / st_ranges;
+ * num_pairs has 1 element (per-tile lists) or 2 (SEELE_BIN_SUPER: pairs,
+ * entries), and capacity bounds the pairs or the entries respectively. */
 int32_t seele_bin_sort_ex(int32_t flags, const seele_splat* splats, const int32_t* n_tiles,
                           int64_t n, const seele_camera* cams, int32_t n_views, int32_t tile,
                           void* workspace, size_t workspace_bytes, uint32_t* entry_keys,

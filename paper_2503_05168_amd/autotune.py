@@ -56,7 +56,7 @@ def _time_frame(renderer: Renderer, g, cams, segments, reps: int) -> float:
         f = renderer.render(g, cams, segments, check=False)
     stop.record()
     torch.cuda.synchronize()
-    assert int(f.num_pairs.item()) <= renderer.capacity
+    assert f.list_need() <= renderer.capacity
     return start.elapsed_time(stop) / reps
 
 
@@ -78,9 +78,9 @@ def autotune(g, cams, settings: Settings | None = None, segments=None, reps: int
                         ms=c["ms"], table=c["table"], cached=True)
     table = []
     best = None
-    skipped_tiles = set()
+    skipped = set()  # (tile, lists) whose lists do not fit one call
     for tile, batch, sch, lists in _candidates(tiles, schedules):
-        if tile in skipped_tiles:
+        if (tile, lists) in skipped:
             continue
         st = dataclasses.replace(settings, tile=tile, lds_batch=batch)
         try:
@@ -91,7 +91,8 @@ def autotune(g, cams, settings: Settings | None = None, segments=None, reps: int
                               skipped=str(e)))
             if log:
                 log(f"[autotune] tile={tile} batch={batch}: skipped ({e})")
-            skipped_tiles.add(tile)  # the pair count depends on the tile size only
+            # the list length depends on the tile size and the list form only
+            skipped.add((tile, lists))
             continue
         table.append(dict(tile=tile, lds_batch=batch, schedule=sch, lists=lists, ms=ms))
         if log:

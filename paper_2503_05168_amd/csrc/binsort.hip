@@ -44,6 +44,7 @@ struct Hdr {
   uint64_t p_total;    // pairs the frame needs
   uint32_t n_ent;      // super-tile entries (0 when the frame overflows)
   uint32_t n_seg;      // write segments
+  uint64_t e_total;    // entries the frame needs (counted with atomics)
 };
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -58,6 +59,7 @@ __global__ void k_zero_hdr(Hdr* h) {
     h->p_total = 0;
     h->n_ent = 0;
     h->n_seg = 0;
+    h->e_total = 0;
   }
 }
 
@@ -201,12 +203,15 @@ __device__ uint64_t scan_in_place(uint64_t* __restrict__ partial, int64_t nb) {
 
 // One workgroup.  mode 1 with partial2 also scans the entry partials after
 // the pair partials (mode 2's result), in the same launch.
+// With super_lists the entries, not the pairs, must fit the capacity, and
+// num_pairs[1] receives the entry count.
 __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __restrict__ partial,
                                                                  int64_t nb, Hdr* __restrict__ hdr,
                                                                  int mode, int64_t capacity,
                                                                  int64_t* __restrict__ num_pairs,
                                                                  uint64_t* __restrict__ partial2 =
-                                                                     nullptr) {
+                                                                     nullptr,
+                                                                 int super_lists = 0) {
   const uint64_t carry = scan_in_place(partial, nb);
   uint64_t carry2 = 0;
   if (partial2) carry2 = scan_in_place(partial2, nb);
@@ -215,9 +220,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t* __rest
       hdr->n_vis = (uint32_t)carry;
     } else if (mode == 1) {
       hdr->p_total = carry;
-      *num_pairs = (int64_t)carry;
+      hdr->e_total = carry2;
+      num_pairs[0] = (int64_t)carry;
+      if (super_lists) num_pairs[1] = (int64_t)carry2;
       hdr->n_pairs = carry <= (uint64_t)capacity ? (uint32_t)carry : 0u;
-      if (partial2) hdr->n_ent = carry <= (uint64_t)capacity ? (uint32_t)carry2 : 0u;
+      const bool fits = (super_lists ? carry2 : carry) <= (uint64_t)capacity;
+      if (partial2) hdr->n_ent = fits ? (uint32_t)carry2 : 0u;
     } else if (mode == 2) {
       hdr->n_ent = hdr->p_total <= (uint64_t)capacity ? (uint32_t)carry : 0u;
     } else if (mode == 3) {
@@ -257,46 +265,42 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
   }
 }
 
-static_assert(B >= 256, "one thread per stage slot of a span");
-
-// Staged compaction: span s (256 records) holds its visible records' keys
-// and ids at stage slots [256 s, 256 s + count); after the scan of the counts
-// (in place) the run goes to [off[s], off[s] + count).
-__global__ __launch_bounds__(B) void k_span_gather(const uint64_t* __restrict__ off, int64_t nspan,
-                                                    const Hdr* __restrict__ hdr,
-                                                    const uint32_t* __restrict__ skeys,
-                                                    const uint32_t* __restrict__ sids,
-                                                    uint32_t* __restrict__ keys,
-                                                    uint32_t* __restrict__ vals) {
-  const uint64_t nvis = hdr->n_vis;
-  for (int64_t s = blockIdx.x; s < nspan; s += gridDim.x) {
-    const uint64_t a = off[s];
-    const uint64_t e = s + 1 < nspan ? off[s + 1] : nvis;
-    if ((uint64_t)threadIdx.x < e - a) {
-      keys[a + threadIdx.x] = skeys[s * 256 + threadIdx.x];
-      vals[a + threadIdx.x] = sids[s * 256 + threadIdx.x];
-    }
-  }
-}
-
 // ---- stable LSD radix sort of (u32 key, u32 value) with a device-side count
 //
 // A radix block owns BLK = 256 * IT consecutive items; a fixed grid loops
 // over the live blocks.  hist layout: [digit][block] with row stride
 // `stride`.
 
+// Input items: either [0, *d_count) or (staged, d_count null) the stage
+// slots [0, nslots) of which slot j is live when j % 256 < span_cnt[j / 256];
+// the staged pass also clears the header's totals for the later kernels.
+__device__ __forceinline__ bool radix_item_live(int64_t idx, uint32_t count,
+                                                const uint64_t* __restrict__ span_cnt) {
+  if (idx >= count) return false;
+  return !span_cnt || (uint64_t)(idx & 255) < span_cnt[idx >> 8];
+}
+
 template <int IT>
 __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ d_count, int shift,
                                                    int bits, uint32_t* __restrict__ hist,
-                                                   int stride) {
+                                                   int stride,
+                                                   const uint64_t* __restrict__ span_cnt = nullptr,
+                                                   uint32_t nslots = 0, Hdr* hdr = nullptr) {
   constexpr int BLK = B * IT;
   __shared__ uint32_t h[WAVES][256];
   const int radix = 1 << bits;
   const int w = threadIdx.x >> 6;
-  const uint32_t count = *d_count;
+  const uint32_t count = d_count ? *d_count : nslots;
   const uint32_t nbl = (uint32_t)(((uint64_t)count + BLK - 1) / BLK);
   const uint32_t mask = (uint32_t)radix - 1u;
+  if (hdr && blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->n_pairs = 0;
+    hdr->p_total = 0;
+    hdr->n_ent = 0;
+    hdr->n_seg = 0;
+    hdr->e_total = 0;
+  }
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
     for (int d = threadIdx.x; d < WAVES * 256; d += B) (&h[0][0])[d] = 0;
     __syncthreads();
@@ -304,7 +308,8 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ k
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int64_t idx = begin + it * B + threadIdx.x;
-      if (idx < count) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
+      if (radix_item_live(idx, count, span_cnt))
+        atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < radix; d += B) {
@@ -320,12 +325,14 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ k
 // One block per digit: exclusive scan of that digit's per-block counts over
 // the live blocks, in place (16 consecutive entries per thread); the digit
 // total goes to digit_total[d].
+// (d_count null: the count is nslots.)
 __global__ __launch_bounds__(B) void k_radix_rowscan(uint32_t* __restrict__ hist, int stride,
                                                       const uint32_t* __restrict__ d_count,
-                                                      int blk, uint32_t* __restrict__ digit_total) {
+                                                      int blk, uint32_t* __restrict__ digit_total,
+                                                      uint32_t nslots = 0) {
   constexpr int R = 16;
   __shared__ uint32_t s[WAVES + 1];
-  const int nblocks = (int)(((uint64_t)*d_count + blk - 1) / blk);
+  const int nblocks = (int)(((uint64_t)(d_count ? *d_count : nslots) + blk - 1) / blk);
   uint32_t* row = hist + (int64_t)blockIdx.x * stride;
   uint32_t carry = 0;
   for (int base = 0; base < nblocks; base += B * R) {
@@ -361,7 +368,8 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count,
     int shift, int bits, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ digit_total, int stride) {
+    const uint32_t* __restrict__ digit_total, int stride,
+    const uint64_t* __restrict__ span_cnt = nullptr, uint32_t nslots = 0, Hdr* hdr = nullptr) {
   constexpr int BLK = B * IT;
   __shared__ uint32_t s_k[BLK];
   __shared__ uint32_t s_v[BLK];
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
   __shared__ uint32_t s_loc[256];
   __shared__ uint32_t s_w[WAVES][256];
   __shared__ uint32_t s_tmp[WAVES + 1];
-  const uint32_t count = *d_count;
+  const uint32_t count = d_count ? *d_count : nslots;
   const uint32_t nbl = (uint32_t)(((uint64_t)count + BLK - 1) / BLK);
   if (blockIdx.x >= nbl) return;  // uniform per block
   const int radix = 1 << bits;
@@ -381,6 +389,8 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<uint32_t>(t, s_tmp, tot);
     if (tid < radix) s_dig[tid] = ex;
+    // a staged pass learns the number of live items here
+    if (hdr && blockIdx.x == 0 && tid == 0) hdr->n_vis = tot;
   }
   const uint64_t lt = lanemask_lt();
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
@@ -394,13 +404,14 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int64_t idx = wbase + it * 64 + lane;
-      k[it] = idx < count ? kin[idx] : 0u;
-      v[it] = idx < count ? vin[idx] : 0u;
+      const bool live = radix_item_live(idx, count, span_cnt);
+      k[it] = live ? kin[idx] : 0u;
+      v[it] = live ? vin[idx] : 0u;
+      rank[it] = live ? 0u : 0xffffffffu;  // marks a dead slot until ranked
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int64_t idx = wbase + it * 64 + lane;
-      const bool valid = idx < count;
+      const bool valid = rank[it] == 0u;
       const uint32_t d = (k[it] >> shift) & mask;
       uint64_t peers = __ballot(valid);
       for (int b = 0; b < bits; ++b) {
@@ -410,12 +421,12 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
       }
       const uint32_t below = (uint32_t)__popcll(peers & lt);
       const uint32_t before = s_w[w][d];
-      rank[it] = before + below;
+      rank[it] = valid ? before + below : 0xffffffffu;
       if (valid && below == 0) s_w[w][d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();  // s_w complete
     // per digit: wave offsets, block total, block-local digit start
-    uint32_t dtot = 0;
+    uint32_t dtot = 0, n_here = 0;
     if (tid < radix) {
 #pragma unroll
       for (int ww = 0; ww < WAVES; ++ww) {
@@ -428,12 +439,12 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
       uint32_t tot;
       const uint32_t ex = block_exclusive_scan<uint32_t>(tid < radix ? dtot : 0u, s_tmp, tot);
       if (tid < radix) s_loc[tid] = ex;
+      n_here = tot;  // live items of the block
     }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int64_t idx = wbase + it * 64 + lane;
-      if (idx < count) {
+      if (rank[it] != 0xffffffffu) {
         const uint32_t d = (k[it] >> shift) & mask;
         const uint32_t lp = s_loc[d] + s_w[w][d] + rank[it];
         s_k[lp] = k[it];
@@ -441,7 +452,6 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
       }
     }
     __syncthreads();
-    const uint32_t n_here = (uint32_t)min<int64_t>(BLK, (int64_t)count - begin);
     for (uint32_t j = tid; j < n_here; j += B) {
       const uint32_t kk = s_k[j];
       const uint32_t d = (kk >> shift) & mask;
@@ -545,7 +555,7 @@ __global__ __launch_bounds__(B) void k_entry_emit(const uint32_t* __restrict__ i
   const int w = threadIdx.x >> 6, lane = lane_id();
   const uint32_t nv = hdr->n_vis;
   const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
-  if (begin >= nv || hdr->p_total > (uint64_t)capacity) return;  // per wave; no barriers
+  if (begin >= nv || hdr->n_ent == 0) return;  // overflow (or nothing to emit); per wave
   uint64_t carry = partial[(int64_t)blockIdx.x * WAVES + w];
 #pragma unroll 1
   for (int it = 0; it < kWaveSpan / 64; ++it) {
@@ -672,6 +682,304 @@ __global__ void k_st_ranges(const uint32_t* __restrict__ keys, const Hdr* __rest
     if (i == 0 || (keys[i - 1] & kStMask) != s) st_range[2 * (int64_t)s] = (int32_t)i;
     if (i == cnt - 1 || (keys[i + 1] & kStMask) != s)
       st_range[2 * (int64_t)s + 1] = (int32_t)(i + 1);
+  }
+}
+
+// ---- one-pass super-tile bucketing (frames with at most kEmitMaxSt
+// super-tiles over all views)
+//
+// The depth-ordered records are cut into blocks of kEmitBlock.  k_st_count
+// counts each block's entries per super-tile (hist[s][block]) and the frame's
+// pair and entry totals; a row scan over the blocks of every super-tile and a
+// scan of the super-tile totals give each (super-tile, block) its first slot;
+// k_st_emit then writes every entry straight to its slot.  Inside a block,
+// per-wave counts order the waves; inside a wave the entries are walked in
+// (record, row-major super-tile) order, 64 at a time, and an entry's rank
+// among the step's entries of the same super-tile comes from ballots over the
+// super-tile bits.  A record has at most one entry per super-tile, so entries
+// of one super-tile keep the records' depth order: the lists equal those of
+// the stable radix sort by super-tile id.
+constexpr int kEmitMaxSt = 2048;
+constexpr int kEmitPerThread = 16;
+constexpr int kEmitBlock = B * kEmitPerThread;      // records per block
+constexpr int kEmitWaveRecs = kEmitBlock / WAVES;   // records per wave
+
+// k / d for k < 2^22 (float quotient estimate, corrected once).
+__device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t d) {
+  uint32_t q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)d));
+  const int32_t rem = (int32_t)(k - q * d);
+  if (rem < 0) --q;
+  else if (rem >= (int32_t)d) ++q;
+  return q;
+}
+
+// One depth-ordered record: its clipped rectangle, entry count, entry-row
+// width, its view's super-tile grid width and first super-tile.
+struct EmitRec {
+  Rect r;
+  uint32_t m, sw, sgw, stb, id;
+};
+
+__device__ __forceinline__ EmitRec emit_rec(uint32_t id, uint32_t rx, uint32_t ry,
+                                            const BinViews& views) {
+  EmitRec e;
+  e.id = id;
+  e.r = Rect{rx & 0xffffu, rx >> 16, ry & 0xffffu, ry >> 16};
+  e.m = st_count(e.r);
+  e.sw = 1;
+  e.sgw = 0;
+  e.stb = 0;
+  if (e.m > 0) {
+    const BinView bv = views.v[view_of(id, views)];
+    e.sgw = ((uint32_t)bv.grid_w + ST - 1) / ST;
+    e.stb = (uint32_t)bv.st_base;
+    e.sw = (e.r.x1 - 1) / ST - e.r.x0 / ST + 1;
+  }
+  return e;
+}
+
+// Add every record's entries to the LDS counts h[super-tile]: rectangles of
+// at most kLaneEntries super-tiles by their own lane, larger ones by the
+// whole wave.  Call with the whole wave.
+__device__ __forceinline__ void count_entries(const EmitRec& e, uint32_t* h, int lane) {
+  if (e.m > 0 && e.m <= kLaneEntries) {
+    for (uint32_t sy = e.r.y0 / ST; sy <= (e.r.y1 - 1) / ST; ++sy)
+      for (uint32_t sx = e.r.x0 / ST; sx <= (e.r.x1 - 1) / ST; ++sx)
+        atomicAdd(&h[e.stb + sy * e.sgw + sx], 1u);
+  }
+  uint64_t big = __ballot(e.m > kLaneEntries);
+  while (big != 0) {
+    const int src = __builtin_ctzll(big);
+    big &= big - 1;
+    const uint32_t mb = __builtin_amdgcn_readlane(e.m, src);
+    const uint32_t swb = __builtin_amdgcn_readlane(e.sw, src);
+    const uint32_t sgwb = __builtin_amdgcn_readlane(e.sgw, src);
+    const uint32_t s0 = __builtin_amdgcn_readlane(
+        e.stb + (e.r.y0 / ST) * e.sgw + e.r.x0 / ST, src);
+    for (uint32_t k = lane; k < mb; k += 64) {
+      const uint32_t dy = div_small(k, swb);
+      atomicAdd(&h[s0 + dy * sgwb + (k - dy * swb)], 1u);
+    }
+  }
+}
+
+__global__ __launch_bounds__(B) void k_st_count(const uint32_t* __restrict__ ids,
+                                                 const uint2* __restrict__ rid, BinViews views,
+                                                 Hdr* __restrict__ hdr,
+                                                 uint32_t* __restrict__ rx_s,
+                                                 uint32_t* __restrict__ ry_s,
+                                                 uint32_t* __restrict__ hist, int stride) {
+  __shared__ uint32_t s_h[kEmitMaxSt];
+  const int tid = threadIdx.x, lane = lane_id();
+  const int n_st = (int)views.n_st;
+  const uint32_t nv = hdr->n_vis;
+  const uint32_t nbl = (nv + kEmitBlock - 1) / kEmitBlock;
+  for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
+    for (int t = tid; t < n_st; t += B) s_h[t] = 0u;
+    __syncthreads();
+    uint64_t c = 0, q = 0;
+#pragma unroll 2
+    for (int it = 0; it < kEmitPerThread; ++it) {
+      const int64_t i = (int64_t)vb * kEmitBlock + it * B + tid;
+      EmitRec e{};
+      e.sw = 1;
+      if (i < nv) {
+        const uint32_t id = ids[i];
+        const uint2 rr = rid[id];
+        const Rect r = rect_of(rr.x, rr.y, views.v[view_of(id, views)]);
+        const uint32_t rx = r.x0 | (r.x1 << 16), ry = r.y0 | (r.y1 << 16);
+        rx_s[i] = rx;
+        ry_s[i] = ry;
+        e = emit_rec(id, rx, ry, views);
+        if (e.m > 0) c += (uint64_t)(r.x1 - r.x0) * (r.y1 - r.y0);
+        q += e.m;
+      }
+      count_entries(e, s_h, lane);
+    }
+    c = wave_sum(c);
+    q = wave_sum(q);
+    if (lane == 0 && q != 0) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->p_total), (unsigned long long)c);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->e_total), (unsigned long long)q);
+    }
+    __syncthreads();
+    for (int t = tid; t < n_st; t += B) hist[(int64_t)t * stride + vb] = s_h[t];
+    __syncthreads();
+  }
+}
+
+// Owner map of positions [0, W) of a wave's entry window: every position
+// takes the largest lane that marked a position at or before it (lane l
+// scans the chunk [l*C, (l+1)*C) after a max-scan of the chunk maxima).
+__device__ __forceinline__ void owner_fill(uint8_t* own, uint32_t W, int lane) {
+  const uint32_t C = (W + 63) / 64;
+  const uint32_t c0 = (uint32_t)lane * C;
+  uint32_t run = 0;
+  for (uint32_t c = 0; c < C; ++c)
+    if (c0 + c < W) run = max(run, (uint32_t)own[c0 + c]);
+  uint32_t inc_max = run;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc_max, d, 64);
+    if (lane >= d) inc_max = max(inc_max, y);
+  }
+  uint32_t cur = __shfl_up(inc_max, 1, 64);
+  if (lane == 0) cur = 0;
+  wave_lds_sync();
+  for (uint32_t c = 0; c < C; ++c)
+    if (c0 + c < W) {
+      cur = max(cur, (uint32_t)own[c0 + c]);
+      own[c0 + c] = (uint8_t)cur;
+    }
+}
+
+// NST: LDS capacity in super-tiles (a multiple of the block size, >= n_st).
+// Block 0 also writes every super-tile range ([0, 0) when empty or when the
+// frame overflows the capacity), the pair count and the header totals; on
+// overflow no entry is written.
+template <int NST>
+__global__ __launch_bounds__(B) void k_st_emit(const uint32_t* __restrict__ ids,
+                                                const uint32_t* __restrict__ rx_s,
+                                                const uint32_t* __restrict__ ry_s, BinViews views,
+                                                Hdr* __restrict__ hdr,
+                                                const uint32_t* __restrict__ hist, int stride,
+                                                const uint32_t* __restrict__ st_total,
+                                                int64_t capacity, int nbits,
+                                                uint32_t* __restrict__ ekeys,
+                                                uint32_t* __restrict__ evals,
+                                                int32_t* __restrict__ st_range,
+                                                int64_t* __restrict__ num_pairs, int super_lists) {
+  static_assert(NST % B == 0, "whole super-tiles per thread");
+  constexpr int PT = NST / B;
+  __shared__ uint32_t s_base[NST];
+  __shared__ uint32_t s_w[WAVES][NST];
+  __shared__ uint8_t s_own[WAVES][kStage];
+  __shared__ uint32_t s_tmp[WAVES + 1];
+  const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  const int n_st = (int)views.n_st;
+  const uint32_t nv = hdr->n_vis;
+  const uint64_t P = hdr->p_total, E = hdr->e_total;
+  // the stored lists must fit: entries for super-tile lists, pairs otherwise
+  const bool fits = (super_lists ? E : P) <= (uint64_t)capacity;
+  // first slot of every super-tile: exclusive scan of the totals
+  uint32_t tv[PT], start[PT], sum = 0;
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    const int st = tid * PT + r;
+    tv[r] = st < n_st ? st_total[st] : 0u;
+    sum += tv[r];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan<uint32_t>(sum, s_tmp, tot);
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    start[r] = run;
+    run += tv[r];
+  }
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int st = tid * PT + r;
+      if (st < n_st) {
+        const bool ok = fits && tv[r] > 0;
+        st_range[2 * (int64_t)st] = ok ? (int32_t)start[r] : 0;
+        st_range[2 * (int64_t)st + 1] = ok ? (int32_t)(start[r] + tv[r]) : 0;
+      }
+    }
+    if (tid == 0) {
+      num_pairs[0] = (int64_t)P;
+      if (super_lists) num_pairs[1] = (int64_t)E;
+      hdr->n_pairs = P <= (uint64_t)capacity ? (uint32_t)P : 0u;
+      hdr->n_ent = fits ? (uint32_t)E : 0u;
+    }
+  }
+  if (!fits) return;  // uniform over the grid
+  const uint32_t nbl = (nv + kEmitBlock - 1) / kEmitBlock;
+  const uint64_t lt = lanemask_lt();
+  for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int st = tid * PT + r;
+      if (st < n_st) s_base[st] = start[r] + hist[(int64_t)st * stride + vb];
+    }
+    for (int t = tid; t < WAVES * NST; t += B) (&s_w[0][0])[t] = 0u;
+    __syncthreads();
+    const int64_t wbeg = (int64_t)vb * kEmitBlock + w * kEmitWaveRecs;
+    // this wave's entries per super-tile
+#pragma unroll 1
+    for (int step = 0; step < kEmitWaveRecs / 64; ++step) {
+      const int64_t i = wbeg + step * 64 + lane;
+      EmitRec e{};
+      e.sw = 1;
+      if (i < nv) e = emit_rec(ids[i], rx_s[i], ry_s[i], views);
+      count_entries(e, s_w[w], lane);
+    }
+    __syncthreads();
+    // wave w's first slot per super-tile
+    for (int st = tid; st < n_st; st += B) {
+      uint32_t b = s_base[st];
+#pragma unroll
+      for (int ww = 0; ww < WAVES; ++ww) {
+        const uint32_t c = s_w[ww][st];
+        s_w[ww][st] = b;
+        b += c;
+      }
+    }
+    __syncthreads();
+    uint32_t* next = s_w[w];
+    uint8_t* own = s_own[w];
+#pragma unroll 1
+    for (int step = 0; step < kEmitWaveRecs / 64; ++step) {
+      const int64_t i = wbeg + step * 64 + lane;
+      if (wbeg + step * 64 >= (int64_t)nv) break;  // wave-uniform
+      EmitRec e{};
+      e.sw = 1;
+      if (i < nv) e = emit_rec(ids[i], rx_s[i], ry_s[i], views);
+      const uint32_t inc = wave_inclusive_scan(e.m);
+      const uint32_t rel = inc - e.m;
+      const uint32_t T = __builtin_amdgcn_readlane(inc, 63);
+      const uint32_t rxp = e.r.x0 | (e.r.x1 << 16), ryp = e.r.y0 | (e.r.y1 << 16);
+      const uint32_t swg = e.sw | (e.sgw << 16);
+      for (uint32_t a = 0; a < T; a += kStage) {
+        const uint32_t W = min(kStage, T - a);
+        for (uint32_t j = lane; j < W; j += 64) own[j] = 0;
+        wave_lds_sync();
+        if (e.m > 0 && rel < a + W && rel + e.m > a) own[max(rel, a) - a] = (uint8_t)lane;
+        wave_lds_sync();
+        owner_fill(own, W, lane);
+        wave_lds_sync();
+        for (uint32_t j0 = 0; j0 < W; j0 += 64) {
+          const uint32_t j = j0 + (uint32_t)lane;
+          const bool valid = j < W;
+          const int o = valid ? (int)own[j] : 0;
+          const uint32_t ro = __shfl(rel, o, 64);
+          const uint32_t rxo = __shfl(rxp, o, 64), ryo = __shfl(ryp, o, 64);
+          const uint32_t swgo = __shfl(swg, o, 64), stbo = __shfl(e.stb, o, 64);
+          const uint32_t ido = __shfl(e.id, o, 64);
+          uint32_t key = 0, st = 0;
+          if (valid) {
+            const Rect ro_r{rxo & 0xffffu, rxo >> 16, ryo & 0xffffu, ryo >> 16};
+            key = entry_key(ro_r, a + j - ro, swgo & 0xffffu, swgo >> 16, stbo);
+            st = key & kStMask;
+          }
+          uint64_t peers = __ballot(valid);
+          for (int b = 0; b < nbits; ++b) {
+            const bool bit = (st >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+          }
+          const uint32_t below = (uint32_t)__popcll(peers & lt);
+          const uint32_t before = next[st];
+          if (valid && below == 0) next[st] = before + (uint32_t)__popcll(peers);
+          if (valid) {
+            ekeys[before + below] = key;
+            evals[before + below] = ido;
+          }
+        }
+        wave_lds_sync();  // map reads finish before the next window's writes
+      }
+    }
+    __syncthreads();  // s_base and s_w are rewritten for the next block
   }
 }
 
@@ -914,22 +1222,26 @@ int64_t nblocks_for(int64_t n) { return (n + TILE - 1) / TILE; }
 
 int grid_for(int64_t nb) { return (int)std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGrid)); }
 
-// One radix pass over a device-side count of at most max_count items.
+// One radix pass over a device-side count of at most max_count items, or
+// (span_cnt given, d_count null) over the live slots of a staged input of
+// max_count slots; the staged pass also resets the header and sets n_vis.
 template <int IT>
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       const uint32_t* d_count, int64_t max_count, int shift, int bits,
-                      uint32_t* hist, uint32_t* digits, hipStream_t stream) {
+                      uint32_t* hist, uint32_t* digits, hipStream_t stream,
+                      const uint64_t* span_cnt = nullptr, Hdr* hdr = nullptr) {
   constexpr int BLK = B * IT;
   const int64_t nb = (max_count + BLK - 1) / BLK;
   if (nb == 0) return hipSuccess;
   const int stride = (int)nb;
   const dim3 grid(grid_for(nb));
+  const uint32_t nslots = span_cnt ? (uint32_t)max_count : 0u;
   hipLaunchKernelGGL((k_radix_hist<IT>), grid, dim3(B), 0, stream, kin, d_count, shift, bits, hist,
-                     stride);
+                     stride, span_cnt, nslots, hdr);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(B), 0, stream, hist, stride, d_count,
-                     BLK, digits);
+                     BLK, digits, nslots);
   hipLaunchKernelGGL((k_radix_scatter<IT>), grid, dim3(B), 0, stream, kin, vin, kout, vout,
-                     d_count, shift, bits, hist, digits, stride);
+                     d_count, shift, bits, hist, digits, stride, span_cnt, nslots, hdr);
   return hipGetLastError();
 }
 
@@ -996,8 +1308,12 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   const int64_t nb_rec = std::max<int64_t>(nblocks_for(n_records), 1);
   const int64_t nb_span = std::max<int64_t>((n_records + kSpanBlock - 1) / kSpanBlock, 1);
   const int64_t rblk = (int64_t)B * kRadixIT;
-  const int64_t nb_hist =
-      std::max<int64_t>({(n_records + rblk - 1) / rblk, (capacity + rblk - 1) / rblk, 1});
+  // buffer 1 of the depth sort also holds the stage: 256 slots per span of
+  // 256 records and view, so up to n_records + 256 * kMaxViewsBin; the first
+  // staged pass runs over all of them
+  const int64_t stage_slots = n_records + 256 * (int64_t)kMaxViewsBin;
+  const int64_t nb_hist = std::max<int64_t>({(stage_slots + rblk - 1) / rblk,
+                                             (capacity + rblk - 1) / rblk, 1});
   const int64_t nb_part = std::max<int64_t>(
       {WAVES * nb_span, nblocks_for(p.max_st), nblocks_for(n_tiles_total), 1});
   size_t off = 0;
@@ -1009,13 +1325,10 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_hdr = take(sizeof(Hdr));
   p.off_partial = take(8 * (size_t)nb_part);
   p.off_partial2 = take(8 * WAVES * (size_t)nb_span);
-  // buffer 1 of the depth sort also holds the stage: 256 slots per span of
-  // 256 records and view, so up to n_records + 256 * kMaxViewsBin
-  const size_t stage_slots = (size_t)n_records + 256 * (size_t)kMaxViewsBin;
   p.off_dkeys0 = take(4 * (size_t)n_records);
-  p.off_dkeys1 = take(4 * stage_slots);
+  p.off_dkeys1 = take(4 * (size_t)stage_slots);
   p.off_dvals0 = take(4 * (size_t)n_records);
-  p.off_dvals1 = take(4 * stage_slots);
+  p.off_dvals1 = take(4 * (size_t)stage_slots);
   p.off_skeys0 = take(4 * (size_t)capacity);
   p.off_skeys1 = take(4 * (size_t)capacity);
   p.off_svals0 = take(4 * (size_t)capacity);
@@ -1024,8 +1337,9 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_ry = take(4 * (size_t)n_records);
   p.off_rid = take(8 * (size_t)n_records);
   p.off_span = take(8 * ((size_t)(n_records + 255) / 256 + kMaxViewsBin));
-  p.off_hist = take(4 * 256 * (size_t)nb_hist);
-  p.off_digits = take(4 * 256);
+  const int64_t nb_emit = (n_records + kEmitBlock - 1) / kEmitBlock;
+  p.off_hist = take(4 * std::max<size_t>(256 * (size_t)nb_hist, (size_t)kEmitMaxSt * nb_emit));
+  p.off_digits = take(4 * (size_t)kEmitMaxSt);
   p.off_st_range = take(8 * (size_t)p.max_st);
   p.off_st_seg = take(4 * (size_t)p.max_st);
   p.off_seg_st = take(16 * (size_t)p.max_seg);  // per segment {super-tile, begin, end, 0}
@@ -1076,83 +1390,126 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
   const int64_t TT = p.n_tiles_total;
   hipError_t e;
 
-  hipLaunchKernelGGL(k_zero_hdr, dim3(1), dim3(64), 0, stream, hdr);
-  if (n_st > 0)
+  const int64_t R = p.n_records;
+  const int nbR = (int)((R + kSpanBlock - 1) / kSpanBlock);  // record-span workgroups
+  // one-pass super-tile bucketing when the frame has few enough super-tiles
+  const bool emit1 = n_st <= kEmitMaxSt;
+  // a staged depth sort resets the header in its first pass
+  if (!(staged && nbR > 0)) hipLaunchKernelGGL(k_zero_hdr, dim3(1), dim3(64), 0, stream, hdr);
+  if (!emit1 && n_st > 0)
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((2 * n_st + 255) / 256)), dim3(256), 0, stream,
                        st_range, 2 * n_st, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t R = p.n_records;
-  const int nbR = (int)((R + kSpanBlock - 1) / kSpanBlock);  // record-span workgroups
+  const uint32_t* ids_sorted = dv[0];
   if (nbR > 0) {
-    // 1. visible records (n_tiles > 0) in id order with their depth keys
+    // 1. visible records with their depth keys, stably sorted by float32
+    //    depth bits (4 x 8-bit passes)
     if (staged) {
-      // from the stage: scan of the span counts, then each span's run copied
+      // pass 0 reads the live slots of the stage (buffer 1) directly; the
+      // passes end in buffer 1
       const BinStage bs = bin_stage_of(p, ws, views.n);
-      const int64_t nspan = (int64_t)views.n_views * bs.n_blocks;
-      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, bs.span_count,
-                         nspan, hdr, 0, p.capacity, num_pairs);
-      hipLaunchKernelGGL(k_span_gather, dim3(grid_for(nspan)), dim3(B), 0, stream,
-                         bs.span_count, nspan, hdr, bs.keys, bs.ids, dk[0], dv[0]);
+      const int64_t nslots = (int64_t)views.n_views * bs.n_blocks * 256;
+      e = radix_pass<kRadixIT>(bs.keys, bs.ids, dk[0], dv[0], nullptr, nslots, 0, 8, hist, digits,
+                               stream, bs.span_count, hdr);
+      if (e != hipSuccess) return e;
+      for (int pass = 1; pass < 4; ++pass) {
+        const int src = (pass + 1) & 1, dst = src ^ 1;
+        e = radix_pass<kRadixIT>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8,
+                                 hist, digits, stream);
+        if (e != hipSuccess) return e;
+      }
+      ids_sorted = dv[1];
     } else {
       hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
       hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
                          WAVES * (int64_t)nbR, hdr, 0, p.capacity, num_pairs);
       hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats,
                          partial, dk[0], dv[0], rid);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      for (int pass = 0; pass < 4; ++pass) {
+        const int src = pass & 1, dst = src ^ 1;
+        e = radix_pass<kRadixIT>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8,
+                                 hist, digits, stream);
+        if (e != hipSuccess) return e;
+      }
     }
+  }
+  const uint32_t* ekeys;
+  const uint32_t* evals;
+  if (emit1) {
+    // 2. entries per (super-tile, record block), their slots, the emission
+    uint32_t* ek = super ? entry_keys : at(p.off_skeys0);
+    uint32_t* ev = super ? sorted_ids : at(p.off_svals0);
+    const int64_t nbE = std::max<int64_t>((R + kEmitBlock - 1) / kEmitBlock, 1);
+    const int stride = (int)nbE;
+    const dim3 gridE(grid_for(nbE));
+    if (nbR > 0)
+      hipLaunchKernelGGL(k_st_count, gridE, dim3(B), 0, stream, ids_sorted, rid, views, hdr, rx_s,
+                         ry_s, hist, stride);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)std::max<int64_t>(n_st, 1)), dim3(B), 0,
+                       stream, hist, stride, d_nvis, kEmitBlock, digits, 0u);
+    int nbits = 0;
+    while (((int64_t)1 << nbits) < n_st) ++nbits;
+    if (n_st <= 512)
+      hipLaunchKernelGGL(k_st_emit<512>, gridE, dim3(B), 0, stream, ids_sorted, rx_s, ry_s, views,
+                         hdr, hist, stride, digits, p.capacity, nbits, ek, ev, st_range,
+                         num_pairs, super ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_st_emit<kEmitMaxSt>, gridE, dim3(B), 0, stream, ids_sorted, rx_s, ry_s,
+                         views, hdr, hist, stride, digits, p.capacity, nbits, ek, ev, st_range,
+                         num_pairs, super ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    //    stable sort by float32 depth bits (4 x 8-bit passes, ends in buffer 0)
-    for (int pass = 0; pass < 4; ++pass) {
-      const int src = pass & 1, dst = src ^ 1;
-      e = radix_pass<kRadixIT>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8, hist,
-                               digits, stream);
-      if (e != hipSuccess) return e;
-    }
+    ekeys = ek;
+    evals = ev;
+  } else {
     // 2. pair and entry totals (pairs -> num_pairs)
-    hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, dv[0], rid, views, hdr,
-                       rx_s, ry_s, partial, partial2);
+    if (nbR > 0)
+      hipLaunchKernelGGL(k_pair_count, dim3(nbR), dim3(B), 0, stream, ids_sorted, rid, views, hdr,
+                         rx_s, ry_s, partial, partial2);
+    // pair partials, then entry partials (whose count depends on the pair
+    // total), in one launch
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
+                       WAVES * (int64_t)nbR, hdr, 1, p.capacity, num_pairs, partial2,
+                       super ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    //    entries, then sorted by super-tile id (balanced digit widths <= 8).
+    //    Per-tile lists: the value buffers alternate between svals0 and
+    //    sorted_ids so that the last pass ends in svals0.  Super-tile lists:
+    //    keys and values end in the caller's entry_keys and sorted_ids.
+    int st_bits = 0;
+    while (st_bits < 24 && ((int64_t)1 << st_bits) < n_st) ++st_bits;
+    const int passes = std::max(1, (st_bits + 7) / 8);
+    const int per = (st_bits + passes - 1) / passes;
+    const int fin = passes & 1;  // buffer index the last pass writes
+    uint32_t* sk[2] = {at(p.off_skeys0), at(p.off_skeys1)};
+    uint32_t* sv[2] = {(passes % 2 == 0) ? at(p.off_svals0) : sorted_ids,
+                       (passes % 2 == 0) ? sorted_ids : at(p.off_svals0)};
+    if (super) {
+      sk[fin] = entry_keys;
+      sk[fin ^ 1] = at(p.off_skeys0);
+      sv[fin] = sorted_ids;
+      sv[fin ^ 1] = at(p.off_svals0);
+    }
+    if (nbR > 0)
+      hipLaunchKernelGGL(k_entry_emit, dim3(nbR), dim3(B), 0, stream, ids_sorted, rx_s, ry_s,
+                         views, hdr, partial2, p.capacity, sk[0], sv[0]);
+    int shift = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int src = pass & 1, dst = src ^ 1;
+      const int bits = std::min(per, st_bits - shift);
+      e = radix_pass<kRadixIT>(sk[src], sv[src], sk[dst], sv[dst], d_nent, p.capacity, shift,
+                               bits, hist, digits, stream);
+      if (e != hipSuccess) return e;
+      shift += bits;
+    }
+    ekeys = sk[fin];
+    evals = sv[fin];
+    // 3. super-tile ranges
+    if (p.capacity > 0)
+      hipLaunchKernelGGL(k_st_ranges, dim3(grid_for((p.capacity + 255) / 256)), dim3(256), 0,
+                         stream, ekeys, hdr, st_range);
   }
-  // pair partials, then entry partials (whose count depends on the pair
-  // total), in one launch
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
-                     WAVES * (int64_t)nbR, hdr, 1, p.capacity, num_pairs, partial2);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  //    entries, then sorted by super-tile id (balanced digit widths <= 8).
-  //    Per-tile lists: the value buffers alternate between svals0 and
-  //    sorted_ids so that the last pass ends in svals0.  Super-tile lists:
-  //    keys and values end in the caller's entry_keys and sorted_ids.
-  int st_bits = 0;
-  while (st_bits < 24 && ((int64_t)1 << st_bits) < n_st) ++st_bits;
-  const int passes = std::max(1, (st_bits + 7) / 8);
-  const int per = (st_bits + passes - 1) / passes;
-  const int fin = passes & 1;  // buffer index the last pass writes
-  uint32_t* sk[2] = {at(p.off_skeys0), at(p.off_skeys1)};
-  uint32_t* sv[2] = {(passes % 2 == 0) ? at(p.off_svals0) : sorted_ids,
-                     (passes % 2 == 0) ? sorted_ids : at(p.off_svals0)};
-  if (super) {
-    sk[fin] = entry_keys;
-    sk[fin ^ 1] = at(p.off_skeys0);
-    sv[fin] = sorted_ids;
-    sv[fin ^ 1] = at(p.off_svals0);
-  }
-  if (nbR > 0)
-    hipLaunchKernelGGL(k_entry_emit, dim3(nbR), dim3(B), 0, stream, dv[0], rx_s, ry_s, views, hdr,
-                       partial2, p.capacity, sk[0], sv[0]);
-  int shift = 0;
-  for (int pass = 0; pass < passes; ++pass) {
-    const int src = pass & 1, dst = src ^ 1;
-    const int bits = std::min(per, st_bits - shift);
-    e = radix_pass<kRadixIT>(sk[src], sv[src], sk[dst], sv[dst], d_nent, p.capacity, shift, bits,
-                             hist, digits, stream);
-    if (e != hipSuccess) return e;
-    shift += bits;
-  }
-  const uint32_t* ekeys = sk[fin];
-  const uint32_t* evals = sv[fin];
-  // 3. super-tile ranges, segments, per-tile counts, tile ranges, write
-  if (p.capacity > 0)
-    hipLaunchKernelGGL(k_st_ranges, dim3(grid_for((p.capacity + 255) / 256)), dim3(256), 0,
-                       stream, ekeys, hdr, st_range);
+  // 3. per-tile lists: segments, per-tile counts, tile ranges, write
   if (super) return hipGetLastError();
   const int nbS = (int)nblocks_for(n_st);
   if (nbS > 0) {

@@ -8,12 +8,13 @@
 // For a blended entry j with colour c_j and the colour S accumulated behind
 // it (background included):
 //   T_j = T / (1 - alpha_j)                     (transmittance before j)
-//   dL/dalpha_j = sum_ch g_ch (T_j c_j - S / (1 - alpha_j))
+//   dL/dalpha_j = T_j (g . c_j) - (g . S) / (1 - alpha_j)
 //   dL/dc_j = T_j alpha_j g
 // and through alpha = o exp(-q/2), q = d^T A d (zero where the alpha clamp
-// was active).  Per-Gaussian gradients are reduced across the wave (DPP),
-// summed over the block's waves in LDS, and added to the record's 9 gradient
-// slots in HBM with one set of float atomics per tile.
+// was active).  Only the scalar g . S is carried (S itself is never needed).
+// Per-record terms are reduced across the wave (DPP), summed over the
+// block's waves in LDS, turned into the record's 9 gradient slots and added
+// to HBM with one set of float atomics per tile.
 //
 // As in the forward kernels, each wave visits only the records whose culling
 // bit for its 8x8 block is set (quad_mask), and only those below the largest
@@ -94,14 +95,23 @@ __device__ __forceinline__ void wave_accumulate9(const float (&v)[9], float* acc
 }
 
 // One record of the reverse walk for one pixel: recompute alpha, undo the
-// blend (T, S) if the forward blended it, and add the record's 2D gradients
-// (reduced over the wave) to the record's LDS accumulator `acc` (9 floats,
-// shared by the block's waves and flushed to HBM once per batch).
+// blend (T and GS = g . S, the loss gradient dotted with the colour S
+// accumulated behind the record, background included) if the forward blended
+// it, and add the record's per-pixel terms (reduced over the wave) to its
+// LDS accumulator `acc` (9 floats, shared by the block's waves and turned
+// into gradients once per batch).  With d = pixel - mean, A = conic and
+// p = alpha dL/dalpha below the alpha clamp:
+//   dL/do    = p / o
+//   dL/dA    = -p d d^T / 2   (off-diagonal: -p dx dy for the b of q)
+//   dL/dmean = p A d
+// so the accumulated terms are p, p dx, p dy, p dx^2, p dx dy, p dy^2 and
+// the colour terms T_j alpha g; the record's constants (A, 1/o) multiply the
+// sums once per batch.
 template <int MODE>
 __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx, float fy,
                                            int leader_lane, int lane, float amin, float amax,
-                                           float g0, float g1, float g2, float& T, float& S0,
-                                           float& S1, float& S2, float* acc) {
+                                           float g0, float g1, float g2, float& T, float& GS,
+                                           float* acc) {
   const float4 a = e.a, b = e.b;  // b.y = log2(opacity), as the forward stages it
   float dx, dy;
   const float qo = splat_qo(fx, fy, a.x, a.y, a.z, a.w, b.x, b.y, dx, dy);
@@ -113,42 +123,53 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
     const float lead = __shfl(alpha, leader_lane, 64);
     blended = blended && lead >= amin;
   }
-  float gmx = 0.0f, gmy = 0.0f, gca = 0.0f, gcb = 0.0f, gcc = 0.0f, gop = 0.0f;
+  float tp = 0.0f, tx = 0.0f, ty = 0.0f, txx = 0.0f, txy = 0.0f, tyy = 0.0f;
   float gr = 0.0f, gg = 0.0f, gbl = 0.0f;
   if (blended) {
-    const float4 cc = e.c;
+    const float cb = e.c.x;
     const float om = 1.0f - alpha;
     const float rom = __builtin_amdgcn_rcpf(om);  // 1 - alpha >= 1 - alpha_max > 0
     const float Tj = T * rom;
     const float ta = Tj * alpha;
     // fused multiply-adds from here on: the gradient chain needs no
     // bit-identity with the forward (only alpha and the decisions do)
-    const float dal = __builtin_fmaf(
-        g2, __builtin_fmaf(Tj, cc.x, -S2 * rom),
-        __builtin_fmaf(g1, __builtin_fmaf(Tj, b.w, -S1 * rom),
-                       g0 * __builtin_fmaf(Tj, b.z, -S0 * rom)));
+    const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, b.w, g0 * b.z));  // g . c
+    // dL/dalpha = T_j (g . c) - (g . S) / (1 - alpha)
+    const float dal = __builtin_fmaf(Tj, gc, -(rom * GS));
+    GS = __builtin_fmaf(ta, gc, GS);
+    T = Tj;
     gr = ta * g0;
     gg = ta * g1;
     gbl = ta * g2;
-    S0 = __builtin_fmaf(ta, b.z, S0);
-    S1 = __builtin_fmaf(ta, b.w, S1);
-    S2 = __builtin_fmaf(ta, cc.x, S2);
-    T = Tj;
     if (raw <= amax) {
-      gop = dal * raw * e.inv_o;  // d alpha / d o = alpha / o below the clamp
-      const float dq = -0.5f * alpha * dal;  // dL/dq
-      // q = a dx^2 + 2 b dx dy + c dy^2 with d = pixel - mean: dq/dmean = -2 A d
-      gmx = -2.0f * dq * __builtin_fmaf(cc.y, dx, cc.z * dy);
-      gmy = -2.0f * dq * __builtin_fmaf(cc.z, dx, cc.w * dy);
-      gca = dq * dx * dx;
-      gcb = dq * 2.0f * dx * dy;
-      gcc = dq * dy * dy;
+      tp = alpha * dal;
+      tx = tp * dx;
+      ty = tp * dy;
+      txx = tx * dx;
+      txy = tx * dy;
+      tyy = ty * dy;
     }
   }
   if (__ballot(blended) != 0) {
-    const float v[9] = {gmx, gmy, gca, gcb, gcc, gop, gr, gg, gbl};
+    const float v[9] = {tx, ty, txx, txy, tyy, tp, gr, gg, gbl};
     wave_accumulate9(v, acc, lane);
   }
+}
+
+// Gradient slots of a record (mean x, mean y, conic a, b, c, opacity, r, g,
+// b) from its accumulated terms {sum p dx, sum p dy, sum p dx^2,
+// sum p dx dy, sum p dy^2, sum p, colour x3}.
+__device__ __forceinline__ void record_grads(const LdsBwd& e, const float* t, float* out) {
+  const float ca = e.c.y, cbb = e.c.z, cc = e.c.w;
+  out[0] = __builtin_fmaf(ca, t[0], cbb * t[1]);
+  out[1] = __builtin_fmaf(cbb, t[0], cc * t[1]);
+  out[2] = -0.5f * t[2];
+  out[3] = -t[3];
+  out[4] = -0.5f * t[4];
+  out[5] = t[5] * e.inv_o;
+  out[6] = t[6];
+  out[7] = t[7];
+  out[8] = t[8];
 }
 
 template <int TS, int MODE>
@@ -207,7 +228,8 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
     g1 = g[hw + pix];
     g2 = g[2 * hw + pix];
   }
-  float S0 = T * rp.bg0, S1 = T * rp.bg1, S2 = T * rp.bg2;
+  // g . S with S = T bg, the colour behind the last blended record
+  float GS = T * __builtin_fmaf(g2, rp.bg2, __builtin_fmaf(g1, rp.bg1, g0 * rp.bg0));
 
   if (tid == 0) s_max = 0;
   __syncthreads();
@@ -244,18 +266,18 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
         const int k = c + 63 - __builtin_clzll(bits);
         bits &= ~(1ull << (k - c));
         blend_grad<MODE>(s_e[k], lo + k < last, fx, fy, leader_lane, lane, amin, amax, g0, g1,
-                         g2, T, S0, S1, S2, s_g[k]);
+                         g2, T, GS, s_g[k]);
       }
     }
     __syncthreads();
     // one set of global atomics per record and tile
     if (tid < hi - lo) {
       float* dst = grad2d + (int64_t)s_id[tid] * 9;
+      float gq[9];
+      record_grads(s_e[tid], s_g[tid], gq);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const float v = s_g[tid][q];
-        if (v != 0.0f) atomicAdd(dst + q, v);
-      }
+      for (int q = 0; q < 9; ++q)
+        if (gq[q] != 0.0f) atomicAdd(dst + q, gq[q]);
     }
   }
 }

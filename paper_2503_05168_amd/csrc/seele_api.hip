@@ -287,7 +287,7 @@ const char* seele_status_string(int32_t s) {
   }
 }
 
-int32_t seele_abi_version(void) { return 100; }
+int32_t seele_abi_version(void) { return 101; }
 
 int64_t seele_total_tiles(const seele_camera* cams, int32_t n_views, int32_t tile) {
   if (!cams || n_views < 1 || (tile != 8 && tile != 16)) return -1;

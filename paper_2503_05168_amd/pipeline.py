@@ -191,7 +191,7 @@ def seele_bin_sort_ex(splats, n_tiles, n: int, cams, tile: int, capacity: int,
     _need(workspace, bin_sort_workspace_size(V * n, capacity, TT), torch.uint8, "workspace")
     _need(ids, capacity, torch.int32, "ids")
     _need(ranges, 2 * nr, torch.int32, "ranges")
-    _need(num_pairs, 1, torch.int64, "num_pairs")
+    _need(num_pairs, 2 if super_lists else 1, torch.int64, "num_pairs")
     if super_lists:
         _need(entry_keys, capacity, torch.int32, "entry_keys")
     if not staged:
@@ -248,7 +248,8 @@ def total_super_tiles(cams, tile: int) -> int:
 def seele_bin_sort_super(splats, n_tiles, n: int, cams, tile: int, capacity: int,
                          workspace: torch.Tensor | None = None, entry_keys=None, entry_ids=None,
                          st_ranges=None, num_pairs=None, stream=None):
-    """Super-tile lists: (entry_keys, entry_ids, st_ranges, num_pairs, workspace)."""
+    """Super-tile lists: (entry_keys, entry_ids, st_ranges, num_pairs, workspace);
+    num_pairs holds [pairs, entries] and capacity bounds the entries."""
     dev = splats.device
     V = len(cams)
     TT = total_tiles(cams, tile)
@@ -263,13 +264,13 @@ def seele_bin_sort_super(splats, n_tiles, n: int, cams, tile: int, capacity: int
     if st_ranges is None:
         st_ranges = torch.empty((NS, 2), dtype=torch.int32, device=dev)
     if num_pairs is None:
-        num_pairs = torch.empty(1, dtype=torch.int64, device=dev)
+        num_pairs = torch.empty(2, dtype=torch.int64, device=dev)
     _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
     _need(n_tiles, V * n, torch.int32, "n_tiles")
     _need(entry_keys, capacity, torch.int32, "entry_keys")
     _need(entry_ids, capacity, torch.int32, "entry_ids")
     _need(st_ranges, 2 * NS, torch.int32, "st_ranges")
-    _need(num_pairs, 1, torch.int64, "num_pairs")
+    _need(num_pairs, 2, torch.int64, "num_pairs")
     _need(workspace, ws_bytes, torch.uint8, "workspace")
     st = A.lib().seele_bin_sort_super(_p(splats), _p(n_tiles), n, A.camera_array(cams), V, tile,
                                       _p(workspace), workspace.numel(), _p(entry_keys),
@@ -540,18 +541,27 @@ class Frame:
     num_pairs: torch.Tensor
     cams: list = field(default_factory=list)
     # super-tile lists (Renderer(lists="super")): sorted_ids holds the entry
-    # ids, tile_ranges the super-tile ranges and entry_keys the entry keys
+    # ids, tile_ranges the super-tile ranges and entry_keys the entry keys;
+    # num_entries the entries the frame needs
     entry_keys: torch.Tensor | None = None
+    num_entries: torch.Tensor | None = None
 
     def images(self):
         return split_views(self.image, self.cams, 3)
 
+    def list_need(self) -> int:
+        """Length of the stored lists the frame needs (entries for super-tile
+        lists, pairs otherwise): at most the capacity when the frame fit."""
+        t = self.num_entries if self.num_entries is not None else self.num_pairs
+        return int(t.item())
 
-MAX_PAIRS = (1 << 31) - 1  # pair capacity limit of seele_bin_sort (int32 tile ranges)
+
+MAX_PAIRS = (1 << 31) - 1  # list capacity limit of seele_bin_sort (int32 ranges)
 
 
 class CapacityError(RuntimeError):
-    """A frame needs more Gaussian-tile pairs than one bin_sort call can hold."""
+    """A frame needs longer lists (pairs, or super-tile entries) than one
+    bin_sort call can hold."""
 
 
 class Renderer:
@@ -599,17 +609,19 @@ class Renderer:
             ids = torch.empty(cap, dtype=torch.int32, device=dev)
             ranges = torch.empty((total_super_tiles(cams, s.tile) if sup else TT, 2),
                                  dtype=torch.int32, device=dev)
-            npairs = torch.empty(1, dtype=torch.int64, device=dev)
+            npairs = torch.empty(2 if sup else 1, dtype=torch.int64, device=dev)
             seele_bin_sort_ex(splats, n_tiles, g.n, cams, s.tile, self.capacity, self._ws, ids,
                               ranges, npairs, keys, super_lists=sup, staged=True, stream=stream)
             if not check:
                 break
-            need = int(npairs.item())
+            # super-tile lists store entries, per-tile lists pairs
+            need = int(npairs[1 if sup else 0].item())
             if need <= self.capacity:
                 break
             if need > MAX_PAIRS:
-                raise CapacityError(f"the frame needs {need} Gaussian-tile pairs, more than the "
-                                    f"{MAX_PAIRS} one call can sort: render fewer views per call")
+                what = "super-tile entries" if sup else "Gaussian-tile pairs"
+                raise CapacityError(f"the frame needs {need} {what}, more than the {MAX_PAIRS} "
+                                    f"one call can sort: render fewer views per call")
             self.capacity = min(int(need * 1.5) + 1024, MAX_PAIRS)
         if self.lists == "super":
             image, final_T, n_contrib = seele_rasterize_fwd_super(splats, keys, ids, ranges, cams,
@@ -621,5 +633,5 @@ class Renderer:
             order = "heaviest" if self.schedule == "queue_heavy" else "list"
             image, final_T, n_contrib, self._qws = seele_rasterize_fwd_queue(
                 splats, ids, ranges, cams, s, order, self._qws, stream=stream)
-        return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs, list(cams),
-                     keys)
+        return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs[:1],
+                     list(cams), keys, npairs[1:] if sup else None)

@@ -124,7 +124,7 @@ def test_super_lists_batched_eager_and_graph_replay(c5_small):
         keys = torch.empty(cap, dtype=torch.int32, device="cuda")
         ids = torch.empty(cap, dtype=torch.int32, device="cuda")
         ranges = torch.empty((NS, 2), dtype=torch.int32, device="cuda")
-        npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+        npairs = torch.empty(2, dtype=torch.int64, device="cuda")  # pairs, entries
         image = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
         final_T = torch.empty(npix, dtype=torch.float32, device="cuda")
         n_contrib = torch.empty(npix, dtype=torch.int32, device="cuda")

@@ -67,7 +67,7 @@ def super_frame(scene, cams, st, capacity=1 << 22, segments=None):
     splats, n_tiles = seele_preprocess(g, cams, st, segments)
     keys, ids, rng, npairs, ws = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile,
                                                       capacity)
-    need = int(npairs.item())
+    need = int(npairs[1].item())  # entries
     if need > capacity:  # the frame reported its need: sort again with room for it
         keys, ids, rng, npairs, _ = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile,
                                                          need)
@@ -81,7 +81,8 @@ def check_against_tile_path(scene, cams, st, counters=True, segments=None):
                                                                          segments=segments)
     f = gu.run(scene, cams, st, capacity=1 << 22, segments=segments)
     P = int(f.num_pairs.item())
-    assert int(npairs.item()) == P
+    assert int(npairs[0].item()) == P
+    assert int(npairs[1].item()) == int(rng[:, 1].max().item()) <= P
     assert rng.shape == (total_super_tiles(cams, st.tile), 2)
     # the super-tile lists expand to the per-tile lists exactly
     e_ids, e_ranges = expand_super(keys.cpu().numpy(), ids.cpu().numpy(), rng.cpu().numpy(),
@@ -145,14 +146,28 @@ def test_super_overflow_and_empty_scene():
     keys, ids, rng, npairs, _ = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile, 64)
     img, T, nc = seele_rasterize_fwd_super(splats, keys, ids, rng, cams, st)
     torch.cuda.synchronize()
-    assert int(npairs.item()) > 64
+    pairs, entries = int(npairs[0].item()), int(npairs[1].item())
+    assert pairs >= entries > 64
     assert int(rng.abs().sum().item()) == 0  # every super-tile list left empty
     assert torch.all(nc == 0) and torch.all(T == 1.0)
+    # the capacity bounds the entries: exactly the entry count fits although
+    # the pairs exceed it, and the lists equal those sorted with room to spare
+    assert pairs > entries
+    big = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile, pairs)
+    exact = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile, entries)
+    torch.cuda.synchronize()
+    assert torch.equal(big[3], exact[3])
+    assert torch.equal(big[2], exact[2]) and int(exact[2][:, 1].max().item()) == entries
+    assert torch.equal(big[0][:entries], exact[0][:entries])
+    assert torch.equal(big[1][:entries], exact[1][:entries])
+    short = seele_bin_sort_super(splats, n_tiles, g.n, cams, st.tile, entries - 1)
+    torch.cuda.synchronize()
+    assert torch.equal(short[3], big[3]) and int(short[2].abs().sum().item()) == 0
     # nothing visible: all lists empty, background everywhere
     far = [synthetic.look_at((0.0, 0.0, 30.0), target=(0.0, 0.0, 60.0), width=96, height=64)]
     st2 = Settings(bg=(0.25, 0.5, 0.75))
     _, _, _, keys, ids, rng, npairs, img, T, nc = super_frame(scene, far, st2)
-    assert int(npairs.item()) == 0 and int(rng.abs().sum().item()) == 0
+    assert int(npairs.abs().sum().item()) == 0 and int(rng.abs().sum().item()) == 0
     assert torch.all(T == 1.0) and torch.all(nc == 0)
     im = img.reshape(3, -1)
     for ch, b in enumerate(st2.bg):
@@ -284,7 +299,7 @@ def test_staged_preprocessing_bins_identically(name, build, settings, sup):
             keys = torch.empty(cap, dtype=torch.int32, device="cuda")
             ids = torch.empty(cap, dtype=torch.int32, device="cuda")
             rng = torch.empty((NR, 2), dtype=torch.int32, device="cuda")
-            npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+            npairs = torch.empty(2 if sup else 1, dtype=torch.int64, device="cuda")
             if staged:
                 sp, nt = seele_preprocess_staged(g, cams, st, cap, ws)
             else:
@@ -292,7 +307,7 @@ def test_staged_preprocessing_bins_identically(name, build, settings, sup):
             seele_bin_sort_ex(sp, nt, n, cams, st.tile, cap, ws, ids, rng, npairs, keys,
                               super_lists=sup, staged=staged)
             torch.cuda.synchronize()
-            need = int(npairs.item())
+            need = int(npairs[-1].item())  # the stored list length
             if need <= cap:
                 break
             cap = need
@@ -329,7 +344,7 @@ def test_staged_preprocessing_with_inactive_segments():
         keys = torch.empty(cap, dtype=torch.int32, device="cuda")
         ids = torch.empty(cap, dtype=torch.int32, device="cuda")
         rng = torch.empty((NS, 2), dtype=torch.int32, device="cuda")
-        npairs = torch.empty(1, dtype=torch.int64, device="cuda")
+        npairs = torch.empty(2, dtype=torch.int64, device="cuda")
         if staged:
             sp, nt = seele_preprocess_staged(g, cams, st, cap, ws, segs)
         else:
@@ -337,7 +352,7 @@ def test_staged_preprocessing_with_inactive_segments():
         seele_bin_sort_ex(sp, nt, n, cams, st.tile, cap, ws, ids, rng, npairs, keys,
                           super_lists=True, staged=staged)
         torch.cuda.synchronize()
-        res.append((nt, keys, ids, rng, int(npairs.item())))
+        res.append((nt, keys, ids, rng, int(npairs[0].item())))
     (nt0, k0, i0, r0, p0), (nt1, k1, i1, r1, p1) = res
     assert p0 == p1 and 0 < p0 <= cap and torch.equal(nt0, nt1) and torch.equal(r0, r1)
     ne = int(r0[:, 1].max().item())
