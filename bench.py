@@ -91,6 +91,8 @@ def parse():
                     help="weight of the FLIP term in the integrated fine-tuning run")
     ap.add_argument("--ft-lr-scale", type=float, default=1.0,
                     help="scale of the 3DGS learning rates in the integrated fine-tuning run")
+    ap.add_argument("--no-cluster-sweep", action="store_true",
+                    help="skip the cluster-count x neighbour-count sweep")
     ap.add_argument("--no-groups", action="store_true",
                     help="skip the contribution-aware group-size sweep")
     ap.add_argument("--lists", choices=("super", "tile"), default="super",
@@ -507,6 +509,41 @@ def run_group_sweep(g, cams, steps, warmup, groups=((1, 1), (2, 2), (2, 4), (4, 
     return out
 
 
+def run_cluster_sweep(g, cams, steps, warmup, clusters=(8, 16, 24, 32), Ms=(0, 1, 3, 7)):
+    """Sensitivity of hybrid preprocessing to the number of view clusters
+    and of neighbouring clusters M (the structure of Fig. 6, on the
+    synthetic 1080p scene): the view-dependent representation is built from
+    the 128 sampled orbit poses for each cluster count, then rendered with
+    the nearest cluster + M neighbours and the opacity-aware extent;
+    frames/s, active Gaussians, and the image error against the plain
+    full-scene image over the first four orbit views."""
+    import torch
+    import synthetic
+    import paper_2503_05168_amd as P
+
+    poses = synthetic.sampled_orbit_poses(6, 128, 1920, 1080)
+    out = []
+    for K in clusters:
+        t = time.time()
+        vd = P.build_view_dependent(g, poses, K, k=32, settings=P.Settings(), views_per_call=8)
+        torch.cuda.synchronize()
+        build_s = time.time() - t
+        for M in Ms:
+            if M >= K:
+                continue
+            form = dict(g=vd.gaussians, st=P.Settings(extent="opacity"), hp=vd, M=M)
+            res = run_form(f"built-K{K}-M{M}", form, cams, steps, warmup)
+            q = form_quality(g, form, cams)
+            out.append(dict(clusters=K, M=M, fps=res["fps"], active=res["active"],
+                            visible=res["visible"], build_s=build_s,
+                            shared=vd.stats["shared"], unused=vd.stats["unused"], **q))
+            log(f"[bench] clusters={K} M={M}: {res['fps']:.1f} fps, active {res['active']:.3e}, "
+                f"PSNR vs plain full {q['psnr_vs_plain_full']:.2f} dB")
+        del vd
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_fwd_bwd(n, n_views, steps, warmup, mode):
     """Fine-tuning step of the paper's Sec. 3.5 on the 1.0M-Gaussian workload:
     the 8 views rendered in one batched call, the loss L_3DGS (0.8 L1 + 0.2
@@ -780,6 +817,11 @@ def main():
         groups = run_group_sweep(forms["plain"]["g"], cams, max(8, args.steps // 2),
                                  max(2, args.warmup // 2))
         log(f"[bench] t+{time.time() - t_start:.0f}s group sweep done")
+    clusters = None
+    if not args.no_cluster_sweep and "plain" in forms:
+        clusters = run_cluster_sweep(forms["plain"]["g"], cams, max(8, args.steps // 2),
+                                     max(2, args.warmup // 2))
+        log(f"[bench] t+{time.time() - t_start:.0f}s cluster sweep done")
     fwd_bwd = None
     if not args.no_bwd:
         del forms
@@ -868,6 +910,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batched_64_views": batched,
         "contrib_group_sweep": groups,
+        "hp_cluster_sweep": clusters,
         "scene_prefetch": prefetch,
         "integrated_finetune": finetune,
         "roofline": roof,

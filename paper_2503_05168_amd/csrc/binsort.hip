@@ -688,21 +688,27 @@ __global__ void k_st_ranges(const uint32_t* __restrict__ keys, const Hdr* __rest
 // ---- one-pass super-tile bucketing (frames with at most kEmitMaxSt
 // super-tiles over all views)
 //
-// The depth-ordered records are cut into blocks of kEmitBlock.  k_st_count
-// counts each block's entries per super-tile (hist[s][block]) and the frame's
-// pair and entry totals; a row scan over the blocks of every super-tile and a
-// scan of the super-tile totals give each (super-tile, block) its first slot;
-// k_st_emit then writes every entry straight to its slot.  Inside a block,
-// per-wave counts order the waves; inside a wave the entries are walked in
-// (record, row-major super-tile) order, 64 at a time, and an entry's rank
-// among the step's entries of the same super-tile comes from ballots over the
-// super-tile bits.  A record has at most one entry per super-tile, so entries
-// of one super-tile keep the records' depth order: the lists equal those of
-// the stable radix sort by super-tile id.
+// The depth-ordered records are cut into blocks of EW waves x kEmitWaveRecs
+// records.  k_st_count counts each block's entries per super-tile
+// (hist[s][block]) and the frame's pair and entry totals; a row scan over the
+// blocks of every super-tile and a scan of the super-tile totals give each
+// (super-tile, block) its first slot; k_st_emit then writes every entry
+// straight to its slot.  Inside a block, per-wave counts order the waves;
+// inside a wave the entries are walked in (record, row-major super-tile)
+// order, 64 at a time, and an entry's rank among the step's entries of the
+// same super-tile comes from ballots over the super-tile bits.  A record has
+// at most one entry per super-tile, so entries of one super-tile keep the
+// records' depth order: the lists equal those of the stable radix sort by
+// super-tile id.  Each wave takes 256 records (4 steps of 64) and issues all
+// their loads first; many waves per block keep the per-block count table
+// small while the chip stays full.
 constexpr int kEmitMaxSt = 2048;
-constexpr int kEmitPerThread = 16;
-constexpr int kEmitBlock = B * kEmitPerThread;      // records per block
-constexpr int kEmitWaveRecs = kEmitBlock / WAVES;   // records per wave
+constexpr int kEmitWaveRecs = 256;                  // records per wave
+constexpr int kEmitSteps = kEmitWaveRecs / 64;
+// (super-tile capacity, waves per block) of the two instantiations
+constexpr int kEmitSmallSt = 512, kEmitSmallWaves = 16;
+constexpr int kEmitLargeWaves = 8;
+constexpr int kEmitMinBlock = kEmitLargeWaves * kEmitWaveRecs;  // smallest block (records)
 
 // k / d for k < 2^22 (float quotient estimate, corrected once).
 __device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t d) {
@@ -738,6 +744,12 @@ __device__ __forceinline__ EmitRec emit_rec(uint32_t id, uint32_t rx, uint32_t r
   return e;
 }
 
+__device__ __forceinline__ EmitRec no_rec() {
+  EmitRec e{};
+  e.sw = 1;
+  return e;
+}
+
 // Add every record's entries to the LDS counts h[super-tile]: rectangles of
 // at most kLaneEntries super-tiles by their own lane, larger ones by the
 // whole wave.  Call with the whole wave.
@@ -763,47 +775,86 @@ __device__ __forceinline__ void count_entries(const EmitRec& e, uint32_t* h, int
   }
 }
 
-__global__ __launch_bounds__(B) void k_st_count(const uint32_t* __restrict__ ids,
-                                                 const uint2* __restrict__ rid, BinViews views,
-                                                 Hdr* __restrict__ hdr,
-                                                 uint32_t* __restrict__ rx_s,
-                                                 uint32_t* __restrict__ ry_s,
-                                                 uint32_t* __restrict__ hist, int stride) {
-  __shared__ uint32_t s_h[kEmitMaxSt];
-  const int tid = threadIdx.x, lane = lane_id();
+// Exclusive scan over the NTH threads of a block (NTH / 64 waves); returns
+// the prefix and the total in `total`.  Contains barriers.
+template <int NTH, typename T>
+__device__ __forceinline__ T block_scan_n(T x, T* smem, T& total) {
+  constexpr int NW = NTH / 64;
+  const int w = threadIdx.x >> 6;
+  const T inc = wave_inclusive_scan(x);
+  if (lane_id() == 63) smem[w] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const T s = smem[i];
+    if (i < w) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - x;
+}
+
+// Pairs of block b go to ppart[b] (no atomics: same-address device atomics
+// from every wave serialise across the chip).
+template <int NST, int EW>
+__global__ __launch_bounds__(EW * 64) void k_st_count(const uint32_t* __restrict__ ids,
+                                                       const uint2* __restrict__ rid,
+                                                       BinViews views, const Hdr* __restrict__ hdr,
+                                                       uint32_t* __restrict__ rx_s,
+                                                       uint32_t* __restrict__ ry_s,
+                                                       uint32_t* __restrict__ hist, int stride,
+                                                       uint64_t* __restrict__ ppart) {
+  constexpr int NTH = EW * 64;
+  constexpr int EBLK = EW * kEmitWaveRecs;
+  __shared__ uint32_t s_h[NST];
+  __shared__ uint64_t s_p[EW];
+  const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const int n_st = (int)views.n_st;
   const uint32_t nv = hdr->n_vis;
-  const uint32_t nbl = (nv + kEmitBlock - 1) / kEmitBlock;
+  const uint32_t nbl = (nv + EBLK - 1) / EBLK;
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
-    for (int t = tid; t < n_st; t += B) s_h[t] = 0u;
-    __syncthreads();
-    uint64_t c = 0, q = 0;
-#pragma unroll 2
-    for (int it = 0; it < kEmitPerThread; ++it) {
-      const int64_t i = (int64_t)vb * kEmitBlock + it * B + tid;
-      EmitRec e{};
-      e.sw = 1;
+    for (int t = tid; t < n_st; t += NTH) s_h[t] = 0u;
+    // every load of the thread's records first: ids, then their rectangles
+    uint32_t id[kEmitSteps];
+    uint2 rr[kEmitSteps];
+#pragma unroll
+    for (int it = 0; it < kEmitSteps; ++it) {
+      const int64_t i = (int64_t)vb * EBLK + it * NTH + tid;
+      id[it] = i < nv ? ids[i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kEmitSteps; ++it) {
+      const int64_t i = (int64_t)vb * EBLK + it * NTH + tid;
+      rr[it] = i < nv ? rid[id[it]] : make_uint2(0u, 0u);
+    }
+    __syncthreads();  // s_h cleared
+    uint64_t c = 0;  // pairs of this thread's records
+#pragma unroll
+    for (int it = 0; it < kEmitSteps; ++it) {
+      const int64_t i = (int64_t)vb * EBLK + it * NTH + tid;
+      EmitRec e = no_rec();
       if (i < nv) {
-        const uint32_t id = ids[i];
-        const uint2 rr = rid[id];
-        const Rect r = rect_of(rr.x, rr.y, views.v[view_of(id, views)]);
+        const Rect r = rect_of(rr[it].x, rr[it].y, views.v[view_of(id[it], views)]);
         const uint32_t rx = r.x0 | (r.x1 << 16), ry = r.y0 | (r.y1 << 16);
         rx_s[i] = rx;
         ry_s[i] = ry;
-        e = emit_rec(id, rx, ry, views);
+        e = emit_rec(id[it], rx, ry, views);
         if (e.m > 0) c += (uint64_t)(r.x1 - r.x0) * (r.y1 - r.y0);
-        q += e.m;
       }
       count_entries(e, s_h, lane);
     }
-    c = wave_sum(c);
-    q = wave_sum(q);
-    if (lane == 0 && q != 0) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->p_total), (unsigned long long)c);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->e_total), (unsigned long long)q);
-    }
+    const uint64_t cw = wave_sum(c);
+    if (lane == 0) s_p[w] = cw;
     __syncthreads();
-    for (int t = tid; t < n_st; t += B) hist[(int64_t)t * stride + vb] = s_h[t];
+    for (int t = tid; t < n_st; t += NTH) hist[(int64_t)t * stride + vb] = s_h[t];
+    if (tid == 0) {
+      uint64_t tot = 0;
+#pragma unroll
+      for (int k = 0; k < EW; ++k) tot += s_p[k];
+      ppart[vb] = tot;
+    }
     __syncthreads();
   }
 }
@@ -833,44 +884,53 @@ __device__ __forceinline__ void owner_fill(uint8_t* own, uint32_t W, int lane) {
     }
 }
 
-// NST: LDS capacity in super-tiles (a multiple of the block size, >= n_st).
-// Block 0 also writes every super-tile range ([0, 0) when empty or when the
-// frame overflows the capacity), the pair count and the header totals; on
-// overflow no entry is written.
-template <int NST>
-__global__ __launch_bounds__(B) void k_st_emit(const uint32_t* __restrict__ ids,
-                                                const uint32_t* __restrict__ rx_s,
-                                                const uint32_t* __restrict__ ry_s, BinViews views,
-                                                Hdr* __restrict__ hdr,
-                                                const uint32_t* __restrict__ hist, int stride,
-                                                const uint32_t* __restrict__ st_total,
-                                                int64_t capacity, int nbits,
-                                                uint32_t* __restrict__ ekeys,
-                                                uint32_t* __restrict__ evals,
-                                                int32_t* __restrict__ st_range,
-                                                int64_t* __restrict__ num_pairs, int super_lists) {
-  static_assert(NST % B == 0, "whole super-tiles per thread");
-  constexpr int PT = NST / B;
+// NST: LDS capacity in super-tiles (>= n_st; NBITS = log2 NST bits rank the
+// super-tile ids); EW waves per block.  Block 0
+// also writes every super-tile range ([0, 0) when empty or when the frame
+// overflows the capacity), the counts and the header totals; on overflow no
+// entry is written.
+template <int NST, int EW, int NBITS = (NST <= 512 ? 9 : 11)>
+__global__ __launch_bounds__(EW * 64) void k_st_emit(const uint32_t* __restrict__ ids,
+                                                      const uint32_t* __restrict__ rx_s,
+                                                      const uint32_t* __restrict__ ry_s,
+                                                      BinViews views, Hdr* __restrict__ hdr,
+                                                      const uint32_t* __restrict__ hist,
+                                                      int stride,
+                                                      const uint32_t* __restrict__ st_total,
+                                                      int64_t capacity,
+                                                      uint32_t* __restrict__ ekeys,
+                                                      uint32_t* __restrict__ evals,
+                                                      int32_t* __restrict__ st_range,
+                                                      int64_t* __restrict__ num_pairs,
+                                                      int super_lists,
+                                                      const uint64_t* __restrict__ ppart) {
+  constexpr int NTH = EW * 64;
+  constexpr int EBLK = EW * kEmitWaveRecs;
+  constexpr int PT = (NST + NTH - 1) / NTH;  // super-tiles per thread in the scans
   __shared__ uint32_t s_base[NST];
-  __shared__ uint32_t s_w[WAVES][NST];
-  __shared__ uint8_t s_own[WAVES][kStage];
-  __shared__ uint32_t s_tmp[WAVES + 1];
+  __shared__ uint32_t s_w[EW][NST];
+  __shared__ uint8_t s_own[EW][kStage];
+  __shared__ uint64_t s_tmp[EW + 1];
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const int n_st = (int)views.n_st;
   const uint32_t nv = hdr->n_vis;
-  const uint64_t P = hdr->p_total, E = hdr->e_total;
-  // the stored lists must fit: entries for super-tile lists, pairs otherwise
-  const bool fits = (super_lists ? E : P) <= (uint64_t)capacity;
-  // first slot of every super-tile: exclusive scan of the totals
-  uint32_t tv[PT], start[PT], sum = 0;
+  const uint32_t nbl = (nv + EBLK - 1) / EBLK;
+  // the frame's entries (sum of the super-tile totals) and pairs (sum of the
+  // per-block partials), and the first slot of every super-tile (exclusive
+  // scan of the totals)
+  uint64_t tv[PT], start[PT], sum = 0, psum = 0;
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
     const int st = tid * PT + r;
     tv[r] = st < n_st ? st_total[st] : 0u;
     sum += tv[r];
   }
-  uint32_t tot;
-  uint32_t run = block_exclusive_scan<uint32_t>(sum, s_tmp, tot);
+  for (uint32_t b = tid; b < nbl; b += NTH) psum += ppart[b];
+  uint64_t E, P;
+  uint64_t run = block_scan_n<NTH, uint64_t>(sum, s_tmp, E);
+  block_scan_n<NTH, uint64_t>(psum, s_tmp, P);
+  // the stored lists must fit: entries for super-tile lists, pairs otherwise
+  const bool fits = (super_lists ? E : P) <= (uint64_t)capacity;
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
     start[r] = run;
@@ -894,47 +954,48 @@ __global__ __launch_bounds__(B) void k_st_emit(const uint32_t* __restrict__ ids,
     }
   }
   if (!fits) return;  // uniform over the grid
-  const uint32_t nbl = (nv + kEmitBlock - 1) / kEmitBlock;
   const uint64_t lt = lanemask_lt();
+  uint32_t* next = s_w[w];
+  uint8_t* own = s_own[w];
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
+    const int64_t wbeg = (int64_t)vb * EBLK + w * kEmitWaveRecs;
+    // this wave's records (all loads first)
+    uint32_t rid_[kEmitSteps], rx[kEmitSteps], ry[kEmitSteps];
+#pragma unroll
+    for (int st = 0; st < kEmitSteps; ++st) {
+      const int64_t i = wbeg + st * 64 + lane;
+      const bool in = i < nv;
+      rid_[st] = in ? ids[i] : 0u;
+      rx[st] = in ? rx_s[i] : 0u;
+      ry[st] = in ? ry_s[i] : 0u;
+    }
 #pragma unroll
     for (int r = 0; r < PT; ++r) {
       const int st = tid * PT + r;
-      if (st < n_st) s_base[st] = start[r] + hist[(int64_t)st * stride + vb];
+      if (st < n_st) s_base[st] = (uint32_t)start[r] + hist[(int64_t)st * stride + vb];
     }
-    for (int t = tid; t < WAVES * NST; t += B) (&s_w[0][0])[t] = 0u;
+    for (int t = tid; t < EW * NST; t += NTH) (&s_w[0][0])[t] = 0u;
     __syncthreads();
-    const int64_t wbeg = (int64_t)vb * kEmitBlock + w * kEmitWaveRecs;
-    // this wave's entries per super-tile
-#pragma unroll 1
-    for (int step = 0; step < kEmitWaveRecs / 64; ++step) {
-      const int64_t i = wbeg + step * 64 + lane;
-      EmitRec e{};
-      e.sw = 1;
-      if (i < nv) e = emit_rec(ids[i], rx_s[i], ry_s[i], views);
-      count_entries(e, s_w[w], lane);
-    }
+    // this wave's entries per super-tile (rx = ry = 0: no entries)
+#pragma unroll
+    for (int st = 0; st < kEmitSteps; ++st)
+      count_entries(emit_rec(rid_[st], rx[st], ry[st], views), next, lane);
     __syncthreads();
     // wave w's first slot per super-tile
-    for (int st = tid; st < n_st; st += B) {
+    for (int st = tid; st < n_st; st += NTH) {
       uint32_t b = s_base[st];
 #pragma unroll
-      for (int ww = 0; ww < WAVES; ++ww) {
+      for (int ww = 0; ww < EW; ++ww) {
         const uint32_t c = s_w[ww][st];
         s_w[ww][st] = b;
         b += c;
       }
     }
     __syncthreads();
-    uint32_t* next = s_w[w];
-    uint8_t* own = s_own[w];
 #pragma unroll 1
-    for (int step = 0; step < kEmitWaveRecs / 64; ++step) {
-      const int64_t i = wbeg + step * 64 + lane;
+    for (int step = 0; step < kEmitSteps; ++step) {
       if (wbeg + step * 64 >= (int64_t)nv) break;  // wave-uniform
-      EmitRec e{};
-      e.sw = 1;
-      if (i < nv) e = emit_rec(ids[i], rx_s[i], ry_s[i], views);
+      const EmitRec e = emit_rec(rid_[step], rx[step], ry[step], views);
       const uint32_t inc = wave_inclusive_scan(e.m);
       const uint32_t rel = inc - e.m;
       const uint32_t T = __builtin_amdgcn_readlane(inc, 63);
@@ -952,6 +1013,27 @@ __global__ __launch_bounds__(B) void k_st_emit(const uint32_t* __restrict__ ids,
           const uint32_t j = j0 + (uint32_t)lane;
           const bool valid = j < W;
           const int o = valid ? (int)own[j] : 0;
+          const int o0 = __builtin_amdgcn_readfirstlane(o);
+          if (__ballot(valid && o != o0) == 0) {
+            // every entry of the chunk belongs to one record: distinct
+            // super-tiles, so each lane's rank is 0 and its count 1
+            const uint32_t ro = __builtin_amdgcn_readlane(rel, o0);
+            const uint32_t rxo = __builtin_amdgcn_readlane(rxp, o0);
+            const uint32_t ryo = __builtin_amdgcn_readlane(ryp, o0);
+            const uint32_t swgo = __builtin_amdgcn_readlane(swg, o0);
+            const uint32_t stbo = __builtin_amdgcn_readlane(e.stb, o0);
+            const uint32_t ido = __builtin_amdgcn_readlane(e.id, o0);
+            if (valid) {
+              const Rect ro_r{rxo & 0xffffu, rxo >> 16, ryo & 0xffffu, ryo >> 16};
+              const uint32_t key = entry_key(ro_r, a + j - ro, swgo & 0xffffu, swgo >> 16, stbo);
+              const uint32_t st = key & kStMask;
+              const uint32_t pos = next[st];
+              next[st] = pos + 1u;
+              ekeys[pos] = key;
+              evals[pos] = ido;
+            }
+            continue;
+          }
           const uint32_t ro = __shfl(rel, o, 64);
           const uint32_t rxo = __shfl(rxp, o, 64), ryo = __shfl(ryp, o, 64);
           const uint32_t swgo = __shfl(swg, o, 64), stbo = __shfl(e.stb, o, 64);
@@ -962,11 +1044,15 @@ __global__ __launch_bounds__(B) void k_st_emit(const uint32_t* __restrict__ ids,
             key = entry_key(ro_r, a + j - ro, swgo & 0xffffu, swgo >> 16, stbo);
             st = key & kStMask;
           }
+          // lanes whose super-tile equals this lane's: the AND over the
+          // super-tile bits of (ballot of the bit, inverted where this
+          // lane's bit is 0)
           uint64_t peers = __ballot(valid);
-          for (int b = 0; b < nbits; ++b) {
-            const bool bit = (st >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
+#pragma unroll
+          for (int b = 0; b < NBITS; ++b) {
+            const uint64_t bb = __ballot((st >> b) & 1u);
+            const uint64_t flip = ((st >> b) & 1u) ? 0ull : ~0ull;
+            peers &= bb ^ flip;
           }
           const uint32_t below = (uint32_t)__popcll(peers & lt);
           const uint32_t before = next[st];
@@ -1337,7 +1423,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_ry = take(4 * (size_t)n_records);
   p.off_rid = take(8 * (size_t)n_records);
   p.off_span = take(8 * ((size_t)(n_records + 255) / 256 + kMaxViewsBin));
-  const int64_t nb_emit = (n_records + kEmitBlock - 1) / kEmitBlock;
+  const int64_t nb_emit = (n_records + kEmitMinBlock - 1) / kEmitMinBlock;
   p.off_hist = take(4 * std::max<size_t>(256 * (size_t)nb_hist, (size_t)kEmitMaxSt * nb_emit));
   p.off_digits = take(4 * (size_t)kEmitMaxSt);
   p.off_st_range = take(8 * (size_t)p.max_st);
@@ -1440,24 +1526,32 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     // 2. entries per (super-tile, record block), their slots, the emission
     uint32_t* ek = super ? entry_keys : at(p.off_skeys0);
     uint32_t* ev = super ? sorted_ids : at(p.off_svals0);
-    const int64_t nbE = std::max<int64_t>((R + kEmitBlock - 1) / kEmitBlock, 1);
+    const bool small = n_st <= kEmitSmallSt;
+    const int ebl = (small ? kEmitSmallWaves : kEmitLargeWaves) * kEmitWaveRecs;
+    const int64_t nbE = std::max<int64_t>((R + ebl - 1) / ebl, 1);
     const int stride = (int)nbE;
     const dim3 gridE(grid_for(nbE));
-    if (nbR > 0)
-      hipLaunchKernelGGL(k_st_count, gridE, dim3(B), 0, stream, ids_sorted, rid, views, hdr, rx_s,
-                         ry_s, hist, stride);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)std::max<int64_t>(n_st, 1)), dim3(B), 0,
-                       stream, hist, stride, d_nvis, kEmitBlock, digits, 0u);
-    int nbits = 0;
-    while (((int64_t)1 << nbits) < n_st) ++nbits;
-    if (n_st <= 512)
-      hipLaunchKernelGGL(k_st_emit<512>, gridE, dim3(B), 0, stream, ids_sorted, rx_s, ry_s, views,
-                         hdr, hist, stride, digits, p.capacity, nbits, ek, ev, st_range,
-                         num_pairs, super ? 1 : 0);
-    else
-      hipLaunchKernelGGL(k_st_emit<kEmitMaxSt>, gridE, dim3(B), 0, stream, ids_sorted, rx_s, ry_s,
-                         views, hdr, hist, stride, digits, p.capacity, nbits, ek, ev, st_range,
-                         num_pairs, super ? 1 : 0);
+    if (small) {
+      constexpr int NT = kEmitSmallWaves * 64;
+      if (nbR > 0)
+        hipLaunchKernelGGL((k_st_count<kEmitSmallSt, kEmitSmallWaves>), gridE, dim3(NT), 0, stream,
+                           ids_sorted, rid, views, hdr, rx_s, ry_s, hist, stride, partial);
+      hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)std::max<int64_t>(n_st, 1)), dim3(B), 0,
+                         stream, hist, stride, d_nvis, ebl, digits, 0u);
+      hipLaunchKernelGGL((k_st_emit<kEmitSmallSt, kEmitSmallWaves>), gridE, dim3(NT), 0, stream,
+                         ids_sorted, rx_s, ry_s, views, hdr, hist, stride, digits, p.capacity,
+                         ek, ev, st_range, num_pairs, super ? 1 : 0, partial);
+    } else {
+      constexpr int NT = kEmitLargeWaves * 64;
+      if (nbR > 0)
+        hipLaunchKernelGGL((k_st_count<kEmitMaxSt, kEmitLargeWaves>), gridE, dim3(NT), 0, stream,
+                           ids_sorted, rid, views, hdr, rx_s, ry_s, hist, stride, partial);
+      hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)n_st), dim3(B), 0, stream, hist, stride,
+                         d_nvis, ebl, digits, 0u);
+      hipLaunchKernelGGL((k_st_emit<kEmitMaxSt, kEmitLargeWaves>), gridE, dim3(NT), 0, stream,
+                         ids_sorted, rx_s, ry_s, views, hdr, hist, stride, digits, p.capacity,
+                         ek, ev, st_range, num_pairs, super ? 1 : 0, partial);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ekeys = ek;
     evals = ev;
