@@ -257,6 +257,27 @@ int32_t seele_bin_sort_ex(int32_t flags, const seele_splat* splats, const int32_
                           uint32_t* ids, int64_t capacity, int32_t* ranges, int64_t* num_pairs,
                           void* stream);
 
+/* Bytes of the per-device scratch array behind seele_bin_sort_noalloc. */
+#define SEELE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* seele_bin_sort_ex for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the binning workspace is a file-scope device array of
+ * SEELE_NOALLOC_SCRATCH_BYTES in the library (one per GPU, held until the
+ * process ends), so the call takes no workspace and allocates nothing.
+ * flags: 0 (per-tile lists) or SEELE_BIN_SUPER; SEELE_BIN_STAGED is refused
+ * (its input lives in a caller workspace).  Every other argument, output and
+ * overflow rule is seele_bin_sort_ex's.  SEELE_ERR_CAPACITY when
+ * seele_bin_sort_workspace_size(n_views * n, capacity, total tiles) exceeds
+ * SEELE_NOALLOC_SCRATCH_BYTES (e.g. about 1M records with 2.5M pairs fit).
+ * The array is shared by every call on a GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (different streams or host
+ * threads without ordering) race and give undefined results. */
+int32_t seele_bin_sort_noalloc(int32_t flags, const seele_splat* splats, const int32_t* n_tiles,
+                               int64_t n, const seele_camera* cams, int32_t n_views, int32_t tile,
+                               uint32_t* entry_keys, uint32_t* ids, int64_t capacity,
+                               int32_t* ranges, int64_t* num_pairs, void* stream);
+
 /* Front-to-back blending of every tile of every view (Eqs. 1-2; Algorithm 1
  * when opts->mode == SEELE_RASTER_CONTRIB).
  *   image     device, per view [3][H][W] float32, views concatenated

@@ -14,6 +14,7 @@ from .pipeline import (  # noqa: F401
     seele_bin_sort,
     seele_bin_sort_super,
     seele_bin_sort_ex,
+    seele_bin_sort_noalloc,
     seele_preprocess_staged,
     seele_rasterize_fwd,
     seele_rasterize_fwd_super,

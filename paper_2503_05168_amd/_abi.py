@@ -25,6 +25,7 @@ SEELE_BIN_SUPER = 1
 SEELE_BIN_STAGED = 2
 SEELE_QUEUE_LIST = 0
 SEELE_QUEUE_HEAVIEST_FIRST = 1
+SEELE_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class seele_gaussians(ctypes.Structure):
@@ -85,6 +86,9 @@ SIGNATURES = {
     "seele_bin_sort_ex": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, POINTER(seele_camera),
                                     c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
                                     c_int64, c_void_p, c_void_p, c_void_p]),
+    "seele_bin_sort_noalloc": (c_int32, [c_int32, c_void_p, c_void_p, c_int64,
+                                         POINTER(seele_camera), c_int32, c_int32, c_void_p,
+                                         c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "seele_bin_sort_super": (c_int32, [c_void_p, c_void_p, c_int64, POINTER(seele_camera),
                                        c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
                                        c_int64, c_void_p, c_void_p, c_void_p]),

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <algorithm>
 #include <array>
 #include <string>
@@ -470,6 +471,73 @@ int32_t seele_bin_sort_ex(int32_t flags, const seele_splat* splats, const int32_
   return bin_sort_impl(super, (flags & SEELE_BIN_STAGED) != 0, splats, n_tiles, n, cams, n_views,
                        tile, workspace, workspace_bytes, super ? entry_keys : nullptr, ids,
                        capacity, ranges, num_pairs, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of seele_bin_sort_noalloc: one copy per GPU, in the code object's
+// zero-initialised device data.  In host code `scratch` is only a stand-in
+// symbol; its device address comes from hipGetSymbolAddress, per device.
+__device__ __align__(256) unsigned char scratch[SEELE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device with that device current.
+int32_t scratch_for_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SEELE_ERR_UNSUPPORTED, "device %d beyond the %d the scratch table holds", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(SEELE_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SEELE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_bin_sort_noalloc(int32_t flags, const seele_splat* splats, const int32_t* n_tiles,
+                               int64_t n, const seele_camera* cams, int32_t n_views, int32_t tile,
+                               uint32_t* entry_keys, uint32_t* ids, int64_t capacity,
+                               int32_t* ranges, int64_t* num_pairs, void* stream) {
+  if (flags & ~SEELE_BIN_SUPER)
+    return fail(SEELE_ERR_INVALID_ARG, "bin_sort_noalloc flags must be 0 or SEELE_BIN_SUPER");
+  // size check before the device is touched, so an oversized call fails the
+  // same way on any host
+  const int32_t s = check_cams(cams, n_views, tile, kMaxViewsBin);
+  if (s != SEELE_OK) return s;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SEELE_ERR_INVALID_ARG, "n out of range");
+  if (capacity < 0 || capacity >= ((int64_t)1 << 31))
+    return fail(SEELE_ERR_INVALID_ARG, "capacity must be in [0, 2^31)");
+  const size_t need =
+      plan_bin_sort((int64_t)n_views * n, capacity, seele_total_tiles(cams, n_views, tile)).total;
+  if (need > SEELE_NOALLOC_SCRATCH_BYTES)
+    return fail(SEELE_ERR_CAPACITY,
+                "bin_sort_noalloc needs %zu workspace bytes, more than the %zu of its scratch "
+                "array; use seele_bin_sort_ex with a caller workspace",
+                need, (size_t)SEELE_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  const int32_t sc = scratch_for_current_device(&ws);
+  if (sc != SEELE_OK) return sc;
+  const bool super = (flags & SEELE_BIN_SUPER) != 0;
+  return bin_sort_impl(super, false, splats, n_tiles, n, cams, n_views, tile, ws,
+                       SEELE_NOALLOC_SCRATCH_BYTES, super ? entry_keys : nullptr, ids, capacity,
+                       ranges, num_pairs, stream);
 }
 
 }  // extern "C"

@@ -206,6 +206,32 @@ def seele_bin_sort_ex(splats, n_tiles, n: int, cams, tile: int, capacity: int,
     return ids, ranges, num_pairs
 
 
+def seele_bin_sort_noalloc(splats, n_tiles, n: int, cams, tile: int, capacity: int,
+                           ids: torch.Tensor, ranges: torch.Tensor, num_pairs: torch.Tensor,
+                           entry_keys: torch.Tensor | None = None, super_lists: bool = False,
+                           stream=None):
+    """seele_bin_sort(_super) on the library's own per-device scratch array
+    (no workspace argument, no allocation); every output buffer is the
+    caller's."""
+    V = len(cams)
+    TT = total_tiles(cams, tile)
+    nr = total_super_tiles(cams, tile) if super_lists else TT
+    _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
+    _need(n_tiles, V * n, torch.int32, "n_tiles")
+    _need(ids, capacity, torch.int32, "ids")
+    _need(ranges, 2 * nr, torch.int32, "ranges")
+    _need(num_pairs, 2 if super_lists else 1, torch.int64, "num_pairs")
+    if super_lists:
+        _need(entry_keys, capacity, torch.int32, "entry_keys")
+    flags = A.SEELE_BIN_SUPER if super_lists else 0
+    st = A.lib().seele_bin_sort_noalloc(flags, _p(splats), _p(n_tiles), n, A.camera_array(cams),
+                                        V, tile, _p(entry_keys) if super_lists else None,
+                                        _p(ids), capacity, _p(ranges), _p(num_pairs),
+                                        _stream(stream))
+    A.check(st, "seele_bin_sort_noalloc")
+    return ids, ranges, num_pairs
+
+
 def bin_sort_workspace_size(n_records: int, capacity: int, n_tiles_total: int) -> int:
     return int(A.lib().seele_bin_sort_workspace_size(n_records, capacity, n_tiles_total))
 

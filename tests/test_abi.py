@@ -148,6 +148,24 @@ def test_bin_sort_rejects_bad_arguments():
                             ctypes.c_void_p(0x10004), None) == A.SEELE_ERR_INVALID_ARG
 
 
+def test_bin_sort_noalloc_refuses_before_touching_the_device():
+    """The no-allocation binning refuses staged input and any frame whose
+    workspace exceeds its scratch array, with no GPU call (runs on CPU)."""
+    L = A.lib()
+    cams = _cam()
+    call = lambda flags, n, cap: L.seele_bin_sort_noalloc(flags, FAKE, FAKE, n, cams, 1, 16, FAKE,
+                                                           FAKE, cap, FAKE, FAKE, None)
+    assert call(A.SEELE_BIN_STAGED, 10, 1000) == A.SEELE_ERR_INVALID_ARG
+    assert call(4, 10, 1000) == A.SEELE_ERR_INVALID_ARG
+    assert call(0, -1, 1000) == A.SEELE_ERR_INVALID_ARG
+    assert call(0, 10, 1 << 31) == A.SEELE_ERR_INVALID_ARG
+    big = 4 << 20
+    assert L.seele_bin_sort_workspace_size(big, 1, 12) > A.SEELE_NOALLOC_SCRATCH_BYTES
+    assert call(0, big, 1) == A.SEELE_ERR_CAPACITY
+    assert call(A.SEELE_BIN_SUPER, 1000, 20 << 20) == A.SEELE_ERR_CAPACITY
+    assert b"scratch" in L.seele_last_error()
+
+
 def test_total_tiles_and_workspace_size():
     L = A.lib()
     cams = A.camera_array([synthetic.look_at((0, 0, -3), width=w, height=h)
