@@ -123,33 +123,26 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
     const float lead = __shfl(alpha, leader_lane, 64);
     blended = blended && lead >= amin;
   }
-  float tp = 0.0f, tx = 0.0f, ty = 0.0f, txx = 0.0f, txy = 0.0f, tyy = 0.0f;
-  float gr = 0.0f, gg = 0.0f, gbl = 0.0f;
-  if (blended) {
-    const float cb = e.c.x;
-    const float om = 1.0f - alpha;
-    const float rom = __builtin_amdgcn_rcpf(om);  // 1 - alpha >= 1 - alpha_max > 0
-    const float Tj = T * rom;
-    const float ta = Tj * alpha;
-    // fused multiply-adds from here on: the gradient chain needs no
-    // bit-identity with the forward (only alpha and the decisions do)
-    const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, b.w, g0 * b.z));  // g . c
-    // dL/dalpha = T_j (g . c) - (g . S) / (1 - alpha)
-    const float dal = __builtin_fmaf(Tj, gc, -(rom * GS));
-    GS = __builtin_fmaf(ta, gc, GS);
-    T = Tj;
-    gr = ta * g0;
-    gg = ta * g1;
-    gbl = ta * g2;
-    if (raw <= amax) {
-      tp = alpha * dal;
-      tx = tp * dx;
-      ty = tp * dy;
-      txx = tx * dx;
-      txy = tx * dy;
-      tyy = ty * dy;
-    }
-  }
+  // branch-free: every lane computes the step, the selects keep only the
+  // blended lanes' effects (1 - alpha >= 1 - alpha_max > 0 everywhere)
+  const float cb = e.c.x;
+  const float om = 1.0f - alpha;
+  const float rom = __builtin_amdgcn_rcpf(om);
+  const float Tj = T * rom;
+  const float ta = Tj * alpha;
+  // fused multiply-adds from here on: the gradient chain needs no
+  // bit-identity with the forward (only alpha and the decisions do)
+  const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, b.w, g0 * b.z));  // g . c
+  // dL/dalpha = T_j (g . c) - (g . S) / (1 - alpha)
+  const float dal = __builtin_fmaf(Tj, gc, -(rom * GS));
+  GS = blended ? __builtin_fmaf(ta, gc, GS) : GS;
+  T = blended ? Tj : T;
+  const float wc = blended ? ta : 0.0f;
+  const float gr = wc * g0, gg = wc * g1, gbl = wc * g2;
+  // p = alpha dL/dalpha where the clamp is inactive (d alpha / d o = alpha / o)
+  const float tp = (blended && raw <= amax) ? alpha * dal : 0.0f;
+  const float tx = tp * dx, ty = tp * dy;
+  const float txx = tx * dx, txy = tx * dy, tyy = ty * dy;
   if (__ballot(blended) != 0) {
     const float v[9] = {tx, ty, txx, txy, tyy, tp, gr, gg, gbl};
     wave_accumulate9(v, acc, lane);
@@ -257,14 +250,19 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
       for (int q = 0; q < 9; ++q) s_g[tid][q] = 0.0f;
     }
     __syncthreads();
-    // this wave's records of the batch, highest position first, 64 at a time
+    // this wave's records of the batch, highest position first, 64 at a time;
+    // the ballot is walked in scalar registers (readfirstlane keeps it there)
     const int nb = min(hi, wave_last) - lo;
     for (int c = (nb - 1) & ~63; c >= 0; c -= 64) {
       const int jj = c + lane;
-      uint64_t bits = __ballot(jj < nb && ((s_qm[jj] >> wave) & 1u));
+      const uint64_t bal = __ballot(jj < nb && ((s_qm[jj] >> wave) & 1u));
+      const uint32_t blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bal);
+      const uint32_t bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(bal >> 32));
+      uint64_t bits = ((uint64_t)bhi << 32) | (uint64_t)blo;
       while (bits != 0) {
-        const int k = c + 63 - __builtin_clzll(bits);
-        bits &= ~(1ull << (k - c));
+        const int top = 63 - __builtin_clzll(bits);
+        bits &= ~(1ull << top);
+        const int k = c + top;
         blend_grad<MODE>(s_e[k], lo + k < last, fx, fy, leader_lane, lane, amin, amax, g0, g1,
                          g2, T, GS, s_g[k]);
       }
