@@ -702,13 +702,13 @@ __global__ void k_st_ranges(const uint32_t* __restrict__ keys, const Hdr* __rest
 // super-tile id.  Each wave takes 256 records (4 steps of 64) and issues all
 // their loads first; many waves per block keep the per-block count table
 // small while the chip stays full.
-constexpr int kEmitMaxSt = 2048;
+// (Measured: with up to 2048 super-tiles -- eight 720p views -- the one pass
+// was slower than the radix passes it replaces, so larger frames take those.)
+constexpr int kEmitMaxSt = 512;
 constexpr int kEmitWaveRecs = 256;                  // records per wave
 constexpr int kEmitSteps = kEmitWaveRecs / 64;
-// (super-tile capacity, waves per block) of the two instantiations
-constexpr int kEmitSmallSt = 512, kEmitSmallWaves = 16;
-constexpr int kEmitLargeWaves = 8;
-constexpr int kEmitMinBlock = kEmitLargeWaves * kEmitWaveRecs;  // smallest block (records)
+constexpr int kEmitWaves = 16;                      // waves per block
+constexpr int kEmitBlock = kEmitWaves * kEmitWaveRecs;  // records per block
 
 // k / d for k < 2^22 (float quotient estimate, corrected once).
 __device__ __forceinline__ uint32_t div_small(uint32_t k, uint32_t d) {
@@ -1423,7 +1423,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_ry = take(4 * (size_t)n_records);
   p.off_rid = take(8 * (size_t)n_records);
   p.off_span = take(8 * ((size_t)(n_records + 255) / 256 + kMaxViewsBin));
-  const int64_t nb_emit = (n_records + kEmitMinBlock - 1) / kEmitMinBlock;
+  const int64_t nb_emit = (n_records + kEmitBlock - 1) / kEmitBlock;
   p.off_hist = take(4 * std::max<size_t>(256 * (size_t)nb_hist, (size_t)kEmitMaxSt * nb_emit));
   p.off_digits = take(4 * (size_t)kEmitMaxSt);
   p.off_st_range = take(8 * (size_t)p.max_st);
@@ -1526,32 +1526,18 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     // 2. entries per (super-tile, record block), their slots, the emission
     uint32_t* ek = super ? entry_keys : at(p.off_skeys0);
     uint32_t* ev = super ? sorted_ids : at(p.off_svals0);
-    const bool small = n_st <= kEmitSmallSt;
-    const int ebl = (small ? kEmitSmallWaves : kEmitLargeWaves) * kEmitWaveRecs;
-    const int64_t nbE = std::max<int64_t>((R + ebl - 1) / ebl, 1);
+    const int64_t nbE = std::max<int64_t>((R + kEmitBlock - 1) / kEmitBlock, 1);
     const int stride = (int)nbE;
     const dim3 gridE(grid_for(nbE));
-    if (small) {
-      constexpr int NT = kEmitSmallWaves * 64;
-      if (nbR > 0)
-        hipLaunchKernelGGL((k_st_count<kEmitSmallSt, kEmitSmallWaves>), gridE, dim3(NT), 0, stream,
-                           ids_sorted, rid, views, hdr, rx_s, ry_s, hist, stride, partial);
-      hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)std::max<int64_t>(n_st, 1)), dim3(B), 0,
-                         stream, hist, stride, d_nvis, ebl, digits, 0u);
-      hipLaunchKernelGGL((k_st_emit<kEmitSmallSt, kEmitSmallWaves>), gridE, dim3(NT), 0, stream,
-                         ids_sorted, rx_s, ry_s, views, hdr, hist, stride, digits, p.capacity,
-                         ek, ev, st_range, num_pairs, super ? 1 : 0, partial);
-    } else {
-      constexpr int NT = kEmitLargeWaves * 64;
-      if (nbR > 0)
-        hipLaunchKernelGGL((k_st_count<kEmitMaxSt, kEmitLargeWaves>), gridE, dim3(NT), 0, stream,
-                           ids_sorted, rid, views, hdr, rx_s, ry_s, hist, stride, partial);
-      hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)n_st), dim3(B), 0, stream, hist, stride,
-                         d_nvis, ebl, digits, 0u);
-      hipLaunchKernelGGL((k_st_emit<kEmitMaxSt, kEmitLargeWaves>), gridE, dim3(NT), 0, stream,
-                         ids_sorted, rx_s, ry_s, views, hdr, hist, stride, digits, p.capacity,
-                         ek, ev, st_range, num_pairs, super ? 1 : 0, partial);
-    }
+    constexpr int NT = kEmitWaves * 64;
+    if (nbR > 0)
+      hipLaunchKernelGGL((k_st_count<kEmitMaxSt, kEmitWaves>), gridE, dim3(NT), 0, stream,
+                         ids_sorted, rid, views, hdr, rx_s, ry_s, hist, stride, partial);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)std::max<int64_t>(n_st, 1)), dim3(B), 0,
+                       stream, hist, stride, d_nvis, kEmitBlock, digits, 0u);
+    hipLaunchKernelGGL((k_st_emit<kEmitMaxSt, kEmitWaves>), gridE, dim3(NT), 0, stream,
+                       ids_sorted, rx_s, ry_s, views, hdr, hist, stride, digits, p.capacity, ek,
+                       ev, st_range, num_pairs, super ? 1 : 0, partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ekeys = ek;
     evals = ev;
