@@ -592,7 +592,12 @@ def run_fwd_bwd(n, n_views, steps, warmup, mode):
     # work of the backward (untimed): blends of the 8 views from the
     # instrumented forward, and the visible records
     f = ft.renderer.render(g, cams)
-    cnt = P.seele_rasterize_fwd_counted(f.splats, f.sorted_ids, f.tile_ranges, cams, st)[3]
+    if f.entry_keys is not None:  # super-tile lists
+        cnt = torch.zeros(6, dtype=torch.int64, device="cuda")
+        P.seele_rasterize_fwd_super(f.splats, f.entry_keys, f.sorted_ids, f.tile_ranges, cams, st,
+                                    counters=cnt)
+    else:
+        cnt = P.seele_rasterize_fwd_counted(f.splats, f.sorted_ids, f.tile_ranges, cams, st)[3]
     blends = int(cnt[1].item())
     n_vis = int((f.n_tiles > 0).sum().item())
     del f

@@ -293,15 +293,21 @@ int32_t seele_rasterize_fwd(const seele_splat* splats, const uint32_t* sorted_id
 /* seele_rasterize_fwd reading the super-tile lists of seele_bin_sort_super
  * (each tile keeps the entries whose clip covers it, in list order): the
  * outputs are bit-identical to seele_rasterize_fwd on the per-tile lists,
- * and n_contrib still counts positions in the tile's own list.  counters:
- * NULL, or device [6] uint64 as for seele_rasterize_fwd_counted (then the
- * instrumented kernel runs).  Default LDS batch (opts->lds_batch 0 or
- * tile * tile) only; SEELE_ERR_UNSUPPORTED otherwise. */
+ * and n_contrib still counts positions in the tile's own list.
+ *   last_entry NULL, or device, per view [H][W] int32: 1 + the index, from
+ *              the start of the pixel's super-tile list, of the last entry
+ *              the pixel blended (0 if none); the input of
+ *              seele_rasterize_bwd_super
+ *   counters   NULL, or device [6] uint64 as for seele_rasterize_fwd_counted
+ *              (then the instrumented kernel runs).
+ * Default LDS batch (opts->lds_batch 0 or tile * tile) only;
+ * SEELE_ERR_UNSUPPORTED otherwise. */
 int32_t seele_rasterize_fwd_super(const seele_splat* splats, const uint32_t* entry_keys,
                                   const uint32_t* entry_ids, const int32_t* st_ranges,
                                   const seele_camera* cams, int32_t n_views,
                                   const seele_raster_opts* opts, float* image, float* final_T,
-                                  int32_t* n_contrib, uint64_t* counters, void* stream);
+                                  int32_t* n_contrib, int32_t* last_entry, uint64_t* counters,
+                                  void* stream);
 
 /* Offline contribution pass of the view-dependent representation (Sec. 3.3
  * "Offline Clustering"): the plain blend of every pixel (Eqs. 1-2, exactly
@@ -381,6 +387,24 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
                             const float* final_T, const int32_t* n_contrib,
                             const float* dL_dimage, float* grad2d,
                             const seele_gaussian_grads* grads, void* stream);
+
+/* seele_rasterize_bwd over the super-tile lists of seele_bin_sort_super (the
+ * lists seele_rasterize_fwd_super read): same outputs, gradients equal up to
+ * the order of float sums (Sec. 3.5).  One workgroup takes a 2 x 2-tile
+ * quadrant of a super-tile and walks the super-tile's list backwards, so a
+ * record's gradient is flushed to grad2d once per quadrant instead of once
+ * per tile.  entry_keys / entry_ids / st_ranges as seele_bin_sort_super
+ * writes them; last_entry as seele_rasterize_fwd_super wrote it for the same
+ * lists (it takes the place of n_contrib).  16 x 16 tiles only
+ * (SEELE_ERR_UNSUPPORTED otherwise). */
+int32_t seele_rasterize_bwd_super(const seele_gaussians* g, const seele_camera* cams,
+                                  int32_t n_views, const seele_preprocess_opts* popts,
+                                  const seele_raster_opts* ropts, const seele_splat* splats,
+                                  const int32_t* n_tiles, const uint32_t* entry_keys,
+                                  const uint32_t* entry_ids, const int32_t* st_ranges,
+                                  const float* final_T, const int32_t* last_entry,
+                                  const float* dL_dimage, float* grad2d,
+                                  const seele_gaussian_grads* grads, void* stream);
 
 /* Offline view-dependent representation (Sec. 3.3 "Offline Clustering").
  *

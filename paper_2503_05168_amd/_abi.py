@@ -98,7 +98,7 @@ SIGNATURES = {
     "seele_rasterize_fwd_super": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                             POINTER(seele_camera), c_int32,
                                             POINTER(seele_raster_opts), c_void_p, c_void_p,
-                                            c_void_p, c_void_p, c_void_p]),
+                                            c_void_p, c_void_p, c_void_p, c_void_p]),
     "seele_contrib_topk": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera), c_int32,
                                      c_int64, POINTER(seele_raster_opts), c_int32, c_void_p,
                                      c_void_p, c_void_p]),
@@ -110,6 +110,12 @@ SIGNATURES = {
     "seele_rasterize_fwd_counted": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(seele_camera),
                                               c_int32, POINTER(seele_raster_opts), c_void_p,
                                               c_void_p, c_void_p, c_void_p, c_void_p]),
+    "seele_rasterize_bwd_super": (c_int32, [POINTER(seele_gaussians), POINTER(seele_camera),
+                                            c_int32, POINTER(seele_preprocess_opts),
+                                            POINTER(seele_raster_opts), c_void_p, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                            c_void_p, c_void_p, POINTER(seele_gaussian_grads),
+                                            c_void_p]),
     "seele_rasterize_bwd": (c_int32, [POINTER(seele_gaussians), POINTER(seele_camera), c_int32,
                                       POINTER(seele_preprocess_opts), POINTER(seele_raster_opts),
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

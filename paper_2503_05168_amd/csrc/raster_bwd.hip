@@ -165,6 +165,16 @@ __device__ __forceinline__ void record_grads(const LdsBwd& e, const float* t, fl
   out[8] = t[8];
 }
 
+// Gradient slot k of record_grads alone.
+__device__ __forceinline__ float record_grad(const LdsBwd& e, const float* t, int k) {
+  if (k < 2) {
+    const float ca = e.c.y, cbb = e.c.z, cc = e.c.w;
+    return k == 0 ? __builtin_fmaf(ca, t[0], cbb * t[1]) : __builtin_fmaf(cbb, t[0], cc * t[1]);
+  }
+  const float sc = k == 5 ? e.inv_o : (k == 2 || k == 4) ? -0.5f : k == 3 ? -1.0f : 1.0f;
+  return sc * t[k];
+}
+
 template <int TS, int MODE>
 __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, RasterParams rp,
                                                        const seele_splat* __restrict__ splats,
@@ -280,6 +290,194 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
   }
 }
 
+// ---- the same backward over super-tile lists, one workgroup per quadrant
+//
+// A workgroup takes a 2 x 2-tile quadrant of a super-tile (16 waves: wave w
+// on local tile w / 4 of the quadrant, 8 x 8 block w % 4 of that tile) and
+// walks the super-tile's depth-ordered entry list backwards, keeping the
+// entries whose clipped rectangle covers a tile of the quadrant.  The
+// forward over the same lists recorded, per pixel, the list index of the
+// last entry it blended (last_entry, 1-based), so a pixel's records are the
+// entries covering its tile up to that index: no positions in the per-tile
+// lists are needed, and the walk starts at the quadrant's largest index.
+// Everything per pixel is blend_grad's, so the gradients equal the per-tile
+// kernel's up to the order of the float sums; but every record is flushed
+// to HBM once per quadrant instead of once per tile of it, which halves the
+// flush atomics that bound that kernel.
+constexpr int kQuadThreads = 1024;
+constexpr int kQuadBatch = 512;  // entries scanned per batch (threads 0..511)
+
+// (x0, x1, y0, y1) of an entry's clip cover local tile (lx, ly)?
+__device__ __forceinline__ bool clip_covers(uint32_t key, int lx, int ly) {
+  const uint32_t c = key >> kClipShift;
+  const int x0 = (int)(c & 3u), x1 = (int)((c >> 2) & 3u);
+  const int y0 = (int)((c >> 4) & 3u), y1 = (int)((c >> 6) & 3u);
+  return x0 <= lx && lx <= x1 && y0 <= ly && ly <= y1;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void k_raster_bwd_quad(
+    RasterViews views, RasterParams rp, const seele_splat* __restrict__ splats,
+    const uint32_t* __restrict__ entry_ids, const uint32_t* __restrict__ entry_keys,
+    const int32_t* __restrict__ st_ranges, const float* __restrict__ final_T,
+    const int32_t* __restrict__ last_entry, const float* __restrict__ dL_dimage,
+    float* __restrict__ grad2d) {
+  constexpr int NB = kQuadBatch;
+  constexpr int SW = NB / 64;  // staging waves
+  __shared__ LdsBwd s_e[NB];
+  __shared__ uint32_t s_id[NB];
+  __shared__ uint32_t s_qm[NB];   // 4 block bits per quadrant tile (bit 4 t + block)
+  __shared__ int32_t s_ent[NB];   // list index of the staged entry
+  __shared__ float s_g[NB][9];
+  __shared__ int s_L[4];          // per quadrant tile: largest last_entry of its pixels
+  __shared__ uint32_t s_cnt[SW];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // super-tile and quadrant of this workgroup, and its view
+  const int64_t s = (int64_t)views.v[0].st_base + (blockIdx.x >> 2);
+  int v = 0;
+  for (int k = 1; k < views.n_views; ++k)
+    if (views.v[k].st_base <= s) v = k;
+  const RasterView rv = views.v[v];
+  const int sgw = (rv.grid_w + kSuperTile - 1) / kSuperTile;
+  const int ls = (int)(s - rv.st_base);
+  const int sy = ls / sgw, sx = ls - sy * sgw;
+  const int q = blockIdx.x & 3;
+  const int tq = wave >> 2, wb = wave & 3;
+  const int lxq0 = 2 * (q & 1), lyq0 = 2 * (q >> 1);
+  const int lx = lxq0 + (tq & 1), ly = lyq0 + (tq >> 1);
+  const int tile_x = sx * kSuperTile + lx, tile_y = sy * kSuperTile + ly;
+  const int grid_h = (rv.H + 15) / 16;
+  const bool tile_ok = tile_x < rv.grid_w && tile_y < grid_h;
+  const int wx = (wb & 1) * 8, wy = (wb >> 1) * 8;
+  const int gw = MODE ? rp.group_w : 1, gh = MODE ? rp.group_h : 1;
+  const int gsz = gw * gh, gpr = 8 / gw;
+  const int grp = lane / gsz, r = lane % gsz;
+  const int leader_lane = lane - r;
+  const int x = tile_x * 16 + wx + (grp % gpr) * gw + r % gw;
+  const int y = tile_y * 16 + wy + (grp / gpr) * gh + r / gw;
+  const bool inside = tile_ok && x < rv.W && y < rv.H;
+  const float fx = (float)x + 0.5f, fy = (float)y + 0.5f;
+  const int start = st_ranges[2 * s];
+  const float amin = rp.alpha_min, l2ia = rp.log2_inv_alpha_min, amax = rp.alpha_max;
+
+  float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  int last = 0;  // 1 + list index of the pixel's last blended entry (0: none)
+  if (inside) {
+    const int64_t hw = (int64_t)rv.W * rv.H;
+    const int64_t pix = (int64_t)y * rv.W + x;
+    T = final_T[rv.pix_base + pix];
+    last = last_entry[rv.pix_base + pix];
+    const float* g = dL_dimage + 3 * rv.pix_base;
+    g0 = g[pix];
+    g1 = g[hw + pix];
+    g2 = g[2 * hw + pix];
+  }
+  float GS = T * __builtin_fmaf(g2, rp.bg2, __builtin_fmaf(g1, rp.bg1, g0 * rp.bg0));
+  if (tid < 4) s_L[tid] = 0;
+  int wave_last = last;
+  for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
+  __syncthreads();
+  if (lane == 0 && wave_last > 0) atomicMax(&s_L[tq], wave_last);
+  __syncthreads();
+  int L[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) L[t] = s_L[t];
+  const int top = max(max(L[0], L[1]), max(L[2], L[3])) - 1;
+
+  // reverse walk, NB entries per batch: threads 0..NB-1 load the entries
+  // hi, hi - 1, ... and keep those some quadrant tile still needs (covering
+  // it at an index below its largest last_entry), compacted in walk order
+  const int bit = 4 * tq + wb;
+  // key and id of the thread's entry, loaded one batch ahead
+  uint32_t nkey = 0, nid = 0;
+  if (wave < SW && top - tid >= 0) {
+    nkey = entry_keys[start + top - tid];
+    nid = entry_ids[start + top - tid];
+  }
+  for (int hi = top; hi >= 0; hi -= NB) {
+    const int e = hi - tid;
+    const uint32_t key = nkey, id = nid;
+    uint32_t cb = 0;  // quadrant tiles this entry covers and that need it
+    uint32_t slot = 0;
+    if (wave < SW) {  // uniform per wave
+      if (e - NB >= 0) {
+        nkey = entry_keys[start + e - NB];
+        nid = entry_ids[start + e - NB];
+      }
+      if (e >= 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (e < L[t] && clip_covers(key, lxq0 + (t & 1), lyq0 + (t >> 1))) cb |= 1u << t;
+      }
+      const uint64_t nb = __ballot(cb != 0u);
+      if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(nb);
+      slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(nb >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)nb, 0u));
+    }
+    __syncthreads();
+    uint32_t nslots = 0;
+#pragma unroll
+    for (int k = 0; k < SW; ++k) {
+      const uint32_t c = s_cnt[k];
+      if (k < wave) slot += c;
+      nslots += c;
+    }
+    if (cb != 0u) {
+      const float4* src = reinterpret_cast<const float4*>(splats + id);
+      const float4 A = src[0], Bv = src[1];
+      const float l2o = __log2f(Bv.y);
+      s_e[slot].a = A;
+      s_e[slot].b = make_float4(Bv.x, l2o, Bv.z, Bv.w);
+      s_e[slot].c = src[2];
+      s_e[slot].inv_o = __builtin_amdgcn_rcpf(Bv.y);
+      s_id[slot] = id;
+      s_ent[slot] = e;
+      uint32_t qm = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if ((cb >> t) & 1u) {
+          const int tx = sx * kSuperTile + lxq0 + (t & 1), ty = sy * kSuperTile + lyq0 + (t >> 1);
+          qm |= quad_mask<16>(A.x, A.y, A.z, A.w, Bv.x, l2o, l2ia, tx * 16, ty * 16) << (4 * t);
+        }
+      }
+      s_qm[slot] = qm;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s_g[slot][k] = 0.0f;
+    }
+    __syncthreads();
+    // this wave's slots (block bit set, index within its pixels' range), in
+    // walk order, 64 at a time, the ballot walked in scalar registers
+    for (int c0 = 0; c0 < (int)nslots; c0 += 64) {
+      const int k0 = c0 + lane;
+      const bool vis = k0 < (int)nslots && ((s_qm[k0] >> bit) & 1u) && s_ent[k0] < wave_last;
+      const uint64_t bal = __ballot(vis);
+      const uint32_t blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bal);
+      const uint32_t bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(bal >> 32));
+      uint64_t bits = ((uint64_t)bhi << 32) | (uint64_t)blo;
+      while (bits != 0) {
+        const int b0 = __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int k = c0 + b0;
+        blend_grad<MODE>(s_e[k], s_ent[k] < last, fx, fy, leader_lane, lane, amin, amax, g0, g1,
+                         g2, T, GS, s_g[k]);
+      }
+    }
+    __syncthreads();
+    // one set of global atomics per record and quadrant, component-major
+    // over the whole workgroup: consecutive lanes add the nine consecutive
+    // floats of a record, so an atomic instruction touches a few records'
+    // lines instead of 64 (the next batch writes LDS only after its first
+    // barrier, which every flush precedes)
+    for (int i = tid; i < 9 * (int)nslots; i += kQuadThreads) {
+      const int sl = i / 9, k = i - 9 * sl;
+      const float gk = record_grad(s_e[sl], s_g[sl], k);
+      if (gk != 0.0f) atomicAdd(grad2d + (int64_t)s_id[sl] * 9 + k, gk);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_raster_bwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
@@ -304,6 +502,25 @@ hipError_t launch_raster_bwd(int tile, int mode, const RasterViews& views, int n
       hipLaunchKernelGGL((k_raster_bwd<8, 0>), grid, dim3(64), 0, stream, views, rp, splats,
                          sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, grad2d);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd_quad(int mode, const RasterViews& views, int n_st_launch,
+                                  const RasterParams& rp, const seele_splat* splats,
+                                  const uint32_t* entry_ids, const uint32_t* entry_keys,
+                                  const int32_t* st_ranges, const float* final_T,
+                                  const int32_t* last_entry, const float* dL_dimage, float* grad2d,
+                                  hipStream_t stream) {
+  if (n_st_launch <= 0) return hipSuccess;
+  const dim3 grid((unsigned)(4 * n_st_launch));
+  if (mode == SEELE_RASTER_CONTRIB)
+    hipLaunchKernelGGL(k_raster_bwd_quad<1>, grid, dim3(kQuadThreads), 0, stream, views, rp,
+                       splats, entry_ids, entry_keys, st_ranges, final_T, last_entry, dL_dimage,
+                       grad2d);
+  else
+    hipLaunchKernelGGL(k_raster_bwd_quad<0>, grid, dim3(kQuadThreads), 0, stream, views, rp,
+                       splats, entry_ids, entry_keys, st_ranges, final_T, last_entry, dL_dimage,
+                       grad2d);
   return hipGetLastError();
 }
 

@@ -38,7 +38,9 @@ namespace {
 struct LdsRec {
   float4 a;  // mean_x, mean_y, l11, l21  (Cholesky factor of k * conic)
   float4 b;  // l22, log2(opacity), r, g
-  float blue, pad0, pad1, pad2;
+  float blue;
+  int entry;  // super-tile lists: the record's index in the list
+  float pad1, pad2;
 };
 
 __device__ __forceinline__ float alpha_at(float px, float py, const float4& a, const float4& b,
@@ -118,7 +120,10 @@ __device__ __forceinline__ void blend_select(float fx, float fy, const float4& a
 // order, into the batch (so a batch holds up to 2 * BATCH records), and the
 // running count of covered entries gives each record's position in the
 // tile's own list.  Everything after staging is shared, so the outputs are
-// bit-identical to the per-tile lists'.
+// bit-identical to the per-tile lists'.  With last_entry, each pixel also
+// gets 1 + the super-list index of its last blended entry: the staged
+// records carry their list index, and once per batch a pixel whose last
+// blend fell in the batch reads it from its record's slot.
 template <int TS, int MODE, bool COUNT, int BATCH, bool SUPER = false>
 __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& views,
                                             const RasterParams& rp,
@@ -129,7 +134,8 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
                                             float* __restrict__ image,
                                             float* __restrict__ final_T,
                                             int32_t* __restrict__ n_contrib,
-                                            unsigned long long* __restrict__ counters) {
+                                            unsigned long long* __restrict__ counters,
+                                            int32_t* __restrict__ last_entry = nullptr) {
   constexpr int NT = TS * TS;
   constexpr int NW = NT / 64;
   static_assert(BATCH <= NT && BATCH % 64 == 0 || BATCH == NT, "batch depth");
@@ -201,6 +207,8 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
   // pixels outside the image start stopped
   float T = inside ? 1.0f : -1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
   int last = 0;
+  int last_e = 0;  // SUPER with last_entry: 1 + list index of the last blend
+  const bool want_e = SUPER && last_entry != nullptr;  // uniform
 
   // Staging loads are software-pipelined: while a batch is blended, each
   // staging thread already has the next batch's record and the id of the
@@ -306,12 +314,14 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         s_rec[sl].a = pa;
         s_rec[sl].b = staged_b(pb);
         s_rec[sl].blue = pblue;
+        if (want_e) s_rec[sl].entry = j;
       }
       if (cv1) {
         const uint32_t sl = tot0 + off1 + r1;
         s_rec[sl].a = qa1;
         s_rec[sl].b = staged_b(qb1);
         s_rec[sl].blue = ql1;
+        if (want_e) s_rec[sl].entry = j + BATCH;
       }
       __syncthreads();
       // culling masks over the compacted records, one per thread, so that
@@ -484,7 +494,12 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
         }
       }
     }
-    if (SUPER) run += cnt;
+    if (SUPER) {
+      // the batch's records are still staged (the next batch writes them
+      // after the barrier below)
+      if (want_e && last > run) last_e = s_rec[last - run - 1].entry + 1;
+      run += cnt;
+    }
     __syncthreads();
   }
 
@@ -510,6 +525,7 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
     img[2 * hw + pix] = c2 + Tf * rp.bg2;
     final_T[rv.pix_base + pix] = Tf;
     n_contrib[rv.pix_base + pix] = last;
+    if (want_e) last_entry[rv.pix_base + pix] = last_e;
   }
 }
 
@@ -532,9 +548,11 @@ __global__ __launch_bounds__(TS* TS) void k_raster_fwd_super(
     RasterViews views, RasterParams rp, const seele_splat* __restrict__ splats,
     const uint32_t* __restrict__ entry_ids, const uint32_t* __restrict__ entry_keys,
     const int32_t* __restrict__ st_ranges, float* __restrict__ image, float* __restrict__ final_T,
-    int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ counters) {
+    int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ counters,
+    int32_t* __restrict__ last_entry) {
   raster_tile<TS, MODE, COUNT, BATCH, true>(blockIdx.x, views, rp, splats, entry_ids, entry_keys,
-                                            st_ranges, image, final_T, n_contrib, counters);
+                                            st_ranges, image, final_T, n_contrib, counters,
+                                            last_entry);
 }
 
 // Persistent form for batches of views: a fixed grid of workgroups pulls
@@ -715,13 +733,13 @@ void launch_super(int mode, bool count, dim3 grid, const RasterViews& views,
                   const RasterParams& rp, const seele_splat* splats, const uint32_t* entry_keys,
                   const uint32_t* entry_ids, const int32_t* st_ranges, float* image,
                   float* final_T, int32_t* n_contrib, unsigned long long* counters,
-                  hipStream_t stream) {
+                  int32_t* last_entry, hipStream_t stream) {
   constexpr int BT = TS * TS;
   const dim3 block(BT);
 #define SEELE_SUPER(M, C)                                                                       \
   hipLaunchKernelGGL((k_raster_fwd_super<TS, M, C, BT>), grid, block, 0, stream, views, rp,     \
                      splats, entry_ids, entry_keys, st_ranges, image, final_T, n_contrib,       \
-                     counters)
+                     counters, last_entry)
   if (mode == SEELE_RASTER_CONTRIB) {
     if (count) SEELE_SUPER(1, true);
     else SEELE_SUPER(1, false);
@@ -739,15 +757,16 @@ hipError_t launch_raster_fwd_super(int tile, int mode, const RasterViews& views,
                                    const seele_splat* splats, const uint32_t* entry_keys,
                                    const uint32_t* entry_ids, const int32_t* st_ranges,
                                    float* image, float* final_T, int32_t* n_contrib,
-                                   unsigned long long* counters, hipStream_t stream) {
+                                   unsigned long long* counters, int32_t* last_entry,
+                                   hipStream_t stream) {
   if (n_tiles_launch <= 0) return hipSuccess;
   const dim3 grid(n_tiles_launch);
   if (tile == 16)
     launch_super<16>(mode, counters != nullptr, grid, views, rp, splats, entry_keys, entry_ids,
-                     st_ranges, image, final_T, n_contrib, counters, stream);
+                     st_ranges, image, final_T, n_contrib, counters, last_entry, stream);
   else
     launch_super<8>(mode, counters != nullptr, grid, views, rp, splats, entry_keys, entry_ids,
-                    st_ranges, image, final_T, n_contrib, counters, stream);
+                    st_ranges, image, final_T, n_contrib, counters, last_entry, stream);
   return hipGetLastError();
 }
 

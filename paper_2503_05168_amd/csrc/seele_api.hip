@@ -288,7 +288,7 @@ const char* seele_status_string(int32_t s) {
   }
 }
 
-int32_t seele_abi_version(void) { return 101; }
+int32_t seele_abi_version(void) { return 102; }
 
 int64_t seele_total_tiles(const seele_camera* cams, int32_t n_views, int32_t tile) {
   if (!cams || n_views < 1 || (tile != 8 && tile != 16)) return -1;
@@ -554,7 +554,7 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
                   const int32_t* tile_ranges, const seele_camera* cams, int32_t n_views,
                   const seele_raster_opts* opts, float* image, float* final_T,
                   int32_t* n_contrib, uint64_t* counters, void* stream, bool super = false,
-                  const uint32_t* entry_keys = nullptr) {
+                  const uint32_t* entry_keys = nullptr, int32_t* last_entry = nullptr) {
   int32_t s = check_raster_opts(opts);
   if (s != SEELE_OK) return s;
   if ((s = check_cams(cams, n_views, opts->tile, 1 << 20)) != SEELE_OK) return s;
@@ -567,6 +567,8 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
       return fail(SEELE_ERR_UNSUPPORTED, "more than 2^24 super-tiles");
     if (entry_keys && !aligned(entry_keys, 4))
       return fail(SEELE_ERR_INVALID_ARG, "entry_keys misaligned");
+    if (last_entry && !aligned(last_entry, 4))
+      return fail(SEELE_ERR_INVALID_ARG, "last_entry misaligned");
   }
   if (!tile_ranges || !aligned(tile_ranges, 4))
     return fail(SEELE_ERR_INVALID_ARG, "tile_ranges null or misaligned");
@@ -592,7 +594,7 @@ int32_t rasterize(const seele_splat* splats, const uint32_t* sorted_ids,
     const hipError_t e =
         super ? launch_raster_fwd_super(opts->tile, opts->mode, rv, (int)t, rp, splats,
                                         entry_keys, sorted_ids, tile_ranges, image, final_T,
-                                        n_contrib, cnt, st)
+                                        n_contrib, cnt, last_entry, st)
               : launch_raster_fwd(opts->tile, opts->mode, batch_of(opts), rv, (int)t, rp, splats,
                                   sorted_ids, tile_ranges, image, final_T, n_contrib, cnt, st);
     if (e != hipSuccess) return hip_fail(e, "raster launch");
@@ -653,9 +655,10 @@ int32_t seele_rasterize_fwd_super(const seele_splat* splats, const uint32_t* ent
                                   const uint32_t* entry_ids, const int32_t* st_ranges,
                                   const seele_camera* cams, int32_t n_views,
                                   const seele_raster_opts* opts, float* image, float* final_T,
-                                  int32_t* n_contrib, uint64_t* counters, void* stream) {
+                                  int32_t* n_contrib, int32_t* last_entry, uint64_t* counters,
+                                  void* stream) {
   return rasterize(splats, entry_ids, st_ranges, cams, n_views, opts, image, final_T, n_contrib,
-                   counters, stream, true, entry_keys);
+                   counters, stream, true, entry_keys, last_entry);
 }
 
 size_t seele_raster_queue_workspace_size(int64_t n_tiles_total) {
@@ -750,28 +753,39 @@ int32_t seele_rasterize_fwd_counted(const seele_splat* splats, const uint32_t* s
                    n_contrib, counters, stream);
 }
 
-int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
-                            const seele_preprocess_opts* popts, const seele_raster_opts* ropts,
-                            const seele_splat* splats, const int32_t* n_tiles,
-                            const uint32_t* sorted_ids, const int32_t* tile_ranges,
-                            const float* final_T, const int32_t* n_contrib,
-                            const float* dL_dimage, float* grad2d,
-                            const seele_gaussian_grads* grads, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared by both list forms: per-tile lists (sorted_ids, tile_ranges) or
+// (super) super-tile lists (entry ids, entry keys, super-tile ranges).
+int32_t rasterize_bwd_impl(bool super, const seele_gaussians* g, const seele_camera* cams,
+                           int32_t n_views, const seele_preprocess_opts* popts,
+                           const seele_raster_opts* ropts, const seele_splat* splats,
+                           const int32_t* n_tiles, const uint32_t* ids, const uint32_t* entry_keys,
+                           const int32_t* ranges, const float* final_T, const int32_t* n_contrib,
+                           const float* dL_dimage, float* grad2d,
+                           const seele_gaussian_grads* grads, void* stream) {
+  // super: n_contrib holds the last-entry indices of seele_rasterize_fwd_super
   int32_t s = check_gaussians(g);
   if (s != SEELE_OK) return s;
   if ((s = check_preprocess_opts(popts, g->n)) != SEELE_OK) return s;
   if ((s = check_raster_opts(ropts)) != SEELE_OK) return s;
   if (popts->tile != ropts->tile)
     return fail(SEELE_ERR_INVALID_ARG, "preprocess and raster tile sizes differ");
+  if (super && ropts->tile != 16)
+    return fail(SEELE_ERR_UNSUPPORTED, "the super-tile backward takes 16x16 tiles");
   if ((s = check_cams(cams, n_views, ropts->tile, 1 << 20)) != SEELE_OK) return s;
   const int64_t R = (int64_t)n_views * g->n;
   if (R >= ((int64_t)1 << 32)) return fail(SEELE_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
   const int64_t TT = seele_total_tiles(cams, n_views, ropts->tile);
   if (TT >= ((int64_t)1 << 31)) return fail(SEELE_ERR_UNSUPPORTED, "too many tiles");
   if (!grads) return fail(SEELE_ERR_INVALID_ARG, "grads is null");
-  if (!tile_ranges || !aligned(tile_ranges, 4) || !final_T || !aligned(final_T, 4) ||
+  if (!ranges || !aligned(ranges, 4) || !final_T || !aligned(final_T, 4) ||
       !n_contrib || !aligned(n_contrib, 4) || !dL_dimage || !aligned(dL_dimage, 4))
-    return fail(SEELE_ERR_INVALID_ARG, "tile_ranges/final_T/n_contrib/dL_dimage null or misaligned");
+    return fail(SEELE_ERR_INVALID_ARG, "ranges/final_T/n_contrib/dL_dimage null or misaligned");
+  if (super && (!entry_keys || !aligned(entry_keys, 4) || !ids || !aligned(ids, 4)))
+    return fail(SEELE_ERR_INVALID_ARG, "entry_keys/entry_ids null or misaligned");
   if (R > 0) {
     if (!splats || !aligned(splats, 16) || !n_tiles || !aligned(n_tiles, 4) || !grad2d ||
         !aligned(grad2d, 4))
@@ -795,8 +809,15 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
     const int nv = std::min(kMaxViewsRaster, n_views - v0);
     int64_t t = 0, npx = 0;
     const RasterViews rv = make_raster_views(cams, v0, nv, ropts->tile, tile_base, pix_base, t, npx);
-    e = launch_raster_bwd(ropts->tile, ropts->mode, rv, (int)t, rp, splats, sorted_ids,
-                          tile_ranges, final_T, n_contrib, dL_dimage, grad2d, st);
+    if (super) {
+      int64_t nst = 0;
+      for (int k = 0; k < nv; ++k) nst += super_tiles_of(cams[v0 + k], ropts->tile);
+      e = launch_raster_bwd_quad(ropts->mode, rv, (int)nst, rp, splats, ids, entry_keys, ranges,
+                                 final_T, n_contrib /* last_entry */, dL_dimage, grad2d, st);
+    } else {
+      e = launch_raster_bwd(ropts->tile, ropts->mode, rv, (int)t, rp, splats, ids, ranges,
+                            final_T, n_contrib, dL_dimage, grad2d, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "raster backward launch");
     tile_base += t;
     pix_base += npx;
@@ -812,6 +833,35 @@ int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, 
     if (e != hipSuccess) return hip_fail(e, "preprocess backward launch");
   }
   return SEELE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t seele_rasterize_bwd(const seele_gaussians* g, const seele_camera* cams, int32_t n_views,
+                            const seele_preprocess_opts* popts, const seele_raster_opts* ropts,
+                            const seele_splat* splats, const int32_t* n_tiles,
+                            const uint32_t* sorted_ids, const int32_t* tile_ranges,
+                            const float* final_T, const int32_t* n_contrib,
+                            const float* dL_dimage, float* grad2d,
+                            const seele_gaussian_grads* grads, void* stream) {
+  return rasterize_bwd_impl(false, g, cams, n_views, popts, ropts, splats, n_tiles, sorted_ids,
+                            nullptr, tile_ranges, final_T, n_contrib, dL_dimage, grad2d, grads,
+                            stream);
+}
+
+int32_t seele_rasterize_bwd_super(const seele_gaussians* g, const seele_camera* cams,
+                                  int32_t n_views, const seele_preprocess_opts* popts,
+                                  const seele_raster_opts* ropts, const seele_splat* splats,
+                                  const int32_t* n_tiles, const uint32_t* entry_keys,
+                                  const uint32_t* entry_ids, const int32_t* st_ranges,
+                                  const float* final_T, const int32_t* last_entry,
+                                  const float* dL_dimage, float* grad2d,
+                                  const seele_gaussian_grads* grads, void* stream) {
+  return rasterize_bwd_impl(true, g, cams, n_views, popts, ropts, splats, n_tiles, entry_ids,
+                            entry_keys, st_ranges, final_T, last_entry, dL_dimage, grad2d, grads,
+                            stream);
 }
 
 }  // extern "C"

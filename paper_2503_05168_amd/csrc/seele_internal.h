@@ -294,7 +294,8 @@ hipError_t launch_raster_fwd_super(int tile, int mode, const RasterViews& views,
                                    const seele_splat* splats, const uint32_t* entry_keys,
                                    const uint32_t* entry_ids, const int32_t* st_ranges,
                                    float* image, float* final_T, int32_t* n_contrib,
-                                   unsigned long long* counters, hipStream_t stream);
+                                   unsigned long long* counters, int32_t* last_entry,
+                                   hipStream_t stream);
 
 hipError_t launch_raster_fwd(int tile, int mode, int batch, const RasterViews& views,
                              int n_tiles_launch, const RasterParams& rp,
@@ -324,6 +325,12 @@ hipError_t launch_preprocess_bwd(const PreArgs& a, const seele_gaussians& g,
                                  const seele_gaussian_grads& out, bool accumulate,
                                  hipStream_t stream);
 
+hipError_t launch_raster_bwd_quad(int mode, const RasterViews& views, int n_st_launch,
+                                  const RasterParams& rp, const seele_splat* splats,
+                                  const uint32_t* entry_ids, const uint32_t* entry_keys,
+                                  const int32_t* st_ranges, const float* final_T,
+                                  const int32_t* last_entry, const float* dL_dimage, float* grad2d,
+                                  hipStream_t stream);
 hipError_t launch_raster_bwd(int tile, int mode, const RasterViews& views, int n_tiles_launch,
                              const RasterParams& rp, const seele_splat* splats,
                              const uint32_t* sorted_ids, const int32_t* tile_ranges,

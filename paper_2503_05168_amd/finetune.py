@@ -102,7 +102,10 @@ class FineTuner:
 
     def __init__(self, g: GaussianTensors, settings: Settings | None = None, lam: float = 0.2,
                  opts: AdamOpts | None = None, extent: float = 1.0, capacity: int = 1 << 22,
-                 gamma: float = 0.1, ppd: float | None = None):
+                 gamma: float = 0.1, ppd: float | None = None, lists: str = "super"):
+        """lists: "super" (super-tile lists; the backward flushes each record
+        once per 2 x 2-tile quadrant; 16 x 16 tiles) or "tile" (per-tile
+        lists, any tile size)."""
         self.g = g
         self.settings = settings or Settings()
         self.lam = lam
@@ -113,7 +116,9 @@ class FineTuner:
         self.m = zeros_like_gaussians(g)
         self.v = zeros_like_gaussians(g)
         self.grads = zeros_like_gaussians(g)
-        self.renderer = Renderer(self.settings, capacity=capacity, lists="tile")
+        if lists == "super" and self.settings.tile != 16:
+            lists = "tile"  # the super-tile backward takes 16 x 16 tiles
+        self.renderer = Renderer(self.settings, capacity=capacity, lists=lists, last_entry=True)
         self.t = 0
         self._ws = None
         self._fws = None
@@ -122,8 +127,9 @@ class FineTuner:
         self.last_flip = None
 
     def renderer_last_pairs(self):
-        """Device count of Gaussian-tile pairs of the last step's render (to
-        check the capacity after steps run with check=False)."""
+        """Device count of the stored list length of the last step's render
+        (super-tile entries, or pairs for per-tile lists), to check the
+        capacity after steps run with check=False."""
         return self._pairs
 
     def step(self, cams, target, segments=None, check: bool = True, events=None):
@@ -132,7 +138,7 @@ class FineTuner:
         events recorded after render, photometric loss, FLIP, backward,
         Adam."""
         f = self.renderer.render(self.g, cams, segments, check=check)
-        self._pairs = f.num_pairs
+        self._pairs = f.num_entries if f.num_entries is not None else f.num_pairs
         if events is not None:
             events[0].record()
         loss, dL, self._ws = seele_photometric_loss(f.image, target, cams, self.lam, self._ws)
@@ -148,7 +154,8 @@ class FineTuner:
             self._grad2d = torch.empty((n_rec, 9), dtype=torch.float32, device=self.g.means.device)
         seele_rasterize_bwd(self.g, cams, self.settings, f.splats, f.n_tiles, f.sorted_ids,
                             f.tile_ranges, f.final_T, f.n_contrib, dL, segments,
-                            self._grad2d[:n_rec], self.grads)
+                            self._grad2d[:n_rec], self.grads, entry_keys=f.entry_keys,
+                            last_entry=f.last_entry)
         if events is not None:
             events[3].record()
         self.t += 1

@@ -308,9 +308,12 @@ def seele_bin_sort_super(splats, n_tiles, n: int, cams, tile: int, capacity: int
 
 def seele_rasterize_fwd_super(splats, entry_keys, entry_ids, st_ranges, cams, settings: Settings,
                               image=None, final_T=None, n_contrib=None, counters=None,
-                              stream=None):
+                              stream=None, last_entry=None):
     """Forward over super-tile lists; counters (device [6] int64) selects the
-    instrumented kernel.  Returns (image, final_T, n_contrib)."""
+    instrumented kernel; last_entry (device int32, one per pixel), when
+    given, receives 1 + the super-list index of each pixel's last blended
+    entry (what seele_rasterize_bwd_super takes).  Returns (image, final_T,
+    n_contrib)."""
     dev = st_ranges.device
     npix = pixel_count(cams)
     if image is None:
@@ -325,11 +328,14 @@ def seele_rasterize_fwd_super(splats, entry_keys, entry_ids, st_ranges, cams, se
     _need(n_contrib, npix, torch.int32, "n_contrib")
     if counters is not None:
         _need(counters, 6, torch.int64, "counters")
+    if last_entry is not None:
+        _need(last_entry, npix, torch.int32, "last_entry")
     opts = settings.raster_opts()
     st = A.lib().seele_rasterize_fwd_super(_p(splats), _p(entry_keys), _p(entry_ids),
                                            _p(st_ranges), A.camera_array(cams), len(cams),
                                            ctypes.byref(opts), _p(image), _p(final_T),
-                                           _p(n_contrib), _p(counters), _stream(stream))
+                                           _p(n_contrib), _p(last_entry), _p(counters),
+                                           _stream(stream))
     A.check(st, "seele_rasterize_fwd_super")
     return image, final_T, n_contrib
 
@@ -464,10 +470,13 @@ def seele_hp_segments(layout_begin, layout_count, clusters):
 
 def seele_rasterize_bwd(g: GaussianTensors, cams, settings: Settings, splats, n_tiles,
                         sorted_ids, tile_ranges, final_T, n_contrib, dL_dimage, segments=None,
-                        grad2d=None, grads=None, stream=None):
+                        grad2d=None, grads=None, stream=None, entry_keys=None, last_entry=None):
     """Backward of preprocess + rasterize: returns (grads, grad2d) where grads
     has the layout of the Gaussian arrays and grad2d holds per-record
-    dL/d(mean_x, mean_y, conic a, b, c, opacity, r, g, b)."""
+    dL/d(mean_x, mean_y, conic a, b, c, opacity, r, g, b).  With entry_keys
+    the lists are super-tile lists (sorted_ids = entry ids, tile_ranges =
+    super-tile ranges) and seele_rasterize_bwd_super runs on the forward's
+    last_entry (n_contrib is then not read)."""
     dev = g.means.device
     V, n = len(cams), g.n
     if grad2d is None:
@@ -483,21 +492,34 @@ def seele_rasterize_bwd(g: GaussianTensors, cams, settings: Settings, splats, n_
     npix = pixel_count(cams)
     _need(splats, V * n * SPLAT_FLOATS, torch.float32, "splats")
     _need(n_tiles, V * n, torch.int32, "n_tiles")
-    _need(tile_ranges, 2 * total_tiles(cams, settings.tile), torch.int32, "tile_ranges")
+    sup = entry_keys is not None
+    if sup and last_entry is None:
+        raise ValueError("the super-tile backward needs the forward's last_entry")
+    nr = total_super_tiles(cams, settings.tile) if sup else total_tiles(cams, settings.tile)
+    _need(tile_ranges, 2 * nr, torch.int32, "tile_ranges")
     _need(final_T, npix, torch.float32, "final_T")
-    _need(n_contrib, npix, torch.int32, "n_contrib")
+    if sup:
+        _need(last_entry, npix, torch.int32, "last_entry")
+    else:
+        _need(n_contrib, npix, torch.int32, "n_contrib")
     _need(grad2d, V * n * 9, torch.float32, "grad2d")
     popts, keep = settings.preprocess_opts(segments)
     ropts = settings.raster_opts()
     gst = g.struct()
     dL = _need(dL_dimage.contiguous(), 3 * npix, torch.float32, "dL_dimage")
-    st = A.lib().seele_rasterize_bwd(ctypes.byref(gst), A.camera_array(cams), V,
-                                     ctypes.byref(popts), ctypes.byref(ropts), _p(splats),
-                                     _p(n_tiles), _p(sorted_ids), _p(tile_ranges), _p(final_T),
-                                     _p(n_contrib), _p(dL), _p(grad2d), ctypes.byref(gs),
-                                     _stream(stream))
+    if sup:
+        st = A.lib().seele_rasterize_bwd_super(
+            ctypes.byref(gst), A.camera_array(cams), V, ctypes.byref(popts), ctypes.byref(ropts),
+            _p(splats), _p(n_tiles), _p(entry_keys), _p(sorted_ids), _p(tile_ranges), _p(final_T),
+            _p(last_entry), _p(dL), _p(grad2d), ctypes.byref(gs), _stream(stream))
+    else:
+        st = A.lib().seele_rasterize_bwd(ctypes.byref(gst), A.camera_array(cams), V,
+                                         ctypes.byref(popts), ctypes.byref(ropts), _p(splats),
+                                         _p(n_tiles), _p(sorted_ids), _p(tile_ranges),
+                                         _p(final_T), _p(n_contrib), _p(dL), _p(grad2d),
+                                         ctypes.byref(gs), _stream(stream))
     del keep
-    A.check(st, "seele_rasterize_bwd")
+    A.check(st, "seele_rasterize_bwd_super" if sup else "seele_rasterize_bwd")
     return grads, grad2d
 
 
@@ -571,6 +593,9 @@ class Frame:
     # num_entries the entries the frame needs
     entry_keys: torch.Tensor | None = None
     num_entries: torch.Tensor | None = None
+    # Renderer(lists="super", last_entry=True): 1 + the super-list index of
+    # each pixel's last blended entry (the input of the super-tile backward)
+    last_entry: torch.Tensor | None = None
 
     def images(self):
         return split_views(self.image, self.cams, 3)
@@ -598,11 +623,13 @@ class Renderer:
     host read (the caller then checks ``num_pairs`` itself)."""
 
     def __init__(self, settings: Settings | None = None, capacity: int = 1 << 20,
-                 schedule: str = "grid", lists: str = "tile"):
+                 schedule: str = "grid", lists: str = "tile", last_entry: bool = False):
         """schedule: "grid" (one workgroup per tile), "queue" or "queue_heavy"
         (persistent work queue in list / heaviest-first order).  lists:
         "tile" (per-tile lists) or "super" (super-tile lists, read by each
-        tile directly; grid schedule only)."""
+        tile directly; grid schedule only).  last_entry (super-tile lists):
+        frames also carry the per-pixel last-entry indices the super-tile
+        backward reads."""
         if lists not in ("tile", "super"):
             raise ValueError(f"unknown list form {lists!r}")
         if lists == "super" and schedule != "grid":
@@ -611,6 +638,7 @@ class Renderer:
         self.capacity = int(capacity)
         self.schedule = schedule
         self.lists = lists
+        self.last_entry = bool(last_entry) and lists == "super"
         self._ek = None
         self._ws = None
         self._qws = None
@@ -649,9 +677,13 @@ class Renderer:
                 raise CapacityError(f"the frame needs {need} {what}, more than the {MAX_PAIRS} "
                                     f"one call can sort: render fewer views per call")
             self.capacity = min(int(need * 1.5) + 1024, MAX_PAIRS)
+        last_e = None
         if self.lists == "super":
+            if self.last_entry:
+                last_e = torch.empty(pixel_count(cams), dtype=torch.int32, device=splats.device)
             image, final_T, n_contrib = seele_rasterize_fwd_super(splats, keys, ids, ranges, cams,
-                                                                  s, stream=stream)
+                                                                  s, stream=stream,
+                                                                  last_entry=last_e)
         elif self.schedule == "grid":
             image, final_T, n_contrib = seele_rasterize_fwd(splats, ids, ranges, cams, s,
                                                             stream=stream)
@@ -660,4 +692,4 @@ class Renderer:
             image, final_T, n_contrib, self._qws = seele_rasterize_fwd_queue(
                 splats, ids, ranges, cams, s, order, self._qws, stream=stream)
         return Frame(image, final_T, n_contrib, splats, n_tiles, ids, ranges, npairs[:1],
-                     list(cams), keys, npairs[1:] if sup else None)
+                     list(cams), keys, npairs[1:] if sup else None, last_e)
