@@ -699,13 +699,16 @@ __global__ void k_st_ranges(const uint32_t* __restrict__ keys, const Hdr* __rest
 // same super-tile comes from ballots over the super-tile bits.  A record has
 // at most one entry per super-tile, so entries of one super-tile keep the
 // records' depth order: the lists equal those of the stable radix sort by
-// super-tile id.  Each wave takes 256 records (4 steps of 64) and issues all
-// their loads first; many waves per block keep the per-block count table
-// small while the chip stays full.
+// super-tile id.  Each wave takes 64 records (one step) and issues all their
+// loads first; many waves per block keep the per-block count table small
+// while the chip stays full.  A wave's time grows with its records' entries,
+// and the nearest records have hundreds each: short waves keep the slowest
+// ones short (measured on a 1080p frame of 3M Gaussians: 256, 128 and 64
+// records per wave, bin/sort 0.319, 0.296 and 0.285 ms).
 // (Measured: with up to 2048 super-tiles -- eight 720p views -- the one pass
 // was slower than the radix passes it replaces, so larger frames take those.)
 constexpr int kEmitMaxSt = 512;
-constexpr int kEmitWaveRecs = 256;                  // records per wave
+constexpr int kEmitWaveRecs = 64;                   // records per wave
 constexpr int kEmitSteps = kEmitWaveRecs / 64;
 constexpr int kEmitWaves = 16;                      // waves per block
 constexpr int kEmitBlock = kEmitWaves * kEmitWaveRecs;  // records per block

@@ -138,7 +138,7 @@ __device__ __forceinline__ void raster_tile(const int gt, const RasterViews& vie
                                             int32_t* __restrict__ last_entry = nullptr) {
   constexpr int NT = TS * TS;
   constexpr int NW = NT / 64;
-  static_assert(BATCH <= NT && BATCH % 64 == 0 || BATCH == NT, "batch depth");
+  static_assert((BATCH <= NT && BATCH % 64 == 0) || BATCH == NT, "batch depth");
   constexpr int CAP = SUPER ? 2 * BATCH : BATCH;  // records per LDS batch
   constexpr int E = CAP;                          // list entries per batch
   constexpr int SW = BATCH / 64;                  // staging waves
