@@ -124,7 +124,13 @@ __device__ __forceinline__ StLoc st_locate(const BinViews& views, uint32_t s) {
 // ---- visible-record compaction.  Wave w of block b owns records
 // [b*kSpanBlock + w*kWaveSpan, +kWaveSpan): per-wave counts, one scan, then each
 // wave writes its (depth, id) pairs independently (ballot ranks).
-constexpr int kRadixIT = 8;                       // radix items per thread (2048 per block)
+// Radix passes of the binning: 512 threads x 8 items (4096 per block); 8
+// waves per block shorten each block's serial chain (the passes are bound by
+// latency, one round of blocks; measured on a 1080p frame of 3M Gaussians,
+// bin/sort: 256 x 8 0.284 ms, 512 x 4 0.272, 512 x 8 0.269, 512 x 12 0.275,
+// 512 x 16 0.297, 768 x 8 0.293, 1024 x 4 0.282)
+constexpr int kRadixIT = 8;
+constexpr int kRadixThreads = 512;
 constexpr int kWaveSpan = 256;                    // records per wave (4 steps of 64)
 constexpr int kSpanBlock = WAVES * kWaveSpan;      // records per workgroup
 
@@ -267,9 +273,9 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
 
 // ---- stable LSD radix sort of (u32 key, u32 value) with a device-side count
 //
-// A radix block owns BLK = 256 * IT consecutive items; a fixed grid loops
-// over the live blocks.  hist layout: [digit][block] with row stride
-// `stride`.
+// A radix block of NT threads owns BLK = NT * IT consecutive items; a fixed
+// grid loops over the live blocks.  hist layout: [digit][block] with row
+// stride `stride`.
 
 // Input items: either [0, *d_count) or (staged, d_count null) the stage
 // slots [0, nslots) of which slot j is live when j % 256 < span_cnt[j / 256];
@@ -280,15 +286,37 @@ __device__ __forceinline__ bool radix_item_live(int64_t idx, uint32_t count,
   return !span_cnt || (uint64_t)(idx & 255) < span_cnt[idx >> 8];
 }
 
-template <int IT>
-__global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ keys,
+// Exclusive scan over the NT threads of a block; returns the prefix and the
+// total in `total` (smem: NT / 64 + 1 elements).  Contains barriers.
+template <int NT, typename T>
+__device__ __forceinline__ T block_scan_nt(T x, T* smem, T& total) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6;
+  const T inc = wave_inclusive_scan(x);
+  if (lane_id() == 63) smem[w] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const T v = smem[q];
+    if (q < w) base += v;
+    tot += v;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - x;
+}
+
+template <int IT, int NT>
+__global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ d_count, int shift,
                                                    int bits, uint32_t* __restrict__ hist,
                                                    int stride,
                                                    const uint64_t* __restrict__ span_cnt = nullptr,
                                                    uint32_t nslots = 0, Hdr* hdr = nullptr) {
-  constexpr int BLK = B * IT;
-  __shared__ uint32_t h[WAVES][256];
+  constexpr int BLK = NT * IT;
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t h[NW][256];
   const int radix = 1 << bits;
   const int w = threadIdx.x >> 6;
   const uint32_t count = d_count ? *d_count : nslots;
@@ -302,20 +330,20 @@ __global__ __launch_bounds__(B) void k_radix_hist(const uint32_t* __restrict__ k
     hdr->e_total = 0;
   }
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
-    for (int d = threadIdx.x; d < WAVES * 256; d += B) (&h[0][0])[d] = 0;
+    for (int d = threadIdx.x; d < NW * 256; d += NT) (&h[0][0])[d] = 0;
     __syncthreads();
     const int64_t begin = (int64_t)vb * BLK;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int64_t idx = begin + it * B + threadIdx.x;
+      const int64_t idx = begin + it * NT + threadIdx.x;
       if (radix_item_live(idx, count, span_cnt))
         atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < radix; d += B) {
+    for (int d = threadIdx.x; d < radix; d += NT) {
       uint32_t t = 0;
 #pragma unroll
-      for (int ww = 0; ww < WAVES; ++ww) t += h[ww][d];
+      for (int ww = 0; ww < NW; ++ww) t += h[ww][d];
       hist[(int64_t)d * stride + vb] = t;
     }
     __syncthreads();
@@ -363,21 +391,22 @@ __global__ __launch_bounds__(B) void k_radix_rowscan(uint32_t* __restrict__ hist
 // order the waves.  Items are first placed in LDS in block-sorted order and
 // then written out digit run by digit run, so consecutive lanes store to
 // consecutive addresses.  Input order is preserved among equal digits.
-template <int IT>
-__global__ __launch_bounds__(B) void k_radix_scatter(
+template <int IT, int NT>
+__global__ __launch_bounds__(NT) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count,
     int shift, int bits, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ digit_total, int stride,
     const uint64_t* __restrict__ span_cnt = nullptr, uint32_t nslots = 0, Hdr* hdr = nullptr) {
-  constexpr int BLK = B * IT;
+  constexpr int BLK = NT * IT;
+  constexpr int NW = NT / 64;
   __shared__ uint32_t s_k[BLK];
   __shared__ uint32_t s_v[BLK];
   __shared__ uint32_t s_dig[256];     // global start of each digit
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loc[256];
-  __shared__ uint32_t s_w[WAVES][256];
-  __shared__ uint32_t s_tmp[WAVES + 1];
+  __shared__ uint32_t s_w[NW][256];
+  __shared__ uint32_t s_tmp[NW + 1];
   const uint32_t count = d_count ? *d_count : nslots;
   const uint32_t nbl = (uint32_t)(((uint64_t)count + BLK - 1) / BLK);
   if (blockIdx.x >= nbl) return;  // uniform per block
@@ -387,7 +416,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
   {
     const uint32_t t = tid < radix ? digit_total[tid] : 0u;
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(t, s_tmp, tot);
+    const uint32_t ex = block_scan_nt<NT, uint32_t>(t, s_tmp, tot);
     if (tid < radix) s_dig[tid] = ex;
     // a staged pass learns the number of live items here
     if (hdr && blockIdx.x == 0 && tid == 0) hdr->n_vis = tot;
@@ -396,7 +425,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
   for (uint32_t vb = blockIdx.x; vb < nbl; vb += gridDim.x) {
     const int64_t begin = (int64_t)vb * BLK;
     if (tid < radix) s_base[tid] = s_dig[tid] + hist[(int64_t)tid * stride + vb];
-    for (int d = tid; d < WAVES * 256; d += B) (&s_w[0][0])[d] = 0;
+    for (int d = tid; d < NW * 256; d += NT) (&s_w[0][0])[d] = 0;
     __syncthreads();
 
     uint32_t k[IT], v[IT], rank[IT];
@@ -429,7 +458,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     uint32_t dtot = 0, n_here = 0;
     if (tid < radix) {
 #pragma unroll
-      for (int ww = 0; ww < WAVES; ++ww) {
+      for (int ww = 0; ww < NW; ++ww) {
         const uint32_t c = s_w[ww][tid];
         s_w[ww][tid] = dtot;
         dtot += c;
@@ -437,7 +466,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
     }
     {
       uint32_t tot;
-      const uint32_t ex = block_exclusive_scan<uint32_t>(tid < radix ? dtot : 0u, s_tmp, tot);
+      const uint32_t ex = block_scan_nt<NT, uint32_t>(tid < radix ? dtot : 0u, s_tmp, tot);
       if (tid < radix) s_loc[tid] = ex;
       n_here = tot;  // live items of the block
     }
@@ -452,7 +481,7 @@ __global__ __launch_bounds__(B) void k_radix_scatter(
       }
     }
     __syncthreads();
-    for (uint32_t j = tid; j < n_here; j += B) {
+    for (uint32_t j = tid; j < n_here; j += NT) {
       const uint32_t kk = s_k[j];
       const uint32_t d = (kk >> shift) & mask;
       const uint32_t pos = s_base[d] + (j - s_loc[d]);
@@ -1314,22 +1343,22 @@ int grid_for(int64_t nb) { return (int)std::max<int64_t>(1, std::min<int64_t>(nb
 // One radix pass over a device-side count of at most max_count items, or
 // (span_cnt given, d_count null) over the live slots of a staged input of
 // max_count slots; the staged pass also resets the header and sets n_vis.
-template <int IT>
+template <int IT, int NT = kRadixThreads>
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       const uint32_t* d_count, int64_t max_count, int shift, int bits,
                       uint32_t* hist, uint32_t* digits, hipStream_t stream,
                       const uint64_t* span_cnt = nullptr, Hdr* hdr = nullptr) {
-  constexpr int BLK = B * IT;
+  constexpr int BLK = NT * IT;
   const int64_t nb = (max_count + BLK - 1) / BLK;
   if (nb == 0) return hipSuccess;
   const int stride = (int)nb;
   const dim3 grid(grid_for(nb));
   const uint32_t nslots = span_cnt ? (uint32_t)max_count : 0u;
-  hipLaunchKernelGGL((k_radix_hist<IT>), grid, dim3(B), 0, stream, kin, d_count, shift, bits, hist,
-                     stride, span_cnt, nslots, hdr);
+  hipLaunchKernelGGL((k_radix_hist<IT, NT>), grid, dim3(NT), 0, stream, kin, d_count, shift, bits,
+                     hist, stride, span_cnt, nslots, hdr);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(B), 0, stream, hist, stride, d_count,
                      BLK, digits, nslots);
-  hipLaunchKernelGGL((k_radix_scatter<IT>), grid, dim3(B), 0, stream, kin, vin, kout, vout,
+  hipLaunchKernelGGL((k_radix_scatter<IT, NT>), grid, dim3(NT), 0, stream, kin, vin, kout, vout,
                      d_count, shift, bits, hist, digits, stride, span_cnt, nslots, hdr);
   return hipGetLastError();
 }
@@ -1374,7 +1403,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int bits,
   for (int pass = 0; pass < passes; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     const int pb = std::min(8, bits - 8 * pass);
-    const hipError_t e = radix_pass<ITEMS>(k[src], v[src], k[dst], v[dst], d_count, n, 8 * pass,
+    const hipError_t e = radix_pass<ITEMS, B>(k[src], v[src], k[dst], v[dst], d_count, n, 8 * pass,
                                            pb, hist, digits, stream);
     if (e != hipSuccess) return e;
   }
@@ -1396,7 +1425,7 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.max_seg = max_segments(capacity, p.max_st);
   const int64_t nb_rec = std::max<int64_t>(nblocks_for(n_records), 1);
   const int64_t nb_span = std::max<int64_t>((n_records + kSpanBlock - 1) / kSpanBlock, 1);
-  const int64_t rblk = (int64_t)B * kRadixIT;
+  const int64_t rblk = (int64_t)kRadixThreads * kRadixIT;
   // buffer 1 of the depth sort also holds the stage: 256 slots per span of
   // 256 records and view, so up to n_records + 256 * kMaxViewsBin; the first
   // staged pass runs over all of them
