@@ -269,7 +269,7 @@ int32_t seele_bin_sort_ex(int32_t flags, const seele_splat* splats, const int32_
  * (its input lives in a caller workspace).  Every other argument, output and
  * overflow rule is seele_bin_sort_ex's.  SEELE_ERR_CAPACITY when
  * seele_bin_sort_workspace_size(n_views * n, capacity, total tiles) exceeds
- * SEELE_NOALLOC_SCRATCH_BYTES (e.g. about 1M records with 2.5M pairs fit).
+ * SEELE_NOALLOC_SCRATCH_BYTES (e.g. 980k records with 2.45M pairs fit).
  * The array is shared by every call on a GPU and keeps the last call's
  * contents: calls that overlap on one GPU (different streams or host
  * threads without ordering) race and give undefined results. */

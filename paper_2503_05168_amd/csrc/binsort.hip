@@ -245,7 +245,8 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
                                                     const uint64_t* __restrict__ partial,
                                                     uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals,
-                                                    uint2* __restrict__ rid) {
+                                                    uint2* __restrict__ rid,
+                                                    uint32_t* __restrict__ prect) {
   const int w = threadIdx.x >> 6, lane = lane_id();
   const int64_t begin = (int64_t)blockIdx.x * kSpanBlock + w * kWaveSpan;
   if (begin >= n) return;  // per wave; no barriers below
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(B) void k_vis_compact(const int32_t* __restrict__ n
       keys[pos] = __float_as_uint(q.x);
       vals[pos] = (uint32_t)idx;
       rr = make_uint2(__float_as_uint(q.y), __float_as_uint(q.z));
+      prect[pos] = pack_rect8(rr.x, rr.y);
     }
     if (in) rid[idx] = rr;
     carry += (uint32_t)__popcll(bal);
@@ -391,17 +393,20 @@ __global__ __launch_bounds__(B) void k_radix_rowscan(uint32_t* __restrict__ hist
 // order the waves.  Items are first placed in LDS in block-sorted order and
 // then written out digit run by digit run, so consecutive lanes store to
 // consecutive addresses.  Input order is preserved among equal digits.
-template <int IT, int NT>
+// PAY: a second 32-bit value (pin -> pout) moves with each item.
+template <int IT, int NT, bool PAY>
 __global__ __launch_bounds__(NT) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_count,
     int shift, int bits, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ digit_total, int stride,
-    const uint64_t* __restrict__ span_cnt = nullptr, uint32_t nslots = 0, Hdr* hdr = nullptr) {
+    const uint64_t* __restrict__ span_cnt, uint32_t nslots, Hdr* hdr,
+    const uint32_t* __restrict__ pin, uint32_t* __restrict__ pout) {
   constexpr int BLK = NT * IT;
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_k[BLK];
   __shared__ uint32_t s_v[BLK];
+  __shared__ uint32_t s_p[PAY ? BLK : 1];
   __shared__ uint32_t s_dig[256];     // global start of each digit
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_loc[256];
@@ -428,7 +433,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     for (int d = tid; d < NW * 256; d += NT) (&s_w[0][0])[d] = 0;
     __syncthreads();
 
-    uint32_t k[IT], v[IT], rank[IT];
+    uint32_t k[IT], v[IT], pl[IT], rank[IT];
     const int64_t wbase = begin + (int64_t)w * 64 * IT;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -436,6 +441,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
       const bool live = radix_item_live(idx, count, span_cnt);
       k[it] = live ? kin[idx] : 0u;
       v[it] = live ? vin[idx] : 0u;
+      pl[it] = (PAY && live) ? pin[idx] : 0u;
       rank[it] = live ? 0u : 0xffffffffu;  // marks a dead slot until ranked
     }
 #pragma unroll
@@ -478,6 +484,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         const uint32_t lp = s_loc[d] + s_w[w][d] + rank[it];
         s_k[lp] = k[it];
         s_v[lp] = v[it];
+        if (PAY) s_p[lp] = pl[it];
       }
     }
     __syncthreads();
@@ -487,6 +494,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
       const uint32_t pos = s_base[d] + (j - s_loc[d]);
       kout[pos] = kk;
       vout[pos] = s_v[j];
+      if (PAY) pout[pos] = s_p[j];
     }
     __syncthreads();  // LDS is reused by the next block
   }
@@ -776,6 +784,12 @@ __device__ __forceinline__ EmitRec emit_rec(uint32_t id, uint32_t rx, uint32_t r
   return e;
 }
 
+// The rx / ry words (x0 | x1 << 16, y0 | y1 << 16) of a pack_rect8 value.
+__device__ __forceinline__ void unpack_rect8(uint32_t p, uint32_t& rx, uint32_t& ry) {
+  rx = (p & 0xffu) | (((p >> 8) & 0xffu) + 1u) << 16;
+  ry = ((p >> 16) & 0xffu) | ((p >> 24) + 1u) << 16;
+}
+
 __device__ __forceinline__ EmitRec no_rec() {
   EmitRec e{};
   e.sw = 1;
@@ -829,10 +843,13 @@ __device__ __forceinline__ T block_scan_n(T x, T* smem, T& total) {
 }
 
 // Pairs of block b go to ppart[b] (no atomics: same-address device atomics
-// from every wave serialise across the chip).
-template <int NST, int EW>
+// from every wave serialise across the chip).  PACKED: the rectangles come
+// in depth order with the ids (prect, carried by the depth sort) instead of
+// from the id-indexed rid, and rx_s / ry_s are not written.
+template <int NST, int EW, bool PACKED>
 __global__ __launch_bounds__(EW * 64) void k_st_count(const uint32_t* __restrict__ ids,
                                                        const uint2* __restrict__ rid,
+                                                       const uint32_t* __restrict__ prect,
                                                        BinViews views, const Hdr* __restrict__ hdr,
                                                        uint32_t* __restrict__ rx_s,
                                                        uint32_t* __restrict__ ry_s,
@@ -855,11 +872,18 @@ __global__ __launch_bounds__(EW * 64) void k_st_count(const uint32_t* __restrict
     for (int it = 0; it < kEmitSteps; ++it) {
       const int64_t i = (int64_t)vb * EBLK + it * NTH + tid;
       id[it] = i < nv ? ids[i] : 0u;
+      if (PACKED) {
+        uint32_t rx = 0, ry = 0;
+        if (i < nv) unpack_rect8(prect[i], rx, ry);
+        rr[it] = make_uint2(rx, ry);
+      }
     }
+    if (!PACKED) {
 #pragma unroll
-    for (int it = 0; it < kEmitSteps; ++it) {
-      const int64_t i = (int64_t)vb * EBLK + it * NTH + tid;
-      rr[it] = i < nv ? rid[id[it]] : make_uint2(0u, 0u);
+      for (int it = 0; it < kEmitSteps; ++it) {
+        const int64_t i = (int64_t)vb * EBLK + it * NTH + tid;
+        rr[it] = i < nv ? rid[id[it]] : make_uint2(0u, 0u);
+      }
     }
     __syncthreads();  // s_h cleared
     uint64_t c = 0;  // pairs of this thread's records
@@ -870,8 +894,10 @@ __global__ __launch_bounds__(EW * 64) void k_st_count(const uint32_t* __restrict
       if (i < nv) {
         const Rect r = rect_of(rr[it].x, rr[it].y, views.v[view_of(id[it], views)]);
         const uint32_t rx = r.x0 | (r.x1 << 16), ry = r.y0 | (r.y1 << 16);
-        rx_s[i] = rx;
-        ry_s[i] = ry;
+        if (!PACKED) {
+          rx_s[i] = rx;
+          ry_s[i] = ry;
+        }
         e = emit_rec(id[it], rx, ry, views);
         if (e.m > 0) c += (uint64_t)(r.x1 - r.x0) * (r.y1 - r.y0);
       }
@@ -921,10 +947,11 @@ __device__ __forceinline__ void owner_fill(uint8_t* own, uint32_t W, int lane) {
 // also writes every super-tile range ([0, 0) when empty or when the frame
 // overflows the capacity), the counts and the header totals; on overflow no
 // entry is written.
-template <int NST, int EW, int NBITS = (NST <= 512 ? 9 : 11)>
+template <int NST, int EW, bool PACKED, int NBITS = (NST <= 512 ? 9 : 11)>
 __global__ __launch_bounds__(EW * 64) void k_st_emit(const uint32_t* __restrict__ ids,
                                                       const uint32_t* __restrict__ rx_s,
                                                       const uint32_t* __restrict__ ry_s,
+                                                      const uint32_t* __restrict__ prect,
                                                       BinViews views, Hdr* __restrict__ hdr,
                                                       const uint32_t* __restrict__ hist,
                                                       int stride,
@@ -998,8 +1025,14 @@ __global__ __launch_bounds__(EW * 64) void k_st_emit(const uint32_t* __restrict_
       const int64_t i = wbeg + st * 64 + lane;
       const bool in = i < nv;
       rid_[st] = in ? ids[i] : 0u;
-      rx[st] = in ? rx_s[i] : 0u;
-      ry[st] = in ? ry_s[i] : 0u;
+      if (PACKED) {
+        rx[st] = 0u;
+        ry[st] = 0u;
+        if (in) unpack_rect8(prect[i], rx[st], ry[st]);
+      } else {
+        rx[st] = in ? rx_s[i] : 0u;
+        ry[st] = in ? ry_s[i] : 0u;
+      }
     }
 #pragma unroll
     for (int r = 0; r < PT; ++r) {
@@ -1347,7 +1380,8 @@ template <int IT, int NT = kRadixThreads>
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       const uint32_t* d_count, int64_t max_count, int shift, int bits,
                       uint32_t* hist, uint32_t* digits, hipStream_t stream,
-                      const uint64_t* span_cnt = nullptr, Hdr* hdr = nullptr) {
+                      const uint64_t* span_cnt = nullptr, Hdr* hdr = nullptr,
+                      const uint32_t* pin = nullptr, uint32_t* pout = nullptr) {
   constexpr int BLK = NT * IT;
   const int64_t nb = (max_count + BLK - 1) / BLK;
   if (nb == 0) return hipSuccess;
@@ -1358,8 +1392,14 @@ hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
                      hist, stride, span_cnt, nslots, hdr);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << bits), dim3(B), 0, stream, hist, stride, d_count,
                      BLK, digits, nslots);
-  hipLaunchKernelGGL((k_radix_scatter<IT, NT>), grid, dim3(NT), 0, stream, kin, vin, kout, vout,
-                     d_count, shift, bits, hist, digits, stride, span_cnt, nslots, hdr);
+  if (pin)
+    hipLaunchKernelGGL((k_radix_scatter<IT, NT, true>), grid, dim3(NT), 0, stream, kin, vin, kout,
+                       vout, d_count, shift, bits, hist, digits, stride, span_cnt, nslots, hdr,
+                       pin, pout);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<IT, NT, false>), grid, dim3(NT), 0, stream, kin, vin,
+                       kout, vout, d_count, shift, bits, hist, digits, stride, span_cnt, nslots,
+                       hdr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1451,8 +1491,12 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.off_skeys1 = take(4 * (size_t)capacity);
   p.off_svals0 = take(4 * (size_t)capacity);
   p.off_svals1 = 0;  // the second value buffer is the caller's sorted_ids
+  // the packed rectangles of the depth sort share rx / ry (the packed path
+  // never writes those, the others only after the sort): ry holds the stage
   p.off_rx = take(4 * (size_t)n_records);
-  p.off_ry = take(4 * (size_t)n_records);
+  p.off_ry = take(4 * (size_t)stage_slots);
+  p.off_prect0 = p.off_rx;
+  p.off_prect1 = p.off_ry;
   p.off_rid = take(8 * (size_t)n_records);
   p.off_span = take(8 * ((size_t)(n_records + 255) / 256 + kMaxViewsBin));
   const int64_t nb_emit = (n_records + kEmitBlock - 1) / kEmitBlock;
@@ -1475,6 +1519,7 @@ BinStage bin_stage_of(const BinSortPlan& p, void* ws, int64_t n) {
   s.ids = reinterpret_cast<uint32_t*>(base + p.off_dvals1);
   s.span_count = reinterpret_cast<uint64_t*>(base + p.off_span);
   s.rid = reinterpret_cast<uint2*>(base + p.off_rid);
+  s.prect = reinterpret_cast<uint32_t*>(base + p.off_prect1);
   s.n_blocks = (n + 255) / 256;
   return s;
 }
@@ -1519,6 +1564,14 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
                        st_range, 2 * n_st, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t* ids_sorted = dv[0];
+  // The one-pass bucketing on grids of at most 256 x 256 tiles takes each
+  // record's rectangle packed into 32 bits along the depth sort (a third
+  // value per item) instead of gathering it by id afterwards.
+  bool packed = emit1;
+  for (int k = 0; k < views.n_views; ++k)
+    packed = packed && views.v[k].grid_w <= 256 && views.v[k].grid_h <= 256;
+  uint32_t* pr[2] = {at(p.off_prect0), at(p.off_prect1)};
+  const uint32_t* prect_sorted = pr[0];
   if (nbR > 0) {
     // 1. visible records with their depth keys, stably sorted by float32
     //    depth bits (4 x 8-bit passes)
@@ -1528,26 +1581,29 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
       const BinStage bs = bin_stage_of(p, ws, views.n);
       const int64_t nslots = (int64_t)views.n_views * bs.n_blocks * 256;
       e = radix_pass<kRadixIT>(bs.keys, bs.ids, dk[0], dv[0], nullptr, nslots, 0, 8, hist, digits,
-                               stream, bs.span_count, hdr);
+                               stream, bs.span_count, hdr, packed ? bs.prect : nullptr, pr[0]);
       if (e != hipSuccess) return e;
       for (int pass = 1; pass < 4; ++pass) {
         const int src = (pass + 1) & 1, dst = src ^ 1;
         e = radix_pass<kRadixIT>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8,
-                                 hist, digits, stream);
+                                 hist, digits, stream, nullptr, nullptr,
+                                 packed ? pr[src] : nullptr, pr[dst]);
         if (e != hipSuccess) return e;
       }
       ids_sorted = dv[1];
+      prect_sorted = pr[1];
     } else {
       hipLaunchKernelGGL(k_vis_count, dim3(nbR), dim3(B), 0, stream, n_tiles, R, partial);
       hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partial,
                          WAVES * (int64_t)nbR, hdr, 0, p.capacity, num_pairs);
       hipLaunchKernelGGL(k_vis_compact, dim3(nbR), dim3(B), 0, stream, n_tiles, R, splats,
-                         partial, dk[0], dv[0], rid);
+                         partial, dk[0], dv[0], rid, pr[0]);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       for (int pass = 0; pass < 4; ++pass) {
         const int src = pass & 1, dst = src ^ 1;
         e = radix_pass<kRadixIT>(dk[src], dv[src], dk[dst], dv[dst], d_nvis, R, 8 * pass, 8,
-                                 hist, digits, stream);
+                                 hist, digits, stream, nullptr, nullptr,
+                                 packed ? pr[src] : nullptr, pr[dst]);
         if (e != hipSuccess) return e;
       }
     }
@@ -1562,14 +1618,26 @@ hipError_t launch_bin_sort(const BinSortPlan& p, const BinViews& views, const se
     const int stride = (int)nbE;
     const dim3 gridE(grid_for(nbE));
     constexpr int NT = kEmitWaves * 64;
-    if (nbR > 0)
-      hipLaunchKernelGGL((k_st_count<kEmitMaxSt, kEmitWaves>), gridE, dim3(NT), 0, stream,
-                         ids_sorted, rid, views, hdr, rx_s, ry_s, hist, stride, partial);
+    if (nbR > 0) {
+      if (packed)
+        hipLaunchKernelGGL((k_st_count<kEmitMaxSt, kEmitWaves, true>), gridE, dim3(NT), 0, stream,
+                           ids_sorted, rid, prect_sorted, views, hdr, rx_s, ry_s, hist, stride,
+                           partial);
+      else
+        hipLaunchKernelGGL((k_st_count<kEmitMaxSt, kEmitWaves, false>), gridE, dim3(NT), 0,
+                           stream, ids_sorted, rid, nullptr, views, hdr, rx_s, ry_s, hist, stride,
+                           partial);
+    }
     hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)std::max<int64_t>(n_st, 1)), dim3(B), 0,
                        stream, hist, stride, d_nvis, kEmitBlock, digits, 0u);
-    hipLaunchKernelGGL((k_st_emit<kEmitMaxSt, kEmitWaves>), gridE, dim3(NT), 0, stream,
-                       ids_sorted, rx_s, ry_s, views, hdr, hist, stride, digits, p.capacity, ek,
-                       ev, st_range, num_pairs, super ? 1 : 0, partial);
+    if (packed)
+      hipLaunchKernelGGL((k_st_emit<kEmitMaxSt, kEmitWaves, true>), gridE, dim3(NT), 0, stream,
+                         ids_sorted, rx_s, ry_s, prect_sorted, views, hdr, hist, stride, digits,
+                         p.capacity, ek, ev, st_range, num_pairs, super ? 1 : 0, partial);
+    else
+      hipLaunchKernelGGL((k_st_emit<kEmitMaxSt, kEmitWaves, false>), gridE, dim3(NT), 0, stream,
+                         ids_sorted, rx_s, ry_s, nullptr, views, hdr, hist, stride, digits,
+                         p.capacity, ek, ev, st_range, num_pairs, super ? 1 : 0, partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ekeys = ek;
     evals = ev;

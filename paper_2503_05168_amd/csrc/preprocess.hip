@@ -186,8 +186,9 @@ __device__ __forceinline__ void project(const CamK& c, const Act& g, float lowpa
 // STAGE also does the binning's first step for each view: the workgroup's
 // visible records (n_tiles > 0) are compacted in record order into their
 // span (view, workgroup) of the stage arrays -- float32 depth bits and record
-// id -- with the span's count, and every record's packed tile rectangle (zero
-// if not visible) goes to the dense id-indexed array rid.  The binning then
+// id, and its tile rectangle packed into 32 bits (for grids of at most 256 x
+// 256 tiles) -- with the span's count, and every record's tile rectangle
+// (zero if not visible) goes to the dense id-indexed array rid.  The binning then
 // starts from a scan of the span counts instead of re-reading the records.
 template <int NB, bool ONE, bool STAGE>
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __restrict__ means,
@@ -308,6 +309,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a, const float* __re
                                             __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
         bs.keys[span * 256 + pos] = dkey;
         bs.ids[span * 256 + pos] = (uint32_t)rec;
+        bs.prect[span * 256 + pos] = pack_rect8(srx, sry);
       }
       if (threadIdx.x == 0) bs.span_count[span] = tot;
       if (in) bs.rid[rec] = make_uint2(srx, sry);

@@ -244,10 +244,20 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float l11, flo
 struct BinStage {
   uint32_t* keys;
   uint32_t* ids;
+  uint32_t* prect;  // packed tile rectangle per slot (pack_rect8), beside the ids
   uint64_t* span_count;
   uint2* rid;
   int64_t n_blocks;  // ceil(n / 256)
 };
+
+// A non-empty tile rectangle [x0, x1) x [y0, y1) inside a grid of at most
+// 256 x 256 tiles in 32 bits: x0, x1 - 1, y0, y1 - 1, one byte each (rect_x /
+// rect_y hold x0 | x1 << 16 and y0 | y1 << 16).  Outside such grids the
+// value is not used.
+__host__ __device__ inline uint32_t pack_rect8(uint32_t rect_x, uint32_t rect_y) {
+  return (rect_x & 0xffu) | (((rect_x >> 16) - 1u) & 0xffu) << 8 | (rect_y & 0xffu) << 16 |
+         (((rect_y >> 16) - 1u) & 0xffu) << 24;
+}
 
 // ------------------------------------------------------------- host launchers
 hipError_t launch_preprocess(const PreArgs& a, const seele_gaussians& g, seele_splat* splats,
@@ -263,6 +273,7 @@ struct BinSortPlan {
   // workspace carve-up (byte offsets)
   size_t off_hdr, off_partial, off_partial2, off_dkeys0, off_dkeys1, off_dvals0, off_dvals1;
   size_t off_skeys0, off_skeys1, off_svals0, off_svals1, off_rx, off_ry, off_rid, off_span;
+  size_t off_prect0, off_prect1;  // packed rectangles riding along the depth sort
   size_t off_hist, off_digits, off_st_range, off_st_seg, off_seg_st, off_seg_cnt;
   size_t off_tile_cnt, off_tile_start, total;
 };
