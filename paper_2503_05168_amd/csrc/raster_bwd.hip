@@ -94,12 +94,13 @@ __device__ __forceinline__ void wave_accumulate9(const float (&v)[9], float* acc
   }
 }
 
-// One record of the reverse walk for one pixel: recompute alpha, undo the
-// blend (T and GS = g . S, the loss gradient dotted with the colour S
-// accumulated behind the record, background included) if the forward blended
-// it, and add the record's per-pixel terms (reduced over the wave) to its
-// LDS accumulator `acc` (9 floats, shared by the block's waves and turned
-// into gradients once per batch).  With d = pixel - mean, A = conic and
+// One record of the reverse walk for one pixel (pixel_terms): recompute
+// alpha, undo the blend (T and GS = g . S, the loss gradient dotted with the
+// colour S accumulated behind the record, background included) if the
+// forward blended it, and give the record's per-pixel terms v; blend_grad
+// adds them, reduced over the wave, to the record's LDS accumulator `acc` (9
+// floats, shared by the block's waves and turned into gradients once per
+// batch).  With d = pixel - mean, A = conic and
 // p = alpha dL/dalpha below the alpha clamp:
 //   dL/do    = p / o
 //   dL/dA    = -p d d^T / 2   (off-diagonal: -p dx dy for the b of q)
@@ -108,10 +109,10 @@ __device__ __forceinline__ void wave_accumulate9(const float (&v)[9], float* acc
 // the colour terms T_j alpha g; the record's constants (A, 1/o) multiply the
 // sums once per batch.
 template <int MODE>
-__device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx, float fy,
-                                           int leader_lane, int lane, float amin, float amax,
-                                           float g0, float g1, float g2, float& T, float& GS,
-                                           float* acc) {
+__device__ __forceinline__ bool pixel_terms(const LdsBwd& e, bool need, float fx, float fy,
+                                            int leader_lane, float amin, float amax, float g0,
+                                            float g1, float g2, float& T, float& GS,
+                                            float (&v)[9]) {
   const float4 a = e.a, b = e.b;  // b.y = log2(opacity), as the forward stages it
   float dx, dy;
   const float qo = splat_qo(fx, fy, a.x, a.y, a.z, a.w, b.x, b.y, dx, dy);
@@ -142,11 +143,27 @@ __device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx,
   // p = alpha dL/dalpha where the clamp is inactive (d alpha / d o = alpha / o)
   const float tp = (blended && raw <= amax) ? alpha * dal : 0.0f;
   const float tx = tp * dx, ty = tp * dy;
-  const float txx = tx * dx, txy = tx * dy, tyy = ty * dy;
-  if (__ballot(blended) != 0) {
-    const float v[9] = {tx, ty, txx, txy, tyy, tp, gr, gg, gbl};
-    wave_accumulate9(v, acc, lane);
-  }
+  v[0] = tx;
+  v[1] = ty;
+  v[2] = tx * dx;
+  v[3] = tx * dy;
+  v[4] = ty * dy;
+  v[5] = tp;
+  v[6] = gr;
+  v[7] = gg;
+  v[8] = gbl;
+  return blended;
+}
+
+template <int MODE>
+__device__ __forceinline__ void blend_grad(const LdsBwd& e, bool need, float fx, float fy,
+                                           int leader_lane, int lane, float amin, float amax,
+                                           float g0, float g1, float g2, float& T, float& GS,
+                                           float* acc) {
+  float v[9];
+  const bool blended =
+      pixel_terms<MODE>(e, need, fx, fy, leader_lane, amin, amax, g0, g1, g2, T, GS, v);
+  if (__ballot(blended) != 0) wave_accumulate9(v, acc, lane);
 }
 
 // Gradient slots of a record (mean x, mean y, conic a, b, c, opacity, r, g,
@@ -292,20 +309,26 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
 
 // ---- the same backward over super-tile lists, one workgroup per quadrant
 //
-// A workgroup takes a 2 x 2-tile quadrant of a super-tile (16 waves: wave w
-// on local tile w / 4 of the quadrant, 8 x 8 block w % 4 of that tile) and
-// walks the super-tile's depth-ordered entry list backwards, keeping the
-// entries whose clipped rectangle covers a tile of the quadrant.  The
-// forward over the same lists recorded, per pixel, the list index of the
-// last entry it blended (last_entry, 1-based), so a pixel's records are the
-// entries covering its tile up to that index: no positions in the per-tile
-// lists are needed, and the walk starts at the quadrant's largest index.
-// Everything per pixel is blend_grad's, so the gradients equal the per-tile
-// kernel's up to the order of the float sums; but every record is flushed
-// to HBM once per quadrant instead of once per tile of it, which halves the
-// flush atomics that bound that kernel.
-constexpr int kQuadThreads = 1024;
-constexpr int kQuadBatch = 512;  // entries scanned per batch (threads 0..511)
+// A workgroup takes a 2 x 2-tile quadrant of a super-tile and walks the
+// super-tile's depth-ordered entry list backwards, keeping the entries whose
+// clipped rectangle covers a tile of the quadrant.  The forward over the same
+// lists recorded, per pixel, the list index of the last entry it blended
+// (last_entry, 1-based), so a pixel's records are the entries covering its
+// tile up to that index: no positions in the per-tile lists are needed, and
+// the walk starts at the quadrant's largest index.  Every pixel step is
+// pixel_terms', so the gradients equal the per-tile kernel's up to the order
+// of the float sums; but every record is flushed to HBM once per quadrant
+// instead of once per tile of it.
+//
+// Two pixels per lane: 8 waves, wave w on the 16 x 8 half w % 2 of quadrant
+// tile w / 2, a lane on the same pixel of the half's two 8 x 8 blocks (left
+// and right).  A visit runs the pixel step twice and reduces the nine values
+// once for 128 pixels; a wave visits a record when either block's bit is set
+// (a block whose bit is clear cannot blend it: the cull bound is
+// conservative, so its pixels blend nothing).  Measured per 8 x 720p call
+// (plain): one pixel per lane in 16 waves 3.01 ms, two in 8 waves 2.80.
+constexpr int kQuadThreads = 512;
+constexpr int kQuadBatch = 256;  // entries scanned per batch (threads 0..255)
 
 // (x0, x1, y0, y1) of an entry's clip cover local tile (lx, ly)?
 __device__ __forceinline__ bool clip_covers(uint32_t key, int lx, int ly) {
@@ -316,7 +339,7 @@ __device__ __forceinline__ bool clip_covers(uint32_t key, int lx, int ly) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(6)))
 void k_raster_bwd_quad(
     RasterViews views, RasterParams rp, const seele_splat* __restrict__ splats,
     const uint32_t* __restrict__ entry_ids, const uint32_t* __restrict__ entry_keys,
@@ -334,7 +357,6 @@ void k_raster_bwd_quad(
   __shared__ uint32_t s_cnt[SW];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  // super-tile and quadrant of this workgroup, and its view
   const int64_t s = (int64_t)views.v[0].st_base + (blockIdx.x >> 2);
   int v = 0;
   for (int k = 1; k < views.n_views; ++k)
@@ -344,39 +366,45 @@ void k_raster_bwd_quad(
   const int ls = (int)(s - rv.st_base);
   const int sy = ls / sgw, sx = ls - sy * sgw;
   const int q = blockIdx.x & 3;
-  const int tq = wave >> 2, wb = wave & 3;
+  const int tq = wave >> 1, half = wave & 1;
   const int lxq0 = 2 * (q & 1), lyq0 = 2 * (q >> 1);
   const int lx = lxq0 + (tq & 1), ly = lyq0 + (tq >> 1);
   const int tile_x = sx * kSuperTile + lx, tile_y = sy * kSuperTile + ly;
   const int grid_h = (rv.H + 15) / 16;
   const bool tile_ok = tile_x < rv.grid_w && tile_y < grid_h;
-  const int wx = (wb & 1) * 8, wy = (wb >> 1) * 8;
   const int gw = MODE ? rp.group_w : 1, gh = MODE ? rp.group_h : 1;
   const int gsz = gw * gh, gpr = 8 / gw;
   const int grp = lane / gsz, r = lane % gsz;
   const int leader_lane = lane - r;
-  const int x = tile_x * 16 + wx + (grp % gpr) * gw + r % gw;
-  const int y = tile_y * 16 + wy + (grp / gpr) * gh + r / gw;
-  const bool inside = tile_ok && x < rv.W && y < rv.H;
-  const float fx = (float)x + 0.5f, fy = (float)y + 0.5f;
+  const int x0 = tile_x * 16 + (grp % gpr) * gw + r % gw;  // left block; right: + 8
+  const int y = tile_y * 16 + half * 8 + (grp / gpr) * gh + r / gw;
+  const float fy = (float)y + 0.5f;
   const int start = st_ranges[2 * s];
   const float amin = rp.alpha_min, l2ia = rp.log2_inv_alpha_min, amax = rp.alpha_max;
 
-  float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-  int last = 0;  // 1 + list index of the pixel's last blended entry (0: none)
-  if (inside) {
-    const int64_t hw = (int64_t)rv.W * rv.H;
-    const int64_t pix = (int64_t)y * rv.W + x;
-    T = final_T[rv.pix_base + pix];
-    last = last_entry[rv.pix_base + pix];
-    const float* g = dL_dimage + 3 * rv.pix_base;
-    g0 = g[pix];
-    g1 = g[hw + pix];
-    g2 = g[2 * hw + pix];
+  float fx[2], T[2], GS[2], g0[2], g1[2], g2[2];
+  int last[2];  // 1 + list index of the pixel's last blended entry (0: none)
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int x = x0 + 8 * p;
+    fx[p] = (float)x + 0.5f;
+    T[p] = 1.0f;
+    g0[p] = g1[p] = g2[p] = 0.0f;
+    last[p] = 0;
+    if (tile_ok && x < rv.W && y < rv.H) {
+      const int64_t hw = (int64_t)rv.W * rv.H;
+      const int64_t pix = (int64_t)y * rv.W + x;
+      T[p] = final_T[rv.pix_base + pix];
+      last[p] = last_entry[rv.pix_base + pix];
+      const float* g = dL_dimage + 3 * rv.pix_base;
+      g0[p] = g[pix];
+      g1[p] = g[hw + pix];
+      g2[p] = g[2 * hw + pix];
+    }
+    GS[p] = T[p] * __builtin_fmaf(g2[p], rp.bg2, __builtin_fmaf(g1[p], rp.bg1, g0[p] * rp.bg0));
   }
-  float GS = T * __builtin_fmaf(g2, rp.bg2, __builtin_fmaf(g1, rp.bg1, g0 * rp.bg0));
   if (tid < 4) s_L[tid] = 0;
-  int wave_last = last;
+  int wave_last = max(last[0], last[1]);
   for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
   __syncthreads();
   if (lane == 0 && wave_last > 0) atomicMax(&s_L[tq], wave_last);
@@ -386,11 +414,7 @@ void k_raster_bwd_quad(
   for (int t = 0; t < 4; ++t) L[t] = s_L[t];
   const int top = max(max(L[0], L[1]), max(L[2], L[3])) - 1;
 
-  // reverse walk, NB entries per batch: threads 0..NB-1 load the entries
-  // hi, hi - 1, ... and keep those some quadrant tile still needs (covering
-  // it at an index below its largest last_entry), compacted in walk order
-  const int bit = 4 * tq + wb;
-  // key and id of the thread's entry, loaded one batch ahead
+  const uint32_t bits2 = 3u << (4 * tq + 2 * half);  // this wave's two block bits
   uint32_t nkey = 0, nid = 0;
   if (wave < SW && top - tid >= 0) {
     nkey = entry_keys[start + top - tid];
@@ -447,11 +471,9 @@ void k_raster_bwd_quad(
       for (int k = 0; k < 9; ++k) s_g[slot][k] = 0.0f;
     }
     __syncthreads();
-    // this wave's slots (block bit set, index within its pixels' range), in
-    // walk order, 64 at a time, the ballot walked in scalar registers
     for (int c0 = 0; c0 < (int)nslots; c0 += 64) {
       const int k0 = c0 + lane;
-      const bool vis = k0 < (int)nslots && ((s_qm[k0] >> bit) & 1u) && s_ent[k0] < wave_last;
+      const bool vis = k0 < (int)nslots && (s_qm[k0] & bits2) != 0u && s_ent[k0] < wave_last;
       const uint64_t bal = __ballot(vis);
       const uint32_t blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bal);
       const uint32_t bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(bal >> 32));
@@ -460,16 +482,21 @@ void k_raster_bwd_quad(
         const int b0 = __builtin_ctzll(bits);
         bits &= bits - 1;
         const int k = c0 + b0;
-        blend_grad<MODE>(s_e[k], s_ent[k] < last, fx, fy, leader_lane, lane, amin, amax, g0, g1,
-                         g2, T, GS, s_g[k]);
+        const int ent = s_ent[k];
+        float va[9], vb[9];
+        const bool ba = pixel_terms<MODE>(s_e[k], ent < last[0], fx[0], fy, leader_lane, amin,
+                                          amax, g0[0], g1[0], g2[0], T[0], GS[0], va);
+        const bool bb = pixel_terms<MODE>(s_e[k], ent < last[1], fx[1], fy, leader_lane, amin,
+                                          amax, g0[1], g1[1], g2[1], T[1], GS[1], vb);
+        if (__ballot(ba || bb) != 0) {
+          float vs[9];
+#pragma unroll
+          for (int j = 0; j < 9; ++j) vs[j] = va[j] + vb[j];
+          wave_accumulate9(vs, s_g[k], lane);
+        }
       }
     }
     __syncthreads();
-    // one set of global atomics per record and quadrant, component-major
-    // over the whole workgroup: consecutive lanes add the nine consecutive
-    // floats of a record, so an atomic instruction touches a few records'
-    // lines instead of 64 (the next batch writes LDS only after its first
-    // barrier, which every flush precedes)
     for (int i = tid; i < 9 * (int)nslots; i += kQuadThreads) {
       const int sl = i / 9, k = i - 9 * sl;
       const float gk = record_grad(s_e[sl], s_g[sl], k);
