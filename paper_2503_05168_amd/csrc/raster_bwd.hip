@@ -326,8 +326,10 @@ __global__ __launch_bounds__(TS* TS) void k_raster_bwd(RasterViews views, Raster
 // once for 128 pixels; a wave visits a record when either block's bit is set
 // (a block whose bit is clear cannot blend it: the cull bound is
 // conservative, so its pixels blend nothing).  Measured per 8 x 720p call
-// (plain): one pixel per lane in 16 waves 3.01 ms, two in 8 waves 2.80.
-constexpr int kQuadThreads = 512;
+// (plain): one pixel per lane in 16 waves 3.01 ms, two in 8 waves 2.78, four
+// in 4 waves (a wave per tile, 88 VGPRs) 3.29.
+constexpr int kQuadPx = 2;                     // pixels per lane (2: 16 x 8 per wave, 4: 16 x 16)
+constexpr int kQuadThreads = 1024 / kQuadPx;
 constexpr int kQuadBatch = 256;  // entries scanned per batch (threads 0..255)
 
 // (x0, x1, y0, y1) of an entry's clip cover local tile (lx, ly)?
@@ -365,8 +367,9 @@ void k_raster_bwd_quad(
   const int sgw = (rv.grid_w + kSuperTile - 1) / kSuperTile;
   const int ls = (int)(s - rv.st_base);
   const int sy = ls / sgw, sx = ls - sy * sgw;
+  constexpr int PX = kQuadPx;
   const int q = blockIdx.x & 3;
-  const int tq = wave >> 1, half = wave & 1;
+  const int tq = PX == 2 ? wave >> 1 : wave, half = PX == 2 ? wave & 1 : 0;
   const int lxq0 = 2 * (q & 1), lyq0 = 2 * (q >> 1);
   const int lx = lxq0 + (tq & 1), ly = lyq0 + (tq >> 1);
   const int tile_x = sx * kSuperTile + lx, tile_y = sy * kSuperTile + ly;
@@ -377,17 +380,17 @@ void k_raster_bwd_quad(
   const int grp = lane / gsz, r = lane % gsz;
   const int leader_lane = lane - r;
   const int x0 = tile_x * 16 + (grp % gpr) * gw + r % gw;  // left block; right: + 8
-  const int y = tile_y * 16 + half * 8 + (grp / gpr) * gh + r / gw;
-  const float fy = (float)y + 0.5f;
+  const int y0 = tile_y * 16 + half * 8 + (grp / gpr) * gh + r / gw;  // top; bottom: + 8
   const int start = st_ranges[2 * s];
   const float amin = rp.alpha_min, l2ia = rp.log2_inv_alpha_min, amax = rp.alpha_max;
 
-  float fx[2], T[2], GS[2], g0[2], g1[2], g2[2];
-  int last[2];  // 1 + list index of the pixel's last blended entry (0: none)
+  float fx[PX], fy[PX], T[PX], GS[PX], g0[PX], g1[PX], g2[PX];
+  int last[PX];  // 1 + list index of the pixel's last blended entry (0: none)
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int x = x0 + 8 * p;
+  for (int p = 0; p < PX; ++p) {
+    const int x = x0 + 8 * (p & 1), y = y0 + 8 * (p >> 1);
     fx[p] = (float)x + 0.5f;
+    fy[p] = (float)y + 0.5f;
     T[p] = 1.0f;
     g0[p] = g1[p] = g2[p] = 0.0f;
     last[p] = 0;
@@ -404,7 +407,9 @@ void k_raster_bwd_quad(
     GS[p] = T[p] * __builtin_fmaf(g2[p], rp.bg2, __builtin_fmaf(g1[p], rp.bg1, g0[p] * rp.bg0));
   }
   if (tid < 4) s_L[tid] = 0;
-  int wave_last = max(last[0], last[1]);
+  int wave_last = last[0];
+#pragma unroll
+  for (int p = 1; p < PX; ++p) wave_last = max(wave_last, last[p]);
   for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, __shfl_xor(wave_last, o, 64));
   __syncthreads();
   if (lane == 0 && wave_last > 0) atomicMax(&s_L[tq], wave_last);
@@ -414,7 +419,8 @@ void k_raster_bwd_quad(
   for (int t = 0; t < 4; ++t) L[t] = s_L[t];
   const int top = max(max(L[0], L[1]), max(L[2], L[3])) - 1;
 
-  const uint32_t bits2 = 3u << (4 * tq + 2 * half);  // this wave's two block bits
+  // this wave's block bits
+  const uint32_t bits2 = (PX == 2 ? 3u : 15u) << (4 * tq + 2 * half);
   uint32_t nkey = 0, nid = 0;
   if (wave < SW && top - tid >= 0) {
     nkey = entry_keys[start + top - tid];
@@ -483,17 +489,17 @@ void k_raster_bwd_quad(
         bits &= bits - 1;
         const int k = c0 + b0;
         const int ent = s_ent[k];
-        float va[9], vb[9];
-        const bool ba = pixel_terms<MODE>(s_e[k], ent < last[0], fx[0], fy, leader_lane, amin,
-                                          amax, g0[0], g1[0], g2[0], T[0], GS[0], va);
-        const bool bb = pixel_terms<MODE>(s_e[k], ent < last[1], fx[1], fy, leader_lane, amin,
-                                          amax, g0[1], g1[1], g2[1], T[1], GS[1], vb);
-        if (__ballot(ba || bb) != 0) {
-          float vs[9];
+        float vs[9], vp[9];
+        bool any = pixel_terms<MODE>(s_e[k], ent < last[0], fx[0], fy[0], leader_lane, amin,
+                                     amax, g0[0], g1[0], g2[0], T[0], GS[0], vs);
 #pragma unroll
-          for (int j = 0; j < 9; ++j) vs[j] = va[j] + vb[j];
-          wave_accumulate9(vs, s_g[k], lane);
+        for (int p = 1; p < PX; ++p) {
+          any |= pixel_terms<MODE>(s_e[k], ent < last[p], fx[p], fy[p], leader_lane, amin, amax,
+                                   g0[p], g1[p], g2[p], T[p], GS[p], vp);
+#pragma unroll
+          for (int j = 0; j < 9; ++j) vs[j] += vp[j];
         }
+        if (__ballot(any) != 0) wave_accumulate9(vs, s_g[k], lane);
       }
     }
     __syncthreads();
