@@ -15,9 +15,12 @@ imports it; the only common dependency is the seeded input generator in
 
 Every function is pinned by tests against closed forms, library routines
 (SciPy spherical harmonics, SciPy rotations, ``np.lexsort``/``sorted``),
-brute force on tiny inputs and central finite differences.  Nothing here is
-"parity unpinned" except the contribution-aware image's distance from the
-plain image, which the paper bounds only in its (absent) appendix.
+brute force on tiny inputs, hand counts and central finite differences.
+"Parity unpinned": the contribution-aware image's distance from the plain
+image, which the paper bounds only in its (absent) appendix (the distance
+is frozen from this oracle, not derived), and the values of FLIP's CSF and
+feature-detector constants (``flip``), restated from a publication that is
+not available here.
 """
 from . import sh, project, binning, blend, adjoint, hp  # noqa: F401
 from .project import project_view, DEFAULTS  # noqa: F401

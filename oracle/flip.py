@@ -30,6 +30,13 @@ BY (34.1, 0.04, 13.5, 0.025); ppd = 0.7 m * (3840 px / 0.7 m) * pi / 180.
 Readings: images are [3][H][W] sRGB; the consistency term of a step is the
 mean FLIP between each of 7 consecutive views' render and its target image
 (the paper names the metric and the frame count only).
+
+Parity unpinned: the values of the CSF and feature-detector constants above
+(restated from FLIP's publication, which is not available here).  The tests
+pin the colour chain to tabulated CIELAB values of the sRGB primaries, the
+colour-error maximum (green against blue maps to exactly 1), the constants'
+normalisations and the unit-step response, and the gradient by central
+finite differences; a wrong constant value would pass them.
 """
 from __future__ import annotations
 
