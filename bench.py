@@ -79,8 +79,10 @@ def parse():
     ap.add_argument("--forms",
                     default="plain,contrib,hp,hp_contrib,hp_built,plain_generator_order")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-tiles", type=int, default=240,
-                    help="tiles of view 0 the CPU oracle blends (about 10-30 s of CPU work)")
+    ap.add_argument("--cpu-tiles", type=int, default=120,
+                    help="tiles of view 0 each CPU oracle worker blends (about 10-30 s)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="(internal) run the CPU oracle baseline alone and print it as JSON")
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
     ap.add_argument("--no-prefetch", action="store_true",
@@ -729,48 +731,110 @@ def run_batched(n, n_views, mode, reps=3):
     return out
 
 
-def cpu_baseline(scene, cam, n_tiles_sample):
-    """Float64 oracle, one view: full preprocessing; binning of every pair of
-    the Gaussians that touch a random sample of tiles, scaled to all pairs;
-    blending of those sampled tiles, scaled to all tiles."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-    from oracle import binning, blend, project
+# The CPU baseline runs in a child process of its own (started with the
+# interpreter, never a fork of this GPU process); its workers are forks of
+# that child and read the shared inputs from here.
+_CPU = {}
+_PROJ_KEYS = ("visible", "mean2d", "conic", "opacity", "rgb", "depth", "rect", "n_tiles")
 
+
+def _cpu_project(chunk):
+    """Worker: the float64 oracle's projection of one chunk of Gaussians."""
+    import numpy as np
+    from oracle import project
+    lo, hi = chunk
+    t0 = time.perf_counter()
+    p = project.project_view(_CPU["scene"].subset(np.arange(lo, hi)), _CPU["cam"], tile=16)
+    dt = time.perf_counter() - t0
+    return {k: p[k] for k in _PROJ_KEYS}, dt
+
+
+def _cpu_blend(tiles):
+    """Worker: the float64 oracle's blending of a list of tiles."""
+    from oracle import blend
+    t0 = time.perf_counter()
+    blend.render_tiles(_CPU["splats"], _CPU["ranges"], _CPU["ids"], _CPU["W"], _CPU["H"], 16,
+                       tiles=tiles)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n, n_tiles_per_worker):
+    """Float64 oracle on the host cores (one thread per worker process), view
+    0 of the 1080p orbit: preprocessing of every Gaussian split over the
+    workers; binning (one thread) of every pair of the Gaussians that touch a
+    random sample of tiles, scaled to all pairs; blending of those sampled
+    tiles split over the workers, scaled to all tiles.  A phase's time is its
+    slowest worker's; the binning is timed on its second call (the first
+    pays this fresh process's page faults)."""
+    import multiprocessing as mp
+    import numpy as np
+    import synthetic
+    from threadpoolctl import threadpool_limits
+    from oracle import binning, blend
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    scene = synthetic.cluster_scene(2, n)
+    cam = synthetic.orbit_cameras(32, 4.0, 1920, 1080)[0]
+    _CPU.update(scene=scene, cam=cam)
+    ctx = mp.get_context("fork")
     with threadpool_limits(1):
-        t0 = time.perf_counter()
-        p = project.project_view(scene, cam, tile=16)
-        t_pre = time.perf_counter() - t0
-        gw, gh = p["grid_w"], p["grid_h"]
+        bounds = np.linspace(0, n, workers + 1).astype(np.int64)
+        with ctx.Pool(workers) as pool:
+            parts = pool.map(_cpu_project, [(int(bounds[k]), int(bounds[k + 1]))
+                                            for k in range(workers)])
+        t_pre = max(dt for _, dt in parts)
+        p = {k: np.concatenate([q[k] for q, _ in parts]) for k in _PROJ_KEYS}
+        del parts
+        gw, gh = -(-cam.width // 16), -(-cam.height // 16)
         rng = np.random.default_rng(0)
-        tiles = sorted(rng.choice(gw * gh, n_tiles_sample, replace=False).tolist())
+        n_sample = min(gw * gh, n_tiles_per_worker * workers)
+        tiles = sorted(rng.choice(gw * gh, n_sample, replace=False).tolist())
         r = p["rect"]
-        touch = np.zeros(p["visible"].shape[0], dtype=bool)
+        touch = np.zeros(n, dtype=bool)
         for t in tiles:
             tx, ty = t % gw, t // gw
             touch |= (r[:, 0] <= tx) & (tx < r[:, 2]) & (r[:, 1] <= ty) & (ty < r[:, 3])
         nt = np.where(touch, p["n_tiles"], 0)
         all_pairs = int(p["n_tiles"].sum())
+        bin_in = [dict(rect=r, n_tiles=nt, depth_f32=p["depth"].astype(np.float32), grid_w=gw,
+                       grid_h=gh)]
+        binning.bin_and_sort(bin_in, n)  # untimed: this process's first large allocations
         t0 = time.perf_counter()
-        b = binning.bin_and_sort([dict(rect=r, n_tiles=nt, depth_f32=p["depth"].astype(np.float32),
-                                       grid_w=gw, grid_h=gh)], p["visible"].shape[0])
+        b = binning.bin_and_sort(bin_in, n)
         t_bin = (time.perf_counter() - t0) * all_pairs / max(1, b["n_pairs"])
-        t0 = time.perf_counter()
-        blend.render_tiles(blend.splats_from_projection(p), b["ranges"], b["ids"], p["width"],
-                           p["height"], 16, tiles=tiles)
-        t_blend = (time.perf_counter() - t0) * (gw * gh) / len(tiles)
+        _CPU.update(splats=blend.splats_from_projection(p), ranges=b["ranges"], ids=b["ids"],
+                    W=cam.width, H=cam.height)
+        with ctx.Pool(workers) as pool:
+            times = pool.map(_cpu_blend, [tiles[k::workers] for k in range(workers)])
+        t_blend = max(times) * (gw * gh) / len(tiles)
     total = t_pre + t_bin + t_blend
-    return dict(value=1.0 / total, unit="frames/s", cores=1, kind="oracle",
-                sample=(f"view 0: full float64 preprocessing of {scene.n} Gaussians "
-                        f"({t_pre:.1f}s); binning of the {b['n_pairs']} pairs of Gaussians "
-                        f"touching {len(tiles)} random tiles, scaled to all {all_pairs} pairs "
-                        f"({t_bin:.1f}s est.); blending of those {len(tiles)} tiles, scaled to "
-                        f"{gw * gh} tiles ({t_blend:.1f}s est.); one thread"),
+    return dict(value=1.0 / total, unit="frames/s", cores=workers, kind="oracle",
+                sample=(f"view 0 of the 1080p orbit, {workers} worker processes of one thread: "
+                        f"float64 preprocessing of all {n} Gaussians split over the workers "
+                        f"({t_pre:.1f}s); binning (one thread) of the {b['n_pairs']} pairs of "
+                        f"Gaussians touching {len(tiles)} random tiles, scaled to all "
+                        f"{all_pairs} pairs ({t_bin:.1f}s est.); blending of those "
+                        f"{len(tiles)} tiles split over the workers, scaled to {gw * gh} "
+                        f"tiles ({t_blend:.1f}s est.)"),
                 seconds_per_frame=total)
+
+
+def run_cpu_baseline(n, n_tiles_per_worker):
+    """The CPU baseline in a child process that never touches the GPU."""
+    import subprocess
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                          "--n", str(n), "--cpu-tiles", str(n_tiles_per_worker)],
+                         capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed: {out.stderr[-2000:]}")
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def main():
     args = parse()
+    if args.cpu_baseline_only:  # the child process of run_cpu_baseline: no GPU
+        print(json.dumps(cpu_baseline(args.n, args.cpu_tiles)))
+        return
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the hot path shards by view with no "
               "exchange; multi-GPU runs are not part of this build)", file=sys.stderr)
@@ -889,7 +953,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(scene, cams[0], args.cpu_tiles)
+        cpu = run_cpu_baseline(args.n, args.cpu_tiles)
         log(f"[bench] t+{time.time() - t_start:.0f}s cpu baseline {cpu['value']:.3e} frames/s")
     line = {
         "metric": "1080p FPS @3M Gaussians, plain vs contribution-aware; fwd+bwd ms/view",
