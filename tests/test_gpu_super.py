@@ -126,6 +126,11 @@ CASES = [
     ("c2shape-cr-2x4-tile16-2views", lambda: (synthetic.cluster_scene(2, 60_000),
                                               synthetic.orbit_cameras(2, 4.0, 640, 360)),
      Settings(mode="contrib", group=(2, 4))),
+    # a grid wider than 256 tiles: the rectangles are gathered by id
+    ("c2shape-wide-strip-tile8", lambda: (synthetic.cluster_scene(2, 40_000),
+                                          [synthetic.look_at((0.5, 0.2, -3.5), width=2112,
+                                                             height=96)]),
+     Settings(tile=8)),
 ]
 
 
