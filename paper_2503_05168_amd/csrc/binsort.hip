@@ -1463,7 +1463,6 @@ BinSortPlan plan_bin_sort(int64_t n_records, int64_t capacity, int64_t n_tiles_t
   p.n_tiles_total = n_tiles_total;
   p.max_st = std::max<int64_t>(n_tiles_total, 1);
   p.max_seg = max_segments(capacity, p.max_st);
-  const int64_t nb_rec = std::max<int64_t>(nblocks_for(n_records), 1);
   const int64_t nb_span = std::max<int64_t>((n_records + kSpanBlock - 1) / kSpanBlock, 1);
   const int64_t rblk = (int64_t)kRadixThreads * kRadixIT;
   // buffer 1 of the depth sort also holds the stage: 256 slots per span of
