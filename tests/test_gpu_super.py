@@ -277,6 +277,18 @@ STAGED_CASES = [
     ("c2shape-3views-tile8-tilelists", lambda: (synthetic.cluster_scene(2, 50_003),
                                                 synthetic.orbit_cameras(3, 4.0, 640, 480)),
      Settings(tile=8), False),
+    # very small near planes: depth keys over many binades (the shell at
+    # radius 20 against z_near 2e-4, a ratio above 2^16) and records just
+    # past the near plane whose footprints cover the view
+    ("c2shape-znear-2e-4-wide-depth-ratio-super",
+     lambda: (synthetic.cluster_scene(2, 100_001), synthetic.orbit_cameras(2, 4.0, 960, 540)),
+     Settings(z_near=2e-4), True),
+    ("c2shape-znear-1e-6-super",
+     lambda: (synthetic.cluster_scene(3, 60_000), synthetic.orbit_cameras(1, 4.0, 960, 540)),
+     Settings(z_near=1e-6), True),
+    ("c2shape-znear-2e-4-tilelists",
+     lambda: (synthetic.cluster_scene(2, 40_000), synthetic.orbit_cameras(1, 4.0, 640, 480)),
+     Settings(z_near=2e-4), False),
 ]
 
 
