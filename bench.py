@@ -85,6 +85,8 @@ def parse():
                     help="(internal) run the CPU oracle baseline alone and print it as JSON")
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-view batched run")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the plain frames with two in flight")
     ap.add_argument("--no-prefetch", action="store_true",
                     help="skip the scene-prefetching measurement (needs the hp_built form)")
     ap.add_argument("--ft-steps", type=int, default=1000,
@@ -317,6 +319,108 @@ def run_form(name, form, cams, steps, warmup, lists="super"):
     log(f"[bench] {name}: {out['fps']:.1f} fps ({ms:.3f} ms/frame) stages="
         + ", ".join(f"{a}={b:.3f}" for a, b in stage.items())
         + f" pairs={out['pairs']:.3e} vis={out['visible']:.3e} evals={evals:.3e}")
+    return out
+
+
+def run_form_pipelined(name, form, cams, steps, warmup, stages=2):
+    """The same frames with several in flight: with stages=2, frame i+1's
+    preprocessing and binning (one stream) run while frame i is rasterised
+    (a second stream); with stages=3, preprocessing, binning and
+    rasterisation each have a stream, so three frames overlap.  Each frame in
+    flight has its own set of buffers; events order the stages of a frame and
+    the reuse of a set.  Every frame still does all of its work; only
+    throughput is reported."""
+    import torch
+    import paper_2503_05168_amd as P
+
+    g, st = form["g"], form["st"]
+    assert form["hp"] is None, "pipelined frames take the full scene"
+    n = g.n
+    V = len(cams)
+    dev = g.means.device
+    one = [cams[0]]
+    TT = P.total_tiles(one, st.tile)
+    NS = P.total_super_tiles(one, st.tile)
+    npix = P.pixel_count(one)
+    splats0 = torch.empty((n, P.pipeline.SPLAT_FLOATS), dtype=torch.float32, device=dev)
+    nt0 = torch.empty(n, dtype=torch.int32, device=dev)
+    need = []
+    for v in range(V):
+        P.seele_preprocess(g, [cams[v]], st, None, splats0, nt0)
+        need.append(int(nt0.sum(dtype=torch.int64).item()))
+    del splats0, nt0
+    capacity = int(max(need) * 1.02) + 4096
+    K = stages
+    bufs = []
+    for _ in range(K):
+        bufs.append(dict(
+            splats=torch.empty((n, P.pipeline.SPLAT_FLOATS), dtype=torch.float32, device=dev),
+            n_tiles=torch.empty(n, dtype=torch.int32, device=dev),
+            ws=torch.empty(P.pipeline.bin_sort_workspace_size(n, capacity, TT),
+                           dtype=torch.uint8, device=dev),
+            ids=torch.empty(capacity, dtype=torch.int32, device=dev),
+            keys=torch.empty(capacity, dtype=torch.int32, device=dev),
+            ranges=torch.empty((NS, 2), dtype=torch.int32, device=dev),
+            npairs=torch.empty(2, dtype=torch.int64, device=dev),
+            image=torch.empty(3 * npix, dtype=torch.float32, device=dev),
+            final_T=torch.empty(npix, dtype=torch.float32, device=dev),
+            n_contrib=torch.empty(npix, dtype=torch.int32, device=dev)))
+    npairs_log = torch.zeros(steps, dtype=torch.int64, device=dev)
+    # default-priority streams: preprocessing, binning (the first one when
+    # stages=2), rasterisation
+    s_pre = torch.cuda.Stream()
+    s_bin = torch.cuda.Stream() if K == 3 else s_pre
+    s_ras = torch.cuda.Stream()
+    prepped = [torch.cuda.Event() for _ in range(K)]
+    binned = [torch.cuda.Event() for _ in range(K)]
+    rastered = [torch.cuda.Event() for _ in range(K)]
+    torch.cuda.synchronize()
+
+    def frame(i, log_i=None):
+        k = i % K
+        b = bufs[k]
+        cam = [cams[i % V]]
+        with torch.cuda.stream(s_pre):
+            if i >= K:
+                s_pre.wait_event(rastered[k])  # frame i - K is done with b
+            P.seele_preprocess_staged(g, cam, st, capacity, b["ws"], None, b["splats"],
+                                      b["n_tiles"])
+            prepped[k].record(s_pre)
+        with torch.cuda.stream(s_bin):
+            s_bin.wait_event(prepped[k])
+            P.seele_bin_sort_ex(b["splats"], b["n_tiles"], n, cam, st.tile, capacity, b["ws"],
+                                b["ids"], b["ranges"], b["npairs"], b["keys"],
+                                super_lists=True, staged=True)
+            if log_i is not None:
+                npairs_log[log_i:log_i + 1].copy_(b["npairs"][-1:], non_blocking=True)
+            binned[k].record(s_bin)
+        with torch.cuda.stream(s_ras):
+            s_ras.wait_event(binned[k])
+            P.seele_rasterize_fwd_super(b["splats"], b["keys"], b["ids"], b["ranges"], cam, st,
+                                        b["image"], b["final_T"], b["n_contrib"], None)
+            rastered[k].record(s_ras)
+
+    for i in range(warmup):
+        frame(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        frame(warmup + i, i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert int(npairs_log.max().item()) <= capacity, "pair buffer overflow in the timed region"
+    # the last frame equals the same view rendered alone on one stream
+    last = bufs[(warmup + steps - 1) % K]
+    ref = P.Renderer(st, capacity=capacity, lists="super").render(
+        g, [cams[(warmup + steps - 1) % V]])
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ref.image, last["image"]))
+    ms = 1000.0 * wall / steps
+    out = dict(fps=1000.0 / ms, ms_per_frame=ms, frames_in_flight=K, equal_to_sequential=same)
+    log(f"[bench] {name} ({K} frames in flight): {out['fps']:.1f} fps ({ms:.3f} ms/frame), "
+        f"last frame equal to a single render: {same}")
+    del bufs, ref
+    torch.cuda.empty_cache()
     return out
 
 
@@ -858,6 +962,9 @@ def main():
     results = {}
     for name in names:
         results[name] = run_form(name, forms[name], cams, args.steps, args.warmup, args.lists)
+        if name == "plain" and args.lists == "super" and not args.no_pipelined:
+            results[name]["pipelined"] = run_form_pipelined(name, forms[name], cams, args.steps,
+                                                            args.warmup, 2)
         if "extra" in forms[name]:
             results[name].update(forms[name]["extra"])
         if "full_g" in forms[name]:
