@@ -266,9 +266,19 @@ __global__ void k_gather_gaussians(seele_gaussians src, const int64_t* __restric
   for (int k = 0; k < n_sh; ++k) dst.sh[k * nd + c] = src.sh[k * ns + i];
 }
 
-__global__ void k_fill_f32(float* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0f;
+// Zeroes p[0, n) (p 4-byte aligned): the body with 16-byte stores over a
+// bounded grid, the up to three floats before the first 16-byte boundary
+// and after the last one singly.
+__global__ __launch_bounds__(256) void k_zero_f32(float* p, int64_t n) {
+  const int64_t lead = (int64_t)((16u - ((uint32_t)(uintptr_t)p & 15u)) & 15u) / 4;
+  const int64_t head = lead < n ? lead : n;
+  const int64_t nq = (n - head) / 4;
+  const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float4* q = reinterpret_cast<float4*>(p + head);
+  for (int64_t i = tid; i < nq; i += (int64_t)gridDim.x * 256) q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (tid < head) p[tid] = 0.0f;
+  const int64_t t0 = head + 4 * nq;
+  if (tid < n - t0) p[t0 + tid] = 0.0f;
 }
 
 }  // namespace
@@ -800,7 +810,8 @@ int32_t rasterize_bwd_impl(bool super, const seele_gaussians* g, const seele_cam
   hipStream_t st = static_cast<hipStream_t>(stream);
   // 1. per-record 2D gradients, accumulated by the blend backward
   const int64_t n2 = R * 9;
-  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, grad2d, n2);
+  hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)std::min<int64_t>((n2 / 4 + 255) / 256 + 1, 4096)),
+                     dim3(256), 0, st, grad2d, n2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "grad2d reset");
   const RasterParams rp = make_raster_params(ropts);
