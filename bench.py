@@ -940,8 +940,9 @@ def main():
         print(json.dumps(cpu_baseline(args.n, args.cpu_tiles)))
         return
     if args.gpus != 1:
-        print("this benchmark runs on one GPU only (the hot path shards by view with no "
-              "exchange; multi-GPU runs are not part of this build)", file=sys.stderr)
+        print("this benchmark runs on one GPU only: the renderer shards by view with no "
+              "exchange between GPUs, and only the one-GPU path is implemented and measured",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -49,7 +49,7 @@ extern "C" {
 enum {
   SEELE_OK = 0,
   SEELE_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, bad size or option */
-  SEELE_ERR_UNSUPPORTED = 2,  /* valid but not supported by this build       */
+  SEELE_ERR_UNSUPPORTED = 2,  /* valid but not supported by this library     */
   SEELE_ERR_CAPACITY = 3,     /* a caller buffer is too small                */
   SEELE_ERR_HIP = 4           /* a HIP runtime call or launch failed         */
 };
